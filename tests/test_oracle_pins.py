@@ -1,0 +1,402 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these tests compares the oracle with itself: each one checks it
+against a closed form, an invariant the paper proves, an independent
+derivation (Algorithm 1, Newton on the central-path system, the first form of
+the projection formula), a library routine (HiGHS) or brute force.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+import lpgen
+import oracle
+from oracle.abip import Problem, Settings
+
+FAST = [(3, 6, 1), (3, 6, 4), (4, 8, 4), (4, 8, 6), (12, 30, 2), (12, 30, 4)]
+
+
+def _prob(lp):
+    return Problem(lp["A"], lp["b"], lp["c"])
+
+
+# --------------------------------------------------------------------------
+# HSD embedding (Section 3.1)
+# --------------------------------------------------------------------------
+
+def test_Q_is_skew_symmetric_and_matches_implicit_apply():
+    lp = lpgen.dense_planted(7, 13, 0)
+    prob = _prob(lp)
+    Q = oracle.assemble_Q(prob)
+    assert np.array_equal(Q, -Q.T)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        u = rng.standard_normal(7 + 13 + 2)
+        Qu = oracle.apply_Q(prob, u)
+        np.testing.assert_allclose(Qu, Q @ u, rtol=0, atol=1e-12 * np.abs(Q).max() * np.abs(u).sum())
+        assert abs(u @ Qu) <= 1e-13 * (u @ u) * np.linalg.norm(Q, 2)
+
+
+def test_hsd_constants_closed_form():
+    A = np.array([[1.0, 2.0, 0.0], [0.0, -1.0, 3.0]])
+    b = np.array([4.0, 5.0])
+    c = np.array([1.0, -2.0, 0.5])
+    bbar, cbar, zbar = oracle.hsd_constants(Problem(A, b, c))
+    np.testing.assert_array_equal(bbar, [4.0 - 3.0, 5.0 - 2.0])
+    np.testing.assert_array_equal(cbar, [0.0, -3.0, -0.5])
+    assert zbar == 1.0 - 2.0 + 0.5 + 1.0
+
+
+def test_initial_point_is_central_and_inner_test_passes_at_once():
+    """Q u0 = v0 exactly at (y,x,tau,theta) = (0,e,1,1), (s,kappa,xi) = (e,1,-(n+1)),
+    so the first inner test passes and N_0 = 0 (Algorithm 2; Lemma 3.3's proof)."""
+    lp = lpgen.dense_planted(6, 11, 3)
+    prob = _prob(lp)
+    st = oracle.initial_state(prob, Settings())
+    r = oracle.apply_Q(prob, st.u()) - st.v()
+    assert np.abs(r).max() <= 1e-12 * (1 + np.abs(lp["A"]).sum())
+    out = oracle.solve(prob, settings=Settings(max_admm_iters=3))
+    assert out["inner_counts"][0] == 0
+
+
+# --------------------------------------------------------------------------
+# The affine step (eq. Simple-Update:Affine, Section 4.4)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n", [(1, 2), (5, 9), (20, 45)])
+def test_schur_solver_equals_projection_definition(m, n):
+    lp = lpgen.dense_planted(m, n, m + n)
+    prob = _prob(lp)
+    Q = oracle.assemble_Q(prob)
+    N = m + n + 2
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(N)
+    ut = oracle.SchurIQSolver(prob).solve(w)
+    ud = oracle.DenseIQSolver(prob).solve(w)
+    # (I + Q) u~ = w  <=>  u~ + Q u~ = u + v  (Theorem 3.1, step 1)
+    assert np.linalg.norm(ut + Q @ ut - w) <= 1e-12 * np.linalg.norm(w) * (1 + np.linalg.norm(Q, 2))
+    np.testing.assert_allclose(ut, ud, rtol=0, atol=1e-11 * np.linalg.norm(w))
+    # first form of eq. (Simple-Update:Affine): projection of (w, w) onto {Qu = v}
+    up = np.linalg.solve(np.eye(N) + Q.T @ Q, (np.eye(N) - Q) @ w)
+    np.testing.assert_allclose(ut, up, rtol=0, atol=1e-9 * np.linalg.norm(w))
+    assert abs(ut @ (Q @ ut)) <= 1e-12 * (ut @ ut) * np.linalg.norm(Q, 2)
+
+
+# --------------------------------------------------------------------------
+# The barrier prox (eqs. Simple-Update:Barrier-X / -tau)
+# --------------------------------------------------------------------------
+
+def _bisect_prox(w, t):
+    """argmin_{z>0} -t log z + (z-w)^2/2 by bisection on the derivative z - w - t/z."""
+    lo, hi = 1e-300, max(1.0, abs(w)) * 4 + 4 * math.sqrt(t) + 1
+    for _ in range(2000):
+        mid = 0.5 * (lo + hi) if hi / lo < 4 else math.sqrt(lo * hi)
+        if mid - w - t / mid > 0:
+            hi = mid
+        else:
+            lo = mid
+        if hi - lo <= 1e-16 * hi:
+            break
+    return 0.5 * (lo + hi)
+
+
+def _decimal_root(w, t):
+    """Positive root of z^2 - w z - t = 0 in 60-digit decimal arithmetic."""
+    import decimal
+    ctx = decimal.Context(prec=60)
+    W = decimal.Decimal(float(w))
+    T = decimal.Decimal(float(t))
+    r = ctx.sqrt(W * W + 4 * T)
+    z = (W + r) / 2 if W >= 0 else (2 * T) / (r - W)
+    return float(z)
+
+
+def test_prox_is_positive_root_and_minimiser():
+    rng = np.random.default_rng(0)
+    ws = np.concatenate([rng.standard_normal(50) * 10, [0.0, -1e8, 1e8, -3e-3]])
+    for t in [1.0, 1e-4, 1e-10]:
+        z = oracle.barrier_prox(ws, t)
+        assert np.all(z > 0)
+        for w, zz in zip(ws, z):
+            assert abs(zz - _decimal_root(w, t)) <= 4e-16 * zz
+        for w, zz in zip(ws[:10], z[:10]):
+            assert abs(zz - _bisect_prox(w, t)) <= 1e-12 * max(1.0, zz) + 1e-15
+    # far in the tail the root is t/|w| to first order; the naive form rounds to 0
+    z = oracle.barrier_prox(np.array([-1e8]), 1e-10)[0]
+    assert abs(z - 1e-18) <= 1e-24
+
+
+# --------------------------------------------------------------------------
+# Theorem 3.1 and Algorithm 1
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha", [1.0, 1.8])
+@pytest.mark.parametrize("rule", ["heuristic", "sqrt"])
+def test_theorem31_invariants_along_iterations(alpha, rule):
+    lp = lpgen.dense_planted(6, 14, 2)
+    prob = _prob(lp)
+    s = Settings(alpha=alpha, restart_rule=rule, gamma=0.5)
+    solver = oracle.SchurIQSolver(prob)
+    st = oracle.initial_state(prob, s)
+    n = prob.n
+    for k in range(4):
+        for i in range(25):
+            st, v = oracle.admm_iteration(prob, solver, st, s, return_v=True)
+            t = st.mu / s.beta
+            np.testing.assert_allclose(st.x * st.s, t, rtol=1e-10)
+            assert abs(st.tau * st.kappa - t) <= 1e-10 * t
+            assert np.abs(v[:prob.m]).max() <= 1e-12 * (1 + np.abs(st.y).max())
+            assert abs(v[-1] + (n + 1)) <= 1e-12 * (n + 1)
+            assert np.all(st.x > 0) and np.all(st.s > 0) and st.tau > 0 and st.kappa > 0
+        st = oracle.restart(st, s.gamma, rule)
+        np.testing.assert_allclose(st.x * st.s, st.mu / s.beta, rtol=1e-12)
+        assert abs(st.tau * st.kappa - st.mu / s.beta) <= 1e-12 * st.mu
+
+
+def test_algorithm1_equals_algorithm2():
+    """Theorem 3.1: with p0 = v0, q0 = u0 the explicit-multiplier ADMM produces
+    the same (u, v) as the simplified iteration (alpha = 1), including after a
+    sqrt(gamma) restart that re-initialises p = v, q = u."""
+    lp = lpgen.dense_planted(3, 7, 11)
+    prob = _prob(lp)
+    s = Settings(alpha=1.0, gamma=0.5, restart_rule="sqrt")
+    solver = oracle.DenseIQSolver(prob)
+    st = oracle.initial_state(prob, s)
+    for stage in range(2):
+        z = oracle.alg1_initial(st)
+        for i in range(40):
+            st = oracle.admm_iteration(prob, solver, st, s)
+            z = oracle.alg1_iteration(prob, z, st.mu, s.beta)
+            np.testing.assert_allclose(z["u"], st.u(), rtol=1e-8, atol=1e-10)
+            np.testing.assert_allclose(z["v"], st.v(), rtol=1e-8, atol=1e-10)
+            np.testing.assert_allclose(z["p"], st.v(), rtol=1e-8, atol=1e-10)
+            np.testing.assert_allclose(z["q"], st.u(), rtol=1e-8, atol=1e-10)
+        st = oracle.restart(st, s.gamma, "sqrt")
+
+
+# --------------------------------------------------------------------------
+# Inner loop at fixed mu: central point, Lemma 3.2
+# --------------------------------------------------------------------------
+
+def test_central_point_solves_hsd_log_kkt():
+    lp = lpgen.dense_planted(5, 12, 1)
+    prob = _prob(lp)
+    t = 0.05
+    cp = oracle.central_point(prob, t=t)
+    r = oracle.apply_Q(prob, cp.u()) - cp.v()
+    assert np.abs(r).max() < 1e-10
+    np.testing.assert_allclose(cp.x * cp.s, t, rtol=1e-10)
+    assert abs(cp.tau * cp.kappa - t) < 1e-12
+    assert abs(cp.theta - t) < 1e-10          # theta = mu/beta on the central path
+
+
+def test_inner_loop_converges_monotonically_to_central_point():
+    """Lemma 3.2 (alpha = 1): ||u_i - u*||^2 + ||v_i - v*||^2 is non-increasing
+    and tends to 0; theta_i tends to mu/beta."""
+    lp = lpgen.dense_planted(5, 12, 1)
+    prob = _prob(lp)
+    s = Settings(alpha=1.0, gamma=0.2, restart_rule="heuristic")
+    solver = oracle.SchurIQSolver(prob)
+    st = oracle.initial_state(prob, s)
+    st = oracle.restart(st, s.gamma, s.restart_rule)       # mu^1 = gamma * beta
+    t = st.mu / s.beta
+    cp = oracle.central_point(prob, t=t)
+    dist = []
+    for i in range(3000):
+        d = np.sum((st.u() - cp.u()) ** 2) + np.sum((st.v() - cp.v()) ** 2)
+        dist.append(d)
+        st = oracle.admm_iteration(prob, solver, st, s)
+    dist = np.array(dist)
+    assert np.all(np.diff(dist) <= 1e-12 * dist[:-1] + 1e-28)
+    assert dist[-1] < 1e-16 * dist[0] + 1e-20
+    assert abs(st.theta - t) < 1e-8
+
+
+def test_outer_count_in_mu_stop_mode():
+    """With the outer loop stopped once mu^k < eps, the number of outer
+    iterations is ceil(log(mu0/eps)/log(1/gamma)) (proof of Theorem 3.5)."""
+    lp = lpgen.dense_planted(4, 8, 4)
+    for gamma, eps in [(0.5, 3e-3), (0.3, 1e-4), (0.9, 0.2)]:
+        s = Settings(gamma=gamma, mu_stop=eps, beta=1.0)
+        out = oracle.solve(lp["A"], lp["b"], lp["c"], s)
+        assert out["status"] == oracle.MU_STOP
+        expect = math.ceil(math.log(1.0 / eps) / math.log(1.0 / gamma))
+        assert out["ipm_iters"] == expect
+
+
+# --------------------------------------------------------------------------
+# End to end: LP optimum and certificates (Theorems 2.1-2.3, Section 4.1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,seed", FAST[:4])
+def test_solution_matches_vertex_enumeration(m, n, seed):
+    lp = lpgen.dense_planted(m, n, seed)
+    out = oracle.solve(lp["A"], lp["b"], lp["c"], Settings(eps=1e-7))
+    assert out["status"] == oracle.SOLVED
+    pstar, xstar = oracle.vertex_enumeration(lp["A"], lp["b"], lp["c"])
+    assert abs(out["info"]["pobj"] - pstar) <= 1e-5 * (1 + abs(pstar))
+    np.testing.assert_allclose(out["x"], xstar, atol=1e-4)
+    np.testing.assert_allclose(out["x"], lp["x0"], atol=1e-4)     # planted, unique
+    np.testing.assert_allclose(out["y"], lp["y0"], atol=1e-4)
+
+
+@pytest.mark.parametrize("m,n,seed", FAST[4:])
+def test_solution_matches_highs(m, n, seed):
+    lp = lpgen.dense_planted(m, n, seed)
+    out = oracle.solve(lp["A"], lp["b"], lp["c"], Settings(eps=1e-7))
+    assert out["status"] == oracle.SOLVED
+    ref = scipy.optimize.linprog(lp["c"], A_eq=lp["A"], b_eq=lp["b"], bounds=(0, None), method="highs")
+    assert ref.status == 0
+    assert abs(out["info"]["pobj"] - ref.fun) <= 1e-6 * (1 + abs(ref.fun))
+    kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], out["x"], out["y"], out["s"])
+    assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-7
+
+
+def test_toy_two_var_closed_form():
+    lp = lpgen.toy_two_var()
+    out = oracle.solve(lp["A"], lp["b"], lp["c"], Settings(eps=1e-8))
+    assert out["status"] == oracle.SOLVED
+    np.testing.assert_allclose(out["x"], lp["xstar"], atol=1e-6)
+    np.testing.assert_allclose(out["y"], lp["ystar"], atol=1e-6)
+    np.testing.assert_allclose(out["s"], lp["sstar"], atol=1e-6)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_toy_simplex_closed_form(seed):
+    lp = lpgen.toy_simplex(6, seed)
+    out = oracle.solve(lp["A"], lp["b"], lp["c"], Settings(eps=1e-8))
+    assert out["status"] == oracle.SOLVED
+    assert abs(out["info"]["pobj"] - lp["pstar"]) <= 1e-6
+    np.testing.assert_allclose(out["x"], lp["xstar"], atol=1e-5)
+
+
+def test_toy_primal_infeasible_certificate():
+    lp = lpgen.toy_primal_infeasible()
+    out = oracle.solve(lp["A"], lp["b"], lp["c"], Settings())
+    assert out["status"] == oracle.PRIMAL_INFEASIBLE
+    np.testing.assert_allclose(out["y"], lp["certificate"], atol=1e-9)   # y / (b^T y)
+    st = out["state"]
+    assert st.kappa > st.tau            # Theorem 2.2 (ii): tau -> 0, kappa > 0
+
+
+def test_toy_dual_infeasible_certificate():
+    lp = lpgen.toy_dual_infeasible()
+    out = oracle.solve(lp["A"], lp["b"], lp["c"], Settings())
+    assert out["status"] == oracle.DUAL_INFEASIBLE
+    x = out["x"]
+    assert abs(lp["c"] @ x + 1.0) < 1e-12           # -x / (c^T x) has c^T x = -1
+    np.testing.assert_allclose(x / np.linalg.norm(x), lp["ray"], atol=1e-6)
+
+
+def test_planted_farkas_infeasible():
+    lp = lpgen.dense_farkas_infeasible(20, 50, 3)
+    A, b = lp["A"], lp["b"]
+    assert np.all(A.T @ lp["farkas"] < 0) and abs(b @ lp["farkas"] - 1) < 1e-9   # generator check
+    out = oracle.solve(A, b, lp["c"], Settings())
+    assert out["status"] == oracle.PRIMAL_INFEASIBLE
+    y, s = out["y"], out["s"]
+    assert abs(b @ y - 1.0) < 1e-12
+    assert np.linalg.norm(A.T @ y + s) <= 1e-6 / np.linalg.norm(b) * 1.0000001
+    assert np.all(s >= 0)
+
+
+def test_basis_pursuit_recovers_l1_optimum():
+    lp = lpgen.basis_pursuit(20, 40, 3, 7)
+    out = oracle.solve(lp["A"], lp["b"], lp["c"], Settings(eps=1e-7))
+    assert out["status"] == oracle.SOLVED
+    assert abs(out["info"]["pobj"] - lp["pstar"]) <= 1e-5 * (1 + lp["pstar"])
+    N = lp["n"] // 2
+    np.testing.assert_allclose(out["x"][:N] - out["x"][N:], lp["x_true"], atol=1e-4)
+
+
+# --------------------------------------------------------------------------
+# Derivative references
+# --------------------------------------------------------------------------
+
+def test_kkt_adjoint_matches_finite_differences_of_central_point():
+    """The dense adjoint at a central point equals central differences of the
+    central point itself (an independent Newton solve per perturbation)."""
+    lp = lpgen.dense_planted(3, 7, 2)
+    A, b, c = lp["A"], lp["b"], lp["c"]
+    w = np.random.default_rng(9).standard_normal(7)
+    t = 1e-3
+    cp = oracle.central_point(A, b, c, t=t)
+    lam = oracle.kkt_adjoint(A, b, c, cp, w)
+    g = oracle.contract_adjoint(A, b, c, cp, lam, want_A=True)
+
+    def L(A_, b_, c_):
+        p = oracle.central_point(A_, b_, c_, t=t)
+        return w @ p.x / p.tau
+
+    h = 1e-6
+    for k in range(7):
+        e = np.zeros(7)
+        e[k] = h
+        fd = (L(A, b, c + e) - L(A, b, c - e)) / (2 * h)
+        assert abs(fd - g["dc"][k]) <= 1e-5 * (1 + abs(fd))
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        fd = (L(A, b + e, c) - L(A, b - e, c)) / (2 * h)
+        assert abs(fd - g["db"][i]) <= 1e-5 * (1 + abs(fd))
+    for (i, j) in [(0, 0), (1, 3), (2, 6)]:
+        E = np.zeros_like(A)
+        E[i, j] = h
+        fd = (L(A + E, b, c) - L(A - E, b, c)) / (2 * h)
+        assert abs(fd - g["dA"][i, j]) <= 1e-5 * (1 + abs(fd))
+
+
+def test_basis_gradients_match_finite_differences_and_small_t_adjoint():
+    lp = lpgen.dense_planted(4, 9, 5)
+    A, b, c = lp["A"], lp["b"], lp["c"]
+    w = np.random.default_rng(2).standard_normal(9)
+    bg = oracle.basis_gradients(A, b, lp["basis"], w)
+    h = 1e-5
+
+    def Lb(b_):
+        return w @ oracle.basis_gradients(A, b_, lp["basis"], w)["x"]
+
+    for i in range(4):
+        e = np.zeros(4)
+        e[i] = h
+        assert abs((Lb(b + e) - Lb(b - e)) / (2 * h) - bg["db"][i]) < 1e-8
+    # as t -> 0 the central-path derivative tends to the basis derivative
+    cp = oracle.central_point(A, b, c, t=1e-10)
+    g = oracle.contract_adjoint(A, b, c, cp, oracle.kkt_adjoint(A, b, c, cp, w), want_A=True)
+    np.testing.assert_allclose(g["db"], bg["db"], atol=1e-6 * (1 + np.abs(bg["db"]).max()))
+    np.testing.assert_allclose(g["dc"], 0.0, atol=1e-6 * np.linalg.norm(w))
+    np.testing.assert_allclose(g["dA"], bg["dA"], atol=1e-6 * (1 + np.abs(bg["dA"]).max()))
+
+
+# --------------------------------------------------------------------------
+# Planted mistakes: each pin above must notice a plausible bug in the oracle
+# --------------------------------------------------------------------------
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    lp = lpgen.dense_planted(3, 7, 11)
+    prob = _prob(lp)
+    # (1) wrong sign of zbar in Q: the central start point is no longer central
+    orig = oracle.abip.hsd_constants
+    monkeypatch.setattr(oracle.abip, "hsd_constants",
+                        lambda p: (lambda bb, cb, zb: (bb, cb, -zb))(*orig(p)))
+    st = oracle.initial_state(prob, Settings())
+    r = oracle.apply_Q(prob, st.u()) - st.v()
+    assert np.abs(r).max() > 1e-3
+    monkeypatch.setattr(oracle.abip, "hsd_constants", orig)
+    # (2) prox root with the wrong sign of the square root: Algorithm 1 disagrees
+    good = oracle.abip.barrier_prox
+    monkeypatch.setattr(oracle.abip, "barrier_prox",
+                        lambda w, t: np.abs(0.5 * (w - np.sqrt(w * w + 4 * t))))
+    s = Settings(alpha=1.0)
+    st = oracle.initial_state(prob, s)
+    st.mu = 0.5
+    st.x = st.x * np.sqrt(0.5)
+    st.s = st.s * np.sqrt(0.5)
+    st.tau = st.kappa = np.sqrt(0.5)
+    z = oracle.alg1_initial(st)
+    st2 = oracle.admm_iteration(prob, oracle.DenseIQSolver(prob), st, s)
+    monkeypatch.setattr(oracle.abip, "barrier_prox", good)
+    z2 = oracle.alg1_iteration(prob, z, st.mu, s.beta)
+    assert np.abs(z2["u"] - st2.u()).max() > 1e-3
