@@ -1,0 +1,211 @@
+/*
+ * abip.h -- C ABI of the MI355X (gfx950) ABIP solver library (libabip.so).
+ *
+ * ABIP is the ADMM-based interior-point method of Lin, Ma, Ye and Zhang
+ * ("An ADMM-Based Interior-Point Method for Large-Scale Linear Programming",
+ * arXiv:1805.12344).  It solves the standard-form pair
+ *
+ *     (P)  min c^T x  s.t.  A x = b, x >= 0
+ *     (D)  max b^T y  s.t.  A^T y + s = c, s >= 0          (Section 2)
+ *
+ * through the homogeneous self-dual embedding Q u = v of Section 3.1, running
+ * the simplified ADMM of Algorithm 2 (with the over-relaxation of Section 4.2)
+ * inside a path-following loop on the barrier parameter mu, and stopping on the
+ * optimality / infeasibility tests of Section 4.1.
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers (hipMalloc'd or torch-allocated
+ *     memory on the current HIP device) unless the comment says "host".
+ *     Matrices are FP64; dense A is row-major m x n; CSR uses int32 indices.
+ *   - abip_setup* copies A, b, c into the library's own device memory; the
+ *     caller may free its buffers as soon as the call returns.  The returned
+ *     work handle owns every device buffer (data copies, the cached factor of
+ *     G = I + A A^T, the border of the Schur reduction, the iterate) until
+ *     abip_free.
+ *   - Output vectors belong to the caller and must hold the stated length.
+ *   - Work is enqueued on the stream given at setup (a hipStream_t, passed as
+ *     void*; NULL means the null stream).  Entry points that return results in
+ *     host structs (abip_info) synchronise that stream before returning.
+ *   - Errors are negative return codes; abip_last_error() returns a
+ *     thread-local message for the last failing call on that thread.  No
+ *     exception or exit() crosses the ABI.  Non-convergence is not an error:
+ *     it is reported as status ABIP_MAX_ITERS in abip_info.
+ *   - Calls on one work handle must not overlap (they share its buffers).
+ */
+#ifndef ABIP_H
+#define ABIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes (return values) ---------------------------------------- */
+#define ABIP_OK            0
+#define ABIP_E_INVALID    -1   /* bad argument: null pointer, bad enum value */
+#define ABIP_E_DIM        -2   /* bad or unsupported dimensions */
+#define ABIP_E_NONFINITE  -3   /* NaN or Inf in A, b or c */
+#define ABIP_E_HIP        -4   /* a HIP runtime call failed */
+#define ABIP_E_OOM        -5   /* device allocation failed */
+#define ABIP_E_STATE      -6   /* call out of order (e.g. backward before solve) */
+
+/* ---- solve status (abip_info.status), Theorems 2.2-2.3 and Section 4.1 --- */
+#define ABIP_UNSOLVED            0
+#define ABIP_SOLVED              1  /* (x/tau, y/tau, s/tau) meets the three tests */
+#define ABIP_PRIMAL_INFEASIBLE   2  /* y / (b^T y) is a certificate (Section 4.1) */
+#define ABIP_DUAL_INFEASIBLE     3  /* -x / (c^T x) is a certificate (Section 4.1) */
+#define ABIP_MAX_ITERS           4  /* max_admm_iters reached; last iterate returned */
+
+/* ---- enums --------------------------------------------------------------- */
+#define ABIP_DENSE_ROWMAJOR  0
+#define ABIP_CSR             1
+
+#define ABIP_PREC_FP64       0  /* every step in FP64 */
+#define ABIP_PREC_FP32_POLISH 1 /* A and G^{-1} streamed in FP32 (FP64 accumulation,
+                                   FP64 iterate), FP64 factor and checks, then FP64
+                                   iterations until the FP64 tests pass */
+
+#define ABIP_RESTART_HEURISTIC 0 /* Section 5: scale the smaller of (x_j,s_j), (tau,kappa) */
+#define ABIP_RESTART_SQRT      1 /* eq. (update-next-iterate): everything times sqrt(gamma) */
+
+#define ABIP_LIN_AUTO    0  /* dense -> direct, CSR -> CG */
+#define ABIP_LIN_DIRECT  1  /* cached FP64 factorization of G = I + A A^T */
+#define ABIP_LIN_CG      2  /* Jacobi-preconditioned CG on G, matrix-free (CSR) */
+
+#define ABIP_ENGINE_AUTO   0 /* pick by size */
+#define ABIP_ENGINE_WG     1 /* one workgroup owns one LP for the whole solve (persistent) */
+#define ABIP_ENGINE_GRID   2 /* one LP spread over the whole GPU, a few kernels per iteration */
+
+/* Run parameters.  eps is used for all five tolerances of Section 4.1
+ * (eps_pres = eps_dres = eps_gap = eps_pinf = eps_dinf, as in Section 5). */
+typedef struct {
+    double  eps;               /* default 1e-6 */
+    double  alpha;             /* over-relaxation in [0,2], Section 4.2; default 1.8 */
+    double  beta;              /* penalty parameter, mu^0 = beta (Algorithm 2); default 1 */
+    double  gamma;             /* mu reduction factor in (0,1); default 0.5 */
+    int64_t max_admm_iters;    /* default 1e6 (Section 5) */
+    int32_t restart_rule;      /* ABIP_RESTART_*; default heuristic */
+    int32_t precision;         /* ABIP_PREC_*; default FP64 */
+    int32_t lin_solver;        /* ABIP_LIN_*; default auto */
+    int32_t engine;            /* ABIP_ENGINE_*; default auto */
+    int64_t fp32_max_iters;    /* FP32 phase length cap before the FP64 polish
+                                  starts regardless; default 1e6 */
+    double  cg_tol;            /* CG relative tolerance floor; default 1e-10 */
+    int32_t cg_max_iters;      /* per linear solve; default 500 */
+    int32_t block_threads;     /* threads per workgroup for ENGINE_WG; 0 = auto */
+    double  adjoint_tol;       /* relative change that stops the adjoint iteration; default 1e-10 */
+    int64_t adjoint_max_iters; /* default 2e5 */
+} abip_settings;
+
+/* Per-LP result summary (host struct). */
+typedef struct {
+    int32_t status;            /* ABIP_SOLVED ... ABIP_MAX_ITERS */
+    int64_t admm_iters;        /* ADMM updates, all phases */
+    int64_t admm_iters_fp64;   /* of which FP64 (polish or plain) */
+    int64_t ipm_iters;         /* outer (mu) iterations */
+    int64_t cg_iters;          /* total CG iterations (CG solver only) */
+    double  pres, dres, gap;   /* relative residuals of Section 4.1 at the last check */
+    double  pobj, dobj;        /* c^T x / tau, b^T y / tau at the last check */
+    double  tau, kappa, theta, mu;
+    double  setup_ms, solve_ms;/* wall time of setup and of the solve (host clock) */
+} abip_info;
+
+/* A matrix description.  All pointers are device pointers. */
+typedef struct {
+    int32_t m, n;
+    int32_t format;            /* ABIP_DENSE_ROWMAJOR or ABIP_CSR */
+    const double*  val;        /* dense: m*n entries; CSR: nnz values */
+    const int32_t* rowptr;     /* CSR: m+1 offsets (unused for dense) */
+    const int32_t* colidx;     /* CSR: nnz column indices (unused for dense) */
+    int64_t nnz;               /* CSR only */
+} abip_matrix;
+
+typedef struct abip_work abip_work;
+
+/* Fill *s with the defaults listed above.  Returns ABIP_E_INVALID on NULL. */
+int abip_default_settings(abip_settings* s);
+
+/* Set up one LP: validate (dimensions, finiteness), copy A, b, c to the
+ * library, form the HSD constants bbar = b - A e, cbar = c - e,
+ * zbar = c^T e + 1 (eq. bar-b-c-z-re), factor G = I + A A^T once in FP64
+ * (Section 4.4; dense) or prepare CG (CSR), and cache the border Z = M^{-1} H
+ * and K^{-1} of the Schur reduction of I + Q (Section 4.4, with the theta
+ * column kept).  b has length m, c length n.  settings may be NULL (defaults;
+ * host pointer).  stream: hipStream_t or NULL.  On success *out owns all of it. */
+int abip_setup(abip_work** out, const abip_matrix* A, const double* b, const double* c,
+               const abip_settings* settings, void* stream);
+
+/* Set up B independent LPs of any sizes in one work handle (all host arrays of
+ * B entries; each A[k], b[k], c[k] as in abip_setup).  Dense only. */
+int abip_setup_batch(abip_work** out, int32_t B, const abip_matrix* A,
+                     const double* const* b, const double* const* c,
+                     const abip_settings* settings, void* stream);
+
+/* Run Algorithm 2 from its start point (mu^0 = beta, (y,x,tau,theta) = (0,e,1,1),
+ * (s,kappa) = (e,1)) until a test of Section 4.1 passes or max_admm_iters.
+ * Outputs (device, caller-owned): x (n), y (m), s (n):
+ *   SOLVED / MAX_ITERS: x/tau, y/tau, s/tau;
+ *   PRIMAL_INFEASIBLE: y/(b^T y), s/(b^T y), x filled with NaN;
+ *   DUAL_INFEASIBLE:   -x/(c^T x), y and s filled with NaN.
+ * Any output pointer may be NULL to skip it.  info (host) may be NULL.
+ * Requires a work handle made by abip_setup (B = 1). */
+int abip_solve(abip_work* w, double* x, double* y, double* s, abip_info* info);
+
+/* Solve every LP of a batch handle in one persistent launch (one workgroup per
+ * LP, taken from a device work queue, largest first).  x, y, s, info are host
+ * arrays of B entries (device vectors / host structs); entries may be NULL. */
+int abip_solve_batch(abip_work* w, double* const* x, double* const* y, double* const* s,
+                     abip_info* info);
+
+/* Adjoint of the converged HSD fixed point (project extension, not in the paper).
+ * For the loss L(x*) with gradient dL_dx (device, n) at the returned x* = x/tau,
+ * solve the adjoint of the linearised ADMM fixed-point map at the final iterate
+ * by fixed-point iteration (each step reuses the cached factor: (I+Q)^T = I - Q
+ * reduces to the same G), then contract with d(Q u)/d(c, b, A).
+ * Outputs (device, caller-owned): dL_dc (n), dL_db (m), dL_dA (m*n row-major,
+ * may be NULL).  Requires a prior successful abip_solve with status SOLVED,
+ * else ABIP_E_STATE. */
+int abip_backward(abip_work* w, const double* dL_dx, double* dL_dc, double* dL_db,
+                  double* dL_dA);
+
+/* Batched form of abip_backward over a batch handle after abip_solve_batch;
+ * host arrays of B device pointers (dL_dA entries may be NULL). */
+int abip_backward_batch(abip_work* w, const double* const* dL_dx, double* const* dL_dc,
+                        double* const* dL_db, double* const* dL_dA);
+
+/* ---- step-level entry points (parity testing and tracing) ----------------
+ * These expose the pieces of one inner iteration so that each can be compared
+ * with an FP64 reference on identical inputs. */
+
+/* (I+Q)^{-1} w for LP k of the handle (eq. Simple-Update:Affine) using the cached
+ * factor: w and out are device vectors of length m+n+2 ordered (y, x, tau, theta).
+ * FP64 data unless use_fp32 != 0. */
+int abip_apply_iq(abip_work* w, int32_t k, const double* win, double* out, int32_t use_fp32);
+
+/* Load an iterate into LP k: y (m), x (n), s (n) device vectors and host scalars
+ * tau, kappa, theta, mu.  Marks the LP as mid-solve at that mu. */
+int abip_set_state(abip_work* w, int32_t k, const double* y, const double* x, const double* s,
+                   double tau, double kappa, double theta, double mu);
+
+/* Read back LP k's current iterate (device outputs y, x, s; host scalars[4] =
+ * tau, kappa, theta, mu). */
+int abip_get_state(abip_work* w, int32_t k, double* y, double* x, double* s, double* scalars);
+
+/* Run exactly `iters` relaxed ADMM iterations of Algorithm 2 at the current mu
+ * on LP k, without tests or restarts (FP64 data unless use_fp32 != 0). */
+int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_fp32);
+
+/* Release everything owned by the handle.  NULL is accepted. */
+int abip_free(abip_work* w);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* abip_last_error(void);
+
+/* Library version string, e.g. "abip-mi355x 0.1 gfx950". */
+const char* abip_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABIP_H */

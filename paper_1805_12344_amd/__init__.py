@@ -1,0 +1,294 @@
+"""Thin Python binding of libabip (the MI355X ABIP solver).
+
+Each function mirrors one C entry point of ``include/abip.h`` with the same
+name; it only marshals torch tensors (device memory) and the current HIP
+stream into the call.  Every step of the solver runs in the HIP library; if
+the library is missing this module raises on import of the binding -- there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libabip.so")
+
+# error codes / statuses / enums (include/abip.h)
+ABIP_OK = 0
+ABIP_E_INVALID, ABIP_E_DIM, ABIP_E_NONFINITE, ABIP_E_HIP, ABIP_E_OOM, ABIP_E_STATE = -1, -2, -3, -4, -5, -6
+ABIP_UNSOLVED, ABIP_SOLVED, ABIP_PRIMAL_INFEASIBLE, ABIP_DUAL_INFEASIBLE, ABIP_MAX_ITERS = 0, 1, 2, 3, 4
+ABIP_DENSE_ROWMAJOR, ABIP_CSR = 0, 1
+ABIP_PREC_FP64, ABIP_PREC_FP32_POLISH = 0, 1
+ABIP_RESTART_HEURISTIC, ABIP_RESTART_SQRT = 0, 1
+ABIP_LIN_AUTO, ABIP_LIN_DIRECT, ABIP_LIN_CG = 0, 1, 2
+ABIP_ENGINE_AUTO, ABIP_ENGINE_WG, ABIP_ENGINE_GRID = 0, 1, 2
+
+STATUS_NAMES = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasible", 4: "max_iters"}
+
+
+class abip_settings(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("max_admm_iters", ctypes.c_int64),
+        ("restart_rule", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("lin_solver", ctypes.c_int32), ("engine", ctypes.c_int32),
+        ("fp32_max_iters", ctypes.c_int64), ("cg_tol", ctypes.c_double),
+        ("cg_max_iters", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+        ("adjoint_tol", ctypes.c_double), ("adjoint_max_iters", ctypes.c_int64),
+    ]
+
+
+class abip_info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("admm_iters", ctypes.c_int64), ("admm_iters_fp64", ctypes.c_int64),
+        ("ipm_iters", ctypes.c_int64), ("cg_iters", ctypes.c_int64),
+        ("pres", ctypes.c_double), ("dres", ctypes.c_double), ("gap", ctypes.c_double),
+        ("pobj", ctypes.c_double), ("dobj", ctypes.c_double), ("tau", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("theta", ctypes.c_double), ("mu", ctypes.c_double),
+        ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["status_name"] = STATUS_NAMES.get(self.status, "?")
+        return d
+
+
+class abip_matrix(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("format", ctypes.c_int32),
+        ("val", ctypes.c_void_p), ("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p),
+        ("nnz", ctypes.c_int64),
+    ]
+
+
+EXPORTS = [
+    "abip_default_settings", "abip_setup", "abip_setup_batch", "abip_solve", "abip_solve_batch",
+    "abip_backward", "abip_backward_batch", "abip_apply_iq", "abip_set_state", "abip_get_state",
+    "abip_iterate", "abip_free", "abip_last_error", "abip_version",
+]
+
+
+class ABIPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libabip error {code}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"libabip.so not found at {path}; run paper_1805_12344_amd.build.build() first")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.abip_default_settings.argtypes = [ctypes.POINTER(abip_settings)]
+    lib.abip_setup.argtypes = [ctypes.POINTER(P), ctypes.POINTER(abip_matrix), P, P,
+                               ctypes.POINTER(abip_settings), P]
+    lib.abip_setup_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(abip_matrix),
+                                     ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(abip_settings), P]
+    lib.abip_solve.argtypes = [P, P, P, P, ctypes.POINTER(abip_info)]
+    lib.abip_solve_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                     ctypes.POINTER(abip_info)]
+    lib.abip_backward.argtypes = [P, P, P, P, P]
+    lib.abip_backward_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                        ctypes.POINTER(P)]
+    lib.abip_apply_iq.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32]
+    lib.abip_set_state.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double]
+    lib.abip_get_state.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.abip_iterate.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
+    lib.abip_free.argtypes = [P]
+    lib.abip_last_error.restype = ctypes.c_char_p
+    lib.abip_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("abip_last_error", "abip_version"):
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(rc):
+    if rc != ABIP_OK:
+        raise ABIPError(rc, lib().abip_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev(t, shape=None):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    t = t.to(device="cuda", dtype=torch.float64).contiguous()
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def abip_default_settings(**overrides) -> abip_settings:
+    s = abip_settings()
+    _check(lib().abip_default_settings(ctypes.byref(s)))
+    for k, v in overrides.items():
+        if not hasattr(s, k):
+            raise AttributeError(k)
+        setattr(s, k, v)
+    return s
+
+
+class Work:
+    """Owner of an ``abip_work*`` handle plus the device copies it was made from."""
+
+    def __init__(self, handle, dims, keep):
+        self.handle = handle
+        self.dims = dims          # list of (m, n)
+        self._keep = keep
+        self.last_info = None
+
+    @property
+    def B(self):
+        return len(self.dims)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            lib().abip_free(self.handle)
+        self.handle = None
+
+
+def abip_setup(A, b, c, settings: abip_settings | None = None) -> Work:
+    A = _dev(A)
+    m, n = A.shape
+    b = _dev(b, (m,))
+    c = _dev(c, (n,))
+    mat = abip_matrix(m, n, ABIP_DENSE_ROWMAJOR, A.data_ptr(), None, None, 0)
+    h = ctypes.c_void_p()
+    s = settings or abip_default_settings()
+    _check(lib().abip_setup(ctypes.byref(h), ctypes.byref(mat), _ptr(b), _ptr(c), ctypes.byref(s), _stream()))
+    return Work(h, [(m, n)], (A, b, c, s))
+
+
+def abip_setup_batch(As, bs, cs, settings: abip_settings | None = None) -> Work:
+    B = len(As)
+    As = [_dev(A) for A in As]
+    bs = [_dev(b, (A.shape[0],)) for A, b in zip(As, bs)]
+    cs = [_dev(c, (A.shape[1],)) for A, c in zip(As, cs)]
+    mats = (abip_matrix * B)(*[abip_matrix(A.shape[0], A.shape[1], ABIP_DENSE_ROWMAJOR, A.data_ptr(),
+                                           None, None, 0) for A in As])
+    bp = (ctypes.c_void_p * B)(*[b.data_ptr() for b in bs])
+    cp = (ctypes.c_void_p * B)(*[c.data_ptr() for c in cs])
+    h = ctypes.c_void_p()
+    s = settings or abip_default_settings()
+    _check(lib().abip_setup_batch(ctypes.byref(h), B, mats, bp, cp, ctypes.byref(s), _stream()))
+    return Work(h, [(A.shape[0], A.shape[1]) for A in As], (As, bs, cs, s))
+
+
+def abip_solve(w: Work):
+    """Returns (x, y, s, info_dict) as new CUDA float64 tensors."""
+    m, n = w.dims[0]
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(m, dtype=torch.float64, device="cuda")
+    s = torch.empty(n, dtype=torch.float64, device="cuda")
+    info = abip_info()
+    _check(lib().abip_solve(w.handle, _ptr(x), _ptr(y), _ptr(s), ctypes.byref(info)))
+    w.last_info = [info.as_dict()]
+    return x, y, s, w.last_info[0]
+
+
+def abip_solve_batch(w: Work):
+    """Returns lists xs, ys, ss and a list of info dicts."""
+    B = w.B
+    xs = [torch.empty(n, dtype=torch.float64, device="cuda") for (m, n) in w.dims]
+    ys = [torch.empty(m, dtype=torch.float64, device="cuda") for (m, n) in w.dims]
+    ss = [torch.empty(n, dtype=torch.float64, device="cuda") for (m, n) in w.dims]
+    infos = (abip_info * B)()
+    xp = (ctypes.c_void_p * B)(*[t.data_ptr() for t in xs])
+    yp = (ctypes.c_void_p * B)(*[t.data_ptr() for t in ys])
+    sp = (ctypes.c_void_p * B)(*[t.data_ptr() for t in ss])
+    _check(lib().abip_solve_batch(w.handle, xp, yp, sp, infos))
+    w.last_info = [infos[k].as_dict() for k in range(B)]
+    return xs, ys, ss, w.last_info
+
+
+def abip_backward(w: Work, dL_dx, want_A: bool = False):
+    m, n = w.dims[0]
+    g = _dev(dL_dx, (n,))
+    dc = torch.empty(n, dtype=torch.float64, device="cuda")
+    db = torch.empty(m, dtype=torch.float64, device="cuda")
+    dA = torch.empty((m, n), dtype=torch.float64, device="cuda") if want_A else None
+    _check(lib().abip_backward(w.handle, _ptr(g), _ptr(dc), _ptr(db), _ptr(dA)))
+    return dc, db, dA
+
+
+def abip_backward_batch(w: Work, dL_dx, want_A: bool = False):
+    B = w.B
+    gs = [_dev(g, (n,)) for g, (m, n) in zip(dL_dx, w.dims)]
+    dcs = [torch.empty(n, dtype=torch.float64, device="cuda") for (m, n) in w.dims]
+    dbs = [torch.empty(m, dtype=torch.float64, device="cuda") for (m, n) in w.dims]
+    dAs = [torch.empty((m, n), dtype=torch.float64, device="cuda") if want_A else None for (m, n) in w.dims]
+    P = ctypes.c_void_p
+    _check(lib().abip_backward_batch(w.handle, (P * B)(*[g.data_ptr() for g in gs]),
+                                     (P * B)(*[t.data_ptr() for t in dcs]),
+                                     (P * B)(*[t.data_ptr() for t in dbs]),
+                                     (P * B)(*[(t.data_ptr() if t is not None else 0) for t in dAs])))
+    return dcs, dbs, dAs
+
+
+def abip_apply_iq(w: Work, k: int, win, use_fp32: bool = False):
+    m, n = w.dims[k]
+    win = _dev(win, (m + n + 2,))
+    out = torch.empty(m + n + 2, dtype=torch.float64, device="cuda")
+    _check(lib().abip_apply_iq(w.handle, k, _ptr(win), _ptr(out), int(use_fp32)))
+    return out
+
+
+def abip_set_state(w: Work, k: int, y, x, s, tau, kappa, theta, mu):
+    m, n = w.dims[k]
+    y, x, s = _dev(y, (m,)), _dev(x, (n,)), _dev(s, (n,))
+    _check(lib().abip_set_state(w.handle, k, _ptr(y), _ptr(x), _ptr(s), float(tau), float(kappa),
+                                float(theta), float(mu)))
+
+
+def abip_get_state(w: Work, k: int):
+    m, n = w.dims[k]
+    y = torch.empty(m, dtype=torch.float64, device="cuda")
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    s = torch.empty(n, dtype=torch.float64, device="cuda")
+    sc = (ctypes.c_double * 4)()
+    _check(lib().abip_get_state(w.handle, k, _ptr(y), _ptr(x), _ptr(s), sc))
+    return y, x, s, dict(tau=sc[0], kappa=sc[1], theta=sc[2], mu=sc[3])
+
+
+def abip_iterate(w: Work, k: int, iters: int, use_fp32: bool = False):
+    _check(lib().abip_iterate(w.handle, k, int(iters), int(use_fp32)))
+
+
+def abip_free(w: Work):
+    w.free()
+
+
+def abip_version() -> str:
+    return lib().abip_version().decode()
+
+
+def abip_last_error() -> str:
+    return lib().abip_last_error().decode()

@@ -1,0 +1,585 @@
+// Host side of libabip: the C ABI declared in include/abip.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "abip.h"
+#include "abip_internal.h"
+
+// defined in abip_solve_wg.hip
+hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const LPDesc* desc, LPCtrl* ctrl,
+                           const PoolPtrs& P, const SolveParams& prm, const int32_t* order, int32_t B,
+                           int32_t* queue, int64_t fixed_iters, int32_t ldmax);
+size_t wg_smem_bytes(int ldmax, int W);
+hipError_t set_solve_wg_smem_limit(size_t bytes);
+
+// setup kernels (abip_setup.hip)
+__global__ void k_setup_copy(const LPDesc*, const double* const*, double*, float*, int*);
+__global__ void k_setup_rows(const LPDesc*, const double* const*, const double* const*, const double*,
+                             double*, double*, int64_t, int64_t, int*);
+__global__ void k_syrk(const LPDesc*, const double*, double*);
+__global__ void k_chol_inv(const LPDesc*, double*, float*, double*, const int64_t*, int*);
+__global__ void k_setup_border(const LPDesc*, const double*, const double*, double*, double*, int64_t,
+                               int64_t, LPCtrl*);
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            if (e_ == hipErrorOutOfMemory) return fail(ABIP_E_OOM, "%s: out of device memory", #call); \
+            return fail(ABIP_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));              \
+        }                                                                                         \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// small device kernels
+// ---------------------------------------------------------------------------
+__global__ void k_reset_queue(int32_t* q) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
+}
+
+__global__ void k_init_state(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl, double* __restrict__ Mv,
+                             double* __restrict__ Nv, int64_t Mtot, int64_t Ntot, double beta, int phase) {
+    const int k = blockIdx.x;
+    const LPDesc d = desc[k];
+    for (int i = threadIdx.x; i < d.ld; i += blockDim.x) Mv[MF_Y * Mtot + d.om + i] = 0.0;
+    for (int j = threadIdx.x; j < d.n; j += blockDim.x) {
+        Nv[NF_X * Ntot + d.on + j] = 1.0;
+        Nv[NF_S * Ntot + d.on + j] = 1.0;
+    }
+    if (threadIdx.x == 0) {
+        LPCtrl& c = ctrl[k];
+        c.tau = 1.0; c.kappa = 1.0; c.theta = 1.0; c.mu = beta;
+        c.pres = c.dres = c.gap = c.pobj = c.dobj = NAN;
+        c.by = c.cx = 0.0;
+        c.iters = 0; c.iters64 = 0; c.ipm = 0;
+        c.status = 0; c.phase = phase; c.mode = OP_REFRESH; c.flags = 0;
+    }
+}
+
+// Scale the final iterate into the caller's buffers (Section 4.1 candidates
+// and certificates).  outp: 3*B device pointers (x, y, s per LP; may be null).
+__global__ void k_write_outputs(const LPDesc* __restrict__ desc, const LPCtrl* __restrict__ ctrl,
+                                const double* __restrict__ Mv, const double* __restrict__ Nv, int64_t Mtot,
+                                int64_t Ntot, double* const* __restrict__ outp, int32_t first) {
+    const int k = blockIdx.x + first;
+    const LPDesc d = desc[k];
+    const LPCtrl c = ctrl[k];
+    double* xo = outp[3 * blockIdx.x + 0];
+    double* yo = outp[3 * blockIdx.x + 1];
+    double* so = outp[3 * blockIdx.x + 2];
+    const double* y = Mv + MF_Y * Mtot + d.om;
+    const double* x = Nv + NF_X * Ntot + d.on;
+    const double* s = Nv + NF_S * Ntot + d.on;
+    double fx = 1.0 / c.tau, fy = 1.0 / c.tau, fs = 1.0 / c.tau;
+    bool nx = false, ny = false, ns = false;
+    if (c.status == ABIP_PRIMAL_INFEASIBLE) { fy = fs = 1.0 / c.by; nx = true; }
+    else if (c.status == ABIP_DUAL_INFEASIBLE) { fx = -1.0 / c.cx; ny = ns = true; }
+    for (int j = threadIdx.x; j < d.n; j += blockDim.x) {
+        if (xo) xo[j] = nx ? NAN : x[j] * fx;
+        if (so) so[j] = ns ? NAN : s[j] * fs;
+    }
+    for (int i = threadIdx.x; i < d.m; i += blockDim.x)
+        if (yo) yo[i] = ny ? NAN : y[i] * fy;
+}
+
+// Copy LP k's iterate in or out (device vectors) -- step-level API.
+__global__ void k_copy_state(const LPDesc* __restrict__ desc, int k, double* __restrict__ Mv,
+                             double* __restrict__ Nv, int64_t Mtot, int64_t Ntot, double* y, double* x, double* s,
+                             int dir) {
+    const LPDesc d = desc[k];
+    double* Y = Mv + MF_Y * Mtot + d.om;
+    double* X = Nv + NF_X * Ntot + d.on;
+    double* S = Nv + NF_S * Ntot + d.on;
+    for (int i = threadIdx.x; i < d.m; i += blockDim.x) {
+        if (dir == 0) Y[i] = y[i]; else if (y) y[i] = Y[i];
+    }
+    for (int j = threadIdx.x; j < d.n; j += blockDim.x) {
+        if (dir == 0) { X[j] = x[j]; S[j] = s[j]; }
+        else { if (x) x[j] = X[j]; if (s) s[j] = S[j]; }
+    }
+}
+
+// (I+Q)^{-1} w for one LP with the cached data (one workgroup; FP64 or FP32
+// data, FP64 arithmetic): t = w_y - A w_x, a = G^{-1} t, d = w_x + A^T a,
+// border p = K^{-1}(w_q + H^T z), u~ = (z - Z p, p).
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_iq(const LPDesc* __restrict__ desc, const LPCtrl* __restrict__ ctrl,
+                                                  int k, const T* __restrict__ Apool, const T* __restrict__ Gpool,
+                                                  const double* __restrict__ Mv, const double* __restrict__ Nv,
+                                                  int64_t Mtot, int64_t Ntot, const double* __restrict__ w,
+                                                  double* __restrict__ out) {
+    extern __shared__ double sm[];
+    __shared__ double sbuf[4 * 8];
+    const LPDesc d = desc[k];
+    const LPCtrl c = ctrl[k];
+    const int m = d.m, n = d.n, ld = d.ld, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6,
+              W = blockDim.x >> 6;
+    const T* A = Apool + d.oA;
+    const T* G = Gpool + d.oG;
+    double* st = sm;
+    double* sa = sm + ld;
+    for (int i = tid; i < ld; i += blockDim.x) {
+        double s = 0.0;
+        if (i < m) {
+            for (int j = 0; j < n; ++j) s = fma((double)A[(int64_t)j * ld + i], w[m + j], s);
+            s = w[i] - s;
+        }
+        st[i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < ld; i += blockDim.x) {
+        double s = 0.0;
+        if (i < m)
+            for (int q = 0; q < m; ++q) s = fma((double)G[(int64_t)q * ld + i], st[q], s);
+        sa[i] = s;
+    }
+    __syncthreads();
+    // d_j = w_x + (A^T a)_j into out[m + j] (temporarily)
+    for (int j = wave; j < n; j += W) {
+        double s = 0.0;
+        for (int i = lane; i < m; i += 64) s = fma((double)A[(int64_t)j * ld + i], sa[i], s);
+        s = wave_sum(s);
+        if (lane == 0) out[m + j] = w[m + j] + s;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const double* b = Mv + MF_B * Mtot + d.om;
+    const double* bbar = Mv + MF_BBAR * Mtot + d.om;
+    const double* C = Nv + NF_C * Ntot + d.on;
+    const double* CBv = Nv + NF_CBAR * Ntot + d.on;
+    double hz[2] = {0.0, 0.0};
+    for (int i = tid; i < m; i += blockDim.x) {
+        hz[0] = fma(-b[i], sa[i], hz[0]);
+        hz[1] = fma(bbar[i], sa[i], hz[1]);
+    }
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double dj = out[m + j];
+        hz[0] = fma(C[j], dj, hz[0]);
+        hz[1] = fma(-CBv[j], dj, hz[1]);
+    }
+    block_sum_n<2>(hz, sbuf);
+    const double q0 = w[m + n] + hz[0], q1 = w[m + n + 1] + hz[1];
+    const double p0 = c.K00 * q0 + c.K01 * q1, p1 = c.K10 * q0 + c.K11 * q1;
+    const double* Zy0 = Mv + MF_ZY0 * Mtot + d.om;
+    const double* Zy1 = Mv + MF_ZY1 * Mtot + d.om;
+    const double* Zx0 = Nv + NF_ZX0 * Ntot + d.on;
+    const double* Zx1 = Nv + NF_ZX1 * Ntot + d.on;
+    for (int i = tid; i < m; i += blockDim.x) out[i] = sa[i] - Zy0[i] * p0 - Zy1[i] * p1;
+    for (int j = tid; j < n; j += blockDim.x) out[m + j] = out[m + j] - Zx0[j] * p0 - Zx1[j] * p1;
+    if (tid == 0) { out[m + n] = p0; out[m + n + 1] = p1; }
+}
+
+// ---------------------------------------------------------------------------
+// the work handle
+// ---------------------------------------------------------------------------
+struct abip_work {
+    int32_t B = 0;
+    abip_settings set{};
+    hipStream_t stream = nullptr;
+    std::vector<LPDesc> hdesc;
+    LPDesc* ddesc = nullptr;
+    LPCtrl* dctrl = nullptr;
+    double* A64 = nullptr; float* A32 = nullptr;
+    double* G64 = nullptr; float* G32 = nullptr;
+    double* Mv = nullptr; double* Nv = nullptr;
+    int64_t Atot = 0, Gtot = 0, Mtot = 0, Ntot = 0;
+    int32_t* order = nullptr;
+    int32_t* queue = nullptr;
+    int* errflag = nullptr;
+    double** outp = nullptr;     // 3*B device pointer table
+    int ldmax = 0, nch = 1, threads = 512;
+    int cu_count = 256;
+    bool solved = false;
+    double setup_ms = 0.0;
+    std::vector<LPCtrl> hctrl;
+};
+
+static void release(abip_work* w) {
+    if (!w) return;
+    (void)hipFree(w->ddesc); (void)hipFree(w->dctrl);
+    (void)hipFree(w->A64); (void)hipFree(w->A32); (void)hipFree(w->G64); (void)hipFree(w->G32);
+    (void)hipFree(w->Mv); (void)hipFree(w->Nv);
+    (void)hipFree(w->order); (void)hipFree(w->queue); (void)hipFree(w->errflag); (void)hipFree(w->outp);
+}
+
+extern "C" int abip_default_settings(abip_settings* s) {
+    if (!s) return fail(ABIP_E_INVALID, "abip_default_settings: null pointer");
+    memset(s, 0, sizeof *s);
+    s->eps = 1e-6;
+    s->alpha = 1.8;
+    s->beta = 1.0;
+    s->gamma = 0.5;
+    s->max_admm_iters = 1000000;
+    s->restart_rule = ABIP_RESTART_HEURISTIC;
+    s->precision = ABIP_PREC_FP64;
+    s->lin_solver = ABIP_LIN_AUTO;
+    s->engine = ABIP_ENGINE_AUTO;
+    s->fp32_max_iters = 1000000;
+    s->cg_tol = 1e-10;
+    s->cg_max_iters = 500;
+    s->block_threads = 0;
+    s->adjoint_tol = 1e-10;
+    s->adjoint_max_iters = 200000;
+    return ABIP_OK;
+}
+
+static int check_settings(const abip_settings& s) {
+    if (!(s.eps > 0.0) || !std::isfinite(s.eps)) return fail(ABIP_E_INVALID, "settings.eps must be > 0");
+    if (!(s.alpha > 0.0 && s.alpha < 2.0)) return fail(ABIP_E_INVALID, "settings.alpha must lie in (0,2)");
+    if (!(s.beta > 0.0) || !std::isfinite(s.beta)) return fail(ABIP_E_INVALID, "settings.beta must be > 0");
+    if (!(s.gamma > 0.0 && s.gamma < 1.0)) return fail(ABIP_E_INVALID, "settings.gamma must lie in (0,1)");
+    if (s.max_admm_iters < 0) return fail(ABIP_E_INVALID, "settings.max_admm_iters must be >= 0");
+    if (s.restart_rule != ABIP_RESTART_HEURISTIC && s.restart_rule != ABIP_RESTART_SQRT)
+        return fail(ABIP_E_INVALID, "settings.restart_rule: unknown value %d", s.restart_rule);
+    if (s.precision != ABIP_PREC_FP64 && s.precision != ABIP_PREC_FP32_POLISH)
+        return fail(ABIP_E_INVALID, "settings.precision: unknown value %d", s.precision);
+    if (s.block_threads != 0 && s.block_threads != 256 && s.block_threads != 512)
+        return fail(ABIP_E_INVALID, "settings.block_threads must be 0, 256 or 512");
+    return ABIP_OK;
+}
+
+static SolveParams make_params(const abip_settings& s) {
+    SolveParams p;
+    p.eps = s.eps; p.alpha = s.alpha; p.beta = s.beta; p.gamma = s.gamma;
+    p.max_iters = s.max_admm_iters;
+    p.fp32_max_iters = (s.precision == ABIP_PREC_FP32_POLISH) ? s.fp32_max_iters : 0;
+    p.restart_rule = s.restart_rule;
+    p.precision = s.precision;
+    return p;
+}
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static const int MAX_WG_M = 1024;   // largest m the one-workgroup engine holds per lane
+
+static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const double* const* b,
+                       const double* const* c, const abip_settings* settings, void* stream) {
+    if (!out) return fail(ABIP_E_INVALID, "abip_setup: null output handle");
+    *out = nullptr;
+    if (B < 1) return fail(ABIP_E_DIM, "abip_setup_batch: B must be >= 1 (got %d)", B);
+    if (!A || !b || !c) return fail(ABIP_E_INVALID, "abip_setup: null A, b or c");
+    abip_settings s;
+    if (settings) s = *settings; else abip_default_settings(&s);
+    int rc = check_settings(s);
+    if (rc) return rc;
+    const double t0 = now_ms();
+    abip_work* w = new abip_work();
+    w->B = B;
+    w->set = s;
+    w->stream = (hipStream_t)stream;
+    w->hdesc.resize(B);
+    int64_t oA = 0, oG = 0, om = 0, on = 0;
+    for (int k = 0; k < B; ++k) {
+        const abip_matrix& M = A[k];
+        if (M.format != ABIP_DENSE_ROWMAJOR) { delete w; return fail(ABIP_E_INVALID, "LP %d: only dense row-major A is supported by this entry point", k); }
+        if (M.m < 1 || M.n < 1) { delete w; return fail(ABIP_E_DIM, "LP %d: bad dimensions m=%d n=%d", k, M.m, M.n); }
+        if (M.m > MAX_WG_M) { delete w; return fail(ABIP_E_DIM, "LP %d: m=%d exceeds the one-workgroup engine limit %d", k, M.m, MAX_WG_M); }
+        if (!M.val || !b[k] || !c[k]) { delete w; return fail(ABIP_E_INVALID, "LP %d: null data pointer", k); }
+        LPDesc& d = w->hdesc[k];
+        d.m = M.m; d.n = M.n; d.ld = (M.m + 3) & ~3; d.pad = 0;
+        d.oA = oA; d.oG = oG; d.om = om; d.on = on;
+        oA += (int64_t)d.ld * d.n;
+        oG += (int64_t)d.ld * d.m;
+        om += d.ld;
+        on += (d.n + 3) & ~3;
+        w->ldmax = std::max(w->ldmax, d.ld);
+    }
+    w->Atot = oA; w->Gtot = oG; w->Mtot = om; w->Ntot = on;
+    w->nch = (w->ldmax + 255) / 256;
+    w->threads = s.block_threads ? s.block_threads : (w->nch >= 3 ? 256 : 512);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&w->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+#define ALLOC(ptr, count) do { hipError_t e_ = hipMalloc((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count)); \
+        if (e_ != hipSuccess) { release(w); delete w; return fail(e_ == hipErrorOutOfMemory ? ABIP_E_OOM : ABIP_E_HIP, "hipMalloc(%s, %lld elements): %s", #ptr, (long long)(count), hipGetErrorString(e_)); } } while (0)
+    ALLOC(w->ddesc, B);
+    ALLOC(w->dctrl, B);
+    ALLOC(w->A64, oA); ALLOC(w->A32, oA);
+    ALLOC(w->G64, oG); ALLOC(w->G32, oG);
+    ALLOC(w->Mv, (int64_t)NMF * om); ALLOC(w->Nv, (int64_t)NNF * on);
+    ALLOC(w->order, B); ALLOC(w->queue, 1); ALLOC(w->errflag, 1);
+    ALLOC(w->outp, 3 * B);
+    // scratch for the setup
+    std::vector<int64_t> hoW(B);
+    int64_t wtot = 0;
+    for (int k = 0; k < B; ++k) { hoW[k] = wtot; wtot += (int64_t)w->hdesc[k].ld * w->hdesc[k].ld; }
+    double* Wp = nullptr; int64_t* doW = nullptr;
+    const double** dAp = nullptr; const double** dbp = nullptr; const double** dcp = nullptr;
+    ALLOC(Wp, wtot); ALLOC(doW, B);
+    ALLOC(dAp, B); ALLOC(dbp, B); ALLOC(dcp, B);
+#undef ALLOC
+    auto cleanup_scratch = [&]() { (void)hipFree(Wp); (void)hipFree(doW); (void)hipFree(dAp); (void)hipFree(dbp); (void)hipFree(dcp); };
+    auto bail = [&](int code) { cleanup_scratch(); release(w); delete w; return code; };
+    hipStream_t st = w->stream;
+#define SCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return bail(fail(ABIP_E_HIP, "%s: %s", #call, hipGetErrorString(e_))); } while (0)
+    std::vector<const double*> hA(B), hb(B), hc(B);
+    for (int k = 0; k < B; ++k) { hA[k] = A[k].val; hb[k] = b[k]; hc[k] = c[k]; }
+    SCHK(hipMemsetAsync(w->A64, 0, sizeof(double) * oA, st));
+    SCHK(hipMemsetAsync(w->A32, 0, sizeof(float) * oA, st));
+    SCHK(hipMemsetAsync(w->G64, 0, sizeof(double) * oG, st));
+    SCHK(hipMemsetAsync(w->G32, 0, sizeof(float) * oG, st));
+    SCHK(hipMemsetAsync(w->Mv, 0, sizeof(double) * NMF * om, st));
+    SCHK(hipMemsetAsync(w->Nv, 0, sizeof(double) * NNF * on, st));
+    SCHK(hipMemsetAsync(w->dctrl, 0, sizeof(LPCtrl) * B, st));
+    SCHK(hipMemsetAsync(w->errflag, 0, sizeof(int), st));
+    SCHK(hipMemsetAsync(Wp, 0, sizeof(double) * wtot, st));
+    SCHK(hipMemcpyAsync(w->ddesc, w->hdesc.data(), sizeof(LPDesc) * B, hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(doW, hoW.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(dAp, hA.data(), sizeof(double*) * B, hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(dbp, hb.data(), sizeof(double*) * B, hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(dcp, hc.data(), sizeof(double*) * B, hipMemcpyHostToDevice, st));
+    // largest first: LPT order for the persistent work queue
+    std::vector<int32_t> ord(B);
+    for (int k = 0; k < B; ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int bb) {
+        return (int64_t)w->hdesc[a].m * w->hdesc[a].n > (int64_t)w->hdesc[bb].m * w->hdesc[bb].n;
+    });
+    SCHK(hipMemcpyAsync(w->order, ord.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, st));
+    int maxtiles = 0, maxrowblk = 0, maxsyrk = 0;
+    for (auto& d : w->hdesc) {
+        maxtiles = std::max(maxtiles, ((d.m + 63) / 64) * ((d.n + 63) / 64));
+        maxrowblk = std::max(maxrowblk, (d.ld + 255) / 256);
+        const int nt = (d.m + 63) / 64;
+        maxsyrk = std::max(maxsyrk, nt * (nt + 1) / 2);
+    }
+    hipLaunchKernelGGL(k_setup_copy, dim3(maxtiles, B), dim3(256), 0, st, w->ddesc, dAp, w->A64, w->A32, w->errflag);
+    SCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_setup_rows, dim3(maxrowblk, B), dim3(256), 0, st, w->ddesc, dbp, dcp, w->A64, w->Mv, w->Nv,
+                       w->Mtot, w->Ntot, w->errflag);
+    SCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_syrk, dim3(maxsyrk, B), dim3(256), 0, st, w->ddesc, w->A64, w->G64);
+    SCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_chol_inv, dim3(B), dim3(256), 0, st, w->ddesc, w->G64, w->G32, Wp, doW, w->errflag);
+    SCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_setup_border, dim3(B), dim3(512), sizeof(double) * 2 * w->ldmax, st, w->ddesc, w->A64,
+                       w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, w->dctrl);
+    SCHK(hipGetLastError());
+    int hflag = 0;
+    SCHK(hipMemcpyAsync(&hflag, w->errflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    SCHK(hipStreamSynchronize(st));
+#undef SCHK
+    cleanup_scratch();
+    if (hflag & 3) { release(w); delete w; return fail(ABIP_E_NONFINITE, "NaN or Inf in %s", (hflag & 1) ? "A" : "b or c"); }
+    if (hflag & 4) { release(w); delete w; return fail(ABIP_E_HIP, "Cholesky of I + A A^T met a non-positive pivot"); }
+    hipError_t e = set_solve_wg_smem_limit(wg_smem_bytes(w->ldmax, w->threads / 64));
+    if (e != hipSuccess) { release(w); delete w; return fail(ABIP_E_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e)); }
+    w->hctrl.resize(B);
+    w->setup_ms = now_ms() - t0;
+    *out = w;
+    return ABIP_OK;
+}
+
+extern "C" int abip_setup(abip_work** out, const abip_matrix* A, const double* b, const double* c,
+                          const abip_settings* settings, void* stream) {
+    if (!A) return fail(ABIP_E_INVALID, "abip_setup: null A");
+    if (A->format == ABIP_CSR) return fail(ABIP_E_INVALID, "abip_setup: CSR input is not supported yet");
+    const double* bb[1] = {b};
+    const double* cc[1] = {c};
+    return setup_dense(out, 1, A, bb, cc, settings, stream);
+}
+
+extern "C" int abip_setup_batch(abip_work** out, int32_t B, const abip_matrix* A, const double* const* b,
+                                const double* const* c, const abip_settings* settings, void* stream) {
+    return setup_dense(out, B, A, b, c, settings, stream);
+}
+
+static PoolPtrs pools(abip_work* w) {
+    PoolPtrs P;
+    P.A64 = w->A64; P.A32 = w->A32; P.G64 = w->G64; P.G32 = w->G32;
+    P.Mv = w->Mv; P.Nv = w->Nv; P.Mtot = w->Mtot; P.Ntot = w->Ntot;
+    return P;
+}
+
+static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParams& prm) {
+    hipStream_t st = w->stream;
+    const int per_cu = (wg_smem_bytes(w->ldmax, w->threads / 64) <= 76 * 1024 && w->threads <= 512) ? 2 : 1;
+    const int grid = std::max(1, std::min<int>(B, w->cu_count * per_cu));
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, w->queue);
+    HIPCHK(hipGetLastError());
+    HIPCHK(launch_solve_wg(w->nch, grid, w->threads, st, w->ddesc, w->dctrl, pools(w), prm, w->order, B, w->queue,
+                           fixed_iters, w->ldmax));
+    return ABIP_OK;
+}
+
+static void fill_info(abip_info* info, const LPCtrl& c, double setup_ms, double solve_ms) {
+    info->status = c.status;
+    info->admm_iters = c.iters;
+    info->admm_iters_fp64 = c.iters64;
+    info->ipm_iters = c.ipm;
+    info->cg_iters = 0;
+    info->pres = c.pres; info->dres = c.dres; info->gap = c.gap;
+    info->pobj = c.pobj; info->dobj = c.dobj;
+    info->tau = c.tau; info->kappa = c.kappa; info->theta = c.theta; info->mu = c.mu;
+    info->setup_ms = setup_ms;
+    info->solve_ms = solve_ms;
+}
+
+static int solve_all(abip_work* w, double* const* x, double* const* y, double* const* s, abip_info* info) {
+    hipStream_t st = w->stream;
+    const double t0 = now_ms();
+    const SolveParams prm = make_params(w->set);
+    const int phase = (w->set.precision == ABIP_PREC_FP32_POLISH) ? 0 : 1;
+    hipLaunchKernelGGL(k_init_state, dim3(w->B), dim3(256), 0, st, w->ddesc, w->dctrl, w->Mv, w->Nv, w->Mtot, w->Ntot,
+                       w->set.beta, phase);
+    HIPCHK(hipGetLastError());
+    int rc = run_wg(w, w->B, 0, prm);
+    if (rc) return rc;
+    std::vector<double*> tab(3 * w->B);
+    for (int k = 0; k < w->B; ++k) {
+        tab[3 * k] = x ? x[k] : nullptr;
+        tab[3 * k + 1] = y ? y[k] : nullptr;
+        tab[3 * k + 2] = s ? s[k] : nullptr;
+    }
+    HIPCHK(hipMemcpyAsync(w->outp, tab.data(), sizeof(double*) * 3 * w->B, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_write_outputs, dim3(w->B), dim3(256), 0, st, w->ddesc, w->dctrl, w->Mv, w->Nv, w->Mtot,
+                       w->Ntot, w->outp, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(w->hctrl.data(), w->dctrl, sizeof(LPCtrl) * w->B, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double ms = now_ms() - t0;
+    if (info)
+        for (int k = 0; k < w->B; ++k) fill_info(&info[k], w->hctrl[k], w->setup_ms, ms);
+    w->solved = true;
+    return ABIP_OK;
+}
+
+extern "C" int abip_solve(abip_work* w, double* x, double* y, double* s, abip_info* info) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_solve: null handle");
+    if (w->B != 1) return fail(ABIP_E_STATE, "abip_solve: handle holds %d LPs; use abip_solve_batch", w->B);
+    double* xs[1] = {x};
+    double* ys[1] = {y};
+    double* ss[1] = {s};
+    return solve_all(w, xs, ys, ss, info);
+}
+
+extern "C" int abip_solve_batch(abip_work* w, double* const* x, double* const* y, double* const* s, abip_info* info) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_solve_batch: null handle");
+    return solve_all(w, x, y, s, info);
+}
+
+extern "C" int abip_backward(abip_work* w, const double*, double*, double*, double*) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_backward: null handle");
+    return fail(ABIP_E_STATE, "abip_backward: not available in this build");
+}
+
+extern "C" int abip_backward_batch(abip_work* w, const double* const*, double* const*, double* const*,
+                                   double* const*) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_backward_batch: null handle");
+    return fail(ABIP_E_STATE, "abip_backward_batch: not available in this build");
+}
+
+extern "C" int abip_apply_iq(abip_work* w, int32_t k, const double* win, double* out, int32_t use_fp32) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_apply_iq: null handle");
+    if (k < 0 || k >= w->B) return fail(ABIP_E_INVALID, "abip_apply_iq: LP index %d out of range", k);
+    if (!win || !out) return fail(ABIP_E_INVALID, "abip_apply_iq: null vector");
+    const size_t smem = sizeof(double) * 2 * w->hdesc[k].ld;
+    if (use_fp32)
+        hipLaunchKernelGGL(k_apply_iq<float>, dim3(1), dim3(256), smem, w->stream, w->ddesc, w->dctrl, k, w->A32,
+                           w->G32, w->Mv, w->Nv, w->Mtot, w->Ntot, win, out);
+    else
+        hipLaunchKernelGGL(k_apply_iq<double>, dim3(1), dim3(256), smem, w->stream, w->ddesc, w->dctrl, k, w->A64,
+                           w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, win, out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(w->stream));
+    return ABIP_OK;
+}
+
+extern "C" int abip_set_state(abip_work* w, int32_t k, const double* y, const double* x, const double* s,
+                              double tau, double kappa, double theta, double mu) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_set_state: null handle");
+    if (k < 0 || k >= w->B) return fail(ABIP_E_INVALID, "abip_set_state: LP index %d out of range", k);
+    if (!y || !x || !s) return fail(ABIP_E_INVALID, "abip_set_state: null vector");
+    if (!(tau > 0 && kappa > 0 && mu > 0)) return fail(ABIP_E_INVALID, "abip_set_state: tau, kappa, mu must be > 0");
+    hipLaunchKernelGGL(k_copy_state, dim3(1), dim3(256), 0, w->stream, w->ddesc, k, w->Mv, w->Nv, w->Mtot, w->Ntot,
+                       (double*)y, (double*)x, (double*)s, 0);
+    HIPCHK(hipGetLastError());
+    LPCtrl c;
+    HIPCHK(hipMemcpyAsync(&c, w->dctrl + k, sizeof c, hipMemcpyDeviceToHost, w->stream));
+    HIPCHK(hipStreamSynchronize(w->stream));
+    c.tau = tau; c.kappa = kappa; c.theta = theta; c.mu = mu;
+    c.status = 0; c.mode = OP_REFRESH; c.flags = 0;
+    c.iters = 0; c.iters64 = 0; c.ipm = 0;
+    HIPCHK(hipMemcpyAsync(w->dctrl + k, &c, sizeof c, hipMemcpyHostToDevice, w->stream));
+    HIPCHK(hipStreamSynchronize(w->stream));
+    return ABIP_OK;
+}
+
+extern "C" int abip_get_state(abip_work* w, int32_t k, double* y, double* x, double* s, double* scalars) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_get_state: null handle");
+    if (k < 0 || k >= w->B) return fail(ABIP_E_INVALID, "abip_get_state: LP index %d out of range", k);
+    hipLaunchKernelGGL(k_copy_state, dim3(1), dim3(256), 0, w->stream, w->ddesc, k, w->Mv, w->Nv, w->Mtot, w->Ntot,
+                       y, x, s, 1);
+    HIPCHK(hipGetLastError());
+    LPCtrl c;
+    HIPCHK(hipMemcpyAsync(&c, w->dctrl + k, sizeof c, hipMemcpyDeviceToHost, w->stream));
+    HIPCHK(hipStreamSynchronize(w->stream));
+    if (scalars) { scalars[0] = c.tau; scalars[1] = c.kappa; scalars[2] = c.theta; scalars[3] = c.mu; }
+    return ABIP_OK;
+}
+
+// iterate LP k alone: a one-LP work queue that points at k
+__global__ void k_single_order(int32_t* order, int32_t k) {
+    if (threadIdx.x == 0) order[0] = k;
+}
+
+extern "C" int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_fp32) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_iterate: null handle");
+    if (k < 0 || k >= w->B) return fail(ABIP_E_INVALID, "abip_iterate: LP index %d out of range", k);
+    if (iters < 1) return fail(ABIP_E_INVALID, "abip_iterate: iters must be >= 1");
+    LPCtrl c;
+    HIPCHK(hipMemcpyAsync(&c, w->dctrl + k, sizeof c, hipMemcpyDeviceToHost, w->stream));
+    HIPCHK(hipStreamSynchronize(w->stream));
+    c.phase = use_fp32 ? 0 : 1;
+    c.mode = OP_REFRESH;
+    c.flags = 0;
+    HIPCHK(hipMemcpyAsync(w->dctrl + k, &c, sizeof c, hipMemcpyHostToDevice, w->stream));
+    int32_t* ord1 = nullptr;
+    HIPCHK(hipMalloc((void**)&ord1, sizeof(int32_t)));
+    hipLaunchKernelGGL(k_single_order, dim3(1), dim3(64), 0, w->stream, ord1, k);
+    SolveParams prm = make_params(w->set);
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, w->stream, w->queue);
+    hipError_t e = launch_solve_wg(w->nch, 1, w->threads, w->stream, w->ddesc, w->dctrl, pools(w), prm, ord1, 1,
+                                   w->queue, iters, w->ldmax);
+    hipError_t e2 = hipStreamSynchronize(w->stream);
+    (void)hipFree(ord1);
+    if (e != hipSuccess) return fail(ABIP_E_HIP, "abip_iterate launch: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(ABIP_E_HIP, "abip_iterate: %s", hipGetErrorString(e2));
+    return ABIP_OK;
+}
+
+extern "C" int abip_free(abip_work* w) {
+    if (!w) return ABIP_OK;
+    (void)hipStreamSynchronize(w->stream);
+    release(w);
+    delete w;
+    return ABIP_OK;
+}
+
+extern "C" const char* abip_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* abip_version(void) { return "abip-mi355x 0.1 gfx950"; }

@@ -1,0 +1,165 @@
+"""GPU parity of the dense one-workgroup engine against the FP64 oracle.
+
+Every call goes through the C ABI (libabip.so via the thin binding).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lpgen
+import oracle
+from oracle.abip import Problem, Settings
+
+pytestmark = pytest.mark.gpu
+
+abip = pytest.importorskip("paper_1805_12344_amd")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _settings(**kw):
+    return abip.abip_default_settings(**kw)
+
+
+SHAPES = [(7, 13, 0), (50, 100, 1), (130, 301, 2), (300, 650, 3), (20, 1000, 4)]
+
+
+@pytest.mark.parametrize("m,n,seed", SHAPES)
+def test_apply_iq_matches_oracle(m, n, seed):
+    print(f"apply_iq m={m} n={n} seed={seed}", flush=True)
+    lp = lpgen.dense_planted(m, n, seed)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"])
+    rng = np.random.default_rng(seed + 100)
+    win = rng.standard_normal(m + n + 2)
+    ref = oracle.SchurIQSolver(Problem(lp["A"], lp["b"], lp["c"])).solve(win)
+    got = _np(abip.abip_apply_iq(w, 0, win))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, err
+    got32 = _np(abip.abip_apply_iq(w, 0, win, use_fp32=True))
+    err32 = np.abs(got32 - ref).max() / np.abs(ref).max()
+    assert err32 < 1e-4, err32
+
+
+@pytest.mark.parametrize("m,n,seed", SHAPES)
+@pytest.mark.parametrize("rule", ["heuristic", "sqrt"])
+def test_iterations_match_oracle_elementwise(m, n, seed, rule):
+    """Fixed number of relaxed ADMM iterations from the same (restarted) iterate."""
+    print(f"iterate m={m} n={n} seed={seed} rule={rule}", flush=True)
+    lp = lpgen.dense_planted(m, n, seed)
+    prob = Problem(lp["A"], lp["b"], lp["c"])
+    s = Settings(alpha=1.8, gamma=0.5, restart_rule=rule)
+    st = oracle.initial_state(prob, s)
+    st = oracle.restart(st, s.gamma, rule)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"], _settings(restart_rule=0 if rule == "heuristic" else 1))
+    abip.abip_set_state(w, 0, st.y, st.x, st.s, st.tau, st.kappa, st.theta, st.mu)
+    solver = oracle.SchurIQSolver(prob)
+    N = 40
+    for _ in range(N):
+        st = oracle.admm_iteration(prob, solver, st, s)
+    abip.abip_iterate(w, 0, N)
+    y, x, sv, sc = abip.abip_get_state(w, 0)
+    scale = 1.0 + np.abs(st.u()).max()
+    assert np.abs(_np(y) - st.y).max() <= 1e-10 * scale
+    assert np.abs(_np(x) - st.x).max() <= 1e-10 * scale
+    assert np.abs(_np(sv) - st.s).max() <= 1e-10 * scale
+    for key, ref in [("tau", st.tau), ("kappa", st.kappa), ("theta", st.theta)]:
+        assert abs(sc[key] - ref) <= 1e-10 * scale, (key, sc[key], ref)
+    # Theorem 3.1 invariants on the GPU iterate
+    t = st.mu
+    np.testing.assert_allclose(_np(x) * _np(sv), t, rtol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [4, 5, 7])
+def test_solve_config0_matches_oracle(seed):
+    print(f"solve config0 seed={seed}", flush=True)
+    lp = lpgen.config0(seed)
+    ref = oracle.solve(lp["A"], lp["b"], lp["c"], Settings())
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"])
+    x, y, s, info = abip.abip_solve(w)
+    assert info["status"] == abip.ABIP_SOLVED == ref["status"]
+    x, y, s = _np(x), _np(y), _np(s)
+    kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], x, y, s)
+    assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
+    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-6 * (1 + abs(lp["pstar"]))
+    # 1e-6 relative KKT bounds the distance to the planted vertex only up to conditioning
+    assert np.linalg.norm(x - lp["x0"]) / (1 + np.linalg.norm(lp["x0"])) <= 1e-4
+    # same algorithm in FP64: the trajectories agree and stop together
+    assert abs(info["admm_iters"] - ref["admm_iters"]) <= max(3, 0.01 * ref["admm_iters"]), \
+        (info["admm_iters"], ref["admm_iters"])
+    np.testing.assert_allclose(x, ref["x"], atol=1e-6 * (1 + np.abs(ref["x"]).max()))
+
+
+def test_toys_and_certificates():
+    for lp in [lpgen.toy_two_var(), lpgen.toy_primal_infeasible(), lpgen.toy_dual_infeasible(),
+               lpgen.dense_farkas_infeasible(20, 50, 3)]:
+        ref = oracle.solve(lp["A"], lp["b"], lp["c"], Settings())
+        w = abip.abip_setup(lp["A"], lp["b"], lp["c"])
+        x, y, s, info = abip.abip_solve(w)
+        print(lp["status"], info["status_name"], info["admm_iters"], ref["admm_iters"], flush=True)
+        assert info["status"] == ref["status"]
+        if lp["status"] == "primal_infeasible":
+            y = _np(y)
+            assert abs(lp["b"] @ y - 1.0) < 1e-9
+            assert np.linalg.norm(lp["A"].T @ y + _np(s)) <= 1e-6 / np.linalg.norm(lp["b"]) * 1.001
+            assert np.all(np.isnan(_np(x)))
+        elif lp["status"] == "dual_infeasible":
+            x = _np(x)
+            assert abs(lp["c"] @ x + 1.0) < 1e-9 and np.all(x >= 0)
+            assert np.linalg.norm(lp["A"] @ x) <= 1e-6 / np.linalg.norm(lp["c"]) * 1.001
+
+
+def test_batch_uneven_matches_status_and_kkt():
+    lps = [lpgen.dense_planted(m, n, sd) for (m, n, sd) in
+           [(3, 6, 1), (12, 30, 2), (4, 8, 4), (50, 100, 5), (12, 30, 4)]]
+    lps.append(lpgen.dense_farkas_infeasible(20, 50, 3))
+    w = abip.abip_setup_batch([lp["A"] for lp in lps], [lp["b"] for lp in lps], [lp["c"] for lp in lps])
+    xs, ys, ss, infos = abip.abip_solve_batch(w)
+    for lp, x, y, s, info in zip(lps, xs, ys, ss, infos):
+        print(lp["m"], lp["n"], info["status_name"], info["admm_iters"], flush=True)
+        if lp["status"] == "solved":
+            assert info["status"] == abip.ABIP_SOLVED
+            kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s))
+            assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
+        else:
+            assert info["status"] == abip.ABIP_PRIMAL_INFEASIBLE
+    # the batch gives the same answers as one-at-a-time solves
+    for k in [0, 3]:
+        lp = lps[k]
+        w1 = abip.abip_setup(lp["A"], lp["b"], lp["c"])
+        x1, _, _, info1 = abip.abip_solve(w1)
+        assert info1["admm_iters"] == infos[k]["admm_iters"]
+        assert torch.equal(x1, xs[k])
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_fp32_bulk_with_fp64_polish(seed):
+    lp = lpgen.config0(seed)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"], _settings(precision=abip.ABIP_PREC_FP32_POLISH))
+    x, y, s, info = abip.abip_solve(w)
+    print(info, flush=True)
+    assert info["status"] == abip.ABIP_SOLVED
+    kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s))
+    assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
+    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-6 * (1 + abs(lp["pstar"]))
+
+
+def test_boundary_errors():
+    lp = lpgen.dense_planted(5, 9, 0)
+    A = lp["A"].copy()
+    A[1, 2] = np.nan
+    with pytest.raises(abip.ABIPError) as e:
+        abip.abip_setup(A, lp["b"], lp["c"])
+    assert e.value.code == abip.ABIP_E_NONFINITE
+    b = lp["b"].copy()
+    b[0] = np.inf
+    with pytest.raises(abip.ABIPError) as e:
+        abip.abip_setup(lp["A"], b, lp["c"])
+    assert e.value.code == abip.ABIP_E_NONFINITE
+    with pytest.raises(abip.ABIPError) as e:
+        abip.abip_setup(lp["A"], lp["b"], lp["c"], _settings(gamma=1.5))
+    assert e.value.code == abip.ABIP_E_INVALID
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"], _settings(max_admm_iters=5))
+    x, y, s, info = abip.abip_solve(w)
+    assert info["status"] == abip.ABIP_MAX_ITERS and info["admm_iters"] == 5
