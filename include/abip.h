@@ -109,6 +109,10 @@ typedef struct {
     double  pobj, dobj;        /* c^T x / tau, b^T y / tau at the last check */
     double  tau, kappa, theta, mu;
     double  setup_ms, solve_ms;/* wall time of setup and of the solve (host clock) */
+    int64_t colpass_fp32;      /* passes over A streamed in FP32 (updates, restarts, refreshes) */
+    int64_t colpass_fp64;      /* passes over A streamed in FP64 */
+    double  kernel_ms;         /* duration of the persistent solve launch, HIP events on the
+                                  work stream (the same value for every LP of a batch) */
 } abip_info;
 
 /* A matrix description.  All pointers are device pointers. */
@@ -160,9 +164,11 @@ int abip_solve_batch(abip_work* w, double* const* x, double* const* y, double* c
 
 /* Adjoint of the converged HSD fixed point (project extension, not in the paper).
  * For the loss L(x*) with gradient dL_dx (device, n) at the returned x* = x/tau,
- * solve the adjoint of the linearised ADMM fixed-point map at the final iterate
- * by fixed-point iteration (each step reuses the cached factor: (I+Q)^T = I - Q
- * reduces to the same G), then contract with d(Q u)/d(c, b, A).
+ * solve the adjoint of the linearised ADMM fixed-point map at the final iterate,
+ * (I - J^T) lam = dL/dz, by BiCGSTAB; each product with J^T is one transposed
+ * ADMM step that reuses the cached factor ((I+Q)^T = I - Q has the same
+ * G = I + A A^T).  Then contract with d(Q u)/d(c, b, A).  At the final iterate
+ * this equals the adjoint of the central-path system (HSD-log-kkt) there.
  * Outputs (device, caller-owned): dL_dc (n), dL_db (m), dL_dA (m*n row-major,
  * may be NULL).  Requires a prior successful abip_solve with status SOLVED,
  * else ABIP_E_STATE. */
@@ -170,9 +176,14 @@ int abip_backward(abip_work* w, const double* dL_dx, double* dL_dc, double* dL_d
                   double* dL_dA);
 
 /* Batched form of abip_backward over a batch handle after abip_solve_batch;
- * host arrays of B device pointers (dL_dA entries may be NULL). */
+ * host arrays of B device pointers (dL_dA entries may be NULL).  LPs whose solve
+ * did not end SOLVED get NaN gradients. */
 int abip_backward_batch(abip_work* w, const double* const* dL_dx, double* const* dL_dc,
                         double* const* dL_db, double* const* dL_dA);
+
+/* After abip_backward*: BiCGSTAB iterations (host *iters) and final relative
+ * residual (host *rel_resid) of LP k's adjoint solve. */
+int abip_backward_stats(abip_work* w, int32_t k, int64_t* iters, double* rel_resid);
 
 /* ---- step-level entry points (parity testing and tracing) ----------------
  * These expose the pieces of one inner iteration so that each can be compared
@@ -184,7 +195,8 @@ int abip_backward_batch(abip_work* w, const double* const* dL_dx, double* const*
 int abip_apply_iq(abip_work* w, int32_t k, const double* win, double* out, int32_t use_fp32);
 
 /* Load an iterate into LP k: y (m), x (n), s (n) device vectors and host scalars
- * tau, kappa, theta, mu.  Marks the LP as mid-solve at that mu. */
+ * tau, kappa, theta, mu.  Marks the LP as mid-solve at that mu; abip_backward
+ * may then differentiate this iterate directly. */
 int abip_set_state(abip_work* w, int32_t k, const double* y, const double* x, const double* s,
                    double tau, double kappa, double theta, double mu);
 

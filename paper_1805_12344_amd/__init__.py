@@ -49,6 +49,7 @@ class abip_info(ctypes.Structure):
         ("pobj", ctypes.c_double), ("dobj", ctypes.c_double), ("tau", ctypes.c_double),
         ("kappa", ctypes.c_double), ("theta", ctypes.c_double), ("mu", ctypes.c_double),
         ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+        ("colpass_fp32", ctypes.c_int64), ("colpass_fp64", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -68,7 +69,7 @@ class abip_matrix(ctypes.Structure):
 EXPORTS = [
     "abip_default_settings", "abip_setup", "abip_setup_batch", "abip_solve", "abip_solve_batch",
     "abip_backward", "abip_backward_batch", "abip_apply_iq", "abip_set_state", "abip_get_state",
-    "abip_iterate", "abip_free", "abip_last_error", "abip_version",
+    "abip_iterate", "abip_free", "abip_last_error", "abip_version", "abip_backward_stats",
 ]
 
 
@@ -100,6 +101,8 @@ def load_library(path: str = LIB_PATH):
     lib.abip_get_state.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.POINTER(ctypes.c_double)]
     lib.abip_iterate.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
     lib.abip_free.argtypes = [P]
+    lib.abip_backward_stats.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double)]
     lib.abip_last_error.restype = ctypes.c_char_p
     lib.abip_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -253,6 +256,13 @@ def abip_backward_batch(w: Work, dL_dx, want_A: bool = False):
     return dcs, dbs, dAs
 
 
+def abip_backward_stats(w: Work, k: int = 0):
+    it = ctypes.c_int64()
+    rr = ctypes.c_double()
+    _check(lib().abip_backward_stats(w.handle, k, ctypes.byref(it), ctypes.byref(rr)))
+    return it.value, rr.value
+
+
 def abip_apply_iq(w: Work, k: int, win, use_fp32: bool = False):
     m, n = w.dims[k]
     win = _dev(win, (m + n + 2,))
@@ -292,3 +302,33 @@ def abip_version() -> str:
 
 def abip_last_error() -> str:
     return lib().abip_last_error().decode()
+
+
+class ABIPSolve(torch.autograd.Function):
+    """x* = argmin {c^T x : A x = b, x >= 0} as a differentiable function of (A, b, c).
+
+    forward: abip_setup + abip_solve (settings as given); backward: abip_backward,
+    the adjoint of the converged HSD fixed point (reusing the cached factor).
+    Inputs are float64 CUDA tensors; gradients are returned for A, b and c.
+    """
+
+    @staticmethod
+    def forward(ctx, A, b, c, settings=None):
+        w = abip_setup(A, b, c, settings)
+        x, y, s, info = abip_solve(w)
+        if info["status"] != ABIP_SOLVED:
+            raise ABIPError(ABIP_E_STATE, f"solve ended with status {info['status_name']}")
+        ctx.work = w
+        ctx.info = info
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        want_A = ctx.needs_input_grad[0]
+        dc, db, dA = abip_backward(ctx.work, gx.contiguous().to(torch.float64), want_A=want_A)
+        return dA, db, dc, None
+
+
+def abip_solve_diff(A, b, c, settings=None):
+    """Differentiable single-LP solve (see ABIPSolve)."""
+    return ABIPSolve.apply(A, b, c, settings)

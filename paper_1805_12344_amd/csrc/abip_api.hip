@@ -18,6 +18,21 @@ hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const
                            const PoolPtrs& P, const SolveParams& prm, const int32_t* order, int32_t B,
                            int32_t* queue, int64_t fixed_iters, int32_t ldmax);
 size_t wg_smem_bytes(int ldmax, int W);
+struct AdjArgs {
+    double* ws;
+    const int64_t* ows;
+    const double* const* gin;
+    double* const* dc;
+    double* const* db;
+    double* const* dA;
+    int64_t max_iters;
+    double tol;
+    int64_t* iters_out;
+    double* resid_out;
+};
+hipError_t launch_adjoint(int grid, int threads, hipStream_t st, const LPDesc* desc, const LPCtrl* ctrl,
+                          const PoolPtrs& P, const SolveParams& prm, const AdjArgs& aa, const int32_t* order,
+                          int32_t B, int32_t* queue, int32_t ldmax);
 hipError_t set_solve_wg_smem_limit(size_t bytes);
 
 // setup kernels (abip_setup.hip)
@@ -27,7 +42,7 @@ __global__ void k_setup_rows(const LPDesc*, const double* const*, const double* 
 __global__ void k_syrk(const LPDesc*, const double*, double*);
 __global__ void k_chol_inv(const LPDesc*, double*, float*, double*, const int64_t*, int*);
 __global__ void k_setup_border(const LPDesc*, const double*, const double*, double*, double*, int64_t,
-                               int64_t, LPCtrl*);
+                               int64_t, LPCtrl*, int);
 
 // ---------------------------------------------------------------------------
 // error reporting
@@ -74,7 +89,7 @@ __global__ void k_init_state(const LPDesc* __restrict__ desc, LPCtrl* __restrict
         c.tau = 1.0; c.kappa = 1.0; c.theta = 1.0; c.mu = beta;
         c.pres = c.dres = c.gap = c.pobj = c.dobj = NAN;
         c.by = c.cx = 0.0;
-        c.iters = 0; c.iters64 = 0; c.ipm = 0;
+        c.iters = 0; c.iters64 = 0; c.ipm = 0; c.cp32 = 0; c.cp64 = 0;
         c.status = 0; c.phase = phase; c.mode = OP_REFRESH; c.flags = 0;
     }
 }
@@ -214,6 +229,12 @@ struct abip_work {
     int cu_count = 256;
     bool solved = false;
     double setup_ms = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket the persistent solve launch
+    // adjoint workspace (allocated at the first backward call)
+    double* adj_ws = nullptr; int64_t* adj_ows = nullptr;
+    double** adj_ptrs = nullptr;                 // 4*B device pointers: g, dc, db, dA
+    int64_t* adj_iters = nullptr; double* adj_resid = nullptr;
+    std::vector<int64_t> h_adj_iters; std::vector<double> h_adj_resid;
     std::vector<LPCtrl> hctrl;
 };
 
@@ -223,6 +244,10 @@ static void release(abip_work* w) {
     (void)hipFree(w->A64); (void)hipFree(w->A32); (void)hipFree(w->G64); (void)hipFree(w->G32);
     (void)hipFree(w->Mv); (void)hipFree(w->Nv);
     (void)hipFree(w->order); (void)hipFree(w->queue); (void)hipFree(w->errflag); (void)hipFree(w->outp);
+    (void)hipFree(w->adj_ws); (void)hipFree(w->adj_ows); (void)hipFree(w->adj_ptrs);
+    (void)hipFree(w->adj_iters); (void)hipFree(w->adj_resid);
+    if (w->ev0) (void)hipEventDestroy(w->ev0);
+    if (w->ev1) (void)hipEventDestroy(w->ev1);
 }
 
 extern "C" int abip_default_settings(abip_settings* s) {
@@ -376,9 +401,11 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     SCHK(hipGetLastError());
     hipLaunchKernelGGL(k_chol_inv, dim3(B), dim3(256), 0, st, w->ddesc, w->G64, w->G32, Wp, doW, w->errflag);
     SCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_setup_border, dim3(B), dim3(512), sizeof(double) * 2 * w->ldmax, st, w->ddesc, w->A64,
-                       w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, w->dctrl);
-    SCHK(hipGetLastError());
+    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+        hipLaunchKernelGGL(k_setup_border, dim3(B), dim3(512), sizeof(double) * 2 * w->ldmax, st, w->ddesc, w->A64,
+                           w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, w->dctrl, sgn);
+        SCHK(hipGetLastError());
+    }
     int hflag = 0;
     SCHK(hipMemcpyAsync(&hflag, w->errflag, sizeof(int), hipMemcpyDeviceToHost, st));
     SCHK(hipStreamSynchronize(st));
@@ -421,12 +448,19 @@ static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParam
     const int grid = std::max(1, std::min<int>(B, w->cu_count * per_cu));
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, w->queue);
     HIPCHK(hipGetLastError());
+    if (!w->ev0) HIPCHK(hipEventCreate(&w->ev0));
+    if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
+    HIPCHK(hipEventRecord(w->ev0, st));
     HIPCHK(launch_solve_wg(w->nch, grid, w->threads, st, w->ddesc, w->dctrl, pools(w), prm, w->order, B, w->queue,
                            fixed_iters, w->ldmax));
+    HIPCHK(hipEventRecord(w->ev1, st));
     return ABIP_OK;
 }
 
-static void fill_info(abip_info* info, const LPCtrl& c, double setup_ms, double solve_ms) {
+static void fill_info(abip_info* info, const LPCtrl& c, double setup_ms, double solve_ms, double kernel_ms) {
+    info->colpass_fp32 = c.cp32;
+    info->colpass_fp64 = c.cp64;
+    info->kernel_ms = kernel_ms;
     info->status = c.status;
     info->admm_iters = c.iters;
     info->admm_iters_fp64 = c.iters64;
@@ -462,8 +496,10 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
     HIPCHK(hipMemcpyAsync(w->hctrl.data(), w->dctrl, sizeof(LPCtrl) * w->B, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const double ms = now_ms() - t0;
+    float kms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&kms, w->ev0, w->ev1));
     if (info)
-        for (int k = 0; k < w->B; ++k) fill_info(&info[k], w->hctrl[k], w->setup_ms, ms);
+        for (int k = 0; k < w->B; ++k) fill_info(&info[k], w->hctrl[k], w->setup_ms, ms, (double)kms);
     w->solved = true;
     return ABIP_OK;
 }
@@ -482,15 +518,84 @@ extern "C" int abip_solve_batch(abip_work* w, double* const* x, double* const* y
     return solve_all(w, x, y, s, info);
 }
 
-extern "C" int abip_backward(abip_work* w, const double*, double*, double*, double*) {
-    if (!w) return fail(ABIP_E_INVALID, "abip_backward: null handle");
-    return fail(ABIP_E_STATE, "abip_backward: not available in this build");
+static int backward_all(abip_work* w, const double* const* g, double* const* dc, double* const* db,
+                        double* const* dA) {
+    if (!w->solved) return fail(ABIP_E_STATE, "abip_backward: call abip_solve first");
+    for (int k = 0; k < w->B; ++k) {
+        if (!g || !g[k] || !dc || !dc[k] || !db || !db[k])
+            return fail(ABIP_E_INVALID, "abip_backward: null gradient or output pointer (LP %d)", k);
+        if (w->hctrl[k].status != ABIP_SOLVED && !(w->hctrl[k].flags & 4) && w->B == 1)
+            return fail(ABIP_E_STATE, "abip_backward: the solve ended with status %d, not SOLVED", w->hctrl[k].status);
+    }
+    hipStream_t st = w->stream;
+    if (!w->adj_ws) {
+        std::vector<int64_t> ows(w->B);
+        int64_t tot = 0;
+        for (int k = 0; k < w->B; ++k) {
+            const LPDesc& d = w->hdesc[k];
+            ows[k] = tot;
+            tot += 7 * (int64_t)(d.m + 2 * d.n + 3) + 2 * (int64_t)d.n + (d.m + d.n + 2);
+            tot = (tot + 3) & ~(int64_t)3;
+        }
+        HIPCHK(hipMalloc((void**)&w->adj_ws, sizeof(double) * tot));
+        HIPCHK(hipMalloc((void**)&w->adj_ows, sizeof(int64_t) * w->B));
+        HIPCHK(hipMalloc((void**)&w->adj_ptrs, sizeof(double*) * 4 * w->B));
+        HIPCHK(hipMalloc((void**)&w->adj_iters, sizeof(int64_t) * w->B));
+        HIPCHK(hipMalloc((void**)&w->adj_resid, sizeof(double) * w->B));
+        HIPCHK(hipMemcpyAsync(w->adj_ows, ows.data(), sizeof(int64_t) * w->B, hipMemcpyHostToDevice, st));
+        w->h_adj_iters.resize(w->B);
+        w->h_adj_resid.resize(w->B);
+    }
+    std::vector<double*> tab(4 * w->B);
+    for (int k = 0; k < w->B; ++k) {
+        tab[k] = (double*)g[k];
+        tab[w->B + k] = dc[k];
+        tab[2 * w->B + k] = db[k];
+        tab[3 * w->B + k] = dA ? dA[k] : nullptr;
+    }
+    HIPCHK(hipMemcpyAsync(w->adj_ptrs, tab.data(), sizeof(double*) * 4 * w->B, hipMemcpyHostToDevice, st));
+    AdjArgs aa;
+    aa.ws = w->adj_ws; aa.ows = w->adj_ows;
+    aa.gin = w->adj_ptrs; aa.dc = w->adj_ptrs + w->B; aa.db = w->adj_ptrs + 2 * w->B; aa.dA = w->adj_ptrs + 3 * w->B;
+    aa.max_iters = w->set.adjoint_max_iters;
+    aa.tol = w->set.adjoint_tol;
+    aa.iters_out = w->adj_iters; aa.resid_out = w->adj_resid;
+    const SolveParams prm = make_params(w->set);
+    const int threads = 512;
+    const int grid = std::max(1, std::min<int>(w->B, w->cu_count));
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, w->queue);
+    HIPCHK(hipGetLastError());
+    HIPCHK(launch_adjoint(grid, threads, st, w->ddesc, w->dctrl, pools(w), prm, aa, w->order, w->B, w->queue,
+                          w->ldmax));
+    HIPCHK(hipMemcpyAsync(w->h_adj_iters.data(), w->adj_iters, sizeof(int64_t) * w->B, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(w->h_adj_resid.data(), w->adj_resid, sizeof(double) * w->B, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return ABIP_OK;
 }
 
-extern "C" int abip_backward_batch(abip_work* w, const double* const*, double* const*, double* const*,
-                                   double* const*) {
+extern "C" int abip_backward(abip_work* w, const double* dL_dx, double* dL_dc, double* dL_db, double* dL_dA) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_backward: null handle");
+    if (w->B != 1) return fail(ABIP_E_STATE, "abip_backward: handle holds %d LPs; use abip_backward_batch", w->B);
+    const double* g[1] = {dL_dx};
+    double* c[1] = {dL_dc};
+    double* b[1] = {dL_db};
+    double* a[1] = {dL_dA};
+    return backward_all(w, g, c, b, a);
+}
+
+extern "C" int abip_backward_batch(abip_work* w, const double* const* dL_dx, double* const* dL_dc,
+                                   double* const* dL_db, double* const* dL_dA) {
     if (!w) return fail(ABIP_E_INVALID, "abip_backward_batch: null handle");
-    return fail(ABIP_E_STATE, "abip_backward_batch: not available in this build");
+    return backward_all(w, dL_dx, dL_dc, dL_db, dL_dA);
+}
+
+extern "C" int abip_backward_stats(abip_work* w, int32_t k, int64_t* iters, double* rel_resid) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_backward_stats: null handle");
+    if (k < 0 || k >= w->B) return fail(ABIP_E_INVALID, "abip_backward_stats: LP index %d out of range", k);
+    if (w->h_adj_iters.empty()) return fail(ABIP_E_STATE, "abip_backward_stats: no backward call yet");
+    if (iters) *iters = w->h_adj_iters[k];
+    if (rel_resid) *rel_resid = w->h_adj_resid[k];
+    return ABIP_OK;
 }
 
 extern "C" int abip_apply_iq(abip_work* w, int32_t k, const double* win, double* out, int32_t use_fp32) {
@@ -522,10 +627,12 @@ extern "C" int abip_set_state(abip_work* w, int32_t k, const double* y, const do
     HIPCHK(hipMemcpyAsync(&c, w->dctrl + k, sizeof c, hipMemcpyDeviceToHost, w->stream));
     HIPCHK(hipStreamSynchronize(w->stream));
     c.tau = tau; c.kappa = kappa; c.theta = theta; c.mu = mu;
-    c.status = 0; c.mode = OP_REFRESH; c.flags = 0;
+    c.status = 0; c.mode = OP_REFRESH; c.flags = 4;     // 4: loaded iterate, may be differentiated
     c.iters = 0; c.iters64 = 0; c.ipm = 0;
     HIPCHK(hipMemcpyAsync(w->dctrl + k, &c, sizeof c, hipMemcpyHostToDevice, w->stream));
     HIPCHK(hipStreamSynchronize(w->stream));
+    if (w->hctrl.size() == (size_t)w->B) w->hctrl[k] = c;
+    w->solved = true;        // the loaded iterate is what abip_backward differentiates
     return ABIP_OK;
 }
 
@@ -556,7 +663,7 @@ extern "C" int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_
     HIPCHK(hipStreamSynchronize(w->stream));
     c.phase = use_fp32 ? 0 : 1;
     c.mode = OP_REFRESH;
-    c.flags = 0;
+    c.flags &= 4;
     HIPCHK(hipMemcpyAsync(w->dctrl + k, &c, sizeof c, hipMemcpyHostToDevice, w->stream));
     int32_t* ord1 = nullptr;
     HIPCHK(hipMalloc((void**)&ord1, sizeof(int32_t)));

@@ -15,9 +15,9 @@
 #define ABIP_WAVE 64
 
 // m-vector fields
-enum { MF_B = 0, MF_BBAR, MF_AC, MF_ACBAR, MF_ZY0, MF_ZY1, MF_Y, MF_AUX, NMF };
+enum { MF_B = 0, MF_BBAR, MF_AC, MF_ACBAR, MF_ZY0, MF_ZY1, MF_Y, MF_ZY0A, MF_ZY1A, NMF };
 // n-vector fields
-enum { NF_C = 0, NF_CBAR, NF_ZX0, NF_ZX1, NF_X, NF_S, NF_AUX, NNF };
+enum { NF_C = 0, NF_CBAR, NF_ZX0, NF_ZX1, NF_X, NF_S, NF_ZX0A, NF_ZX1A, NNF };
 
 // column-pass operations
 enum { OP_REFRESH = 0, OP_PROX = 1, OP_RESTART = 2 };
@@ -34,10 +34,12 @@ struct LPDesc {
 struct LPCtrl {
     double zbar, nb, nc;
     double K00, K01, K10, K11;        // K^{-1}, K = I2 + S + H^T Z
+    double KA00, KA01, KA10, KA11;    // the same for I - Q (adjoint solves)
     double tau, kappa, theta, mu;
     double pres, dres, gap, pobj, dobj;  // last check (relative residuals)
     double by, cx;                        // b^T y, c^T x at the last check
     int64_t iters, iters64, ipm;
+    int64_t cp32, cp64;                   // column passes per data precision
     int32_t status, phase, mode, flags;  // phase 0 = FP32 bulk, 1 = FP64; mode = next op
 };
 
@@ -122,4 +124,46 @@ __device__ __forceinline__ void block_sum_n(double (&v)[K], double* sbuf) {
         v[k] = s;
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+__device__ __forceinline__ int num_waves() { return __builtin_amdgcn_readfirstlane(blockDim.x >> 6); }
+
+// Reduce K values (K a power of two, 2 <= K <= 16) over the 64 lanes of a wave
+// by recursive halving: at offset o the lanes with bit o set keep the upper
+// half of the still-live values and the others the lower half.  Afterwards
+// the total of value k sits in v[0] of lane lane_of<K>(k) (any lane of a
+// 2^{6-log2 K}-lane block holds the same total); read it with bcast_lane.
+template <int K>
+__device__ __forceinline__ void wave_reduce_scatter(double (&v)[K]) {
+    const int lane = threadIdx.x & 63;
+    constexpr int L = (K >= 16) ? 4 : (K >= 8) ? 3 : (K >= 4) ? 2 : 1;
+#pragma unroll
+    for (int lev = 0; lev < 6; ++lev) {
+        const int o = 32 >> lev;
+        if (lev < L) {
+            const int h = K >> (lev + 1);
+            const bool up = (lane & o) != 0;
+#pragma unroll
+            for (int k = 0; k < h; ++k) {
+                // pin both operands in registers first: otherwise the compiler turns
+                // the per-lane choice into a dynamic index into v[] and lowers it as a
+                // compare/select chain over the whole array
+                double lo = v[k], hi = v[k + h];
+                asm volatile("" : "+v"(lo), "+v"(hi));
+                const double send = up ? lo : hi;
+                const double keep = up ? hi : lo;
+                v[k] = keep + __shfl_xor(send, o, 64);
+            }
+        } else {
+            v[0] += __shfl_xor(v[0], o, 64);
+        }
+    }
+}
+template <int K>
+__device__ __forceinline__ constexpr int lane_of(int k) {
+    int lane = 0;
+    for (int lev = 0; (K >> (lev + 1)) >= 1; ++lev)
+        if (k & (K >> (lev + 1))) lane += 32 >> lev;
+    return lane;
 }

@@ -338,17 +338,22 @@ __global__ __launch_bounds__(256) void k_chol_inv(const LPDesc* __restrict__ des
 }
 
 // ---------------------------------------------------------------------------
-// Border of the Schur reduction (Section 4.4 with the theta column kept):
-// Z = M^{-1} H for H = [(-b; c), (bbar; -cbar)], M^{-1}(e; f) = (a; f + A^T a),
-// a = G^{-1}(e - A f); K = I2 + S + H^T Z with S = [[0, zbar], [-zbar, 0]];
-// stores K^{-1} and zbar, ||b||, ||c|| in the LP's control block.
-// One workgroup per LP (FP64).  LDS: 2*ld doubles.
+// Border of the Schur reduction (Section 4.4 with the theta column kept).
+// sgn = +1: I + Q = [[M, H], [-H^T, I2 + S]] with M = [[I, A], [-A^T, I]],
+//   H = [(-b; c), (bbar; -cbar)], S = [[0, zbar], [-zbar, 0]];
+//   M^{-1}(e; f) = (a; f + A^T a), a = G^{-1}(e - A f).
+// sgn = -1: the same for I - Q = (I + Q)^T, used by the adjoint: A, H, S change
+//   sign, G = I + A A^T is unchanged.
+// Stores Z = M^{-1} H (two M-solves) and K^{-1}, K = I2 + S + H^T Z, plus zbar,
+// ||b||, ||c|| in the LP's control block.  One workgroup per LP (FP64).
+// LDS: 2*ld doubles.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void k_setup_border(const LPDesc* __restrict__ desc,
                                                       const double* __restrict__ A64,
                                                       const double* __restrict__ G64,
                                                       double* __restrict__ Mv, double* __restrict__ Nv,
-                                                      int64_t Mtot, int64_t Ntot, LPCtrl* __restrict__ ctrl) {
+                                                      int64_t Mtot, int64_t Ntot, LPCtrl* __restrict__ ctrl,
+                                                      int sgn) {
     extern __shared__ double sm[];
     __shared__ double sbuf[8 * 8];
     const int k = blockIdx.x;
@@ -360,8 +365,11 @@ __global__ __launch_bounds__(512) void k_setup_border(const LPDesc* __restrict__
     const double* bbar = Mv + MF_BBAR * Mtot + d.om;
     const double* c = Nv + NF_C * Ntot + d.on;
     const double* cbar = Nv + NF_CBAR * Ntot + d.on;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, W = blockDim.x >> 6;
-    double* st = sm;          // t = e - A f
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id(), W = num_waves();
+    const int fzy = (sgn > 0) ? MF_ZY0 : MF_ZY0A;
+    const int fzx = (sgn > 0) ? NF_ZX0 : NF_ZX0A;
+    const double sg = (double)sgn;
+    double* st = sm;          // t = e - sgn A f
     double* sa = sm + ld;     // a = G^{-1} t
 
     // norms and zbar
@@ -372,16 +380,16 @@ __global__ __launch_bounds__(512) void k_setup_border(const LPDesc* __restrict__
     const double nb = sqrt(v3[0]), nc = sqrt(v3[1]), zbar = v3[2] + 1.0;
 
     for (int h = 0; h < 2; ++h) {
-        // h = 0: (e; f) = (-b; c)   h = 1: (e; f) = (bbar; -cbar)
+        // column h of sgn*H: h = 0: sgn*(-b; c)   h = 1: sgn*(bbar; -cbar)
         const double* ev = (h == 0) ? b : bbar;
         const double* fv = (h == 0) ? c : cbar;
-        const double es = (h == 0) ? -1.0 : 1.0;
-        const double fs = (h == 0) ? 1.0 : -1.0;
+        const double es = sg * ((h == 0) ? -1.0 : 1.0);
+        const double fs = sg * ((h == 0) ? 1.0 : -1.0);
         for (int i = tid; i < ld; i += blockDim.x) {
             double s = 0.0;
             if (i < m) {
                 for (int j = 0; j < n; ++j) s = fma(A[(int64_t)j * ld + i], fs * fv[j], s);
-                s = es * ev[i] - s;
+                s = es * ev[i] - sg * s;
             }
             st[i] = s;
         }
@@ -391,24 +399,24 @@ __global__ __launch_bounds__(512) void k_setup_border(const LPDesc* __restrict__
             if (i < m)
                 for (int q = 0; q < m; ++q) s = fma(G[(int64_t)q * ld + i], st[q], s);
             sa[i] = s;
-            if (i < m) Mv[(MF_ZY0 + h) * Mtot + d.om + i] = s;
+            if (i < m) Mv[(fzy + h) * Mtot + d.om + i] = s;
         }
         __syncthreads();
         for (int j = wave; j < n; j += W) {
             double s = 0.0;
             for (int i = lane; i < m; i += 64) s = fma(A[(int64_t)j * ld + i], sa[i], s);
             s = wave_sum(s);
-            if (lane == 0) Nv[(NF_ZX0 + h) * Ntot + d.on + j] = fs * fv[j] + s;
+            if (lane == 0) Nv[(fzx + h) * Ntot + d.on + j] = fs * fv[j] + sg * s;
         }
         __syncthreads();
     }
     __threadfence_block();
     __syncthreads();
-    // H^T Z: entry (r, q) = h_r^T z_q
-    const double* zy0 = Mv + MF_ZY0 * Mtot + d.om;
-    const double* zy1 = Mv + MF_ZY1 * Mtot + d.om;
-    const double* zx0 = Nv + NF_ZX0 * Ntot + d.on;
-    const double* zx1 = Nv + NF_ZX1 * Ntot + d.on;
+    // (sgn H)^T Z: entry (r, q) = h_r^T z_q
+    const double* zy0 = Mv + fzy * Mtot + d.om;
+    const double* zy1 = Mv + (fzy + 1) * Mtot + d.om;
+    const double* zx0 = Nv + fzx * Ntot + d.on;
+    const double* zx1 = Nv + (fzx + 1) * Ntot + d.on;
     double hz[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = tid; i < m; i += blockDim.x) {
         hz[0] = fma(-b[i], zy0[i], hz[0]);
@@ -424,16 +432,17 @@ __global__ __launch_bounds__(512) void k_setup_border(const LPDesc* __restrict__
     }
     block_sum_n<4>(hz, sbuf);
     if (tid == 0) {
-        const double k00 = 1.0 + hz[0], k01 = zbar + hz[1];
-        const double k10 = -zbar + hz[2], k11 = 1.0 + hz[3];
+        const double k00 = 1.0 + sg * hz[0], k01 = sg * zbar + sg * hz[1];
+        const double k10 = -sg * zbar + sg * hz[2], k11 = 1.0 + sg * hz[3];
         const double det = k00 * k11 - k01 * k10;
         LPCtrl& C = ctrl[k];
         C.zbar = zbar;
         C.nb = nb;
         C.nc = nc;
-        C.K00 = k11 / det;
-        C.K01 = -k01 / det;
-        C.K10 = -k10 / det;
-        C.K11 = k00 / det;
+        if (sgn > 0) {
+            C.K00 = k11 / det; C.K01 = -k01 / det; C.K10 = -k10 / det; C.K11 = k00 / det;
+        } else {
+            C.KA00 = k11 / det; C.KA01 = -k01 / det; C.KA10 = -k10 / det; C.KA11 = k00 / det;
+        }
     }
 }

@@ -18,8 +18,6 @@
 #include <hip/hip_runtime.h>
 #include "abip_internal.h"
 
-#define UNR 4
-
 struct WGShared {
     double* y;      // ld
     double* a;      // ld
@@ -37,16 +35,19 @@ struct WGShared {
 // state in sh.Af / sh.Ax and the column-side sums in cs[7]:
 //   c^T x, cbar^T x, c^T s, cbar^T s, ||A^T y + s - c tau||^2, ||A^T y + s||^2,
 //   ||-A^T y + c tau - cbar theta - s||^2.
-template <int NCH, typename T>
-__device__ void column_pass(const T* __restrict__ A, int m, int n, int ld,
-                            double* __restrict__ X, double* __restrict__ S,
-                            const double* __restrict__ C, const double* __restrict__ CB,
-                            const double* __restrict__ ZX0, const double* __restrict__ ZX1,
-                            const WGShared& sh, int op, double p0, double p1, double tmu,
-                            double alpha, double gamma, int rule, double tau, double theta,
-                            double (&cs)[7]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+// Layout: a wave owns whole columns (chunks of 64 consecutive columns, round
+// robin over the waves); lane l holds rows 4l..4l+3 of every 256-row chunk.
+template <int NCH, int UNR, typename T>
+__device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int n, int ld,
+                                         double* __restrict__ X, double* __restrict__ S,
+                                         const double* __restrict__ C, const double* __restrict__ CB,
+                                         const double* __restrict__ ZX0, const double* __restrict__ ZX1,
+                                         const WGShared& sh, int op, double p0, double p1, double tmu,
+                                         double alpha, double gamma, int rule, double tau, double theta,
+                                         double* __restrict__ cs) {
+    const int lane = threadIdx.x & 63, wave = wave_id(), W = num_waves();
     constexpr int R = NCH * 4;
+    constexpr int K = 2 * UNR;
     double ra[R], ry[R], accf[R], accx[R];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
@@ -58,20 +59,23 @@ __device__ void column_pass(const T* __restrict__ A, int m, int n, int ld,
             accf[ch * 4 + q] = 0.0;
             accx[ch * 4 + q] = 0.0;
         }
+    // column-side sums, accumulated by the lane that owns the column update
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     const double sg = sqrt(gamma);
+    const bool prox = (op == OP_PROX);
     for (int cblk = wave; cblk * 64 < n; cblk += W) {
         const int j0 = cblk * 64;
         const int cnt = min(64, n - j0);
-        double xj = 0, sj = 0, cj = 0, cbj = 0, z0 = 0, z1 = 0;
-        if (lane < cnt) {
-            xj = X[j0 + lane]; sj = S[j0 + lane];
-            cj = C[j0 + lane]; cbj = CB[j0 + lane];
-            if (op == OP_PROX) { z0 = ZX0[j0 + lane]; z1 = ZX1[j0 + lane]; }
-        }
-        double xn = xj, sn = sj;
         for (int kk = 0; kk < cnt; kk += UNR) {
-            double v[UNR][R];
+            // lane u < UNR owns column j0+kk+u: its scalar data
+            const int jl = j0 + kk + lane;
+            const bool own = (lane < UNR) && (kk + lane < cnt);
+            double x0 = 0, s0 = 0, c0 = 0, cb0 = 0, zz0 = 0, zz1 = 0;
+            if (own) {
+                x0 = X[jl]; s0 = S[jl]; c0 = C[jl]; cb0 = CB[jl];
+                if (prox) { zz0 = ZX0[jl]; zz1 = ZX1[jl]; }
+            }
+            T v[UNR][R];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const int col = j0 + kk + u;
@@ -79,72 +83,91 @@ __device__ void column_pass(const T* __restrict__ A, int m, int n, int ld,
                 for (int ch = 0; ch < NCH; ++ch) {
                     const int r0 = ch * 256 + lane * 4;
                     if (kk + u < cnt && r0 < ld) {
-                        load4(A + (int64_t)col * ld + r0, &v[u][ch * 4]);
+                        if constexpr (sizeof(T) == 4) {
+                            const float4 q4 = *reinterpret_cast<const float4*>(A + (int64_t)col * ld + r0);
+                            v[u][ch * 4 + 0] = q4.x; v[u][ch * 4 + 1] = q4.y;
+                            v[u][ch * 4 + 2] = q4.z; v[u][ch * 4 + 3] = q4.w;
+                        } else {
+                            const double2 q0 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + r0)[0];
+                            const double2 q1 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + r0)[1];
+                            v[u][ch * 4 + 0] = q0.x; v[u][ch * 4 + 1] = q0.y;
+                            v[u][ch * 4 + 2] = q1.x; v[u][ch * 4 + 3] = q1.y;
+                        }
                     } else {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) v[u][ch * 4 + q] = 0.0;
+                        for (int q = 0; q < 4; ++q) v[u][ch * 4 + q] = (T)0;
                     }
                 }
             }
-            double dots[2 * UNR];
+            double dots[K];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 double da = 0.0, dy = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    da = fma(v[u][r], ra[r], da);
-                    dy = fma(v[u][r], ry[r], dy);
+                    if (prox) da = fma((double)v[u][r], ra[r], da);
+                    dy = fma((double)v[u][r], ry[r], dy);
                 }
                 dots[2 * u] = da;
                 dots[2 * u + 1] = dy;
             }
-            wave_sum_n<2 * UNR>(dots);
+            wave_reduce_scatter<K>(dots);
+            // hand the two column totals of column u to lane u
+            double ata = 0.0, aty = 0.0;
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
-                const int l = kk + u;
-                if (l < cnt) {
-                    const double x0 = bcast_lane(xj, l), s0 = bcast_lane(sj, l);
-                    const double c0 = bcast_lane(cj, l), cb0 = bcast_lane(cbj, l);
-                    double x1, s1;
-                    if (op == OP_PROX) {
-                        const double zz0 = bcast_lane(z0, l), zz1 = bcast_lane(z1, l);
-                        const double dj = (x0 + s0) + dots[2 * u];          // M^{-1} block, x part
-                        const double ut = dj - zz0 * p0 - zz1 * p1;           // u~_x
-                        const double uh = alpha * ut + (1.0 - alpha) * x0;    // relaxation
-                        x1 = prox_root(uh - s0, tmu);                         // barrier prox
-                        s1 = s0 - uh + x1;                                    // dual update
-                    } else if (op == OP_RESTART) {
-                        if (rule == 0) {
-                            if (x0 >= s0) { x1 = x0; s1 = gamma * s0; }
-                            else { x1 = gamma * x0; s1 = s0; }
-                        } else {
-                            x1 = sg * x0; s1 = sg * s0;
-                        }
+                const double a_u = bcast_lane(dots[0], lane_of<K>(2 * u));
+                const double y_u = bcast_lane(dots[0], lane_of<K>(2 * u + 1));
+                if (lane == u) { ata = a_u; aty = y_u; }
+            }
+            // the column update, one column per owning lane
+            double x1 = x0, s1 = s0;
+            if (own) {
+                if (prox) {
+                    const double dj = (x0 + s0) + ata;                     // M^{-1} block, x part
+                    const double ut = dj - zz0 * p0 - zz1 * p1;           // u~_x
+                    const double uh = alpha * ut + (1.0 - alpha) * x0;    // relaxation
+                    x1 = prox_root(uh - s0, tmu);                         // barrier prox
+                    s1 = s0 - uh + x1;                                    // dual update
+                } else if (op == OP_RESTART) {
+                    if (rule == 0) {
+                        if (x0 >= s0) s1 = gamma * s0;
+                        else x1 = gamma * x0;
                     } else {
-                        x1 = x0; s1 = s0;
+                        x1 = sg * x0; s1 = sg * s0;
                     }
-                    if (lane == l) { xn = x1; sn = s1; }
-                    const double f1 = x1 + s1;
+                }
+                if (op != OP_REFRESH) { X[jl] = x1; S[jl] = s1; }
+                const double r1 = aty + s1 - c0 * tau;
+                const double r2 = aty + s1;
+                const double r3 = -aty + c0 * tau - cb0 * theta - s1;
+                acc7[0] = fma(c0, x1, acc7[0]);
+                acc7[1] = fma(cb0, x1, acc7[1]);
+                acc7[2] = fma(c0, s1, acc7[2]);
+                acc7[3] = fma(cb0, s1, acc7[3]);
+                acc7[4] = fma(r1, r1, acc7[4]);
+                acc7[5] = fma(r2, r2, acc7[5]);
+                acc7[6] = fma(r3, r3, acc7[6]);
+            }
+            // A[:, col] (x'+s') and A[:, col] x' for every row this lane holds
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        accf[r] = fma(v[u][r], f1, accf[r]);
-                        accx[r] = fma(v[u][r], x1, accx[r]);
-                    }
-                    const double aty = dots[2 * u + 1];
-                    const double r1 = aty + s1 - c0 * tau;
-                    const double r2 = aty + s1;
-                    const double r3 = -aty + c0 * tau - cb0 * theta - s1;
-                    acc7[0] = fma(c0, x1, acc7[0]);
-                    acc7[1] = fma(cb0, x1, acc7[1]);
-                    acc7[2] = fma(c0, s1, acc7[2]);
-                    acc7[3] = fma(cb0, s1, acc7[3]);
-                    acc7[4] = fma(r1, r1, acc7[4]);
-                    acc7[5] = fma(r2, r2, acc7[5]);
-                    acc7[6] = fma(r3, r3, acc7[6]);
+            for (int u = 0; u < UNR; ++u) {
+                const double xu = bcast_lane(x1, u);
+                const double fu = xu + bcast_lane(s1, u);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    accf[r] = fma((double)v[u][r], fu, accf[r]);
+                    accx[r] = fma((double)v[u][r], xu, accx[r]);
                 }
             }
         }
-        if (lane < cnt && op != OP_REFRESH) { X[j0 + lane] = xn; S[j0 + lane] = sn; }
+    }
+    // column-side sums live in lanes 0..UNR-1: one reduction per pass
+    {
+        double t8[8] = {acc7[0], acc7[1], acc7[2], acc7[3], acc7[4], acc7[5], acc7[6], 0.0};
+        wave_sum_n<8>(t8);
+#pragma unroll
+        for (int q = 0; q < 7; ++q) acc7[q] = t8[q];
     }
     // cross-wave reduction (fixed order: deterministic)
 #pragma unroll
@@ -177,54 +200,38 @@ __device__ void column_pass(const T* __restrict__ A, int m, int n, int ld,
     __syncthreads();
 }
 
-// a = G^{-1} t by column dot products over the symmetric G^{-1} (ld x m).
-template <int NCH, typename T>
-__device__ void ginv_pass(const T* __restrict__ G, int m, int ld, const WGShared& sh) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
-    constexpr int R = NCH * 4;
-    double rt[R];
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = ch * 256 + lane * 4 + q;
-            rt[ch * 4 + q] = (r < ld) ? sh.t[r] : 0.0;
+// a = G^{-1} t with one thread per row (G^{-1} is symmetric, so column j is
+// contiguous and a warp-wide load of column j is coalesced).  When the block
+// has more threads than rows, P thread groups split the columns and their
+// partial sums are added in a fixed order.
+template <typename T>
+__device__ __forceinline__ void ginv_pass(const T* __restrict__ G, int m, int ld, const WGShared& sh) {
+    const int nthr = blockDim.x;
+    int P = nthr / ld;
+    if (P < 1) P = 1;
+    const int Pmax = 2 * (nthr >> 6);
+    if (P > Pmax) P = Pmax;
+    for (int e = threadIdx.x; e < ld * P; e += nthr) {
+        const int r = e % ld, g = e / ld;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int j = g;
+        for (; j + 3 * P < m; j += 4 * P) {
+            s0 = fma((double)G[(int64_t)j * ld + r], sh.t[j], s0);
+            s1 = fma((double)G[(int64_t)(j + P) * ld + r], sh.t[j + P], s1);
+            s2 = fma((double)G[(int64_t)(j + 2 * P) * ld + r], sh.t[j + 2 * P], s2);
+            s3 = fma((double)G[(int64_t)(j + 3 * P) * ld + r], sh.t[j + 3 * P], s3);
         }
-    for (int cblk = wave; cblk * 64 < m; cblk += W) {
-        const int j0 = cblk * 64;
-        const int cnt = min(64, m - j0);
-        double an = 0.0;
-        for (int kk = 0; kk < cnt; kk += UNR) {
-            double dots[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int col = j0 + kk + u;
-                double v[R];
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    const int r0 = ch * 256 + lane * 4;
-                    if (kk + u < cnt && r0 < ld) load4(G + (int64_t)col * ld + r0, &v[ch * 4]);
-                    else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) v[ch * 4 + q] = 0.0;
-                    }
-                }
-                double s = 0.0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) s = fma(v[r], rt[r], s);
-                dots[u] = s;
-            }
-            wave_sum_n<UNR>(dots);
-#pragma unroll
-            for (int u = 0; u < UNR; ++u)
-                if (lane == kk + u) an = dots[u];
-        }
-        if (lane < cnt) sh.a[j0 + lane] = an;
+        for (; j < m; j += P) s0 = fma((double)G[(int64_t)j * ld + r], sh.t[j], s0);
+        sh.red[g * ld + r] = (s0 + s1) + (s2 + s3);
     }
-    for (int i = m + threadIdx.x; i < ld; i += blockDim.x) sh.a[i] = 0.0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < ld; r += nthr) {
+        double s = 0.0;
+        for (int g = 0; g < P; ++g) s += sh.red[g * ld + r];
+        sh.a[r] = (r < m) ? s : 0.0;
+    }
     __syncthreads();
 }
-
 
 // Solve (or iterate) one LP with the calling workgroup.
 // fixed_iters > 0: run exactly that many PROX iterations with no tests and no
@@ -255,6 +262,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     LPCtrl cl = ctrl[k];
     double tau = cl.tau, kappa = cl.kappa, theta = cl.theta, mu = cl.mu;
     int64_t iters = cl.iters, iters64 = cl.iters64, ipm = cl.ipm;
+    int64_t cp32 = cl.cp32, cp64 = cl.cp64;
     int phase = cl.phase;
     int op = cl.mode;          // first pass: OP_REFRESH of the loaded state
     int status = cl.status;
@@ -282,11 +290,12 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         const double tmu = mu / beta;
         double cs[7];
         if (phase == 0)
-            column_pass<NCH, float>(A32, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind, p0, p1, tmu,
-                                    alpha, gamma, prm.restart_rule, tau, theta, cs);
+            column_pass<NCH, (NCH <= 2 ? 4 : 2), float>(A32, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind,
+                                                        p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, cs);
         else
-            column_pass<NCH, double>(A64, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind, p0, p1, tmu,
-                                     alpha, gamma, prm.restart_rule, tau, theta, cs);
+            column_pass<NCH, (NCH == 1 ? 4 : 2), double>(A64, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind,
+                                                         p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, cs);
+        if (phase == 0) ++cp32; else ++cp64;
         const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
                                  (pass_kind == OP_REFRESH && !first);
         if (pass_kind == OP_PROX) {
@@ -374,8 +383,8 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         // ---- the inner update: t = y - A f, a = G^{-1} t, border, scalars, y'
         for (int i = tid; i < ld; i += blockDim.x) sh.t[i] = (i < m) ? sh.y[i] - sh.Af[i] : 0.0;
         __syncthreads();
-        if (phase == 0) ginv_pass<NCH, float>(G32, m, ld, sh);
-        else ginv_pass<NCH, double>(G64, m, ld, sh);
+        if (phase == 0) ginv_pass<float>(G32, m, ld, sh);
+        else ginv_pass<double>(G64, m, ld, sh);
         double bs[4] = {0, 0, 0, 0};
         for (int i = tid; i < m; i += blockDim.x) {
             const double ai = sh.a[i];
@@ -414,15 +423,16 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         o.pres = pres; o.dres = dres; o.gap = gap; o.pobj = pobj; o.dobj = dobj;
         o.by = by_last; o.cx = cx_last;
         o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
+        o.cp32 = cp32; o.cp64 = cp64;
         o.status = status; o.phase = phase;
         o.mode = OP_REFRESH;
-        o.flags = (fixed_iters > 0) ? 1 : 0;
+        o.flags = ((fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);
     }
     __syncthreads();
 }
 
 template <int NCH>
-__global__ __launch_bounds__(512) void k_solve_wg(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl,
+__global__ __launch_bounds__(NCH <= 2 ? 512 : 256) void k_solve_wg(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl,
                                                   PoolPtrs P, SolveParams prm, const int32_t* __restrict__ order,
                                                   int32_t B, int32_t* __restrict__ queue, int64_t fixed_iters,
                                                   int32_t ldmax) {
@@ -475,4 +485,298 @@ hipError_t set_solve_wg_smem_limit(size_t bytes) {
     if ((e = hipFuncSetAttribute((const void*)k_solve_wg<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void*)k_solve_wg<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_solve_wg<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// ===========================================================================
+// Adjoint of the converged HSD fixed point (project extension).
+//
+// One inner iteration is a map T on z = (y, x, tau, theta, s, kappa).  At the
+// final iterate L(z) = w^T x / tau, and dL/dp = lam^T dT/dp where lam solves
+// lam = J_T^T lam + dL/dz (J_T = dT/dz).  One application of J_T^T, from the
+// adjoint (ybar', xbar', taubar', thetabar', sbar', kappabar') of T's output:
+//   rho_x = x/(x+s), rho_t = tau/(tau+kappa) (derivative of the prox root,
+//   using x o s = t e and tau kappa = t, Theorem 3.1)
+//   wx = rho_x xbar' + (rho_x - 1) sbar',  wt = rho_t taubar' + (rho_t - 1) kappabar'
+//   wb = (I - Q)^{-1} alpha (ybar', wx, wt, thetabar')     ((I+Q)^T = I - Q)
+//   J_T^T(.) = ((1-a) ybar' + wb_y, (1-a) wx + wb_x, (1-a) wt + wb_tau,
+//               (1-a) thetabar' + wb_theta, -wx + wb_x, -wt + wb_tau)
+// (I - Q)^{-1} reuses G^{-1} (I - Q has the same G = I + A A^T) and the border
+// Z', K' of I - Q cached at setup.  The linear system (I - J_T^T) lam = dL/dz is
+// solved by BiCGSTAB; then dL/dp = -zeta^T d(Q u)/dp with zeta = wb(lam).
+// ===========================================================================
+
+struct AdjArgs {
+    double* ws;                       // per-LP workspace pool
+    const int64_t* ows;               // offsets into ws
+    const double* const* gin;         // dL/dx* per LP
+    double* const* dc;                // outputs per LP (device)
+    double* const* db;
+    double* const* dA;                // may hold nulls
+    int64_t max_iters;
+    double tol;
+    int64_t* iters_out;               // per LP: BiCGSTAB iterations
+    double* resid_out;                // per LP: final relative residual
+};
+
+// out = in - J_T^T(in); also leaves wb = (I-Q)^{-1}(...) in WB.
+__device__ void adj_op(const LPDesc& d, const LPCtrl& cl, const PoolPtrs& P, const WGShared& sh,
+                       const double* __restrict__ in, double* __restrict__ out, double* __restrict__ WX,
+                       double* __restrict__ Dv, double* __restrict__ WB, double alpha) {
+    const int m = d.m, n = d.n, ld = d.ld, tid = threadIdx.x, lane = threadIdx.x & 63;
+    const int wave = wave_id(), W = num_waves();
+    const int OX = m, OT = m + n, OH = m + n + 1, OS = m + n + 2, OK = m + 2 * n + 2;
+    const double* A = P.A64 + d.oA;
+    const double* X = P.Nv + NF_X * P.Ntot + d.on;
+    const double* S = P.Nv + NF_S * P.Ntot + d.on;
+    const double* b = P.Mv + MF_B * P.Mtot + d.om;
+    const double* bbar = P.Mv + MF_BBAR * P.Mtot + d.om;
+    const double* C = P.Nv + NF_C * P.Ntot + d.on;
+    const double* CBv = P.Nv + NF_CBAR * P.Ntot + d.on;
+    const double* zy0 = P.Mv + MF_ZY0A * P.Mtot + d.om;
+    const double* zy1 = P.Mv + MF_ZY1A * P.Mtot + d.om;
+    const double* zx0 = P.Nv + NF_ZX0A * P.Ntot + d.on;
+    const double* zx1 = P.Nv + NF_ZX1A * P.Ntot + d.on;
+    const double rt = cl.tau / (cl.tau + cl.kappa);
+    const double wt = rt * in[OT] + (rt - 1.0) * in[OK];
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double rx = X[j] / (X[j] + S[j]);
+        WX[j] = rx * in[OX + j] + (rx - 1.0) * in[OS + j];
+    }
+    __threadfence_block();
+    __syncthreads();
+    // t = alpha (in_y + A wx): one thread per row, columns split over P groups
+    {
+        int Pg = blockDim.x / ld;
+        if (Pg < 1) Pg = 1;
+        if (Pg > 2 * W) Pg = 2 * W;
+        for (int e = tid; e < ld * Pg; e += blockDim.x) {
+            const int r = e % ld, g = e / ld;
+            double s0 = 0.0, s1 = 0.0;
+            int j = g;
+            for (; j + Pg < n; j += 2 * Pg) {
+                s0 = fma(A[(int64_t)j * ld + r], WX[j], s0);
+                s1 = fma(A[(int64_t)(j + Pg) * ld + r], WX[j + Pg], s1);
+            }
+            for (; j < n; j += Pg) s0 = fma(A[(int64_t)j * ld + r], WX[j], s0);
+            sh.red[g * ld + r] = s0 + s1;
+        }
+        __syncthreads();
+        for (int r = tid; r < ld; r += blockDim.x) {
+            double s = 0.0;
+            for (int g = 0; g < Pg; ++g) s += sh.red[g * ld + r];
+            sh.t[r] = (r < m) ? alpha * (in[r] + s) : 0.0;
+        }
+        __syncthreads();
+    }
+    ginv_pass<double>(P.G64 + d.oG, m, ld, sh);          // sh.a = G^{-1} t
+    // d_j = alpha wx_j - (A^T a)_j, four columns per wave step
+    double cd = 0.0, cbd = 0.0;
+    for (int j0 = wave * 4; j0 < n; j0 += 4 * W) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double s = 0.0;
+            if (j0 + u < n)
+                for (int i = lane; i < m; i += 64) s = fma(A[(int64_t)(j0 + u) * ld + i], sh.a[i], s);
+            v[u] = s;
+        }
+        wave_reduce_scatter<4>(v);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double tot = bcast_lane(v[0], lane_of<4>(u));
+            if (lane == u && j0 + u < n) {
+                const double dj = alpha * WX[j0 + u] - tot;
+                Dv[j0 + u] = dj;
+                cd = fma(C[j0 + u], dj, cd);
+                cbd = fma(CBv[j0 + u], dj, cbd);
+            }
+        }
+    }
+    double dots[4] = {0.0, 0.0, cd, cbd};
+    for (int i = tid; i < m; i += blockDim.x) {
+        dots[0] = fma(b[i], sh.a[i], dots[0]);
+        dots[1] = fma(bbar[i], sh.a[i], dots[1]);
+    }
+    block_sum_n<4>(dots, sh.buf);      // also orders the Dv writes before their reads
+    // H'^T z with H' = -H:  (b^T a - c^T d, -bbar^T a + cbar^T d)
+    const double q0 = alpha * wt + (dots[0] - dots[2]);
+    const double q1 = alpha * in[OH] + (-dots[1] + dots[3]);
+    const double p0 = cl.KA00 * q0 + cl.KA01 * q1;
+    const double p1 = cl.KA10 * q0 + cl.KA11 * q1;
+    for (int i = tid; i < m; i += blockDim.x) {
+        const double wby = sh.a[i] - zy0[i] * p0 - zy1[i] * p1;
+        WB[i] = wby;
+        out[i] = in[i] - ((1.0 - alpha) * in[i] + wby);
+    }
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double wbx = Dv[j] - zx0[j] * p0 - zx1[j] * p1;
+        const double wx = WX[j];
+        WB[m + j] = wbx;
+        out[OX + j] = in[OX + j] - ((1.0 - alpha) * wx + wbx);
+        out[OS + j] = in[OS + j] - (-wx + wbx);
+    }
+    if (tid == 0) {
+        WB[m + n] = p0;
+        WB[m + n + 1] = p1;
+        out[OT] = in[OT] - ((1.0 - alpha) * wt + p0);
+        out[OH] = in[OH] - ((1.0 - alpha) * in[OH] + p1);
+        out[OK] = in[OK] - (-wt + p0);
+    }
+    __threadfence_block();
+    __syncthreads();
+}
+
+__device__ double adj_dot(const double* a, const double* b, int N, const WGShared& sh) {
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < N; i += blockDim.x) v[0] = fma(a[i], b[i], v[0]);
+    block_sum_n<1>(v, sh.buf);
+    return v[0];
+}
+
+__device__ void adjoint_one(int k, const LPDesc& d, const LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
+                            const SolveParams& prm, const AdjArgs& aa, const WGShared& sh) {
+    const int m = d.m, n = d.n, tid = threadIdx.x;
+    const int Nz = m + 2 * n + 3;
+    const LPCtrl cl = ctrl[k];
+    double* base = aa.ws + aa.ows[k];
+    double* LAM = base;
+    double* Rv = LAM + Nz;
+    double* R0 = Rv + Nz;
+    double* Pv = R0 + Nz;
+    double* V = Pv + Nz;
+    double* Sv = V + Nz;
+    double* Tv = Sv + Nz;
+    double* WX = Tv + Nz;
+    double* Dv = WX + n;
+    double* WB = Dv + n;
+    const double* X = P.Nv + NF_X * P.Ntot + d.on;
+    const double* Y = P.Mv + MF_Y * P.Mtot + d.om;
+    const double* win = aa.gin[k];
+    const double alpha = prm.alpha;
+    const double tau = cl.tau, theta = cl.theta;
+    if ((cl.status != 1 && !(cl.flags & 4)) || !(tau > 0.0)) {   // nothing to differentiate
+        double* dc = aa.dc[k];
+        double* db = aa.db[k];
+        double* dA = aa.dA[k];
+        for (int j = tid; j < n; j += blockDim.x) dc[j] = NAN;
+        for (int i = tid; i < m; i += blockDim.x) db[i] = NAN;
+        if (dA)
+            for (int64_t e = tid; e < (int64_t)m * n; e += blockDim.x) dA[e] = NAN;
+        if (tid == 0) { aa.iters_out[k] = 0; aa.resid_out[k] = NAN; }
+        __syncthreads();
+        return;
+    }
+    // g = dL/dz = (0, w/tau, -w^T x/tau^2, 0, 0, 0)
+    double wx1[1] = {0.0};
+    for (int j = tid; j < n; j += blockDim.x) wx1[0] = fma(win[j], X[j], wx1[0]);
+    block_sum_n<1>(wx1, sh.buf);
+    for (int i = tid; i < Nz; i += blockDim.x) {
+        double g = 0.0;
+        if (i >= m && i < m + n) g = win[i - m] / tau;
+        else if (i == m + n) g = -wx1[0] / (tau * tau);
+        LAM[i] = 0.0; Rv[i] = g; R0[i] = g; Pv[i] = 0.0; V[i] = 0.0;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const double gnorm = sqrt(adj_dot(Rv, Rv, Nz, sh));
+    double rho = 1.0, al = 1.0, om = 1.0, rel = 0.0;
+    int64_t it = 0;
+    if (gnorm > 0.0) {
+        for (it = 1; it <= aa.max_iters; ++it) {
+            const double rho1 = adj_dot(R0, Rv, Nz, sh);
+            const double beta = (rho1 / rho) * (al / om);
+            for (int i = tid; i < Nz; i += blockDim.x) Pv[i] = Rv[i] + beta * (Pv[i] - om * V[i]);
+            __threadfence_block();
+            __syncthreads();
+            adj_op(d, cl, P, sh, Pv, V, WX, Dv, WB, alpha);
+            al = rho1 / adj_dot(R0, V, Nz, sh);
+            for (int i = tid; i < Nz; i += blockDim.x) Sv[i] = Rv[i] - al * V[i];
+            __threadfence_block();
+            __syncthreads();
+            const double sn = sqrt(adj_dot(Sv, Sv, Nz, sh));
+            if (sn <= aa.tol * gnorm) {
+                for (int i = tid; i < Nz; i += blockDim.x) LAM[i] += al * Pv[i];
+                rel = sn / gnorm;
+                break;
+            }
+            adj_op(d, cl, P, sh, Sv, Tv, WX, Dv, WB, alpha);
+            const double tt = adj_dot(Tv, Tv, Nz, sh);
+            const double ts = adj_dot(Tv, Sv, Nz, sh);
+            om = (tt > 0.0) ? ts / tt : 0.0;
+            for (int i = tid; i < Nz; i += blockDim.x) {
+                LAM[i] += al * Pv[i] + om * Sv[i];
+                Rv[i] = Sv[i] - om * Tv[i];
+            }
+            __threadfence_block();
+            __syncthreads();
+            rel = sqrt(adj_dot(Rv, Rv, Nz, sh)) / gnorm;
+            if (rel <= aa.tol || om == 0.0) break;
+            rho = rho1;
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    // zeta = wb(lam): one more application (its "out" is discarded into Tv)
+    adj_op(d, cl, P, sh, LAM, Tv, WX, Dv, WB, alpha);
+    const double zt = WB[m + n], zh = WB[m + n + 1];
+    double* dc = aa.dc[k];
+    double* db = aa.db[k];
+    double* dA = aa.dA[k];
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double xj = X[j];
+        dc[j] = -(WB[m + j] * (tau - theta) + zt * (theta - xj) + zh * (xj - tau));
+    }
+    for (int i = tid; i < m; i += blockDim.x) {
+        const double yi = Y[i];
+        db[i] = -(WB[i] * (theta - tau) + zt * yi - zh * yi);
+    }
+    if (dA) {
+        for (int64_t e = tid; e < (int64_t)m * n; e += blockDim.x) {
+            const int i = (int)(e / n), j = (int)(e % n);
+            const double yi = Y[i];
+            dA[e] = -(WB[i] * (X[j] - theta) - WB[m + j] * yi + zh * yi);
+        }
+    }
+    if (tid == 0) {
+        aa.iters_out[k] = it;
+        aa.resid_out[k] = rel;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void k_adjoint(const LPDesc* __restrict__ desc, const LPCtrl* __restrict__ ctrl,
+                                                 PoolPtrs P, SolveParams prm, AdjArgs aa, const int32_t* order,
+                                                 int32_t B, int32_t* queue, int32_t ldmax) {
+    extern __shared__ double smem[];
+    __shared__ int s_lp;
+    const int W = blockDim.x >> 6;
+    WGShared sh;
+    sh.y = smem;
+    sh.a = sh.y + ldmax;
+    sh.t = sh.a + ldmax;
+    sh.Af = sh.t + ldmax;
+    sh.Ax = sh.Af + ldmax;
+    sh.red = sh.Ax + ldmax;
+    sh.scal = sh.red + 2 * W * ldmax;
+    sh.buf = sh.scal + 8 * W;
+    while (true) {
+        if (threadIdx.x == 0) s_lp = atomicAdd(queue, 1);
+        __syncthreads();
+        const int q = s_lp;
+        __syncthreads();
+        if (q >= B) break;
+        const int k = order[q];
+        const LPDesc d = desc[k];
+        adjoint_one(k, d, ctrl, P, prm, aa, sh);
+    }
+}
+
+hipError_t launch_adjoint(int grid, int threads, hipStream_t st, const LPDesc* desc, const LPCtrl* ctrl,
+                          const PoolPtrs& P, const SolveParams& prm, const AdjArgs& aa, const int32_t* order,
+                          int32_t B, int32_t* queue, int32_t ldmax) {
+    const size_t smem = wg_smem_bytes(ldmax, threads / 64);
+    hipError_t e = hipFuncSetAttribute((const void*)k_adjoint, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adjoint, dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, aa, order, B, queue, ldmax);
+    return hipGetLastError();
 }

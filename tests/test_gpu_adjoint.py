@@ -1,0 +1,78 @@
+"""GPU adjoint (abip_backward) against the dense FP64 KKT adjoint and the
+basis-solution derivative.  All calls go through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import lpgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+abip = pytest.importorskip("paper_1805_12344_amd")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("m,n,seed,t", [(5, 12, 1, 1e-3), (30, 75, 2, 1e-5), (130, 300, 3, 1e-7)])
+def test_backward_equals_kkt_adjoint_at_central_point(m, n, seed, t):
+    print(f"adjoint central m={m} n={n} t={t}", flush=True)
+    lp = lpgen.dense_planted(m, n, seed)
+    A, b, c = lp["A"], lp["b"], lp["c"]
+    cp = oracle.central_point(A, b, c, t=t)
+    w = abip.abip_setup(A, b, c)
+    abip.abip_set_state(w, 0, cp.y, cp.x, cp.s, cp.tau, cp.kappa, cp.theta, t)
+    g = np.random.default_rng(seed).standard_normal(n)
+    dc, db, dA = abip.abip_backward(w, g, want_A=True)
+    it, rr = abip.abip_backward_stats(w)
+    ref = oracle.contract_adjoint(A, b, c, cp, oracle.kkt_adjoint(A, b, c, cp, g), want_A=True)
+    print("bicgstab iters", it, "resid", rr, flush=True)
+    for got, want in [(dc, ref["dc"]), (db, ref["db"]), (dA, ref["dA"])]:
+        err = np.abs(_np(got) - want).max() / (1e-12 + np.abs(want).max())
+        assert err < 1e-7, err
+
+
+def test_backward_after_solve_matches_oracle_and_basis_formula():
+    lp = lpgen.dense_planted(30, 75, 11)
+    A, b, c = lp["A"], lp["b"], lp["c"]
+    g = np.random.default_rng(5).standard_normal(75)
+    w = abip.abip_setup(A, b, c, abip.abip_default_settings(eps=1e-7))
+    x, y, s, info = abip.abip_solve(w)
+    assert info["status"] == abip.ABIP_SOLVED
+    dc, db, dA = abip.abip_backward(w, g, want_A=True)
+    yv, xv, sv, sc = abip.abip_get_state(w, 0)
+    st = oracle.State(_np(yv), _np(xv), sc["tau"], sc["theta"], _np(sv), sc["kappa"], sc["mu"])
+    ref = oracle.contract_adjoint(A, b, c, st, oracle.kkt_adjoint(A, b, c, st, g), want_A=True)
+    for got, want in [(dc, ref["dc"]), (db, ref["db"]), (dA, ref["dA"])]:
+        assert np.abs(_np(got) - want).max() <= 1e-7 * (1 + np.abs(want).max())
+    # the LP derivative at the nondegenerate planted vertex (survey reading c18)
+    bg = oracle.basis_gradients(A, b, lp["basis"], g)
+    assert np.abs(_np(db) - bg["db"]).max() <= 1e-3 * (1 + np.abs(bg["db"]).max())
+    assert np.abs(_np(dc)).max() <= 1e-3 * np.linalg.norm(g)
+
+
+def test_autograd_function_and_batch_backward():
+    lp = lpgen.dense_planted(20, 50, 4)
+    A = torch.tensor(lp["A"], device="cuda", requires_grad=True)
+    b = torch.tensor(lp["b"], device="cuda", requires_grad=True)
+    c = torch.tensor(lp["c"], device="cuda", requires_grad=True)
+    g = torch.randn(50, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+    x = abip.abip_solve_diff(A, b, c)
+    (g * x).sum().backward()
+    bg = oracle.basis_gradients(lp["A"], lp["b"], lp["basis"], _np(g))
+    assert np.abs(_np(b.grad) - bg["db"]).max() <= 1e-3 * (1 + np.abs(bg["db"]).max())
+    assert np.abs(_np(A.grad) - bg["dA"]).max() <= 1e-3 * (1 + np.abs(bg["dA"]).max())
+    # batch: FP32-bulk forward, FP64 adjoint, each LP against its own single backward
+    lps = lpgen.diff_batch(6, 20, 50, 9)
+    wb = abip.abip_setup_batch([l["A"] for l in lps], [l["b"] for l in lps], [l["c"] for l in lps],
+                               abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH))
+    xs, ys, ss, infos = abip.abip_solve_batch(wb)
+    dcs, dbs, _ = abip.abip_backward_batch(wb, [l["w"] for l in lps])
+    for k, l in enumerate(lps):
+        assert infos[k]["status"] == abip.ABIP_SOLVED
+        yv, xv, sv, sc = abip.abip_get_state(wb, k)
+        st = oracle.State(_np(yv), _np(xv), sc["tau"], sc["theta"], _np(sv), sc["kappa"], sc["mu"])
+        ref = oracle.contract_adjoint(l["A"], l["b"], l["c"], st, oracle.kkt_adjoint(l["A"], l["b"], l["c"], st, l["w"]))
+        assert np.abs(_np(dbs[k]) - ref["db"]).max() <= 1e-7 * (1 + np.abs(ref["db"]).max())
+        assert np.abs(_np(dcs[k]) - ref["dc"]).max() <= 1e-7 * (1 + np.abs(ref["dc"]).max())
