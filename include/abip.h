@@ -93,9 +93,10 @@ typedef struct {
                                   starts regardless; default 1e6 */
     double  cg_tol;            /* CG relative tolerance floor; default 1e-10 */
     int32_t cg_max_iters;      /* per linear solve; default 500 */
-    int32_t block_threads;     /* threads per workgroup for ENGINE_WG; 0 = auto */
-    double  adjoint_tol;       /* relative change that stops the adjoint iteration; default 1e-10 */
-    int64_t adjoint_max_iters; /* default 2e5 */
+    int32_t block_threads;     /* threads per workgroup for ENGINE_WG (256 or 512, honoured when
+                                  the largest m <= 256; larger LPs always use 256); 0 = auto */
+    double  adjoint_tol;       /* relative residual that stops the adjoint BiCGSTAB; default 1e-12 */
+    int64_t adjoint_max_iters; /* default 2e5; 0 contracts one transposed step of dL/dz (testing) */
 } abip_settings;
 
 /* Per-LP result summary (host struct). */
@@ -113,6 +114,9 @@ typedef struct {
     int64_t colpass_fp64;      /* passes over A streamed in FP64 */
     double  kernel_ms;         /* duration of the persistent solve launch, HIP events on the
                                   work stream (the same value for every LP of a batch) */
+    int64_t ticks_colpass;     /* device wall-clock ticks (100 MHz) the LP's workgroup spent in */
+    int64_t ticks_ginv;        /* passes over A, in passes over G^{-1}, and in the whole solve */
+    int64_t ticks_total;       /* (one-workgroup engine only; 0 otherwise) */
 } abip_info;
 
 /* A matrix description.  All pointers are device pointers. */
@@ -191,8 +195,9 @@ int abip_backward_stats(abip_work* w, int32_t k, int64_t* iters, double* rel_res
 
 /* (I+Q)^{-1} w for LP k of the handle (eq. Simple-Update:Affine) using the cached
  * factor: w and out are device vectors of length m+n+2 ordered (y, x, tau, theta).
- * FP64 data unless use_fp32 != 0. */
-int abip_apply_iq(abip_work* w, int32_t k, const double* win, double* out, int32_t use_fp32);
+ * flags bit 0: use the FP32 copies of A and G^{-1} (FP64 arithmetic);
+ * flags bit 1: apply (I+Q)^{-T} = (I-Q)^{-1} instead (the adjoint's solve). */
+int abip_apply_iq(abip_work* w, int32_t k, const double* win, double* out, int32_t flags);
 
 /* Load an iterate into LP k: y (m), x (n), s (n) device vectors and host scalars
  * tau, kappa, theta, mu.  Marks the LP as mid-solve at that mu; abip_backward

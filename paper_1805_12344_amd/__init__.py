@@ -50,6 +50,7 @@ class abip_info(ctypes.Structure):
         ("kappa", ctypes.c_double), ("theta", ctypes.c_double), ("mu", ctypes.c_double),
         ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
         ("colpass_fp32", ctypes.c_int64), ("colpass_fp64", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
+        ("ticks_colpass", ctypes.c_int64), ("ticks_ginv", ctypes.c_int64), ("ticks_total", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -263,11 +264,11 @@ def abip_backward_stats(w: Work, k: int = 0):
     return it.value, rr.value
 
 
-def abip_apply_iq(w: Work, k: int, win, use_fp32: bool = False):
+def abip_apply_iq(w: Work, k: int, win, use_fp32: bool = False, transpose: bool = False):
     m, n = w.dims[k]
     win = _dev(win, (m + n + 2,))
     out = torch.empty(m + n + 2, dtype=torch.float64, device="cuda")
-    _check(lib().abip_apply_iq(w.handle, k, _ptr(win), _ptr(out), int(use_fp32)))
+    _check(lib().abip_apply_iq(w.handle, k, _ptr(win), _ptr(out), int(use_fp32) | (2 * int(transpose))))
     return out
 
 

@@ -12,6 +12,7 @@
 
 #include "abip.h"
 #include "abip_internal.h"
+#include "abip_grid.h"
 
 // defined in abip_solve_wg.hip
 hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const LPDesc* desc, LPCtrl* ctrl,
@@ -90,6 +91,7 @@ __global__ void k_init_state(const LPDesc* __restrict__ desc, LPCtrl* __restrict
         c.pres = c.dres = c.gap = c.pobj = c.dobj = NAN;
         c.by = c.cx = 0.0;
         c.iters = 0; c.iters64 = 0; c.ipm = 0; c.cp32 = 0; c.cp64 = 0;
+        c.clk[0] = c.clk[1] = c.clk[2] = 0;
         c.status = 0; c.phase = phase; c.mode = OP_REFRESH; c.flags = 0;
     }
 }
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(256) void k_apply_iq(const LPDesc* __restrict__ des
                                                   int k, const T* __restrict__ Apool, const T* __restrict__ Gpool,
                                                   const double* __restrict__ Mv, const double* __restrict__ Nv,
                                                   int64_t Mtot, int64_t Ntot, const double* __restrict__ w,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, int sgn) {
     extern __shared__ double sm[];
     __shared__ double sbuf[4 * 8];
     const LPDesc d = desc[k];
@@ -156,11 +158,12 @@ __global__ __launch_bounds__(256) void k_apply_iq(const LPDesc* __restrict__ des
     const T* G = Gpool + d.oG;
     double* st = sm;
     double* sa = sm + ld;
+    const double sg = (double)sgn;     // +1: I + Q;  -1: I - Q = (I + Q)^T
     for (int i = tid; i < ld; i += blockDim.x) {
         double s = 0.0;
         if (i < m) {
             for (int j = 0; j < n; ++j) s = fma((double)A[(int64_t)j * ld + i], w[m + j], s);
-            s = w[i] - s;
+            s = w[i] - sg * s;
         }
         st[i] = s;
     }
@@ -177,7 +180,7 @@ __global__ __launch_bounds__(256) void k_apply_iq(const LPDesc* __restrict__ des
         double s = 0.0;
         for (int i = lane; i < m; i += 64) s = fma((double)A[(int64_t)j * ld + i], sa[i], s);
         s = wave_sum(s);
-        if (lane == 0) out[m + j] = w[m + j] + s;
+        if (lane == 0) out[m + j] = w[m + j] + sg * s;
     }
     __threadfence_block();
     __syncthreads();
@@ -196,12 +199,14 @@ __global__ __launch_bounds__(256) void k_apply_iq(const LPDesc* __restrict__ des
         hz[1] = fma(-CBv[j], dj, hz[1]);
     }
     block_sum_n<2>(hz, sbuf);
-    const double q0 = w[m + n] + hz[0], q1 = w[m + n + 1] + hz[1];
-    const double p0 = c.K00 * q0 + c.K01 * q1, p1 = c.K10 * q0 + c.K11 * q1;
-    const double* Zy0 = Mv + MF_ZY0 * Mtot + d.om;
-    const double* Zy1 = Mv + MF_ZY1 * Mtot + d.om;
-    const double* Zx0 = Nv + NF_ZX0 * Ntot + d.on;
-    const double* Zx1 = Nv + NF_ZX1 * Ntot + d.on;
+    const double q0 = w[m + n] + sg * hz[0], q1 = w[m + n + 1] + sg * hz[1];
+    const double k00 = sgn > 0 ? c.K00 : c.KA00, k01 = sgn > 0 ? c.K01 : c.KA01;
+    const double k10 = sgn > 0 ? c.K10 : c.KA10, k11 = sgn > 0 ? c.K11 : c.KA11;
+    const double p0 = k00 * q0 + k01 * q1, p1 = k10 * q0 + k11 * q1;
+    const double* Zy0 = Mv + (sgn > 0 ? MF_ZY0 : MF_ZY0A) * Mtot + d.om;
+    const double* Zy1 = Mv + (sgn > 0 ? MF_ZY1 : MF_ZY1A) * Mtot + d.om;
+    const double* Zx0 = Nv + (sgn > 0 ? NF_ZX0 : NF_ZX0A) * Ntot + d.on;
+    const double* Zx1 = Nv + (sgn > 0 ? NF_ZX1 : NF_ZX1A) * Ntot + d.on;
     for (int i = tid; i < m; i += blockDim.x) out[i] = sa[i] - Zy0[i] * p0 - Zy1[i] * p1;
     for (int j = tid; j < n; j += blockDim.x) out[m + j] = out[m + j] - Zx0[j] * p0 - Zx1[j] * p1;
     if (tid == 0) { out[m + n] = p0; out[m + n + 1] = p1; }
@@ -235,6 +240,12 @@ struct abip_work {
     double** adj_ptrs = nullptr;                 // 4*B device pointers: g, dc, db, dA
     int64_t* adj_iters = nullptr; double* adj_resid = nullptr;
     std::vector<int64_t> h_adj_iters; std::vector<double> h_adj_resid;
+    // grid engine (one LP over the whole GPU)
+    bool grid = false;
+    int grid_nchw = 1;
+    GridArgs ga{};
+    double* gbuf = nullptr;          // Y2, Pf, Px, pcol, prow, pa, t, a
+    GridCtl* gctl = nullptr;         // 2 control blocks
     std::vector<LPCtrl> hctrl;
 };
 
@@ -246,6 +257,7 @@ static void release(abip_work* w) {
     (void)hipFree(w->order); (void)hipFree(w->queue); (void)hipFree(w->errflag); (void)hipFree(w->outp);
     (void)hipFree(w->adj_ws); (void)hipFree(w->adj_ows); (void)hipFree(w->adj_ptrs);
     (void)hipFree(w->adj_iters); (void)hipFree(w->adj_resid);
+    (void)hipFree(w->gbuf); (void)hipFree(w->gctl);
     if (w->ev0) (void)hipEventDestroy(w->ev0);
     if (w->ev1) (void)hipEventDestroy(w->ev1);
 }
@@ -266,7 +278,7 @@ extern "C" int abip_default_settings(abip_settings* s) {
     s->cg_tol = 1e-10;
     s->cg_max_iters = 500;
     s->block_threads = 0;
-    s->adjoint_tol = 1e-10;
+    s->adjoint_tol = 1e-12;
     s->adjoint_max_iters = 200000;
     return ABIP_OK;
 }
@@ -301,6 +313,80 @@ static double now_ms() {
 }
 
 static const int MAX_WG_M = 1024;   // largest m the one-workgroup engine holds per lane
+static const int MAX_GRID_M = 8192; // 4 row chunks of 256 per wave, 8 waves
+static const int64_t GRID_AUTO_MN = 4 * 1024 * 1024;   // one LP this large goes to the grid engine
+
+static int grid_prepare(abip_work* w) {
+    const LPDesc& d = w->hdesc[0];
+    GridArgs& g = w->ga;
+    g.m = d.m; g.n = d.n; g.ld = d.ld;
+    int cw = (d.n + w->cu_count - 1) / w->cu_count;
+    cw = ((cw + 7) / 8) * 8;
+    g.cw = cw;
+    g.NB = (d.n + cw - 1) / cw;
+    g.NR = (d.ld + 255) / 256;
+    int gw = (d.m + w->cu_count - 1) / w->cu_count;
+    gw = ((gw + 7) / 8) * 8;
+    g.gw = gw;
+    g.NG = (d.m + gw - 1) / gw;
+    w->grid_nchw = grid_nchw(d.ld);
+    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * (int64_t)g.NB * d.ld + 8 * (int64_t)g.NB + 8 * (int64_t)g.NR +
+                         4 * (int64_t)g.NG + 2 * (int64_t)d.ld;
+    HIPCHK(hipMalloc((void**)&w->gbuf, sizeof(double) * nbuf));
+    HIPCHK(hipMalloc((void**)&w->gctl, sizeof(GridCtl) * 2));
+    double* p = w->gbuf;
+    g.Y2 = p; p += 2 * d.ld;
+    g.Pf = p; p += (int64_t)g.NB * d.ld;
+    g.Px = p; p += (int64_t)g.NB * d.ld;
+    g.pcol = p; p += 8 * g.NB;
+    g.prow = p; p += 8 * g.NR;
+    g.pa = p; p += 4 * g.NG;
+    g.t = p; p += d.ld;
+    g.a = p; p += d.ld;
+    g.A64 = w->A64 + d.oA; g.A32 = w->A32 + d.oA;
+    g.G64 = w->G64 + d.oG; g.G32 = w->G32 + d.oG;
+    g.b = w->Mv + MF_B * w->Mtot + d.om; g.bbar = w->Mv + MF_BBAR * w->Mtot + d.om;
+    g.Ac = w->Mv + MF_AC * w->Mtot + d.om; g.Acb = w->Mv + MF_ACBAR * w->Mtot + d.om;
+    g.Zy0 = w->Mv + MF_ZY0 * w->Mtot + d.om; g.Zy1 = w->Mv + MF_ZY1 * w->Mtot + d.om;
+    g.C = w->Nv + NF_C * w->Ntot + d.on; g.CB = w->Nv + NF_CBAR * w->Ntot + d.on;
+    g.Zx0 = w->Nv + NF_ZX0 * w->Ntot + d.on; g.Zx1 = w->Nv + NF_ZX1 * w->Ntot + d.on;
+    g.X = w->Nv + NF_X * w->Ntot + d.on; g.S = w->Nv + NF_S * w->Ntot + d.on;
+    g.ctl = w->gctl; g.ctl_next = w->gctl + 1;
+    g.lc = w->dctrl;
+    return ABIP_OK;
+}
+
+// Drive the grid engine: chunks of iterations, then a look at the status.
+static int grid_run(abip_work* w, int64_t fixed, int phase) {
+    hipStream_t st = w->stream;
+    GridArgs g = w->ga;
+    g.prm = make_params(w->set);
+    if (fixed > 0) {
+        const LPDesc& d0 = w->hdesc[0];
+        hipLaunchKernelGGL(k_grid_from_state, dim3(16), dim3(256), 0, st, g, w->Mv + MF_Y * w->Mtot + d0.om,
+                           w->dctrl, phase, fixed);
+    } else {
+        hipLaunchKernelGGL(k_grid_init, dim3(64), dim3(256), 0, st, g, w->set.beta, phase, fixed);
+    }
+    HIPCHK(hipGetLastError());
+    if (!w->ev0) HIPCHK(hipEventCreate(&w->ev0));
+    if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
+    HIPCHK(hipEventRecord(w->ev0, st));
+    GridCtl hc;
+    int chunk = 16;
+    while (true) {
+        for (int i = 0; i < chunk; ++i) HIPCHK(grid_launch_iteration(w->grid_nchw, g, st));
+        HIPCHK(hipMemcpyAsync(&hc, w->gctl, sizeof hc, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hc.status != 0) break;
+        if (chunk < 256) chunk *= 2;
+    }
+    HIPCHK(hipEventRecord(w->ev1, st));
+    const LPDesc& d = w->hdesc[0];
+    hipLaunchKernelGGL(k_grid_finish, dim3(1), dim3(256), 0, st, g, w->Mv + MF_Y * w->Mtot + d.om, w->dctrl);
+    HIPCHK(hipGetLastError());
+    return ABIP_OK;
+}
 
 static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const double* const* b,
                        const double* const* c, const abip_settings* settings, void* stream) {
@@ -323,7 +409,12 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
         const abip_matrix& M = A[k];
         if (M.format != ABIP_DENSE_ROWMAJOR) { delete w; return fail(ABIP_E_INVALID, "LP %d: only dense row-major A is supported by this entry point", k); }
         if (M.m < 1 || M.n < 1) { delete w; return fail(ABIP_E_DIM, "LP %d: bad dimensions m=%d n=%d", k, M.m, M.n); }
-        if (M.m > MAX_WG_M) { delete w; return fail(ABIP_E_DIM, "LP %d: m=%d exceeds the one-workgroup engine limit %d", k, M.m, MAX_WG_M); }
+        const bool want_grid = (B == 1) && (s.engine == ABIP_ENGINE_GRID ||
+                                            (s.engine == ABIP_ENGINE_AUTO &&
+                                             (M.m > MAX_WG_M || (int64_t)M.m * M.n >= GRID_AUTO_MN)));
+        if (want_grid) w->grid = true;
+        if (want_grid && M.m > MAX_GRID_M) { delete w; return fail(ABIP_E_DIM, "m=%d exceeds the grid engine limit %d", M.m, MAX_GRID_M); }
+        if (!want_grid && M.m > MAX_WG_M) { delete w; return fail(ABIP_E_DIM, "LP %d: m=%d exceeds the one-workgroup engine limit %d (use abip_setup for one large LP)", k, M.m, MAX_WG_M); }
         if (!M.val || !b[k] || !c[k]) { delete w; return fail(ABIP_E_INVALID, "LP %d: null data pointer", k); }
         LPDesc& d = w->hdesc[k];
         d.m = M.m; d.n = M.n; d.ld = (M.m + 3) & ~3; d.pad = 0;
@@ -336,7 +427,8 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     }
     w->Atot = oA; w->Gtot = oG; w->Mtot = om; w->Ntot = on;
     w->nch = (w->ldmax + 255) / 256;
-    w->threads = s.block_threads ? s.block_threads : (w->nch >= 3 ? 256 : 512);
+    // the NCH >= 2 kernels are compiled for at most 256 threads
+    w->threads = (w->nch >= 2) ? 256 : (s.block_threads ? s.block_threads : 512);
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&w->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
@@ -413,8 +505,12 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     cleanup_scratch();
     if (hflag & 3) { release(w); delete w; return fail(ABIP_E_NONFINITE, "NaN or Inf in %s", (hflag & 1) ? "A" : "b or c"); }
     if (hflag & 4) { release(w); delete w; return fail(ABIP_E_HIP, "Cholesky of I + A A^T met a non-positive pivot"); }
-    hipError_t e = set_solve_wg_smem_limit(wg_smem_bytes(w->ldmax, w->threads / 64));
+    hipError_t e = w->grid ? grid_set_smem(w->ldmax) : set_solve_wg_smem_limit(wg_smem_bytes(w->ldmax, w->threads / 64));
     if (e != hipSuccess) { release(w); delete w; return fail(ABIP_E_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e)); }
+    if (w->grid) {
+        int rc2 = grid_prepare(w);
+        if (rc2) { release(w); delete w; return rc2; }
+    }
     w->hctrl.resize(B);
     w->setup_ms = now_ms() - t0;
     *out = w;
@@ -458,6 +554,9 @@ static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParam
 }
 
 static void fill_info(abip_info* info, const LPCtrl& c, double setup_ms, double solve_ms, double kernel_ms) {
+    info->ticks_colpass = c.clk[0];
+    info->ticks_ginv = c.clk[1];
+    info->ticks_total = c.clk[2];
     info->colpass_fp32 = c.cp32;
     info->colpass_fp64 = c.cp64;
     info->kernel_ms = kernel_ms;
@@ -481,7 +580,7 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
     hipLaunchKernelGGL(k_init_state, dim3(w->B), dim3(256), 0, st, w->ddesc, w->dctrl, w->Mv, w->Nv, w->Mtot, w->Ntot,
                        w->set.beta, phase);
     HIPCHK(hipGetLastError());
-    int rc = run_wg(w, w->B, 0, prm);
+    int rc = w->grid ? grid_run(w, 0, phase) : run_wg(w, w->B, 0, prm);
     if (rc) return rc;
     std::vector<double*> tab(3 * w->B);
     for (int k = 0; k < w->B; ++k) {
@@ -563,6 +662,7 @@ static int backward_all(abip_work* w, const double* const* g, double* const* dc,
     const SolveParams prm = make_params(w->set);
     const int threads = 512;
     const int grid = std::max(1, std::min<int>(w->B, w->cu_count));
+    if (w->grid) return fail(ABIP_E_STATE, "abip_backward: not available for the grid engine (one large LP)");
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, w->queue);
     HIPCHK(hipGetLastError());
     HIPCHK(launch_adjoint(grid, threads, st, w->ddesc, w->dctrl, pools(w), prm, aa, w->order, w->B, w->queue,
@@ -603,12 +703,13 @@ extern "C" int abip_apply_iq(abip_work* w, int32_t k, const double* win, double*
     if (k < 0 || k >= w->B) return fail(ABIP_E_INVALID, "abip_apply_iq: LP index %d out of range", k);
     if (!win || !out) return fail(ABIP_E_INVALID, "abip_apply_iq: null vector");
     const size_t smem = sizeof(double) * 2 * w->hdesc[k].ld;
-    if (use_fp32)
+    const int sgn = (use_fp32 & 2) ? -1 : 1;
+    if (use_fp32 & 1)
         hipLaunchKernelGGL(k_apply_iq<float>, dim3(1), dim3(256), smem, w->stream, w->ddesc, w->dctrl, k, w->A32,
-                           w->G32, w->Mv, w->Nv, w->Mtot, w->Ntot, win, out);
+                           w->G32, w->Mv, w->Nv, w->Mtot, w->Ntot, win, out, sgn);
     else
         hipLaunchKernelGGL(k_apply_iq<double>, dim3(1), dim3(256), smem, w->stream, w->ddesc, w->dctrl, k, w->A64,
-                           w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, win, out);
+                           w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, win, out, sgn);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(w->stream));
     return ABIP_OK;
@@ -665,6 +766,16 @@ extern "C" int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_
     c.mode = OP_REFRESH;
     c.flags &= 4;
     HIPCHK(hipMemcpyAsync(w->dctrl + k, &c, sizeof c, hipMemcpyHostToDevice, w->stream));
+    if (w->grid) {
+        int rc = grid_run(w, iters, use_fp32 ? 0 : 1);
+        if (rc) return rc;
+        HIPCHK(hipStreamSynchronize(w->stream));
+        LPCtrl c2;
+        HIPCHK(hipMemcpy(&c2, w->dctrl, sizeof c2, hipMemcpyDeviceToHost));
+        c2.flags = c.flags;
+        HIPCHK(hipMemcpy(w->dctrl, &c2, sizeof c2, hipMemcpyHostToDevice));
+        return ABIP_OK;
+    }
     int32_t* ord1 = nullptr;
     HIPCHK(hipMalloc((void**)&ord1, sizeof(int32_t)));
     hipLaunchKernelGGL(k_single_order, dim3(1), dim3(64), 0, w->stream, ord1, k);

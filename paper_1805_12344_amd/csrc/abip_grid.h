@@ -1,0 +1,55 @@
+// Control block and arguments of the grid engine (shared by host and device code).
+#pragma once
+#include "abip_internal.h"
+
+// Host-visible control block of the grid engine (device memory).
+struct GridCtl {
+    // the state the next k_grid_col starts from
+    double tau, kappa, theta, mu;
+    double p0, p1;             // border solution of the pending update (mode OP_PROX)
+    int32_t mode;              // OP_PROX / OP_RESTART / OP_REFRESH for the next column pass
+    int32_t phase;             // 0: FP32-streamed data, 1: FP64
+    int32_t status;            // 0 while running
+    int32_t ybuf;              // which y buffer holds the current y
+    int32_t first;             // 1 until the first decision
+    int32_t pad;
+    int64_t iters, iters64, ipm, cp32, cp64, passes;
+    int64_t fixed_left;        // fixed mode: updates still to run
+    int32_t fixed_mode;        // 1: run exactly fixed_left updates, no tests or restarts
+    int32_t pad2;
+    // last check
+    double pres, dres, gap, pobj, dobj, by, cx;
+    // scalars of the state produced by the last column pass (for the decision)
+    double tau_n, kappa_n, theta_n;
+};
+
+struct GridArgs {
+    int32_t m, n, ld;
+    int32_t NB, NR, NG;        // workgroups of the three kernels
+    int32_t cw, gw;            // columns per workgroup (k_grid_col, k_grid_ginv)
+    const double* A64; const float* A32;
+    const double* G64; const float* G32;
+    const double *b, *bbar, *Ac, *Acb, *Zy0, *Zy1;
+    const double *C, *CB, *Zx0, *Zx1;
+    double *X, *S;
+    double* Y2;                // 2 * ld: current / next y
+    double* Pf;                // NB * ld partial A(x+s)
+    double* Px;                // NB * ld partial A x
+    double* pcol;              // NB * 8 column-side sums
+    double* prow;              // NR * 8 row-side sums
+    double* pa;                // NG * 4 border dots of a
+    double* t;                 // ld
+    double* a;                 // ld
+    GridCtl* ctl;              // read-only inside k_grid_col / k_grid_red / k_grid_ginv
+    GridCtl* ctl_next;         // written by k_grid_ginv (workgroup 0), consumed by k_grid_border
+    const LPCtrl* lc;          // K^{-1}, zbar, norms
+    SolveParams prm;
+};
+
+
+int grid_nchw(int ld);
+hipError_t grid_launch_iteration(int nchw, const GridArgs& g, hipStream_t st);
+hipError_t grid_set_smem(int ld);
+__global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed);
+__global__ void k_grid_finish(GridArgs g, double* Ypool_slice, LPCtrl* lc);
+__global__ void k_grid_from_state(GridArgs g, const double* Yslice, const LPCtrl* lc, int phase, int64_t fixed);

@@ -40,6 +40,7 @@ struct LPCtrl {
     double by, cx;                        // b^T y, c^T x at the last check
     int64_t iters, iters64, ipm;
     int64_t cp32, cp64;                   // column passes per data precision
+    int64_t clk[3];                       // wall-clock ticks: column passes, G^{-1} passes, whole solve
     int32_t status, phase, mode, flags;  // phase 0 = FP32 bulk, 1 = FP64; mode = next op
 };
 
@@ -76,23 +77,56 @@ __device__ __forceinline__ double bcast_lane(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of a wave; every lane receives lane 0's total, so the
-// result is bitwise uniform.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return bcast_first(v);
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+__device__ __forceinline__ int num_waves() { return __builtin_amdgcn_readfirstlane(blockDim.x >> 6); }
+
+// Wave-wide sums with VALU lane exchanges only (no LDS round trips): xor 1 and
+// xor 2 inside quads (DPP quad_perm), lane i <-> 7-i and i <-> 15-i inside rows
+// of 16 (DPP half-mirror / mirror), then rows 0<->1, 2<->3 and halves 0<->1 of
+// the wave (v_permlane16_swap / v_permlane32_swap).  Every step adds two
+// operands that the partner lane adds in the other order; IEEE addition is
+// commutative, so every lane ends with bitwise the same total.
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double swap16_sum(double v) {
+    const auto pl = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
+}
+__device__ __forceinline__ double swap32_sum(double v) {
+    const auto pl = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto ph = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+    v = v + dpp_partner<0xB1>(v);     // quad_perm [1,0,3,2]
+    v = v + dpp_partner<0x4E>(v);     // quad_perm [2,3,0,1]
+    v = v + dpp_partner<0x141>(v);    // row_half_mirror
+    v = v + dpp_partner<0x140>(v);    // row_mirror
+    v = swap16_sum(v);
+    return swap32_sum(v);
+}
+
+// K independent sums at once (the steps are interleaved for ILP).
 template <int K>
 __device__ __forceinline__ void wave_sum_n(double (&v)[K]) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_partner<0xB1>(v[k]);
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], o, 64);
-    }
+    for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_partner<0x4E>(v[k]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = bcast_first(v[k]);
+    for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_partner<0x141>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_partner<0x140>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = swap16_sum(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = swap32_sum(v[k]);
 }
 
 // Load 4 consecutive matrix entries (16-byte aligned) as doubles.
@@ -110,7 +144,7 @@ __device__ __forceinline__ void load4(const double* p, double* o) {
 // (blockDim/64)*K doubles of LDS.  Contains two barriers.
 template <int K>
 __device__ __forceinline__ void block_sum_n(double (&v)[K], double* sbuf) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id(), W = num_waves();
     wave_sum_n<K>(v);
     if (lane == 0) {
 #pragma unroll
@@ -124,46 +158,4 @@ __device__ __forceinline__ void block_sum_n(double (&v)[K], double* sbuf) {
         v[k] = s;
     }
     __syncthreads();
-}
-
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-__device__ __forceinline__ int num_waves() { return __builtin_amdgcn_readfirstlane(blockDim.x >> 6); }
-
-// Reduce K values (K a power of two, 2 <= K <= 16) over the 64 lanes of a wave
-// by recursive halving: at offset o the lanes with bit o set keep the upper
-// half of the still-live values and the others the lower half.  Afterwards
-// the total of value k sits in v[0] of lane lane_of<K>(k) (any lane of a
-// 2^{6-log2 K}-lane block holds the same total); read it with bcast_lane.
-template <int K>
-__device__ __forceinline__ void wave_reduce_scatter(double (&v)[K]) {
-    const int lane = threadIdx.x & 63;
-    constexpr int L = (K >= 16) ? 4 : (K >= 8) ? 3 : (K >= 4) ? 2 : 1;
-#pragma unroll
-    for (int lev = 0; lev < 6; ++lev) {
-        const int o = 32 >> lev;
-        if (lev < L) {
-            const int h = K >> (lev + 1);
-            const bool up = (lane & o) != 0;
-#pragma unroll
-            for (int k = 0; k < h; ++k) {
-                // pin both operands in registers first: otherwise the compiler turns
-                // the per-lane choice into a dynamic index into v[] and lowers it as a
-                // compare/select chain over the whole array
-                double lo = v[k], hi = v[k + h];
-                asm volatile("" : "+v"(lo), "+v"(hi));
-                const double send = up ? lo : hi;
-                const double keep = up ? hi : lo;
-                v[k] = keep + __shfl_xor(send, o, 64);
-            }
-        } else {
-            v[0] += __shfl_xor(v[0], o, 64);
-        }
-    }
-}
-template <int K>
-__device__ __forceinline__ constexpr int lane_of(int k) {
-    int lane = 0;
-    for (int lev = 0; (K >> (lev + 1)) >= 1; ++lev)
-        if (k & (K >> (lev + 1))) lane += 32 >> lev;
-    return lane;
 }

@@ -63,104 +63,124 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     const double sg = sqrt(gamma);
     const bool prox = (op == OP_PROX);
-    for (int cblk = wave; cblk * 64 < n; cblk += W) {
-        const int j0 = cblk * 64;
-        const int cnt = min(64, n - j0);
-        for (int kk = 0; kk < cnt; kk += UNR) {
-            // lane u < UNR owns column j0+kk+u: its scalar data
-            const int jl = j0 + kk + lane;
-            const bool own = (lane < UNR) && (kk + lane < cnt);
-            double x0 = 0, s0 = 0, c0 = 0, cb0 = 0, zz0 = 0, zz1 = 0;
-            if (own) {
-                x0 = X[jl]; s0 = S[jl]; c0 = C[jl]; cb0 = CB[jl];
-                if (prox) { zz0 = ZX0[jl]; zz1 = ZX1[jl]; }
-            }
-            T v[UNR][R];
+    // The wave walks groups of UNR consecutive columns (chunks of 64 columns round
+    // robin over the waves).  Group g+1 is loaded before group g is computed, so
+    // one group of column loads is always in flight behind the arithmetic.
+    constexpr int GPC = 64 / UNR;
+    auto group_col = [&](int g) { return (wave + (g / GPC) * W) * 64 + (g % GPC) * UNR; };
+    struct Grp {
+        T v[UNR][R];
+        double x0, s0, c0, cb0, z0, z1;
+    };
+    // Loads are unconditional (clamped addresses, out-of-range values zeroed by
+    // a select): with no branches around them the compiler can keep the next
+    // group's loads in flight while the current group is computed.
+    const int rl = min(lane * 4, ld - 4);             // valid row start for every lane
+    auto load = [&](int col0, Grp& G) {
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int col = j0 + kk + u;
+        for (int u = 0; u < UNR; ++u) {
+            const int col = min(col0 + u, n - 1);
+            const bool cok = (col0 + u) < n;
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    const int r0 = ch * 256 + lane * 4;
-                    if (kk + u < cnt && r0 < ld) {
-                        if constexpr (sizeof(T) == 4) {
-                            const float4 q4 = *reinterpret_cast<const float4*>(A + (int64_t)col * ld + r0);
-                            v[u][ch * 4 + 0] = q4.x; v[u][ch * 4 + 1] = q4.y;
-                            v[u][ch * 4 + 2] = q4.z; v[u][ch * 4 + 3] = q4.w;
-                        } else {
-                            const double2 q0 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + r0)[0];
-                            const double2 q1 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + r0)[1];
-                            v[u][ch * 4 + 0] = q0.x; v[u][ch * 4 + 1] = q0.y;
-                            v[u][ch * 4 + 2] = q1.x; v[u][ch * 4 + 3] = q1.y;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) v[u][ch * 4 + q] = (T)0;
-                    }
-                }
-            }
-            double dots[K];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                double da = 0.0, dy = 0.0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (prox) da = fma((double)v[u][r], ra[r], da);
-                    dy = fma((double)v[u][r], ry[r], dy);
-                }
-                dots[2 * u] = da;
-                dots[2 * u + 1] = dy;
-            }
-            wave_reduce_scatter<K>(dots);
-            // hand the two column totals of column u to lane u
-            double ata = 0.0, aty = 0.0;
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const double a_u = bcast_lane(dots[0], lane_of<K>(2 * u));
-                const double y_u = bcast_lane(dots[0], lane_of<K>(2 * u + 1));
-                if (lane == u) { ata = a_u; aty = y_u; }
-            }
-            // the column update, one column per owning lane
-            double x1 = x0, s1 = s0;
-            if (own) {
-                if (prox) {
-                    const double dj = (x0 + s0) + ata;                     // M^{-1} block, x part
-                    const double ut = dj - zz0 * p0 - zz1 * p1;           // u~_x
-                    const double uh = alpha * ut + (1.0 - alpha) * x0;    // relaxation
-                    x1 = prox_root(uh - s0, tmu);                         // barrier prox
-                    s1 = s0 - uh + x1;                                    // dual update
-                } else if (op == OP_RESTART) {
-                    if (rule == 0) {
-                        if (x0 >= s0) s1 = gamma * s0;
-                        else x1 = gamma * x0;
-                    } else {
-                        x1 = sg * x0; s1 = sg * s0;
-                    }
-                }
-                if (op != OP_REFRESH) { X[jl] = x1; S[jl] = s1; }
-                const double r1 = aty + s1 - c0 * tau;
-                const double r2 = aty + s1;
-                const double r3 = -aty + c0 * tau - cb0 * theta - s1;
-                acc7[0] = fma(c0, x1, acc7[0]);
-                acc7[1] = fma(cb0, x1, acc7[1]);
-                acc7[2] = fma(c0, s1, acc7[2]);
-                acc7[3] = fma(cb0, s1, acc7[3]);
-                acc7[4] = fma(r1, r1, acc7[4]);
-                acc7[5] = fma(r2, r2, acc7[5]);
-                acc7[6] = fma(r3, r3, acc7[6]);
-            }
-            // A[:, col] (x'+s') and A[:, col] x' for every row this lane holds
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const double xu = bcast_lane(x1, u);
-                const double fu = xu + bcast_lane(s1, u);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    accf[r] = fma((double)v[u][r], fu, accf[r]);
-                    accx[r] = fma((double)v[u][r], xu, accx[r]);
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int r0 = ch * 256 + lane * 4;
+                const bool ok = cok && (r0 < ld);
+                const int rr = (r0 < ld) ? r0 : rl;
+                if constexpr (sizeof(T) == 4) {
+                    const float4 q4 = *reinterpret_cast<const float4*>(A + (int64_t)col * ld + rr);
+                    G.v[u][ch * 4 + 0] = ok ? q4.x : 0.0f; G.v[u][ch * 4 + 1] = ok ? q4.y : 0.0f;
+                    G.v[u][ch * 4 + 2] = ok ? q4.z : 0.0f; G.v[u][ch * 4 + 3] = ok ? q4.w : 0.0f;
+                } else {
+                    const double2 q0 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + rr)[0];
+                    const double2 q1 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + rr)[1];
+                    G.v[u][ch * 4 + 0] = ok ? q0.x : 0.0; G.v[u][ch * 4 + 1] = ok ? q0.y : 0.0;
+                    G.v[u][ch * 4 + 2] = ok ? q1.x : 0.0; G.v[u][ch * 4 + 3] = ok ? q1.y : 0.0;
                 }
             }
         }
+        // lane u < UNR owns column col0+u: its scalar data (other lanes load a
+        // valid neighbour and ignore it)
+        const int jl = min(col0 + (lane < UNR ? lane : 0), n - 1);
+        G.x0 = X[jl]; G.s0 = S[jl]; G.c0 = C[jl]; G.cb0 = CB[jl];
+        G.z0 = ZX0[jl]; G.z1 = ZX1[jl];
+    };
+    auto compute = [&](int col0, const Grp& G) {
+        double dots[K];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            double da = 0.0, dy = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (prox) da = fma((double)G.v[u][r], ra[r], da);
+                dy = fma((double)G.v[u][r], ry[r], dy);
+            }
+            dots[2 * u] = da;
+            dots[2 * u + 1] = dy;
+        }
+        wave_sum_n<K>(dots);
+        // every lane holds every column total; lane u keeps column u's two
+        double ata = 0.0, aty = 0.0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (lane == u) { ata = dots[2 * u]; aty = dots[2 * u + 1]; }
+        // the column update, one column per owning lane
+        const int jl = col0 + lane;
+        const bool own = (lane < UNR) && (jl < n);
+        const double x0 = G.x0, s0 = G.s0, c0 = G.c0, cb0 = G.cb0;
+        double x1 = x0, s1 = s0;
+        if (own) {
+            if (prox) {
+                const double dj = (x0 + s0) + ata;                     // M^{-1} block, x part
+                const double ut = dj - G.z0 * p0 - G.z1 * p1;         // u~_x
+                const double uh = alpha * ut + (1.0 - alpha) * x0;    // relaxation
+                x1 = prox_root(uh - s0, tmu);                         // barrier prox
+                s1 = s0 - uh + x1;                                    // dual update
+            } else if (op == OP_RESTART) {
+                if (rule == 0) {
+                    if (x0 >= s0) s1 = gamma * s0;
+                    else x1 = gamma * x0;
+                } else {
+                    x1 = sg * x0; s1 = sg * s0;
+                }
+            }
+            if (op != OP_REFRESH) { X[jl] = x1; S[jl] = s1; }
+            const double r1 = aty + s1 - c0 * tau;
+            const double r2 = aty + s1;
+            const double r3 = -aty + c0 * tau - cb0 * theta - s1;
+            acc7[0] = fma(c0, x1, acc7[0]);
+            acc7[1] = fma(cb0, x1, acc7[1]);
+            acc7[2] = fma(c0, s1, acc7[2]);
+            acc7[3] = fma(cb0, s1, acc7[3]);
+            acc7[4] = fma(r1, r1, acc7[4]);
+            acc7[5] = fma(r2, r2, acc7[5]);
+            acc7[6] = fma(r3, r3, acc7[6]);
+        }
+        // A[:, col] (x'+s') and A[:, col] x' for every row this lane holds
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const double xu = bcast_lane(x1, u);
+            const double fu = xu + bcast_lane(s1, u);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                accf[r] = fma((double)G.v[u][r], fu, accf[r]);
+                accx[r] = fma((double)G.v[u][r], xu, accx[r]);
+            }
+        }
+    };
+    Grp ga, gb;
+    int g = 0;
+    int c0 = group_col(0);
+    if (c0 < n) load(c0, ga);
+    while (c0 < n) {
+        const int c1 = group_col(g + 1);
+        if (c1 < n) load(c1, gb);
+        compute(c0, ga);
+        if (c1 >= n) break;
+        const int c2 = group_col(g + 2);
+        if (c2 < n) load(c2, ga);
+        compute(c1, gb);
+        c0 = c2;
+        g += 2;
     }
     // column-side sums live in lanes 0..UNR-1: one reduction per pass
     {
@@ -200,12 +220,89 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
     __syncthreads();
 }
 
-// a = G^{-1} t with one thread per row (G^{-1} is symmetric, so column j is
-// contiguous and a warp-wide load of column j is coalesced).  When the block
-// has more threads than rows, P thread groups split the columns and their
-// partial sums are added in a fixed order.
-template <typename T>
+// a = G^{-1} t by column dot products over the symmetric G^{-1} (ld x m): a wave
+// owns chunks of 64 columns, lane l holds rows 4l..4l+3 of every 256-row chunk,
+// and the next group of UNR columns is loaded before the current one is reduced.
+template <int NCH, int UNR, typename T>
 __device__ __forceinline__ void ginv_pass(const T* __restrict__ G, int m, int ld, const WGShared& sh) {
+    const int lane = threadIdx.x & 63, wave = wave_id(), W = num_waves();
+    constexpr int R = NCH * 4;
+    constexpr int GPC = 64 / UNR;
+    double rt[R];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ch * 256 + lane * 4 + q;
+            rt[ch * 4 + q] = (r < ld) ? sh.t[r] : 0.0;
+        }
+    auto group_col = [&](int g) { return (wave + (g / GPC) * W) * 64 + (g % GPC) * UNR; };
+    struct Grp { T v[UNR][R]; };
+    const int rl = min(lane * 4, ld - 4);
+    auto load = [&](int col0, Grp& Gr) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int col = min(col0 + u, m - 1);
+            const bool cok = (col0 + u) < m;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int r0 = ch * 256 + lane * 4;
+                const bool ok = cok && (r0 < ld);
+                const int rr = (r0 < ld) ? r0 : rl;
+                if constexpr (sizeof(T) == 4) {
+                    const float4 q4 = *reinterpret_cast<const float4*>(G + (int64_t)col * ld + rr);
+                    Gr.v[u][ch * 4 + 0] = ok ? q4.x : 0.0f; Gr.v[u][ch * 4 + 1] = ok ? q4.y : 0.0f;
+                    Gr.v[u][ch * 4 + 2] = ok ? q4.z : 0.0f; Gr.v[u][ch * 4 + 3] = ok ? q4.w : 0.0f;
+                } else {
+                    const double2 q0 = reinterpret_cast<const double2*>(G + (int64_t)col * ld + rr)[0];
+                    const double2 q1 = reinterpret_cast<const double2*>(G + (int64_t)col * ld + rr)[1];
+                    Gr.v[u][ch * 4 + 0] = ok ? q0.x : 0.0; Gr.v[u][ch * 4 + 1] = ok ? q0.y : 0.0;
+                    Gr.v[u][ch * 4 + 2] = ok ? q1.x : 0.0; Gr.v[u][ch * 4 + 3] = ok ? q1.y : 0.0;
+                }
+            }
+        }
+    };
+    auto compute = [&](int col0, const Grp& Gr) {
+        double dots[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) s = fma((double)Gr.v[u][r], rt[r], s);
+            dots[u] = s;
+        }
+        wave_sum_n<UNR>(dots);
+        double an = 0.0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (lane == u) an = dots[u];
+        if (lane < UNR && col0 + lane < m) sh.a[col0 + lane] = an;
+    };
+    Grp ga, gb;
+    int g = 0;
+    int c0 = group_col(0);
+    if (c0 < m) load(c0, ga);
+    while (c0 < m) {
+        const int c1 = group_col(g + 1);
+        if (c1 < m) load(c1, gb);
+        compute(c0, ga);
+        if (c1 >= m) break;
+        const int c2 = group_col(g + 2);
+        if (c2 < m) load(c2, ga);
+        compute(c1, gb);
+        c0 = c2;
+        g += 2;
+    }
+    for (int i = m + threadIdx.x; i < ld; i += blockDim.x) sh.a[i] = 0.0;
+    __syncthreads();
+}
+
+// a = G^{-1} t with one thread per row (coalesced: column j of the symmetric
+// G^{-1} is contiguous); when the block has more threads than rows, P thread
+// groups split the columns and their partial sums are added in a fixed order.
+// Used by the adjoint, whose kernel is not specialised on the row count.
+template <typename T>
+__device__ __forceinline__ void ginv_rows(const T* __restrict__ G, int m, int ld, const WGShared& sh) {
     const int nthr = blockDim.x;
     int P = nthr / ld;
     if (P < 1) P = 1;
@@ -285,16 +382,20 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     // without updates are bounded by this cap so the loop always ends
     int64_t passes = 0;
     const int64_t pass_cap = prm.max_iters + 4096;
+    int64_t cyc_col = 0, cyc_ginv = 0, cyc_all = 0;
+    const int64_t t_start = wall_clock64();
     while (true) {
         if (++passes > pass_cap && fixed_iters == 0) { status = 4; break; }
         const double tmu = mu / beta;
         double cs[7];
+        const int64_t t0 = wall_clock64();
         if (phase == 0)
             column_pass<NCH, (NCH <= 2 ? 4 : 2), float>(A32, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind,
                                                         p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, cs);
         else
-            column_pass<NCH, (NCH == 1 ? 4 : 2), double>(A64, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind,
+            column_pass<NCH, 2, double>(A64, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind,
                                                          p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, cs);
+        cyc_col += wall_clock64() - t0;
         if (phase == 0) ++cp32; else ++cp64;
         const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
                                  (pass_kind == OP_REFRESH && !first);
@@ -383,8 +484,10 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         // ---- the inner update: t = y - A f, a = G^{-1} t, border, scalars, y'
         for (int i = tid; i < ld; i += blockDim.x) sh.t[i] = (i < m) ? sh.y[i] - sh.Af[i] : 0.0;
         __syncthreads();
-        if (phase == 0) ginv_pass<float>(G32, m, ld, sh);
-        else ginv_pass<double>(G64, m, ld, sh);
+        const int64_t t1 = wall_clock64();
+        if (phase == 0) ginv_pass<NCH, (NCH == 1 ? 8 : NCH == 2 ? 4 : 2), float>(G32, m, ld, sh);
+        else ginv_pass<NCH, (NCH == 1 ? 4 : 2), double>(G64, m, ld, sh);
+        cyc_ginv += wall_clock64() - t1;
         double bs[4] = {0, 0, 0, 0};
         for (int i = tid; i < m; i += blockDim.x) {
             const double ai = sh.a[i];
@@ -416,9 +519,11 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         pass_kind = OP_PROX;
     }
 
+    cyc_all = wall_clock64() - t_start;
     for (int i = tid; i < m; i += blockDim.x) Yg[i] = sh.y[i];
     if (tid == 0) {
         LPCtrl& o = ctrl[k];
+        o.clk[0] += cyc_col; o.clk[1] += cyc_ginv; o.clk[2] += cyc_all;
         o.tau = tau; o.kappa = kappa; o.theta = theta; o.mu = mu;
         o.pres = pres; o.dres = dres; o.gap = gap; o.pobj = pobj; o.dobj = dobj;
         o.by = by_last; o.cx = cx_last;
@@ -432,7 +537,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
 }
 
 template <int NCH>
-__global__ __launch_bounds__(NCH <= 2 ? 512 : 256) void k_solve_wg(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl,
+__global__ __launch_bounds__(NCH == 1 ? 512 : 256) void k_solve_wg(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl,
                                                   PoolPtrs P, SolveParams prm, const int32_t* __restrict__ order,
                                                   int32_t B, int32_t* __restrict__ queue, int64_t fixed_iters,
                                                   int32_t ldmax) {
@@ -568,7 +673,7 @@ __device__ void adj_op(const LPDesc& d, const LPCtrl& cl, const PoolPtrs& P, con
         }
         __syncthreads();
     }
-    ginv_pass<double>(P.G64 + d.oG, m, ld, sh);          // sh.a = G^{-1} t
+    ginv_rows<double>(P.G64 + d.oG, m, ld, sh);          // sh.a = G^{-1} t
     // d_j = alpha wx_j - (A^T a)_j, four columns per wave step
     double cd = 0.0, cbd = 0.0;
     for (int j0 = wave * 4; j0 < n; j0 += 4 * W) {
@@ -580,10 +685,10 @@ __device__ void adj_op(const LPDesc& d, const LPCtrl& cl, const PoolPtrs& P, con
                 for (int i = lane; i < m; i += 64) s = fma(A[(int64_t)(j0 + u) * ld + i], sh.a[i], s);
             v[u] = s;
         }
-        wave_reduce_scatter<4>(v);
+        wave_sum_n<4>(v);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const double tot = bcast_lane(v[0], lane_of<4>(u));
+            const double tot = v[u];
             if (lane == u && j0 + u < n) {
                 const double dj = alpha * WX[j0 + u] - tot;
                 Dv[j0 + u] = dj;
@@ -674,7 +779,8 @@ __device__ void adjoint_one(int k, const LPDesc& d, const LPCtrl* __restrict__ c
         double g = 0.0;
         if (i >= m && i < m + n) g = win[i - m] / tau;
         else if (i == m + n) g = -wx1[0] / (tau * tau);
-        LAM[i] = 0.0; Rv[i] = g; R0[i] = g; Pv[i] = 0.0; V[i] = 0.0;
+        LAM[i] = (aa.max_iters == 0) ? g : 0.0;   // 0 iterations: contract one step of dL/dz
+        Rv[i] = g; R0[i] = g; Pv[i] = 0.0; V[i] = 0.0;
     }
     __threadfence_block();
     __syncthreads();

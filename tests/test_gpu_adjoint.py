@@ -28,9 +28,15 @@ def test_backward_equals_kkt_adjoint_at_central_point(m, n, seed, t):
     it, rr = abip.abip_backward_stats(w)
     ref = oracle.contract_adjoint(A, b, c, cp, oracle.kkt_adjoint(A, b, c, cp, g), want_A=True)
     print("bicgstab iters", it, "resid", rr, flush=True)
-    for got, want in [(dc, ref["dc"]), (db, ref["db"]), (dA, ref["dA"])]:
+    # dL/db and dL/dA are O(1); dL/dc tends to 0 at the optimum (a nondegenerate
+    # vertex is locally constant in c), so it is compared on the scale of the
+    # terms it is made of (|zeta| x |u|, zeta the adjoint), not relative to itself
+    for got, want in [(db, ref["db"]), (dA, ref["dA"])]:
         err = np.abs(_np(got) - want).max() / (1e-12 + np.abs(want).max())
         assert err < 1e-7, err
+    lam = oracle.kkt_adjoint(A, b, c, cp, g)
+    scale = np.abs(lam).max() * (1.0 + np.abs(cp.u()).max())
+    assert np.abs(_np(dc) - ref["dc"]).max() <= 1e-9 * scale
 
 
 def test_backward_after_solve_matches_oracle_and_basis_formula():
@@ -44,8 +50,10 @@ def test_backward_after_solve_matches_oracle_and_basis_formula():
     yv, xv, sv, sc = abip.abip_get_state(w, 0)
     st = oracle.State(_np(yv), _np(xv), sc["tau"], sc["theta"], _np(sv), sc["kappa"], sc["mu"])
     ref = oracle.contract_adjoint(A, b, c, st, oracle.kkt_adjoint(A, b, c, st, g), want_A=True)
-    for got, want in [(dc, ref["dc"]), (db, ref["db"]), (dA, ref["dA"])]:
+    for got, want in [(db, ref["db"]), (dA, ref["dA"])]:
         assert np.abs(_np(got) - want).max() <= 1e-7 * (1 + np.abs(want).max())
+    lam = oracle.kkt_adjoint(A, b, c, st, g)
+    assert np.abs(_np(dc) - ref["dc"]).max() <= 1e-9 * np.abs(lam).max() * (1.0 + np.abs(st.u()).max())
     # the LP derivative at the nondegenerate planted vertex (survey reading c18)
     bg = oracle.basis_gradients(A, b, lp["basis"], g)
     assert np.abs(_np(db) - bg["db"]).max() <= 1e-3 * (1 + np.abs(bg["db"]).max())
@@ -75,4 +83,5 @@ def test_autograd_function_and_batch_backward():
         st = oracle.State(_np(yv), _np(xv), sc["tau"], sc["theta"], _np(sv), sc["kappa"], sc["mu"])
         ref = oracle.contract_adjoint(l["A"], l["b"], l["c"], st, oracle.kkt_adjoint(l["A"], l["b"], l["c"], st, l["w"]))
         assert np.abs(_np(dbs[k]) - ref["db"]).max() <= 1e-7 * (1 + np.abs(ref["db"]).max())
-        assert np.abs(_np(dcs[k]) - ref["dc"]).max() <= 1e-7 * (1 + np.abs(ref["dc"]).max())
+        lam = oracle.kkt_adjoint(l["A"], l["b"], l["c"], st, l["w"])
+        assert np.abs(_np(dcs[k]) - ref["dc"]).max() <= 1e-9 * np.abs(lam).max() * (1.0 + np.abs(st.u()).max())

@@ -40,6 +40,12 @@ def test_apply_iq_matches_oracle(m, n, seed):
     got32 = _np(abip.abip_apply_iq(w, 0, win, use_fp32=True))
     err32 = np.abs(got32 - ref).max() / np.abs(ref).max()
     assert err32 < 1e-4, err32
+    # the adjoint's solve: (I+Q)^{-T} = (I-Q)^{-1}, against a dense solve
+    Q = oracle.assemble_Q(Problem(lp["A"], lp["b"], lp["c"]))
+    reft = np.linalg.solve(np.eye(m + n + 2) - Q, win)
+    gott = _np(abip.abip_apply_iq(w, 0, win, transpose=True))
+    errt = np.abs(gott - reft).max() / np.abs(reft).max()
+    assert errt < 1e-10, errt
 
 
 @pytest.mark.parametrize("m,n,seed", SHAPES)
@@ -82,7 +88,9 @@ def test_solve_config0_matches_oracle(seed):
     x, y, s = _np(x), _np(y), _np(s)
     kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], x, y, s)
     assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
-    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-6 * (1 + abs(lp["pstar"]))
+    # 1e-6 relative KKT bounds the objective error only through ||y*|| ||Ax - b|| etc.
+    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
+    assert abs(kk["pobj"] - ref["info"]["pobj"]) <= 1e-7 * (1 + abs(lp["pstar"]))
     # 1e-6 relative KKT bounds the distance to the planted vertex only up to conditioning
     assert np.linalg.norm(x - lp["x0"]) / (1 + np.linalg.norm(lp["x0"])) <= 1e-4
     # same algorithm in FP64: the trajectories agree and stop together
@@ -142,7 +150,7 @@ def test_fp32_bulk_with_fp64_polish(seed):
     assert info["status"] == abip.ABIP_SOLVED
     kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s))
     assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
-    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-6 * (1 + abs(lp["pstar"]))
+    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
 
 
 def test_boundary_errors():
