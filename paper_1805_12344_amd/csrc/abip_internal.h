@@ -88,8 +88,9 @@ __device__ __forceinline__ int num_waves() { return __builtin_amdgcn_readfirstla
 // commutative, so every lane ends with bitwise the same total.
 template <int CTRL>
 __device__ __forceinline__ double dpp_partner(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    // every lane reads a valid lane for the patterns used here, so no old value
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double swap16_sum(double v) {
@@ -127,6 +128,69 @@ __device__ __forceinline__ void wave_sum_n(double (&v)[K]) {
     for (int k = 0; k < K; ++k) v[k] = swap16_sum(v[k]);
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = swap32_sum(v[k]);
+}
+
+// Pairwise exchange-and-add across the wave halves: lanes 0..31 end with
+// a(own) + a(partner), lanes 32..63 with b(partner) + b(own), where the partner
+// is lane ^ 32.  v_permlane32_swap exchanges the upper 32 lanes of its first
+// operand with the lower 32 lanes of its second.
+__device__ __forceinline__ double rs_pair32(double a, double b) {
+    const auto pl = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto ph = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
+}
+// The same across rows of 16 (partner lane ^ 16): even rows keep a, odd rows
+// keep b (v_permlane16_swap exchanges the odd rows of its first operand with
+// the even rows of its second).
+__device__ __forceinline__ double rs_pair16(double a, double b) {
+    const auto pl = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
+}
+
+// Reduce-scatter of K per-lane values to V wave totals per lane.  The K values
+// are split S = K/V ways across lane groups of 64/S consecutive lanes: lane L
+// ends with the totals of values V*(L/(64/S)) .. V*(L/(64/S)) + V - 1 in
+// v[0..V-1], bitwise the same in every lane of its group.  Halving steps over
+// lane bits 5, 4 and 3 (each value is added once per step, not once per
+// lane), then an all-reduce over the lane bits left.  Far fewer lane
+// exchanges than K separate all-reduces: about K + 2V log2(64/S) instead of
+// 6K.
+template <int K, int V>
+__device__ __forceinline__ void wave_rs(double (&v)[K]) {
+    constexpr int S = K / V;
+    static_assert(S * V == K && (S == 2 || S == 4 || S == 8), "wave_rs: 2, 4 or 8 lane groups");
+#pragma unroll
+    for (int k = 0; k < K / 2; ++k) v[k] = rs_pair32(v[k], v[k + K / 2]);
+    if constexpr (S >= 4) {
+#pragma unroll
+        for (int k = 0; k < K / 4; ++k) v[k] = rs_pair16(v[k], v[k + K / 4]);
+    }
+    if constexpr (S >= 8) {
+        // lane ^ 8 inside a row: DPP row rotate by 8 (no swap form exists)
+        const bool up = ((threadIdx.x >> 3) & 1) != 0;
+#pragma unroll
+        for (int k = 0; k < K / 8; ++k) {
+            const double lo = v[k], hi = v[k + K / 8];
+            const double send = up ? lo : hi;
+            const double keep = up ? hi : lo;
+            v[k] = keep + dpp_partner<0x128>(send);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = v[k] + dpp_partner<0xB1>(v[k]);
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = v[k] + dpp_partner<0x4E>(v[k]);
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = v[k] + dpp_partner<0x141>(v[k]);
+    if constexpr (S <= 4) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) v[k] = v[k] + dpp_partner<0x140>(v[k]);
+    }
+    if constexpr (S <= 2) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) v[k] = swap16_sum(v[k]);
+    }
 }
 
 // Load 4 consecutive matrix entries (16-byte aligned) as doubles.

@@ -83,27 +83,26 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
     const int j_end = min(n, j_begin + g.cw);
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     T va[U][R], vb[U][R];
+    // unmasked loads from clamped addresses: rows past ld have zero weights,
+    // columns past j_end are skipped with a uniform test in step()
+    const int rl = min(lane * 4, ld - 4);
     auto load = [&](int col0, T (&v)[U][R]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int col = col0 + u;
+            const int col = min(col0 + u, j_end - 1);
 #pragma unroll
             for (int ch = 0; ch < NCHW; ++ch) {
                 const int r0 = (ch * GRID_W + wave) * 256 + lane * 4;
-                if (col < j_end && r0 < ld) {
-                    if constexpr (sizeof(T) == 4) {
-                        const float4 q4 = *reinterpret_cast<const float4*>(A + (int64_t)col * ld + r0);
-                        v[u][ch * 4 + 0] = q4.x; v[u][ch * 4 + 1] = q4.y;
-                        v[u][ch * 4 + 2] = q4.z; v[u][ch * 4 + 3] = q4.w;
-                    } else {
-                        const double2 q0 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + r0)[0];
-                        const double2 q1 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + r0)[1];
-                        v[u][ch * 4 + 0] = q0.x; v[u][ch * 4 + 1] = q0.y;
-                        v[u][ch * 4 + 2] = q1.x; v[u][ch * 4 + 3] = q1.y;
-                    }
+                const int rr = (r0 < ld) ? r0 : rl;
+                if constexpr (sizeof(T) == 4) {
+                    const float4 q4 = *reinterpret_cast<const float4*>(A + (int64_t)col * ld + rr);
+                    v[u][ch * 4 + 0] = q4.x; v[u][ch * 4 + 1] = q4.y;
+                    v[u][ch * 4 + 2] = q4.z; v[u][ch * 4 + 3] = q4.w;
                 } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) v[u][ch * 4 + q] = (T)0;
+                    const double2 q0 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + rr)[0];
+                    const double2 q1 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + rr)[1];
+                    v[u][ch * 4 + 0] = q0.x; v[u][ch * 4 + 1] = q0.y;
+                    v[u][ch * 4 + 2] = q1.x; v[u][ch * 4 + 3] = q1.y;
                 }
             }
         }
@@ -116,7 +115,7 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
             double da = 0.0, dy = 0.0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (prox) da = fma((double)v[u][r], ra[r], da);
+                da = fma((double)v[u][r], ra[r], da);
                 dy = fma((double)v[u][r], ry[r], dy);
             }
             dots[2 * u] = da;
@@ -168,7 +167,8 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const double xu = sx[2 * u], fu = sx[2 * u + 1];
+            const bool cv = (col0 + u) < j_end;           // uniform
+            const double xu = cv ? sx[2 * u] : 0.0, fu = cv ? sx[2 * u + 1] : 0.0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 accf[r] = fma((double)v[u][r], fu, accf[r]);
@@ -310,12 +310,11 @@ __device__ void grid_ginv_body(const GridArgs& g, const T* __restrict__ G, doubl
 #pragma unroll
             for (int ch = 0; ch < NCHW; ++ch) {
                 const int r0 = (ch * GRID_W + wave) * 256 + lane * 4;
-                if (col < j_end && r0 < ld) {
-                    double v4[4];
-                    load4(G + (int64_t)col * ld + r0, v4);
+                const int rr = (r0 < ld) ? r0 : min(lane * 4, ld - 4);
+                double v4[4];
+                load4(G + (int64_t)min(col, j_end - 1) * ld + rr, v4);     // weights are 0 past ld
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) s = fma(v4[q], rt[ch * 4 + q], s);
-                }
+                for (int q = 0; q < 4; ++q) s = fma(v4[q], rt[ch * 4 + q], s);
             }
             dots[u] = s;
         }

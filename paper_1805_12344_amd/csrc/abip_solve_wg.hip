@@ -63,44 +63,48 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     const double sg = sqrt(gamma);
     const bool prox = (op == OP_PROX);
-    // The wave walks groups of UNR consecutive columns (chunks of 64 columns round
-    // robin over the waves).  Group g+1 is loaded before group g is computed, so
-    // one group of column loads is always in flight behind the arithmetic.
-    constexpr int GPC = 64 / UNR;
-    auto group_col = [&](int g) { return (wave + (g / GPC) * W) * 64 + (g % GPC) * UNR; };
+    // Groups of UNR consecutive columns go round robin over the waves, so every
+    // wave has work even when n is small.  Group g+1 is loaded before group g
+    // is computed: one group of column loads is always in flight behind the
+    // arithmetic.  After the reduce-scatter of the column dots, the LPC lanes
+    // myu*LPC .. myu*LPC+LPC-1 hold column myu of the group; the first of
+    // them writes it back.
+    constexpr int LPC = 64 / UNR;
+    const int myu = lane / LPC;
+    const bool lead = (lane % LPC) == 0;
+    auto group_col = [&](int g) { return (wave + g * W) * UNR; };
     struct Grp {
         T v[UNR][R];
         double x0, s0, c0, cb0, z0, z1;
     };
-    // Loads are unconditional (clamped addresses, out-of-range values zeroed by
-    // a select): with no branches around them the compiler can keep the next
-    // group's loads in flight while the current group is computed.
+    // Loads are unconditional and unmasked (addresses clamped into the LP's
+    // own data): with nothing consuming them at load time the compiler keeps
+    // the next group's loads in flight while the current group is computed.
+    // Rows past ld carry zero weights (ra, ry) and are never written back;
+    // columns past n are skipped with a wave-uniform test in compute().
     const int rl = min(lane * 4, ld - 4);             // valid row start for every lane
     auto load = [&](int col0, Grp& G) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const int col = min(col0 + u, n - 1);
-            const bool cok = (col0 + u) < n;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int r0 = ch * 256 + lane * 4;
-                const bool ok = cok && (r0 < ld);
                 const int rr = (r0 < ld) ? r0 : rl;
                 if constexpr (sizeof(T) == 4) {
                     const float4 q4 = *reinterpret_cast<const float4*>(A + (int64_t)col * ld + rr);
-                    G.v[u][ch * 4 + 0] = ok ? q4.x : 0.0f; G.v[u][ch * 4 + 1] = ok ? q4.y : 0.0f;
-                    G.v[u][ch * 4 + 2] = ok ? q4.z : 0.0f; G.v[u][ch * 4 + 3] = ok ? q4.w : 0.0f;
+                    G.v[u][ch * 4 + 0] = q4.x; G.v[u][ch * 4 + 1] = q4.y;
+                    G.v[u][ch * 4 + 2] = q4.z; G.v[u][ch * 4 + 3] = q4.w;
                 } else {
                     const double2 q0 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + rr)[0];
                     const double2 q1 = reinterpret_cast<const double2*>(A + (int64_t)col * ld + rr)[1];
-                    G.v[u][ch * 4 + 0] = ok ? q0.x : 0.0; G.v[u][ch * 4 + 1] = ok ? q0.y : 0.0;
-                    G.v[u][ch * 4 + 2] = ok ? q1.x : 0.0; G.v[u][ch * 4 + 3] = ok ? q1.y : 0.0;
+                    G.v[u][ch * 4 + 0] = q0.x; G.v[u][ch * 4 + 1] = q0.y;
+                    G.v[u][ch * 4 + 2] = q1.x; G.v[u][ch * 4 + 3] = q1.y;
                 }
             }
         }
-        // lane u < UNR owns column col0+u: its scalar data (other lanes load a
-        // valid neighbour and ignore it)
-        const int jl = min(col0 + (lane < UNR ? lane : 0), n - 1);
+        // the column this lane updates (clamped: lanes past n compute and drop)
+        const int jl = min(col0 + myu, n - 1);
         G.x0 = X[jl]; G.s0 = S[jl]; G.c0 = C[jl]; G.cb0 = CB[jl];
         G.z0 = ZX0[jl]; G.z1 = ZX1[jl];
     };
@@ -110,39 +114,34 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
         for (int u = 0; u < UNR; ++u) {
             double da = 0.0, dy = 0.0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (prox) da = fma((double)G.v[u][r], ra[r], da);
+            for (int r = 0; r < R; ++r) {        // (A^T a)_j is only used by updates
+                da = fma((double)G.v[u][r], ra[r], da);
                 dy = fma((double)G.v[u][r], ry[r], dy);
             }
             dots[2 * u] = da;
             dots[2 * u + 1] = dy;
         }
-        wave_sum_n<K>(dots);
-        // every lane holds every column total; lane u keeps column u's two
-        double ata = 0.0, aty = 0.0;
-#pragma unroll
-        for (int u = 0; u < UNR; ++u)
-            if (lane == u) { ata = dots[2 * u]; aty = dots[2 * u + 1]; }
-        // the column update, one column per owning lane
-        const int jl = col0 + lane;
-        const bool own = (lane < UNR) && (jl < n);
+        wave_rs<K, 2>(dots);
+        const double ata = dots[0], aty = dots[1];        // column col0 + myu
+        // the column update, computed by all LPC lanes of the column
+        const int jl = col0 + myu;
         const double x0 = G.x0, s0 = G.s0, c0 = G.c0, cb0 = G.cb0;
         double x1 = x0, s1 = s0;
-        if (own) {
-            if (prox) {
-                const double dj = (x0 + s0) + ata;                     // M^{-1} block, x part
-                const double ut = dj - G.z0 * p0 - G.z1 * p1;         // u~_x
-                const double uh = alpha * ut + (1.0 - alpha) * x0;    // relaxation
-                x1 = prox_root(uh - s0, tmu);                         // barrier prox
-                s1 = s0 - uh + x1;                                    // dual update
-            } else if (op == OP_RESTART) {
-                if (rule == 0) {
-                    if (x0 >= s0) s1 = gamma * s0;
-                    else x1 = gamma * x0;
-                } else {
-                    x1 = sg * x0; s1 = sg * s0;
-                }
+        if (prox) {
+            const double dj = (x0 + s0) + ata;                     // M^{-1} block, x part
+            const double ut = dj - G.z0 * p0 - G.z1 * p1;         // u~_x
+            const double uh = alpha * ut + (1.0 - alpha) * x0;    // relaxation
+            x1 = prox_root(uh - s0, tmu);                         // barrier prox
+            s1 = s0 - uh + x1;                                    // dual update
+        } else if (op == OP_RESTART) {
+            if (rule == 0) {
+                if (x0 >= s0) s1 = gamma * s0;
+                else x1 = gamma * x0;
+            } else {
+                x1 = sg * x0; s1 = sg * s0;
             }
+        }
+        if (lead && jl < n) {
             if (op != OP_REFRESH) { X[jl] = x1; S[jl] = s1; }
             const double r1 = aty + s1 - c0 * tau;
             const double r2 = aty + s1;
@@ -158,8 +157,9 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
         // A[:, col] (x'+s') and A[:, col] x' for every row this lane holds
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const double xu = bcast_lane(x1, u);
-            const double fu = xu + bcast_lane(s1, u);
+            const bool cv = (col0 + u) < n;                   // wave-uniform
+            const double xu = cv ? bcast_lane(x1, u * LPC) : 0.0;
+            const double fu = cv ? xu + bcast_lane(s1, u * LPC) : 0.0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 accf[r] = fma((double)G.v[u][r], fu, accf[r]);
@@ -182,7 +182,7 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
         c0 = c2;
         g += 2;
     }
-    // column-side sums live in lanes 0..UNR-1: one reduction per pass
+    // column-side sums live in the lead lanes: one reduction per pass
     {
         double t8[8] = {acc7[0], acc7[1], acc7[2], acc7[3], acc7[4], acc7[5], acc7[6], 0.0};
         wave_sum_n<8>(t8);
@@ -220,14 +220,15 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
     __syncthreads();
 }
 
-// a = G^{-1} t by column dot products over the symmetric G^{-1} (ld x m): a wave
-// owns chunks of 64 columns, lane l holds rows 4l..4l+3 of every 256-row chunk,
-// and the next group of UNR columns is loaded before the current one is reduced.
+// a = G^{-1} t by column dot products over the symmetric G^{-1} (ld x m): groups
+// of UNR columns go round robin over the waves, lane l holds rows 4l..4l+3 of
+// every 256-row chunk, and the next group is loaded before the current one is
+// reduced.
 template <int NCH, int UNR, typename T>
 __device__ __forceinline__ void ginv_pass(const T* __restrict__ G, int m, int ld, const WGShared& sh) {
     const int lane = threadIdx.x & 63, wave = wave_id(), W = num_waves();
     constexpr int R = NCH * 4;
-    constexpr int GPC = 64 / UNR;
+    constexpr int LPC = 64 / UNR;
     double rt[R];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
@@ -236,28 +237,28 @@ __device__ __forceinline__ void ginv_pass(const T* __restrict__ G, int m, int ld
             const int r = ch * 256 + lane * 4 + q;
             rt[ch * 4 + q] = (r < ld) ? sh.t[r] : 0.0;
         }
-    auto group_col = [&](int g) { return (wave + (g / GPC) * W) * 64 + (g % GPC) * UNR; };
+    auto group_col = [&](int g) { return (wave + g * W) * UNR; };
     struct Grp { T v[UNR][R]; };
     const int rl = min(lane * 4, ld - 4);
+    // unmasked loads from clamped addresses (rows past ld have zero weight rt,
+    // columns past m are not written)
     auto load = [&](int col0, Grp& Gr) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const int col = min(col0 + u, m - 1);
-            const bool cok = (col0 + u) < m;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int r0 = ch * 256 + lane * 4;
-                const bool ok = cok && (r0 < ld);
                 const int rr = (r0 < ld) ? r0 : rl;
                 if constexpr (sizeof(T) == 4) {
                     const float4 q4 = *reinterpret_cast<const float4*>(G + (int64_t)col * ld + rr);
-                    Gr.v[u][ch * 4 + 0] = ok ? q4.x : 0.0f; Gr.v[u][ch * 4 + 1] = ok ? q4.y : 0.0f;
-                    Gr.v[u][ch * 4 + 2] = ok ? q4.z : 0.0f; Gr.v[u][ch * 4 + 3] = ok ? q4.w : 0.0f;
+                    Gr.v[u][ch * 4 + 0] = q4.x; Gr.v[u][ch * 4 + 1] = q4.y;
+                    Gr.v[u][ch * 4 + 2] = q4.z; Gr.v[u][ch * 4 + 3] = q4.w;
                 } else {
                     const double2 q0 = reinterpret_cast<const double2*>(G + (int64_t)col * ld + rr)[0];
                     const double2 q1 = reinterpret_cast<const double2*>(G + (int64_t)col * ld + rr)[1];
-                    Gr.v[u][ch * 4 + 0] = ok ? q0.x : 0.0; Gr.v[u][ch * 4 + 1] = ok ? q0.y : 0.0;
-                    Gr.v[u][ch * 4 + 2] = ok ? q1.x : 0.0; Gr.v[u][ch * 4 + 3] = ok ? q1.y : 0.0;
+                    Gr.v[u][ch * 4 + 0] = q0.x; Gr.v[u][ch * 4 + 1] = q0.y;
+                    Gr.v[u][ch * 4 + 2] = q1.x; Gr.v[u][ch * 4 + 3] = q1.y;
                 }
             }
         }
@@ -271,12 +272,9 @@ __device__ __forceinline__ void ginv_pass(const T* __restrict__ G, int m, int ld
             for (int r = 0; r < R; ++r) s = fma((double)Gr.v[u][r], rt[r], s);
             dots[u] = s;
         }
-        wave_sum_n<UNR>(dots);
-        double an = 0.0;
-#pragma unroll
-        for (int u = 0; u < UNR; ++u)
-            if (lane == u) an = dots[u];
-        if (lane < UNR && col0 + lane < m) sh.a[col0 + lane] = an;
+        wave_rs<UNR, 1>(dots);               // lanes u*LPC.. hold column col0 + u
+        const int j = col0 + lane / LPC;
+        if ((lane % LPC) == 0 && j < m) sh.a[j] = dots[0];
     };
     Grp ga, gb;
     int g = 0;
