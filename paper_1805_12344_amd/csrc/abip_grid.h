@@ -21,6 +21,7 @@ struct GridCtl {
     double pres, dres, gap, pobj, dobj, by, cx;
     // scalars of the state produced by the last column pass (for the decision)
     double tau_n, kappa_n, theta_n;
+    StallTrack stall;          // FP32 precision-floor test of the current inner loop
 };
 
 struct GridArgs {

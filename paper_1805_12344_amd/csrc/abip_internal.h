@@ -193,6 +193,31 @@ __device__ __forceinline__ void wave_rs(double (&v)[K]) {
     }
 }
 
+// Precision floor of the FP32 phase.  In exact arithmetic the inner updates
+// for a fixed mu drive ||Qu - v||^2 to zero (the barrier subproblem's fixed
+// point has Qu = v).  With FP32-rounded A and G^{-1} the updates instead settle
+// on a fixed point of the rounded operator whose residual stays at a level set
+// by the rounding; once mu is below that level the inner loop cannot end.  The
+// residual is sampled after 256, 512, 1024, ... updates of the current inner
+// loop: three samples in a row that agree to 1% while still above mu mean the
+// loop has settled above mu (a converging or oscillating loop changes by far
+// more between samples that are a doubling apart), and the FP32 phase hands
+// over to FP64.
+struct StallTrack {
+    int64_t i;          // updates in the current inner loop
+    double r1, r2;      // the last two samples (0: none yet)
+};
+__device__ __forceinline__ void stall_reset(StallTrack& t) { t.i = 0; t.r1 = 0.0; t.r2 = 0.0; }
+// Called after each update with the new residual; true once settled above mu.
+__device__ __forceinline__ bool stall_sample(StallTrack& t, double inner, double mu) {
+    ++t.i;
+    if (t.i < 256 || (t.i & (t.i - 1)) != 0) return false;
+    const bool flat = t.r2 > 0.0 && fabs(inner - t.r1) <= 0.01 * inner && fabs(t.r1 - t.r2) <= 0.01 * t.r1;
+    t.r2 = t.r1;
+    t.r1 = inner;
+    return flat && inner > mu;
+}
+
 // Load 4 consecutive matrix entries (16-byte aligned) as doubles.
 __device__ __forceinline__ void load4(const float* p, double* o) {
     float4 v = *reinterpret_cast<const float4*>(p);

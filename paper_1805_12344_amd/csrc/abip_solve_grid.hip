@@ -420,7 +420,12 @@ __global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
                 if (prm.restart_rule == 0) { if (tau >= kappa) kn *= gamma; else tn *= gamma; }
                 else { const double sg = sqrt(gamma); tn *= sg; kn *= sg; hn *= sg; }
                 c.tau_n = tn; c.kappa_n = kn; c.theta_n = hn;
+                stall_reset(c.stall);
                 next = OP_RESTART;
+                decided = true;
+            } else if (c.phase == 0 && pass == OP_PROX && stall_sample(c.stall, inner, c.mu)) {
+                c.phase = 1;                   // FP32 precision floor reached
+                next = OP_REFRESH;
                 decided = true;
             } else if (c.iters >= prm.max_iters || c.passes > prm.max_iters + 4096) {
                 c.status = 4;
@@ -475,6 +480,7 @@ __global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed) {
         c.p0 = c.p1 = 0.0;
         c.mode = OP_REFRESH; c.phase = phase; c.status = 0; c.ybuf = 0; c.first = 1; c.pad = 0;
         c.iters = c.iters64 = c.ipm = c.cp32 = c.cp64 = c.passes = 0;
+        stall_reset(c.stall);
         c.fixed_left = fixed;
         c.fixed_mode = fixed > 0 ? 1 : 0;
         c.pad2 = 0;
@@ -502,6 +508,7 @@ __global__ void k_grid_from_state(GridArgs g, const double* Yslice, const LPCtrl
         c.p0 = c.p1 = 0.0;
         c.mode = OP_REFRESH; c.phase = phase; c.status = 0; c.ybuf = 0; c.first = 1; c.pad = 0;
         c.iters = c.iters64 = c.ipm = c.cp32 = c.cp64 = c.passes = 0;
+        stall_reset(c.stall);
         c.fixed_left = fixed;
         c.fixed_mode = fixed > 0 ? 1 : 0;
         c.pad2 = 0;

@@ -376,6 +376,8 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     int pass_kind = op;          // what the column pass does
     bool first = true;
     int64_t done_fixed = 0;
+    StallTrack stall;
+    stall_reset(stall);
     // every pass is an update, a restart or a refresh; restarts and refreshes
     // without updates are bounded by this cap so the loop always ends
     int64_t passes = 0;
@@ -397,6 +399,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         if (phase == 0) ++cp32; else ++cp64;
         const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
                                  (pass_kind == OP_REFRESH && !first);
+        const bool was_update = (pass_kind == OP_PROX);
         if (pass_kind == OP_PROX) {
             ++iters;
             if (phase == 1) ++iters64;
@@ -473,7 +476,13 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
                     for (int i = tid; i < m; i += blockDim.x) sh.y[i] *= sg;
                     __syncthreads();
                 }
+                stall_reset(stall);
                 pass_kind = OP_RESTART;
+                continue;
+            }
+            if (phase == 0 && was_update && stall_sample(stall, inner, mu)) {
+                phase = 1;                     // FP32 precision floor reached
+                pass_kind = OP_REFRESH;
                 continue;
             }
             if (iters >= prm.max_iters) { status = 4; break; }

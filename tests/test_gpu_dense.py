@@ -171,3 +171,25 @@ def test_boundary_errors():
     w = abip.abip_setup(lp["A"], lp["b"], lp["c"], _settings(max_admm_iters=5))
     x, y, s, info = abip.abip_solve(w)
     assert info["status"] == abip.ABIP_MAX_ITERS and info["admm_iters"] == 5
+
+
+@pytest.mark.parametrize("engine", ["wg", "grid"])
+def test_fp32_floor_hands_over_to_fp64(engine):
+    """Infeasible LPs whose FP32 inner loop settles above mu: the FP32 phase must
+    hand over to FP64 and the Farkas certificate must still be found."""
+    lps = lpgen.batch(48, 3)
+    picks = [k for k in range(len(lps)) if lps[k]["status"] != "solved"][:3]
+    assert picks
+    eng = abip.ABIP_ENGINE_GRID if engine == "grid" else abip.ABIP_ENGINE_WG
+    for k in picks:
+        lp = lps[k]
+        w = abip.abip_setup(lp["A"], lp["b"], lp["c"],
+                            _settings(precision=abip.ABIP_PREC_FP32_POLISH, engine=eng, max_admm_iters=30000))
+        x, y, s, info = abip.abip_solve(w)
+        print(engine, k, lp["m"], lp["n"], info["status_name"], info["admm_iters"], info["admm_iters_fp64"],
+              flush=True)
+        assert info["status"] == abip.ABIP_PRIMAL_INFEASIBLE
+        y = _np(y)
+        assert abs(lp["b"] @ y - 1.0) < 1e-9
+        assert np.linalg.norm(lp["A"].T @ y + _np(s)) <= 1e-6 / np.linalg.norm(lp["b"]) * 1.001
+        assert info["admm_iters"] - info["admm_iters_fp64"] > 0      # the bulk ran in FP32
