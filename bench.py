@@ -27,6 +27,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM-side traffic of the persistent solve kernel from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of this same default command,
+# scaled by what the counters read for a plain copy of known size
+# (bench.py --copy-calibration).  Keyed by a hash of the kernel's sources: any
+# change to them voids the figure (reported as null until measured again).
+PMC_TRAFFIC = {
+    # "sha256-prefix": {"fetch_kib": ..., "write_kib": ..., "fetch_scale": ..., "write_scale": ...},
+}
+KERNEL_SOURCES = ["paper_1805_12344_amd/csrc/abip_solve_wg.hip", "paper_1805_12344_amd/csrc/abip_internal.h"]
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def copy_calibration(nbytes=1 << 30):
+    """One plain device-to-device copy of known size, for scaling the PMC bytes."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -89,6 +119,13 @@ def algorithmic_bytes(lps, infos, fp32_stream=True):
     return tot
 
 
+def traffic_bytes():
+    t = PMC_TRAFFIC.get(kernel_hash())
+    if t is None:
+        return None
+    return t["fetch_kib"] * 1024.0 * t["fetch_scale"] + t["write_kib"] * 1024.0 * t["write_scale"]
+
+
 def run_batch(abip, As, bs, cs, settings):
     w = abip.abip_setup_batch(As, bs, cs, settings)
     xs, ys, ss, infos = abip.abip_solve_batch(w)
@@ -96,7 +133,7 @@ def run_batch(abip, As, bs, cs, settings):
     return xs, ys, ss, infos
 
 
-def cpu_baseline(lps, gpu_iters, sample_idx, iters_each=800):
+def cpu_baseline(lps, gpu_iters, sample_idx, iters_each=4000):
     """Time the FP64 oracle (as it is) on a bounded sample of the same LPs.
 
     Each sampled LP runs `iters_each` oracle iterations; its per-iteration time
@@ -133,7 +170,12 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy (PMC byte-counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch would shard "
               f"LP-by-LP across GPUs, which this build does not run.", file=sys.stderr)
@@ -198,8 +240,8 @@ def main():
         "solve_kernel_ms": kernel_ms,
         "setup_plus_solve_ms": elapsed / args.steps * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_solve_wg (persistent batched solve)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(),
+                     "kernel": "k_solve_wg (persistent batched solve)", "kernel_src": kernel_hash(),
                      "algorithmic_bytes_per_launch": bytes_launch},
     }
 
@@ -237,7 +279,7 @@ def main():
 
     if not args.no_cpu:
         rng = np.random.default_rng(1)
-        sample = sorted(rng.choice(len(lps), size=4, replace=False).tolist())
+        sample = sorted(rng.choice(len(lps), size=8, replace=False).tolist())
         line["cpu_baseline"] = cpu_baseline(lps, gpu_iters64, sample)
 
     print(json.dumps(line), flush=True)

@@ -117,6 +117,8 @@ typedef struct {
     int64_t ticks_colpass;     /* device wall-clock ticks (100 MHz) the LP's workgroup spent in */
     int64_t ticks_ginv;        /* passes over A, in passes over G^{-1}, and in the whole solve */
     int64_t ticks_total;       /* (one-workgroup engine only; 0 otherwise) */
+    int64_t ticks_check;       /* ... in the check sums and tests after each pass over A */
+    int64_t ticks_update;      /* ... in the border solve and the y update after each pass over G^{-1} */
 } abip_info;
 
 /* A matrix description.  All pointers are device pointers. */

@@ -51,6 +51,7 @@ class abip_info(ctypes.Structure):
         ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
         ("colpass_fp32", ctypes.c_int64), ("colpass_fp64", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
         ("ticks_colpass", ctypes.c_int64), ("ticks_ginv", ctypes.c_int64), ("ticks_total", ctypes.c_int64),
+        ("ticks_check", ctypes.c_int64), ("ticks_update", ctypes.c_int64),
     ]
 
     def as_dict(self):

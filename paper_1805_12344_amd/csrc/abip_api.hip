@@ -91,7 +91,7 @@ __global__ void k_init_state(const LPDesc* __restrict__ desc, LPCtrl* __restrict
         c.pres = c.dres = c.gap = c.pobj = c.dobj = NAN;
         c.by = c.cx = 0.0;
         c.iters = 0; c.iters64 = 0; c.ipm = 0; c.cp32 = 0; c.cp64 = 0;
-        c.clk[0] = c.clk[1] = c.clk[2] = 0;
+        c.clk[0] = c.clk[1] = c.clk[2] = c.clk[3] = c.clk[4] = 0;
         c.status = 0; c.phase = phase; c.mode = OP_REFRESH; c.flags = 0;
     }
 }
@@ -557,6 +557,8 @@ static void fill_info(abip_info* info, const LPCtrl& c, double setup_ms, double 
     info->ticks_colpass = c.clk[0];
     info->ticks_ginv = c.clk[1];
     info->ticks_total = c.clk[2];
+    info->ticks_check = c.clk[3];
+    info->ticks_update = c.clk[4];
     info->colpass_fp32 = c.cp32;
     info->colpass_fp64 = c.cp64;
     info->kernel_ms = kernel_ms;

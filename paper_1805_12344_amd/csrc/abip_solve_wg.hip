@@ -382,7 +382,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     // without updates are bounded by this cap so the loop always ends
     int64_t passes = 0;
     const int64_t pass_cap = prm.max_iters + 4096;
-    int64_t cyc_col = 0, cyc_ginv = 0, cyc_all = 0;
+    int64_t cyc_col = 0, cyc_ginv = 0, cyc_all = 0, cyc_chk = 0, cyc_upd = 0;
     const int64_t t_start = wall_clock64();
     while (true) {
         if (++passes > pass_cap && fixed_iters == 0) { status = 4; break; }
@@ -409,6 +409,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         if (fixed_iters > 0 && done_fixed >= fixed_iters) break;
 
         // ---- m-side sums of the check (Section 4.1) and of ||Qu - v||^2
+        const int64_t tc = wall_clock64();
         double ms[5] = {0, 0, 0, 0, 0};
         for (int i = tid; i < m; i += blockDim.x) {
             const double ax = sh.Ax[i], bi = b[i], bbi = bbar[i], yi = sh.y[i];
@@ -489,12 +490,14 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         }
 
         // ---- the inner update: t = y - A f, a = G^{-1} t, border, scalars, y'
+        cyc_chk += wall_clock64() - tc;
         for (int i = tid; i < ld; i += blockDim.x) sh.t[i] = (i < m) ? sh.y[i] - sh.Af[i] : 0.0;
         __syncthreads();
         const int64_t t1 = wall_clock64();
         if (phase == 0) ginv_pass<NCH, (NCH == 1 ? 8 : NCH == 2 ? 4 : 2), float>(G32, m, ld, sh);
         else ginv_pass<NCH, (NCH == 1 ? 4 : 2), double>(G64, m, ld, sh);
-        cyc_ginv += wall_clock64() - t1;
+        const int64_t t2 = wall_clock64();
+        cyc_ginv += t2 - t1;
         double bs[4] = {0, 0, 0, 0};
         for (int i = tid; i < m; i += blockDim.x) {
             const double ai = sh.a[i];
@@ -523,6 +526,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
             sh.y[i] = alpha * ut + (1.0 - alpha) * sh.y[i];
         }
         __syncthreads();
+        cyc_upd += wall_clock64() - t2;
         pass_kind = OP_PROX;
     }
 
@@ -531,6 +535,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     if (tid == 0) {
         LPCtrl& o = ctrl[k];
         o.clk[0] += cyc_col; o.clk[1] += cyc_ginv; o.clk[2] += cyc_all;
+        o.clk[3] += cyc_chk; o.clk[4] += cyc_upd;
         o.tau = tau; o.kappa = kappa; o.theta = theta; o.mu = mu;
         o.pres = pres; o.dres = dres; o.gap = gap; o.pobj = pobj; o.dobj = dobj;
         o.by = by_last; o.cx = cx_last;
@@ -568,7 +573,13 @@ __global__ __launch_bounds__(NCH == 1 ? 512 : 256) void k_solve_wg(const LPDesc*
         if (q >= B) break;
         const int k = order[q];
         const LPDesc d = desc[k];
-        solve_one<NCH>(k, d, ctrl, P, prm, fixed_iters, sh);
+        // each LP runs the variant for its own row count (the launch's NCH is
+        // the batch maximum): a small LP in a mixed batch holds no idle rows
+        const int nch = (d.ld + 255) >> 8;
+        if (NCH == 1 || nch <= 1) solve_one<1>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else if (NCH == 2 || nch == 2) solve_one<(NCH >= 2 ? 2 : 1)>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else if (NCH == 3 || nch == 3) solve_one<(NCH >= 3 ? 3 : 1)>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else solve_one<NCH>(k, d, ctrl, P, prm, fixed_iters, sh);
     }
 }
 
