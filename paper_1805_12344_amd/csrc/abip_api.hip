@@ -422,7 +422,7 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
         oA += (int64_t)d.ld * d.n;
         oG += (int64_t)d.ld * d.m;
         om += d.ld;
-        on += (d.n + 3) & ~3;
+        on += (d.n + 4) & ~3;          // at least one spare slot past the LP's n entries
         w->ldmax = std::max(w->ldmax, d.ld);
     }
     w->Atot = oA; w->Gtot = oG; w->Mtot = om; w->Ntot = on;

@@ -37,7 +37,10 @@ struct WGShared {
 //   ||-A^T y + c tau - cbar theta - s||^2.
 // Layout: a wave owns whole columns (chunks of 64 consecutive columns, round
 // robin over the waves); lane l holds rows 4l..4l+3 of every 256-row chunk.
-template <int NCH, int UNR, typename T>
+// PROXPASS: the pass is an update (op == OP_PROX); its group body is then
+// straight-line code (no branches on op, write-backs of the lanes that do not
+// lead a valid column go to the spare slot X[n], S[n] past the LP's columns).
+template <int NCH, int UNR, typename T, bool PROXPASS>
 __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int n, int ld,
                                          double* __restrict__ X, double* __restrict__ S,
                                          const double* __restrict__ C, const double* __restrict__ CB,
@@ -62,7 +65,7 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
     // column-side sums, accumulated by the lane that owns the column update
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     const double sg = sqrt(gamma);
-    const bool prox = (op == OP_PROX);
+    const bool prox = PROXPASS || (op == OP_PROX);
     // Groups of UNR consecutive columns go round robin over the waves, so every
     // wave has work even when n is small.  Group g+1 is loaded before group g
     // is computed: one group of column loads is always in flight behind the
@@ -127,7 +130,7 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
         const int jl = col0 + myu;
         const double x0 = G.x0, s0 = G.s0, c0 = G.c0, cb0 = G.cb0;
         double x1 = x0, s1 = s0;
-        if (prox) {
+        if (PROXPASS || prox) {
             const double dj = (x0 + s0) + ata;                     // M^{-1} block, x part
             const double ut = dj - G.z0 * p0 - G.z1 * p1;         // u~_x
             const double uh = alpha * ut + (1.0 - alpha) * x0;    // relaxation
@@ -141,7 +144,24 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
                 x1 = sg * x0; s1 = sg * s0;
             }
         }
-        if (lead && jl < n) {
+        if (PROXPASS) {
+            const bool mine = lead && jl < n;
+            const int js = mine ? jl : n;                          // spare slot
+            X[js] = x1;
+            S[js] = s1;
+            const double mk = mine ? 1.0 : 0.0;
+            const double r1 = (aty + s1 - c0 * tau) * mk;
+            const double r2 = (aty + s1) * mk;
+            const double r3 = (-aty + c0 * tau - cb0 * theta - s1) * mk;
+            const double c0m = c0 * mk, cb0m = cb0 * mk;
+            acc7[0] = fma(c0m, x1, acc7[0]);
+            acc7[1] = fma(cb0m, x1, acc7[1]);
+            acc7[2] = fma(c0m, s1, acc7[2]);
+            acc7[3] = fma(cb0m, s1, acc7[3]);
+            acc7[4] = fma(r1, r1, acc7[4]);
+            acc7[5] = fma(r2, r2, acc7[5]);
+            acc7[6] = fma(r3, r3, acc7[6]);
+        } else if (lead && jl < n) {
             if (op != OP_REFRESH) { X[jl] = x1; S[jl] = s1; }
             const double r1 = aty + s1 - c0 * tau;
             const double r2 = aty + s1;
@@ -331,7 +351,9 @@ __device__ __forceinline__ void ginv_rows(const T* __restrict__ G, int m, int ld
 // Solve (or iterate) one LP with the calling workgroup.
 // fixed_iters > 0: run exactly that many PROX iterations with no tests and no
 // restarts (phase taken from ctrl.phase), for step-level parity checks.
-template <int NCH>
+// NCH: 256-row chunks the LP needs; MAXT: the launch's largest block (512 leaves
+// 256 registers per lane, 256 leaves room for 8-column groups).
+template <int NCH, int MAXT>
 __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
                           const SolveParams& prm, int64_t fixed_iters, const WGShared& sh) {
     const int m = d.m, n = d.n, ld = d.ld;
@@ -389,12 +411,25 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         const double tmu = mu / beta;
         double cs[7];
         const int64_t t0 = wall_clock64();
-        if (phase == 0)
-            column_pass<NCH, (NCH <= 2 ? 4 : 2), float>(A32, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind,
-                                                        p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, cs);
-        else
-            column_pass<NCH, 2, double>(A64, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind,
-                                                         p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, cs);
+        if (phase == 0) {
+            if (pass_kind == OP_PROX)
+                column_pass<NCH, (NCH == 1 ? (MAXT <= 256 ? 8 : 4) : NCH == 2 ? 4 : 2), float, true>(
+                    A32, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind, p0, p1, tmu, alpha, gamma,
+                    prm.restart_rule, tau, theta, cs);
+            else
+                column_pass<NCH, (NCH <= 2 ? 4 : 2), float, false>(
+                    A32, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind, p0, p1, tmu, alpha, gamma,
+                    prm.restart_rule, tau, theta, cs);
+        } else {
+            if (pass_kind == OP_PROX)
+                column_pass<NCH, (NCH == 1 ? 4 : 2), double, true>(
+                    A64, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind, p0, p1, tmu, alpha, gamma,
+                    prm.restart_rule, tau, theta, cs);
+            else
+                column_pass<NCH, 2, double, false>(
+                    A64, m, n, ld, X, S, C, CBv, ZX0, ZX1, sh, pass_kind, p0, p1, tmu, alpha, gamma,
+                    prm.restart_rule, tau, theta, cs);
+        }
         cyc_col += wall_clock64() - t0;
         if (phase == 0) ++cp32; else ++cp64;
         const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
@@ -548,8 +583,8 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     __syncthreads();
 }
 
-template <int NCH>
-__global__ __launch_bounds__(NCH == 1 ? 512 : 256) void k_solve_wg(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl,
+template <int NCH, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_solve_wg(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl,
                                                   PoolPtrs P, SolveParams prm, const int32_t* __restrict__ order,
                                                   int32_t B, int32_t* __restrict__ queue, int64_t fixed_iters,
                                                   int32_t ldmax) {
@@ -576,10 +611,10 @@ __global__ __launch_bounds__(NCH == 1 ? 512 : 256) void k_solve_wg(const LPDesc*
         // each LP runs the variant for its own row count (the launch's NCH is
         // the batch maximum): a small LP in a mixed batch holds no idle rows
         const int nch = (d.ld + 255) >> 8;
-        if (NCH == 1 || nch <= 1) solve_one<1>(k, d, ctrl, P, prm, fixed_iters, sh);
-        else if (NCH == 2 || nch == 2) solve_one<(NCH >= 2 ? 2 : 1)>(k, d, ctrl, P, prm, fixed_iters, sh);
-        else if (NCH == 3 || nch == 3) solve_one<(NCH >= 3 ? 3 : 1)>(k, d, ctrl, P, prm, fixed_iters, sh);
-        else solve_one<NCH>(k, d, ctrl, P, prm, fixed_iters, sh);
+        if (NCH == 1 || nch <= 1) solve_one<1, MAXT>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else if (NCH == 2 || nch == 2) solve_one<(NCH >= 2 ? 2 : 1), MAXT>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else if (NCH == 3 || nch == 3) solve_one<(NCH >= 3 ? 3 : 1), MAXT>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else solve_one<NCH, MAXT>(k, d, ctrl, P, prm, fixed_iters, sh);
     }
 }
 
@@ -592,22 +627,26 @@ hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const
                            const PoolPtrs& P, const SolveParams& prm, const int32_t* order, int32_t B,
                            int32_t* queue, int64_t fixed_iters, int32_t ldmax) {
     const size_t smem = wg_smem_bytes(ldmax, threads / 64);
-    switch (nch) {
-    case 1: hipLaunchKernelGGL(k_solve_wg<1>, dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
-    case 2: hipLaunchKernelGGL(k_solve_wg<2>, dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
-    case 3: hipLaunchKernelGGL(k_solve_wg<3>, dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
-    case 4: hipLaunchKernelGGL(k_solve_wg<4>, dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
+    if (threads > 256 && nch != 1) return hipErrorInvalidValue;      // only NCH = 1 has a 512-thread build
+    switch (nch * 1000 + threads) {
+    case 1512: hipLaunchKernelGGL((k_solve_wg<1, 512>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
+    case 1256: hipLaunchKernelGGL((k_solve_wg<1, 256>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
+    case 2256: hipLaunchKernelGGL((k_solve_wg<2, 256>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
+    case 3256: hipLaunchKernelGGL((k_solve_wg<3, 256>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
+    case 4256: hipLaunchKernelGGL((k_solve_wg<4, 256>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t set_solve_wg_smem_limit(size_t bytes) {
-    hipError_t e;
-    if ((e = hipFuncSetAttribute((const void*)k_solve_wg<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_solve_wg<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_solve_wg<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_solve_wg<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void* fns[] = {(const void*)k_solve_wg<1, 512>, (const void*)k_solve_wg<1, 256>, (const void*)k_solve_wg<2, 256>,
+                         (const void*)k_solve_wg<3, 256>, (const void*)k_solve_wg<4, 256>};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ===========================================================================
