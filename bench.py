@@ -133,7 +133,7 @@ def run_batch(abip, As, bs, cs, settings):
     return xs, ys, ss, infos
 
 
-def cpu_baseline(lps, gpu_iters, sample_idx, iters_each=4000):
+def cpu_baseline(lps, gpu_iters, sample_idx, iters_each=12000):
     """Time the FP64 oracle (as it is) on a bounded sample of the same LPs.
 
     Each sampled LP runs `iters_each` oracle iterations; its per-iteration time

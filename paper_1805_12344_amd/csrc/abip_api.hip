@@ -428,7 +428,7 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     w->Atot = oA; w->Gtot = oG; w->Mtot = om; w->Ntot = on;
     w->nch = (w->ldmax + 255) / 256;
     // the NCH >= 2 kernels are compiled for at most 256 threads
-    w->threads = (w->nch >= 2) ? 256 : (s.block_threads ? s.block_threads : 512);
+    w->threads = (w->nch >= 2) ? 256 : (s.block_threads ? s.block_threads : 256);
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&w->cu_count, hipDeviceAttributeMultiprocessorCount, dev);

@@ -385,6 +385,9 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     int status = cl.status;
     const int check_final_first = cl.flags & 1;   // a loaded post-update state: test it
     double pres = cl.pres, dres = cl.dres, gap = cl.gap, pobj = cl.pobj, dobj = cl.dobj;
+    // raw sums of the last final test; the reported ratios are formed once at the end
+    double l_ms2 = 0.0, l_cs4 = 0.0, l_tau = 0.0;
+    bool l_have = false;
     double by_last = cl.by, cx_last = cl.cx;
     const double zbar = cl.zbar, nb = cl.nb, nc = cl.nc;
     const double alpha = prm.alpha, gamma = prm.gamma, beta = prm.beta, eps = prm.eps;
@@ -408,7 +411,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     const int64_t t_start = wall_clock64();
     while (true) {
         if (++passes > pass_cap && fixed_iters == 0) { status = 4; break; }
-        const double tmu = mu / beta;
+        const double tmu = mu / beta;      // t = mu / beta, eq. (Simple-Update:Barrier-X)
         double cs[7];
         const int64_t t0 = wall_clock64();
         if (phase == 0) {
@@ -464,21 +467,17 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
             // ---- final test on a post-update iterate
             if (post_update) {
                 int st = 0;
+                // Section 4.1's tests multiplied through by tau (> 0) and
+                // squared: no square roots or divisions on the per-iteration path
                 if (tau > 0.0) {
-                    pres = sqrt(ms[2]) / tau;
-                    dres = sqrt(cs[4]) / tau;
-                    pobj = cx / tau;
-                    dobj = by / tau;
-                    gap = fabs(pobj - dobj);
-                    if (pres <= eps * (1.0 + nb) && dres <= eps * (1.0 + nc) &&
-                        gap <= eps * (1.0 + fabs(pobj) + fabs(dobj)))
+                    const double ep = eps * (1.0 + nb) * tau, ed = eps * (1.0 + nc) * tau;
+                    if (ms[2] <= ep * ep && cs[4] <= ed * ed &&
+                        fabs(cx - by) <= eps * (tau + fabs(cx) + fabs(by)))
                         st = 1;
-                    pres /= (1.0 + nb);
-                    dres /= (1.0 + nc);
-                    gap /= (1.0 + fabs(pobj) + fabs(dobj));
                 }
-                if (!st && nb > 0.0 && by > 0.0 && sqrt(cs[5]) <= eps * by / nb) st = 2;
-                if (!st && nc > 0.0 && cx < 0.0 && sqrt(ms[3]) <= eps * (-cx) / nc) st = 3;
+                if (!st && nb > 0.0 && by > 0.0 && cs[5] * (nb * nb) <= (eps * by) * (eps * by)) st = 2;
+                if (!st && nc > 0.0 && cx < 0.0 && ms[3] * (nc * nc) <= (eps * cx) * (eps * cx)) st = 3;
+                l_ms2 = ms[2]; l_cs4 = cs[4]; l_tau = tau; l_have = true;
                 by_last = by;
                 cx_last = cx;
                 if (st) {
@@ -566,6 +565,13 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     }
 
     cyc_all = wall_clock64() - t_start;
+    if (l_have && l_tau > 0.0) {           // the relative residuals of the last test
+        pobj = cx_last / l_tau;
+        dobj = by_last / l_tau;
+        pres = sqrt(l_ms2) / l_tau / (1.0 + nb);
+        dres = sqrt(l_cs4) / l_tau / (1.0 + nc);
+        gap = fabs(pobj - dobj) / (1.0 + fabs(pobj) + fabs(dobj));
+    }
     for (int i = tid; i < m; i += blockDim.x) Yg[i] = sh.y[i];
     if (tid == 0) {
         LPCtrl& o = ctrl[k];
