@@ -91,7 +91,7 @@ typedef struct {
     int32_t engine;            /* ABIP_ENGINE_*; default auto */
     int64_t fp32_max_iters;    /* FP32 phase length cap before the FP64 polish
                                   starts regardless; default 1e6 */
-    double  cg_tol;            /* CG relative tolerance floor; default 1e-10 */
+    double  cg_tol;            /* CG stops when ||r|| <= cg_tol ||rhs|| (sparse engine); default 1e-10 */
     int32_t cg_max_iters;      /* per linear solve; default 500 */
     int32_t block_threads;     /* threads per workgroup for ENGINE_WG (256 or 512, honoured when
                                   the largest m <= 256; larger LPs always use 256); 0 = auto */
@@ -119,9 +119,19 @@ typedef struct {
     int64_t ticks_total;       /* (one-workgroup engine only; 0 otherwise) */
     int64_t ticks_check;       /* ... in the check sums and tests after each pass over A */
     int64_t ticks_update;      /* ... in the border solve and the y update after each pass over G^{-1} */
+                               /* (sparse engine: colpass_fp64 counts updates; ticks_total only) */
 } abip_info;
 
-/* A matrix description.  All pointers are device pointers. */
+/* A matrix description.  All pointers are device pointers; abip_setup copies
+ * what they point to, so the caller may free them afterwards.
+ * CSR (abip_setup only): rowptr nondecreasing with rowptr[0] = 0 and
+ * rowptr[m] = nnz, colidx in [0, n) (any order inside a row; repeats add up),
+ * finite values; violations return ABIP_E_INVALID / ABIP_E_NONFINITE.  A CSR
+ * handle runs the sparse engine: FP64 throughout (settings.precision is not
+ * used), the linear step by Jacobi-preconditioned CG on G = I + A A^T
+ * (Section 4.4, indirect variant) with settings.cg_tol / cg_max_iters, in one
+ * cooperative launch.  abip_backward and abip_apply_iq take dense handles
+ * only (ABIP_E_STATE otherwise). */
 typedef struct {
     int32_t m, n;
     int32_t format;            /* ABIP_DENSE_ROWMAJOR or ABIP_CSR */

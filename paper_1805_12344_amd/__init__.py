@@ -180,7 +180,36 @@ class Work:
         self.handle = None
 
 
+def _csr_parts(A):
+    """(indptr, indices, data, (m, n)) of a scipy.sparse matrix or a dict with those keys."""
+    if isinstance(A, dict):
+        return A["indptr"], A["indices"], A["data"], tuple(A["shape"])
+    if hasattr(A, "tocsr") and hasattr(A, "indptr"):
+        A = A.tocsr()
+        return A.indptr, A.indices, A.data, tuple(A.shape)
+    return None
+
+
 def abip_setup(A, b, c, settings: abip_settings | None = None) -> Work:
+    """Set up one LP.  A: dense (array / tensor, m x n, row-major) or CSR
+    (scipy.sparse matrix, or dict(indptr, indices, data, shape)); the CSR form
+    runs the sparse CG engine."""
+    parts = _csr_parts(A)
+    if parts is not None:
+        indptr, indices, data, (m, n) = parts
+        rp = torch.as_tensor(indptr).to(device="cuda", dtype=torch.int32).contiguous()
+        ci = torch.as_tensor(indices).to(device="cuda", dtype=torch.int32).contiguous()
+        va = torch.as_tensor(data).to(device="cuda", dtype=torch.float64).contiguous()
+        if rp.numel() != m + 1 or ci.numel() != va.numel():
+            raise ValueError("CSR: indptr must have m+1 entries and indices/data the same length")
+        b = _dev(b, (m,))
+        c = _dev(c, (n,))
+        mat = abip_matrix(m, n, ABIP_CSR, va.data_ptr() if va.numel() else None, rp.data_ptr(),
+                          ci.data_ptr() if ci.numel() else None, int(va.numel()))
+        h = ctypes.c_void_p()
+        s = settings or abip_default_settings()
+        _check(lib().abip_setup(ctypes.byref(h), ctypes.byref(mat), _ptr(b), _ptr(c), ctypes.byref(s), _stream()))
+        return Work(h, [(m, n)], (rp, ci, va, b, c, s))
     A = _dev(A)
     m, n = A.shape
     b = _dev(b, (m,))

@@ -13,6 +13,7 @@
 #include "abip.h"
 #include "abip_internal.h"
 #include "abip_grid.h"
+#include "abip_sparse.h"
 
 // defined in abip_solve_wg.hip
 hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const LPDesc* desc, LPCtrl* ctrl,
@@ -90,7 +91,7 @@ __global__ void k_init_state(const LPDesc* __restrict__ desc, LPCtrl* __restrict
         c.tau = 1.0; c.kappa = 1.0; c.theta = 1.0; c.mu = beta;
         c.pres = c.dres = c.gap = c.pobj = c.dobj = NAN;
         c.by = c.cx = 0.0;
-        c.iters = 0; c.iters64 = 0; c.ipm = 0; c.cp32 = 0; c.cp64 = 0;
+        c.iters = 0; c.iters64 = 0; c.ipm = 0; c.cp32 = 0; c.cp64 = 0; c.cg = 0;
         c.clk[0] = c.clk[1] = c.clk[2] = c.clk[3] = c.clk[4] = 0;
         c.status = 0; c.phase = phase; c.mode = OP_REFRESH; c.flags = 0;
     }
@@ -247,6 +248,16 @@ struct abip_work {
     double* gbuf = nullptr;          // Y2, Pf, Px, pcol, prow, pa, t, a
     GridCtl* gctl = nullptr;         // 2 control blocks
     std::vector<LPCtrl> hctrl;
+    // sparse engine (one LP, A in CSR, CG on I + A A^T)
+    bool sparse = false;
+    SpArgs sa{};
+    int sp_nb = 1;
+    int32_t* sp_idx = nullptr;       // rp (m+1), ci (nnz), rpt (n+1), cit (nnz), cursor (n)
+    double* sp_val = nullptr;        // va (nnz), vat (nnz)
+    double* sp_vec = nullptr;        // dG, a, r, z, p, q (m); ATZy0, ATZy1, ATY, ATA, q1 (n); part
+    unsigned* sp_bar = nullptr;      // grid barrier words
+    int* sp_err = nullptr;
+    int64_t* sp_cgit = nullptr;
 };
 
 static void release(abip_work* w) {
@@ -258,6 +269,8 @@ static void release(abip_work* w) {
     (void)hipFree(w->adj_ws); (void)hipFree(w->adj_ows); (void)hipFree(w->adj_ptrs);
     (void)hipFree(w->adj_iters); (void)hipFree(w->adj_resid);
     (void)hipFree(w->gbuf); (void)hipFree(w->gctl);
+    (void)hipFree(w->sp_idx); (void)hipFree(w->sp_val); (void)hipFree(w->sp_vec);
+    (void)hipFree(w->sp_bar); (void)hipFree(w->sp_err); (void)hipFree(w->sp_cgit);
     if (w->ev0) (void)hipEventDestroy(w->ev0);
     if (w->ev1) (void)hipEventDestroy(w->ev1);
 }
@@ -517,10 +530,243 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     return ABIP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// sparse engine: setup and run
+// ---------------------------------------------------------------------------
+static int lanes_for(double avg) {           // lanes per CSR row: about 3 entries per lane
+    int L = 1;
+    while (L < 64 && 3.0 * L < avg) L *= 2;
+    return L;
+}
+
+static double host_sum(const std::vector<double>& v, int k, int nblk) {
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += v[(size_t)k * nblk + i];
+    return s;
+}
+
+static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, const double* c,
+                        const abip_settings* settings, void* stream) {
+    *out = nullptr;
+    abip_settings s;
+    if (settings) s = *settings; else abip_default_settings(&s);
+    int rc = check_settings(s);
+    if (rc) return rc;
+    const int32_t m = A->m, n = A->n;
+    const int64_t nnz = A->nnz;
+    if (m < 1 || n < 1) return fail(ABIP_E_DIM, "CSR: bad dimensions m=%d n=%d", m, n);
+    if (nnz < 0 || nnz > (int64_t)INT32_MAX) return fail(ABIP_E_DIM, "CSR: nnz=%lld out of range", (long long)nnz);
+    if (!A->rowptr || (nnz > 0 && (!A->colidx || !A->val)) || !b || !c)
+        return fail(ABIP_E_INVALID, "CSR: null rowptr / colidx / val / b / c");
+    if (!(s.cg_tol > 0.0) || s.cg_max_iters < 1) return fail(ABIP_E_INVALID, "settings: cg_tol > 0 and cg_max_iters >= 1 required");
+    const double t0 = now_ms();
+    abip_work* w = new abip_work();
+    w->B = 1;
+    w->set = s;
+    w->set.precision = ABIP_PREC_FP64;        // the CG path runs in FP64
+    w->stream = (hipStream_t)stream;
+    w->sparse = true;
+    w->hdesc.resize(1);
+    LPDesc& d = w->hdesc[0];
+    d.m = m; d.n = n; d.ld = (m + 3) & ~3; d.pad = 0; d.oA = 0; d.oG = 0; d.om = 0; d.on = 0;
+    w->ldmax = d.ld;
+    w->Mtot = d.ld;
+    w->Ntot = (n + 4) & ~3;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&w->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    hipStream_t st = w->stream;
+    double* dpart = nullptr;
+    const double** dptrs = nullptr;
+    auto bail = [&](int code) { (void)hipFree(dpart); (void)hipFree(dptrs); dpart = nullptr; dptrs = nullptr;
+                                release(w); delete w; return code; };
+#define SALLOC(ptr, count) do { hipError_t e_ = hipMalloc((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count)); \
+        if (e_ != hipSuccess) return bail(fail(e_ == hipErrorOutOfMemory ? ABIP_E_OOM : ABIP_E_HIP, "hipMalloc(%s): %s", #ptr, hipGetErrorString(e_))); } while (0)
+#define SCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return bail(fail(ABIP_E_HIP, "%s: %s", #call, hipGetErrorString(e_))); } while (0)
+    const int64_t nidx = (int64_t)(m + 1) + nnz + (n + 1) + nnz + n;
+    const int NBLK = 64;
+    const int64_t nvec = 6 * (int64_t)d.ld + 5 * (int64_t)w->Ntot + (int64_t)SP_PS * 4 * w->cu_count;
+    SALLOC(w->ddesc, 1); SALLOC(w->dctrl, 1);
+    SALLOC(w->Mv, (int64_t)NMF * w->Mtot); SALLOC(w->Nv, (int64_t)NNF * w->Ntot);
+    SALLOC(w->errflag, 1); SALLOC(w->outp, 3);
+    SALLOC(w->sp_idx, nidx); SALLOC(w->sp_val, 2 * std::max<int64_t>(nnz, 1));
+    SALLOC(w->sp_vec, nvec);
+    SALLOC(w->sp_bar, 2); SALLOC(w->sp_err, 1); SALLOC(w->sp_cgit, 1);
+    SALLOC(dpart, 8 * NBLK);
+    SALLOC(dptrs, 8);
+    auto freetmp = [&]() { (void)hipFree(dpart); (void)hipFree(dptrs); dpart = nullptr; dptrs = nullptr; };
+    SpArgs& g = w->sa;
+    g.m = m; g.n = n; g.nnz = nnz;
+    int32_t* rp = w->sp_idx;
+    int32_t* ci = rp + (m + 1);
+    int32_t* rpt = ci + nnz;
+    int32_t* cit = rpt + (n + 1);
+    int32_t* cursor = cit + nnz;
+    double* va = w->sp_val;
+    double* vat = va + nnz;
+    g.rp = rp; g.ci = ci; g.va = va; g.rpt = rpt; g.cit = cit; g.vat = vat;
+    double* V = w->sp_vec;
+    double* dG = V; V += d.ld;
+    g.a = V; V += d.ld; g.r = V; V += d.ld; g.z = V; V += d.ld; g.p = V; V += d.ld; g.q = V; V += d.ld;
+    double* ATZy0 = V; V += w->Ntot;
+    double* ATZy1 = V; V += w->Ntot;
+    g.ATY = V; V += w->Ntot; g.ATA = V; V += w->Ntot; g.q1 = V; V += w->Ntot;
+    g.part = V; V += (int64_t)SP_PS * 4 * w->cu_count;          // partial sums of up to 4 workgroups per CU
+    g.dG = dG; g.ATZy0 = ATZy0; g.ATZy1 = ATZy1;
+    double* Mv = w->Mv;
+    double* Nv = w->Nv;
+    double* fb = Mv + MF_B * w->Mtot;  double* fbb = Mv + MF_BBAR * w->Mtot;
+    double* fAc = Mv + MF_AC * w->Mtot; double* fAcb = Mv + MF_ACBAR * w->Mtot;
+    double* fZy0 = Mv + MF_ZY0 * w->Mtot; double* fZy1 = Mv + MF_ZY1 * w->Mtot;
+    double* fC = Nv + NF_C * w->Ntot; double* fCB = Nv + NF_CBAR * w->Ntot;
+    double* fZx0 = Nv + NF_ZX0 * w->Ntot; double* fZx1 = Nv + NF_ZX1 * w->Ntot;
+    g.b = fb; g.bbar = fbb; g.Ac = fAc; g.Acb = fAcb; g.Zy0 = fZy0; g.Zy1 = fZy1;
+    g.C = fC; g.CB = fCB; g.Zx0 = fZx0; g.Zx1 = fZx1;
+    g.Y = Mv + MF_Y * w->Mtot; g.X = Nv + NF_X * w->Ntot; g.S = Nv + NF_S * w->Ntot;
+    g.bar = w->sp_bar; g.err = w->sp_err; g.lc = w->dctrl;
+    g.LA = lanes_for((double)nnz / m);
+    g.LT = lanes_for((double)nnz / n);
+    SCHK(hipMemsetAsync(w->Mv, 0, sizeof(double) * NMF * w->Mtot, st));
+    SCHK(hipMemsetAsync(w->Nv, 0, sizeof(double) * NNF * w->Ntot, st));
+    SCHK(hipMemsetAsync(w->sp_vec, 0, sizeof(double) * nvec, st));
+    SCHK(hipMemsetAsync(w->dctrl, 0, sizeof(LPCtrl), st));
+    SCHK(hipMemsetAsync(w->errflag, 0, sizeof(int), st));
+    SCHK(hipMemsetAsync(w->sp_bar, 0, 2 * sizeof(unsigned), st));
+    SCHK(hipMemsetAsync(w->sp_err, 0, sizeof(int), st));
+    SCHK(hipMemcpyAsync(w->ddesc, &d, sizeof d, hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(rp, A->rowptr, sizeof(int32_t) * (size_t)(m + 1), hipMemcpyDeviceToDevice, st));
+    if (nnz > 0) {
+        SCHK(hipMemcpyAsync(ci, A->colidx, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, st));
+        SCHK(hipMemcpyAsync(va, A->val, sizeof(double) * (size_t)nnz, hipMemcpyDeviceToDevice, st));
+    }
+    SCHK(hipMemcpyAsync(fb, b, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    SCHK(hipMemcpyAsync(fC, c, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    // validation: row pointers, then entries, then b and c
+    int hflag = 0;
+    SCHK(sp_validate_rows(g, w->errflag, st));
+    SCHK(hipMemcpyAsync(&hflag, w->errflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    SCHK(hipStreamSynchronize(st));
+    if (hflag) { freetmp(); return bail(fail(ABIP_E_INVALID, "CSR: row pointers are not a nondecreasing 0..nnz sequence")); }
+    SCHK(sp_validate_entries(g, w->errflag, st));
+    SCHK(sp_check_finite(fb, m, w->errflag, 8, st));
+    SCHK(sp_check_finite(fC, n, w->errflag, 8, st));
+    SCHK(hipMemcpyAsync(&hflag, w->errflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    SCHK(hipStreamSynchronize(st));
+    if (hflag & 2) { freetmp(); return bail(fail(ABIP_E_INVALID, "CSR: column index out of range [0, %d)", n)); }
+    if (hflag & 4) { freetmp(); return bail(fail(ABIP_E_NONFINITE, "NaN or Inf in A")); }
+    if (hflag & 8) { freetmp(); return bail(fail(ABIP_E_NONFINITE, "NaN or Inf in b or c")); }
+    // CSR(A^T), Jacobi diagonal, HSD constants (eq. bar-b-c-z-re)
+    SCHK(sp_transpose(g, rpt, cit, vat, cursor, st));
+    SCHK(sp_rowsq(g, dG, st));
+    SCHK(sp_affine(fC, 0.0, 1.0, n, g.q1, st));                               // e (scratch)
+    SCHK(sp_spmv(rp, ci, va, m, g.q1, -1.0, fb, 1.0, fbb, st));              // bbar = b - A e
+    SCHK(sp_affine(fC, 1.0, -1.0, n, fCB, st));                               // cbar = c - e
+    SCHK(sp_spmv(rp, ci, va, m, fC, 1.0, nullptr, 0.0, fAc, st));            // A c
+    SCHK(sp_spmv(rp, ci, va, m, fCB, 1.0, nullptr, 0.0, fAcb, st));          // A cbar
+    std::vector<double> hp(8 * NBLK);
+    {
+        const double* ys[2] = {g.q1, fC};
+        SCHK(hipMemcpyAsync(dptrs, ys, sizeof ys, hipMemcpyHostToDevice, st));
+        SCHK(sp_dots(fC, dptrs, 2, n, dpart, NBLK, st));                      // c^T e, c^T c
+        SCHK(hipMemcpyAsync(hp.data(), dpart, sizeof(double) * 2 * NBLK, hipMemcpyDeviceToHost, st));
+        SCHK(hipStreamSynchronize(st));
+    }
+    const double zbar = host_sum(hp, 0, NBLK) + 1.0, nc = std::sqrt(host_sum(hp, 1, NBLK));
+    {
+        const double* ys[1] = {fb};
+        SCHK(hipMemcpyAsync(dptrs, ys, sizeof ys, hipMemcpyHostToDevice, st));
+        SCHK(sp_dots(fb, dptrs, 1, m, dpart, NBLK, st));
+        SCHK(hipMemcpyAsync(hp.data(), dpart, sizeof(double) * NBLK, hipMemcpyDeviceToHost, st));
+        SCHK(hipStreamSynchronize(st));
+    }
+    const double nb = std::sqrt(host_sum(hp, 0, NBLK));
+    // the border Z = M^{-1} H (Section 4.4, rank 2): Z_y = G^{-1}(e - A f), Z_x = f + A^T Z_y
+    // for H1 = (-b; c) and H2 = (bbar; -cbar), by CG to near machine precision
+    const int maxb = std::min(sp_max_blocks(w->cu_count), 4 * w->cu_count);
+    w->sp_nb = std::max(1, std::min<int>(maxb, (int)std::min<int64_t>(w->cu_count, (std::max<int64_t>(m, n) + 255) / 256)));
+    double* rhs = g.q;                                                         // m scratch until the solve
+    SCHK(sp_spmv(rp, ci, va, m, fC, -1.0, fb, -1.0, g.r, st));               // -b - A c  (into r, then copied)
+    SCHK(hipMemcpyAsync(rhs, g.r, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    const int32_t bmax = std::max<int32_t>(5000, 20 * s.cg_max_iters);
+    SCHK(sp_cg_solve(g, rhs, fZy0, 1e-14, bmax, w->sp_nb, w->sp_cgit, st));
+    SCHK(sp_spmv(rp, ci, va, m, fCB, 1.0, fbb, 1.0, g.r, st));               // bbar + A cbar
+    SCHK(hipMemcpyAsync(rhs, g.r, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    SCHK(sp_cg_solve(g, rhs, fZy1, 1e-14, bmax, w->sp_nb, w->sp_cgit, st));
+    SCHK(sp_spmv(rpt, cit, vat, n, fZy0, 1.0, nullptr, 0.0, ATZy0, st));     // A^T Z_y0
+    SCHK(sp_spmv(rpt, cit, vat, n, fZy1, 1.0, nullptr, 0.0, ATZy1, st));     // A^T Z_y1
+    SCHK(sp_spmv(rpt, cit, vat, n, fZy0, 1.0, fC, 1.0, fZx0, st));           // Z_x0 = c + A^T Z_y0
+    SCHK(sp_spmv(rpt, cit, vat, n, fZy1, 1.0, fCB, -1.0, fZx1, st));         // Z_x1 = -cbar + A^T Z_y1
+    SCHK(hipMemsetAsync(g.a, 0, sizeof(double) * d.ld, st));                  // CG warm start of the solve: 0
+    int herr = 0;
+    SCHK(hipMemcpyAsync(&herr, w->sp_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    // K = I2 + S + H^T Z
+    {
+        const double* ys[4] = {fZy0, fZy1, nullptr, nullptr};
+        SCHK(hipMemcpyAsync(dptrs, ys, 2 * sizeof(double*), hipMemcpyHostToDevice, st));
+        SCHK(sp_dots(fb, dptrs, 2, m, dpart, NBLK, st));                       // b^T Z_y0, b^T Z_y1
+        SCHK(sp_dots(fbb, dptrs, 2, m, dpart + 2 * NBLK, NBLK, st));           // bbar^T Z_y0, bbar^T Z_y1
+        const double* xs[2] = {fZx0, fZx1};
+        SCHK(hipMemcpyAsync(dptrs + 2, xs, 2 * sizeof(double*), hipMemcpyHostToDevice, st));
+        SCHK(sp_dots(fC, dptrs + 2, 2, n, dpart + 4 * NBLK, NBLK, st));        // c^T Z_x0, c^T Z_x1
+        SCHK(sp_dots(fCB, dptrs + 2, 2, n, dpart + 6 * NBLK, NBLK, st));       // cbar^T Z_x0, cbar^T Z_x1
+        SCHK(hipMemcpyAsync(hp.data(), dpart, sizeof(double) * 8 * NBLK, hipMemcpyDeviceToHost, st));
+        SCHK(hipStreamSynchronize(st));
+    }
+    freetmp();
+    if (herr) return bail(fail(ABIP_E_HIP, "sparse setup: a grid barrier timed out"));
+    const double bZ0 = host_sum(hp, 0, NBLK), bZ1 = host_sum(hp, 1, NBLK);
+    const double bbZ0 = host_sum(hp, 2, NBLK), bbZ1 = host_sum(hp, 3, NBLK);
+    const double cZ0 = host_sum(hp, 4, NBLK), cZ1 = host_sum(hp, 5, NBLK);
+    const double cbZ0 = host_sum(hp, 6, NBLK), cbZ1 = host_sum(hp, 7, NBLK);
+    const double k00 = 1.0 + (-bZ0 + cZ0), k01 = zbar + (-bZ1 + cZ1);
+    const double k10 = -zbar + (bbZ0 - cbZ0), k11 = 1.0 + (bbZ1 - cbZ1);
+    const double det = k00 * k11 - k01 * k10;
+    LPCtrl C{};
+    C.zbar = zbar; C.nb = nb; C.nc = nc;
+    C.K00 = k11 / det; C.K01 = -k01 / det; C.K10 = -k10 / det; C.K11 = k00 / det;
+    C.KA00 = C.KA01 = C.KA10 = C.KA11 = NAN;
+    C.phase = 1;
+    SCHK(hipMemcpyAsync(w->dctrl, &C, sizeof C, hipMemcpyHostToDevice, st));
+    SCHK(hipStreamSynchronize(st));
+#undef SALLOC
+#undef SCHK
+    w->hctrl.resize(1);
+    w->setup_ms = now_ms() - t0;
+    *out = w;
+    return ABIP_OK;
+}
+
+// one cooperative launch for the whole solve (or `fixed` updates)
+static int sparse_run(abip_work* w, int64_t fixed) {
+    hipStream_t st = w->stream;
+    SpArgs g = w->sa;
+    g.prm = make_params(w->set);
+    g.cg_tol = w->set.cg_tol;
+    g.cg_max = w->set.cg_max_iters;
+    g.fixed_iters = fixed;
+    if (fixed == 0) {          // a fresh solve starts CG from a = 0 (reproducible runs)
+        HIPCHK(hipMemsetAsync(g.a, 0, sizeof(double) * (size_t)g.m, st));
+        HIPCHK(hipMemsetAsync(g.ATA, 0, sizeof(double) * (size_t)g.n, st));
+    }
+    HIPCHK(hipMemsetAsync(w->sp_bar, 0, 2 * sizeof(unsigned), st));
+    HIPCHK(hipMemsetAsync(w->sp_err, 0, sizeof(int), st));
+    if (!w->ev0) HIPCHK(hipEventCreate(&w->ev0));
+    if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
+    HIPCHK(hipEventRecord(w->ev0, st));
+    HIPCHK(sp_solve(g, w->sp_nb, st));
+    HIPCHK(hipEventRecord(w->ev1, st));
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, w->sp_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (herr) return fail(ABIP_E_HIP, "sparse solve: a grid barrier timed out");
+    return ABIP_OK;
+}
+
 extern "C" int abip_setup(abip_work** out, const abip_matrix* A, const double* b, const double* c,
                           const abip_settings* settings, void* stream) {
+    if (!out) return fail(ABIP_E_INVALID, "abip_setup: null output handle");
     if (!A) return fail(ABIP_E_INVALID, "abip_setup: null A");
-    if (A->format == ABIP_CSR) return fail(ABIP_E_INVALID, "abip_setup: CSR input is not supported yet");
+    if (A->format == ABIP_CSR) return setup_sparse(out, A, b, c, settings, stream);
     const double* bb[1] = {b};
     const double* cc[1] = {c};
     return setup_dense(out, 1, A, bb, cc, settings, stream);
@@ -566,7 +812,7 @@ static void fill_info(abip_info* info, const LPCtrl& c, double setup_ms, double 
     info->admm_iters = c.iters;
     info->admm_iters_fp64 = c.iters64;
     info->ipm_iters = c.ipm;
-    info->cg_iters = 0;
+    info->cg_iters = c.cg;
     info->pres = c.pres; info->dres = c.dres; info->gap = c.gap;
     info->pobj = c.pobj; info->dobj = c.dobj;
     info->tau = c.tau; info->kappa = c.kappa; info->theta = c.theta; info->mu = c.mu;
@@ -582,7 +828,7 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
     hipLaunchKernelGGL(k_init_state, dim3(w->B), dim3(256), 0, st, w->ddesc, w->dctrl, w->Mv, w->Nv, w->Mtot, w->Ntot,
                        w->set.beta, phase);
     HIPCHK(hipGetLastError());
-    int rc = w->grid ? grid_run(w, 0, phase) : run_wg(w, w->B, 0, prm);
+    int rc = w->sparse ? sparse_run(w, 0) : w->grid ? grid_run(w, 0, phase) : run_wg(w, w->B, 0, prm);
     if (rc) return rc;
     std::vector<double*> tab(3 * w->B);
     for (int k = 0; k < w->B; ++k) {
@@ -621,6 +867,7 @@ extern "C" int abip_solve_batch(abip_work* w, double* const* x, double* const* y
 
 static int backward_all(abip_work* w, const double* const* g, double* const* dc, double* const* db,
                         double* const* dA) {
+    if (w->sparse) return fail(ABIP_E_STATE, "abip_backward: dense handles only");
     if (!w->solved) return fail(ABIP_E_STATE, "abip_backward: call abip_solve first");
     for (int k = 0; k < w->B; ++k) {
         if (!g || !g[k] || !dc || !dc[k] || !db || !db[k])
@@ -704,6 +951,7 @@ extern "C" int abip_apply_iq(abip_work* w, int32_t k, const double* win, double*
     if (!w) return fail(ABIP_E_INVALID, "abip_apply_iq: null handle");
     if (k < 0 || k >= w->B) return fail(ABIP_E_INVALID, "abip_apply_iq: LP index %d out of range", k);
     if (!win || !out) return fail(ABIP_E_INVALID, "abip_apply_iq: null vector");
+    if (w->sparse) return fail(ABIP_E_STATE, "abip_apply_iq: dense handles only");
     const size_t smem = sizeof(double) * 2 * w->hdesc[k].ld;
     const int sgn = (use_fp32 & 2) ? -1 : 1;
     if (use_fp32 & 1)
@@ -731,6 +979,10 @@ extern "C" int abip_set_state(abip_work* w, int32_t k, const double* y, const do
     HIPCHK(hipStreamSynchronize(w->stream));
     c.tau = tau; c.kappa = kappa; c.theta = theta; c.mu = mu;
     c.status = 0; c.mode = OP_REFRESH; c.flags = 4;     // 4: loaded iterate, may be differentiated
+    if (w->sparse) {
+        HIPCHK(hipMemsetAsync(w->sa.a, 0, sizeof(double) * (size_t)w->sa.m, w->stream));
+        HIPCHK(hipMemsetAsync(w->sa.ATA, 0, sizeof(double) * (size_t)w->sa.n, w->stream));
+    }
     c.iters = 0; c.iters64 = 0; c.ipm = 0;
     HIPCHK(hipMemcpyAsync(w->dctrl + k, &c, sizeof c, hipMemcpyHostToDevice, w->stream));
     HIPCHK(hipStreamSynchronize(w->stream));
@@ -764,10 +1016,11 @@ extern "C" int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_
     LPCtrl c;
     HIPCHK(hipMemcpyAsync(&c, w->dctrl + k, sizeof c, hipMemcpyDeviceToHost, w->stream));
     HIPCHK(hipStreamSynchronize(w->stream));
-    c.phase = use_fp32 ? 0 : 1;
+    c.phase = (use_fp32 && !w->sparse) ? 0 : 1;
     c.mode = OP_REFRESH;
     c.flags &= 4;
     HIPCHK(hipMemcpyAsync(w->dctrl + k, &c, sizeof c, hipMemcpyHostToDevice, w->stream));
+    if (w->sparse) return sparse_run(w, iters);
     if (w->grid) {
         int rc = grid_run(w, iters, use_fp32 ? 0 : 1);
         if (rc) return rc;

@@ -40,6 +40,7 @@ struct LPCtrl {
     double by, cx;                        // b^T y, c^T x at the last check
     int64_t iters, iters64, ipm;
     int64_t cp32, cp64;                   // column passes per data precision
+    int64_t cg;                           // CG iterations (sparse engine)
     int64_t clk[5];                       // wall-clock ticks: column passes, G^{-1} passes, whole solve,
                                           // check sums + tests, border + y update
     int32_t status, phase, mode, flags;  // phase 0 = FP32 bulk, 1 = FP64; mode = next op

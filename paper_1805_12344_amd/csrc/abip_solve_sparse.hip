@@ -1,0 +1,625 @@
+// Sparse engine: Algorithm 2 on one LP whose A is given in CSR.  The linear
+// step u~ = (I+Q)^{-1} w keeps the Schur reduction of Section 4.4 (with the
+// theta column, so a rank-2 border), and solves G a = w_y - A w_x,
+// G = I + A A^T, by Jacobi-preconditioned CG (the indirect variant of Section
+// 4.4: every CG iteration is one product with A^T and one with A).  CG starts
+// from the previous solution a, whose A^T a is kept from the last update.
+//
+// One cooperative launch runs the whole solve.  Rows of A and columns (rows of
+// CSR(A^T)) are split into contiguous ranges over the workgroups; phases are
+// separated by a grid barrier; every workgroup reduces the per-workgroup
+// partial sums in the same fixed order and takes the same decisions, so runs
+// are bitwise reproducible.  Per update: the column pass (prox, dual update,
+// A^T y of the new iterate, column sums of the check), the row pass (A x, A s,
+// the row sums of the check, the CG right-hand side and start), then 3
+// barriers per CG iteration.
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cmath>
+#include "abip_internal.h"
+#include "abip_sparse.h"
+
+#define SP_THREADS 256
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+// Sum over aligned groups of L consecutive lanes (L a power of two <= 64);
+// every lane of a group receives the group total (same DPP / permlane steps
+// as the wave sums, stopped after log2 L of them).  All 64 lanes must be active.
+__device__ __forceinline__ double group_sum(double v, int L) {
+    if (L >= 2) v = v + dpp_partner<0xB1>(v);
+    if (L >= 4) v = v + dpp_partner<0x4E>(v);
+    if (L >= 8) v = v + dpp_partner<0x141>(v);
+    if (L >= 16) v = v + dpp_partner<0x140>(v);
+    if (L >= 32) v = swap16_sum(v);
+    if (L >= 64) v = swap32_sum(v);
+    return v;
+}
+
+// Grid-wide barrier for a cooperative launch (all workgroups co-resident).
+// Counter + generation; the last arrival resets the counter and bumps the
+// generation.  A wait that outlasts ~2^22 polls sets *err and returns (the
+// solver loop then exits), so no wave can spin forever.
+__device__ __forceinline__ void grid_sync(unsigned* bar, int* err) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned* cnt = bar;
+        unsigned* gen = bar + 1;
+        __threadfence();
+        const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = atomicAdd(cnt, 1u);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int polls = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++polls > (1 << 22)) { atomicExch(err, 1); break; }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool grid_failed(int* err) {
+    return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Block sum of K per-thread values written to this workgroup's partial slots.
+template <int K>
+__device__ __forceinline__ void put_parts(double (&v)[K], double* part, int slot, double* sbuf) {
+    block_sum_n<K>(v, sbuf);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[(int64_t)blockIdx.x * SP_PS + slot + k] = v[k];
+    }
+}
+
+// Totals of K partial slots over all workgroups, in a fixed order (lane l
+// takes workgroups l, l+64, ...; then the wave sum).  Every thread gets them.
+template <int K>
+__device__ __forceinline__ void get_parts(const double* part, int slot, double (&out)[K], double* sbuf) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+    for (int k = wave; k < K; k += W) {
+        double s = 0.0;
+        for (int bb = lane; bb < (int)gridDim.x; bb += 64) s += part[(int64_t)bb * SP_PS + slot + k];
+        s = wave_sum(s);
+        if (lane == 0) sbuf[k] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = sbuf[k];
+    __syncthreads();
+}
+
+struct Range { int lo, hi; };
+__device__ __forceinline__ Range my_range(int total) {
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int lo = min(total, (int)blockIdx.x * per);
+    return {lo, min(total, lo + per)};
+}
+
+// ---------------------------------------------------------------------------
+// CG on G a = t, G = I + A A^T, Jacobi preconditioned.  On entry r = t - G a,
+// z = r / diag(G), p = z (stored), and rz, rr, tt = ||t||^2 are the totals.
+// Leaves the border dots of the final a in bd.  Three grid barriers per
+// iteration: q1 = A^T p' (p' = z + beta p formed on the fly), q = p' + A q1
+// with p' stored, then the a / r / z update.
+// ---------------------------------------------------------------------------
+__device__ int cg_loop(const SpArgs& g, double rz, double rr, double tt, double (&bd)[4], double* sbuf,
+                       bool want_bd, int maxit, double tol) {
+    const Range R = my_range(g.m), Cc = my_range(g.n);
+    const int tid = threadIdx.x;
+    const double tol2 = tol * tol * tt;
+    double beta = 0.0;
+    int k = 0;
+    while (k < maxit && rr > tol2 && !grid_failed(g.err)) {
+        // q1_j = sum_i A_ij (z_i + beta p_i) over this workgroup's columns
+        {
+            const int L = g.LT, per = SP_THREADS / L;
+            for (int j0 = Cc.lo; j0 < Cc.hi; j0 += per) {
+                const int j = j0 + tid / L, sub = tid % L;
+                double d = 0.0;
+                if (j < Cc.hi) {
+                    const int kb = g.rpt[j], ke = g.rpt[j + 1];
+                    for (int e = kb + sub; e < ke; e += L) {
+                        const int i = g.cit[e];
+                        d = fma(g.vat[e], fma(beta, g.p[i], g.z[i]), d);
+                    }
+                }
+                d = group_sum(d, L);
+                if (j < Cc.hi && sub == 0) g.q1[j] = d;
+            }
+        }
+        grid_sync(g.bar, g.err);
+        // p_i = z_i + beta p_i, q_i = p_i + (A q1)_i, partial p^T q
+        double pq[1] = {0.0};
+        {
+            const int L = g.LA, per = SP_THREADS / L;
+            for (int i0 = R.lo; i0 < R.hi; i0 += per) {
+                const int i = i0 + tid / L, sub = tid % L;
+                double d = 0.0;
+                if (i < R.hi) {
+                    const int kb = g.rp[i], ke = g.rp[i + 1];
+                    for (int e = kb + sub; e < ke; e += L) d = fma(g.va[e], g.q1[g.ci[e]], d);
+                }
+                d = group_sum(d, L);
+                if (i < R.hi && sub == 0) {
+                    const double pn = fma(beta, g.p[i], g.z[i]);
+                    const double qi = pn + d;
+                    g.p[i] = pn;
+                    g.q[i] = qi;
+                    pq[0] = fma(pn, qi, pq[0]);
+                }
+            }
+        }
+        put_parts<1>(pq, g.part, SP_PQ, sbuf);
+        grid_sync(g.bar, g.err);
+        double tpq[1];
+        get_parts<1>(g.part, SP_PQ, tpq, sbuf);
+        const double al = rz / tpq[0];
+        // a += al p, r -= al q, z = r / diag(G); partial r^T z, r^T r, border dots of a
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = R.lo + tid; i < R.hi; i += SP_THREADS) {
+            const double ai = fma(al, g.p[i], g.a[i]);
+            const double ri = fma(-al, g.q[i], g.r[i]);
+            const double zi = ri / g.dG[i];
+            g.a[i] = ai; g.r[i] = ri; g.z[i] = zi;
+            v[0] = fma(ri, zi, v[0]);
+            v[1] = fma(ri, ri, v[1]);
+            if (want_bd) {
+                v[2] = fma(g.b[i], ai, v[2]);
+                v[3] = fma(g.bbar[i], ai, v[3]);
+                v[4] = fma(g.Ac[i], ai, v[4]);
+                v[5] = fma(g.Acb[i], ai, v[5]);
+            }
+        }
+        put_parts<2>(*reinterpret_cast<double(*)[2]>(v), g.part, SP_CG, sbuf);
+        if (want_bd) put_parts<4>(*reinterpret_cast<double(*)[4]>(v + 2), g.part, SP_BD, sbuf);
+        grid_sync(g.bar, g.err);
+        double t2[2];
+        get_parts<2>(g.part, SP_CG, t2, sbuf);
+        if (want_bd) get_parts<4>(g.part, SP_BD, bd, sbuf);
+        beta = t2[0] / rz;
+        rz = t2[0];
+        rr = t2[1];
+        ++k;
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// the solver
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
+    __shared__ double sbuf[64];
+    const int tid = threadIdx.x;
+    const int m = g.m, n = g.n;
+    const Range R = my_range(m), Cc = my_range(n);
+    const LPCtrl cl = *g.lc;
+    const SolveParams& prm = g.prm;
+    const double alpha = prm.alpha, gamma = prm.gamma, beta = prm.beta, eps = prm.eps;
+    const double zbar = cl.zbar, nb = cl.nb, nc = cl.nc, np1 = (double)n + 1.0;
+    const double sg = sqrt(gamma);
+    double tau = cl.tau, kappa = cl.kappa, theta = cl.theta, mu = cl.mu;
+    int64_t iters = cl.iters, ipm = cl.ipm, cgit = cl.cg, done = 0;
+    int status = 0;
+    int op = OP_REFRESH;
+    const bool check_final_first = (cl.flags & 1) != 0;
+    bool first = true;
+    double p0 = 0.0, p1 = 0.0;
+    double l_ms2 = 0.0, l_cs4 = 0.0, l_tau = 0.0, l_by = cl.by, l_cx = cl.cx;
+    bool l_have = false;
+    const int64_t t_start = wall_clock64();
+
+    while (true) {
+        if (grid_failed(g.err)) { status = -1; break; }
+        const double tmu = mu / beta;
+        // ---- column pass: x, s per op; A^T y of the state; 7 column sums
+        double cs[7] = {0, 0, 0, 0, 0, 0, 0};
+        {
+            const int L = g.LT, per = SP_THREADS / L;
+            const double* V = (op == OP_PROX) ? g.a : g.Y;
+            for (int j0 = Cc.lo; j0 < Cc.hi; j0 += per) {
+                const int j = j0 + tid / L, sub = tid % L;
+                double d = 0.0;
+                if (j < Cc.hi) {
+                    const int kb = g.rpt[j], ke = g.rpt[j + 1];
+                    for (int e = kb + sub; e < ke; e += L) d = fma(g.vat[e], V[g.cit[e]], d);
+                }
+                d = group_sum(d, L);
+                if (j < Cc.hi && sub == 0) {
+                    const double x0 = g.X[j], s0 = g.S[j];
+                    double x1 = x0, s1 = s0, aty;
+                    if (op == OP_PROX) {
+                        // d = (A^T a)_j; u~_x = (x + s) + A^T a - Z_x p (Section 4.4)
+                        const double ut = (x0 + s0) + d - g.Zx0[j] * p0 - g.Zx1[j] * p1;
+                        const double uh = alpha * ut + (1.0 - alpha) * x0;          // Section 4.2
+                        x1 = prox_root(uh - s0, tmu);                               // barrier prox
+                        s1 = s0 - uh + x1;                                          // dual update
+                        // A^T y' with y' = alpha (a - Z_y p) + (1 - alpha) y
+                        aty = alpha * (d - g.ATZy0[j] * p0 - g.ATZy1[j] * p1) + (1.0 - alpha) * g.ATY[j];
+                        g.ATA[j] = d;
+                    } else if (op == OP_RESTART) {
+                        if (prm.restart_rule == 0) {
+                            if (x0 >= s0) s1 = gamma * s0;
+                            else x1 = gamma * x0;
+                            aty = d;
+                        } else {
+                            x1 = sg * x0; s1 = sg * s0;
+                            aty = sg * d;            // y is scaled by sqrt(gamma) in the row pass
+                        }
+                    } else {
+                        aty = d;
+                    }
+                    if (op != OP_REFRESH) { g.X[j] = x1; g.S[j] = s1; }
+                    g.ATY[j] = aty;
+                    const double c0 = g.C[j], cb0 = g.CB[j];
+                    const double r1 = aty + s1 - c0 * tau;
+                    const double r2 = aty + s1;
+                    const double r3 = -aty + c0 * tau - cb0 * theta - s1;
+                    cs[0] = fma(c0, x1, cs[0]);
+                    cs[1] = fma(cb0, x1, cs[1]);
+                    cs[2] = fma(c0, s1, cs[2]);
+                    cs[3] = fma(cb0, s1, cs[3]);
+                    cs[4] = fma(r1, r1, cs[4]);
+                    cs[5] = fma(r2, r2, cs[5]);
+                    cs[6] = fma(r3, r3, cs[6]);
+                }
+            }
+        }
+        if (op == OP_PROX) {         // y' = alpha (a - Z_y p) + (1 - alpha) y on this workgroup's rows
+            for (int i = R.lo + tid; i < R.hi; i += SP_THREADS)
+                g.Y[i] = alpha * (g.a[i] - g.Zy0[i] * p0 - g.Zy1[i] * p1) + (1.0 - alpha) * g.Y[i];
+        }
+        put_parts<7>(cs, g.part, SP_COL, sbuf);
+        const bool was_update = (op == OP_PROX);
+        if (was_update) { ++iters; ++done; }
+        grid_sync(g.bar, g.err);
+
+        // ---- row pass: A x, A s, A (A^T a); row sums; CG right-hand side and start
+        double rs[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        {
+            const int L = g.LA, per = SP_THREADS / L;
+            for (int i0 = R.lo; i0 < R.hi; i0 += per) {
+                const int i = i0 + tid / L, sub = tid % L;
+                double ax = 0.0, as = 0.0, aa = 0.0;
+                if (i < R.hi) {
+                    const int kb = g.rp[i], ke = g.rp[i + 1];
+                    for (int e = kb + sub; e < ke; e += L) {
+                        const int j = g.ci[e];
+                        const double v = g.va[e];
+                        ax = fma(v, g.X[j], ax);
+                        as = fma(v, g.S[j], as);
+                        aa = fma(v, g.ATA[j], aa);
+                    }
+                }
+                ax = group_sum(ax, L);
+                as = group_sum(as, L);
+                aa = group_sum(aa, L);
+                if (i < R.hi && sub == 0) {
+                    double yi = g.Y[i];
+                    if (op == OP_RESTART && prm.restart_rule != 0) { yi *= sg; g.Y[i] = yi; }
+                    const double bi = g.b[i], bbi = g.bbar[i];
+                    const double r1 = ax - bi * tau;
+                    const double r3 = r1 + bbi * theta;
+                    rs[0] = fma(bi, yi, rs[0]);
+                    rs[1] = fma(bbi, yi, rs[1]);
+                    rs[2] = fma(r1, r1, rs[2]);
+                    rs[3] = fma(ax, ax, rs[3]);
+                    rs[4] = fma(r3, r3, rs[4]);
+                    // t = y - A (x + s);  r = t - G a = t - a - A (A^T a)
+                    const double ti = yi - (ax + as);
+                    const double ai = g.a[i];
+                    const double ri = ti - ai - aa;
+                    const double zi = ri / g.dG[i];
+                    g.r[i] = ri; g.z[i] = zi; g.p[i] = zi;
+                    rs[5] = fma(ri, zi, rs[5]);
+                    rs[6] = fma(ri, ri, rs[6]);
+                    rs[7] = fma(ti, ti, rs[7]);
+                    rs[8] = fma(bi, ai, rs[8]);
+                    rs[9] = fma(bbi, ai, rs[9]);
+                    rs[10] = fma(g.Ac[i], ai, rs[10]);
+                    rs[11] = fma(g.Acb[i], ai, rs[11]);
+                }
+            }
+        }
+        put_parts<12>(rs, g.part, SP_ROW, sbuf);
+        grid_sync(g.bar, g.err);
+        double tc[7], tr[12];
+        get_parts<7>(g.part, SP_COL, tc, sbuf);
+        get_parts<12>(g.part, SP_ROW, tr, sbuf);
+        const double cx = tc[0], cbx = tc[1], by = tr[0], bby = tr[1];
+
+        if (g.fixed_iters > 0) {
+            if (done >= g.fixed_iters) break;
+        } else {
+            const bool post_update = was_update || (op == OP_REFRESH && !first) || (first && check_final_first);
+            first = false;
+            if (post_update) {
+                // Section 4.1, multiplied through by tau and squared
+                int st = 0;
+                if (tau > 0.0) {
+                    const double ep = eps * (1.0 + nb) * tau, ed = eps * (1.0 + nc) * tau;
+                    if (tr[2] <= ep * ep && tc[4] <= ed * ed && fabs(cx - by) <= eps * (tau + fabs(cx) + fabs(by)))
+                        st = 1;
+                }
+                if (!st && nb > 0.0 && by > 0.0 && tc[5] * (nb * nb) <= (eps * by) * (eps * by)) st = 2;
+                if (!st && nc > 0.0 && cx < 0.0 && tr[3] * (nc * nc) <= (eps * cx) * (eps * cx)) st = 3;
+                l_ms2 = tr[2]; l_cs4 = tc[4]; l_tau = tau; l_by = by; l_cx = cx; l_have = true;
+                if (st) { status = st; break; }
+            }
+            // inner test ||Q u - v||^2 <= mu (eq. inner-stop)
+            const double rt = by - cx + zbar * theta - kappa;
+            const double rth = -bby + cbx - zbar * tau + np1;
+            const double inner = tr[4] + tc[6] + rt * rt + rth * rth;
+            if (inner <= mu) {
+                mu *= gamma;
+                ++ipm;
+                if (prm.restart_rule == 0) {
+                    if (tau >= kappa) kappa *= gamma;
+                    else tau *= gamma;
+                } else {
+                    tau *= sg; kappa *= sg; theta *= sg;
+                }
+                op = OP_RESTART;
+                continue;
+            }
+            if (iters >= prm.max_iters) { status = 4; break; }
+        }
+
+        // ---- the linear step: G a = t by CG from the previous a
+        double bd[4] = {tr[8], tr[9], tr[10], tr[11]};
+        cgit += cg_loop(g, tr[5], tr[6], tr[7], bd, sbuf, true, g.cg_max, g.cg_tol);
+        if (grid_failed(g.err)) { status = -1; break; }
+        // ---- border (Section 4.4, rank 2) and the tau / kappa / theta update
+        const double cs_f = cx + tc[2];
+        const double cbs_f = cbx + tc[3];
+        const double h1z = -bd[0] + cs_f + bd[2];      // c^T d = c^T f + (A c)^T a
+        const double h2z = bd[1] - cbs_f - bd[3];
+        const double q0 = (tau + kappa) + h1z;
+        const double q1 = (theta - np1) + h2z;
+        p0 = cl.K00 * q0 + cl.K01 * q1;
+        p1 = cl.K10 * q0 + cl.K11 * q1;
+        const double uh_tau = alpha * p0 + (1.0 - alpha) * tau;
+        const double uh_theta = alpha * p1 + (1.0 - alpha) * theta;
+        const double tau1 = prox_root(uh_tau - kappa, tmu);
+        kappa = kappa - uh_tau + tau1;
+        tau = tau1;
+        theta = uh_theta;
+        op = OP_PROX;
+    }
+
+    if (blockIdx.x == 0 && tid == 0) {
+        LPCtrl& o = *g.lc;
+        if (l_have && l_tau > 0.0) {
+            o.pobj = l_cx / l_tau;
+            o.dobj = l_by / l_tau;
+            o.pres = sqrt(l_ms2) / l_tau / (1.0 + nb);
+            o.dres = sqrt(l_cs4) / l_tau / (1.0 + nc);
+            o.gap = fabs(o.pobj - o.dobj) / (1.0 + fabs(o.pobj) + fabs(o.dobj));
+        }
+        o.by = l_by; o.cx = l_cx;
+        o.tau = tau; o.kappa = kappa; o.theta = theta; o.mu = mu;
+        o.iters = iters; o.iters64 = iters; o.ipm = ipm; o.cg = cgit;
+        o.cp64 += done;
+        o.status = (status < 0) ? 0 : status;
+        o.phase = 1;
+        o.mode = OP_REFRESH;
+        o.flags = ((g.fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);
+        o.clk[2] += wall_clock64() - t_start;
+    }
+}
+
+// CG for a right-hand side given at setup (the border columns Z).
+__global__ __launch_bounds__(SP_THREADS) void k_sp_cg(SpArgs g, const double* rhs, double tol, int32_t maxit,
+                                                     int64_t* iters) {
+    __shared__ double sbuf[64];
+    const Range R = my_range(g.m);
+    double v[3] = {0, 0, 0};
+    for (int i = R.lo + threadIdx.x; i < R.hi; i += SP_THREADS) {
+        const double ri = rhs[i];
+        const double zi = ri / g.dG[i];
+        g.a[i] = 0.0; g.r[i] = ri; g.z[i] = zi; g.p[i] = zi;
+        v[0] = fma(ri, zi, v[0]);
+        v[1] = fma(ri, ri, v[1]);
+        v[2] = v[1];
+    }
+    put_parts<3>(v, g.part, SP_CG, sbuf);
+    grid_sync(g.bar, g.err);
+    double t[3];
+    get_parts<3>(g.part, SP_CG, t, sbuf);
+    double bd[4];
+    const int k = cg_loop(g, t[0], t[1], t[2], bd, sbuf, false, maxit, tol);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *iters = k;
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+// flag bits: 1 row pointers, 2 column index out of range, 4 non-finite value
+__global__ void k_sp_check_rows(const int32_t* rp, int32_t m, int64_t nnz, int* flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || (int64_t)rp[m] != nnz)) atomicOr(flag, 1);
+    if (i < m && rp[i] > rp[i + 1]) atomicOr(flag, 1);
+}
+__global__ void k_sp_check_entries(const int32_t* ci, const double* va, int64_t nnz, int32_t n, int* flag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) {
+        const int j = ci[e];
+        if (j < 0 || j >= n) atomicOr(flag, 2);
+        if (!isfinite(va[e])) atomicOr(flag, 4);
+    }
+}
+
+// row pointers first (flag bit 1); the entries only once those are known good
+hipError_t sp_validate_rows(const SpArgs& g, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_check_rows, dim3((g.m + 255) / 256), dim3(256), 0, st, g.rp, g.m, g.nnz, flag);
+    return hipGetLastError();
+}
+hipError_t sp_validate_entries(const SpArgs& g, int* flag, hipStream_t st) {
+    if (g.nnz > 0)
+        hipLaunchKernelGGL(k_sp_check_entries, dim3((unsigned)((g.nnz + 255) / 256)), dim3(256), 0, st, g.ci, g.va,
+                           g.nnz, g.n, flag);
+    return hipGetLastError();
+}
+__global__ void k_sp_finite(const double* v, int64_t len, int* flag, int bit) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len && !isfinite(v[i])) atomicOr(flag, bit);
+}
+hipError_t sp_check_finite(const double* v, int64_t len, int* flag, int bit, hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_finite, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, v, len, flag, bit);
+    return hipGetLastError();
+}
+// out[i] = a x[i] + c (elementwise)
+__global__ void k_sp_affine(const double* x, double a, double c, int64_t len, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) out[i] = a * x[i] + c;
+}
+hipError_t sp_affine(const double* x, double a, double c, int64_t len, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_affine, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, x, a, c, len, out);
+    return hipGetLastError();
+}
+
+// CSR(A^T) from CSR(A): column counts, exclusive scan, scatter, then each
+// column's entries sorted by row index (deterministic layout).
+__global__ void k_sp_count(const int32_t* ci, int64_t nnz, int32_t* cnt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) atomicAdd(&cnt[ci[e]], 1);
+}
+// exclusive scan of cnt[0..n) into rpt[0..n] by one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_sp_scan(const int32_t* cnt, int32_t n, int32_t* rpt) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int lo = min(n, t * per), hi = min(n, lo + per);
+    int64_t s = 0;
+    for (int j = lo; j < hi; ++j) s += cnt[j];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < 1024; ++k) { const int64_t v = part[k]; part[k] = run; run += v; }
+        rpt[n] = (int32_t)run;
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int j = lo; j < hi; ++j) { rpt[j] = (int32_t)run; run += cnt[j]; }
+}
+__global__ void k_sp_scatter(const int32_t* rp, const int32_t* ci, const double* va, int32_t m, int32_t* cursor,
+                             int32_t* cit, double* vat) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int pos = atomicAdd(&cursor[ci[e]], 1);
+        cit[pos] = i;
+        vat[pos] = va[e];
+    }
+}
+__global__ void k_sp_sortseg(const int32_t* rpt, int32_t n, int32_t* cit, double* vat) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int lo = rpt[j], hi = rpt[j + 1];
+    for (int e = lo + 1; e < hi; ++e) {          // insertion sort by row index
+        const int key = cit[e];
+        const double val = vat[e];
+        int f = e - 1;
+        while (f >= lo && (cit[f] > key || (cit[f] == key && vat[f] > val))) {
+            cit[f + 1] = cit[f];
+            vat[f + 1] = vat[f];
+            --f;
+        }
+        cit[f + 1] = key;
+        vat[f + 1] = val;
+    }
+}
+
+hipError_t sp_transpose(SpArgs& g, int32_t* rpt, int32_t* cit, double* vat, int32_t* cursor, hipStream_t st) {
+    hipError_t e;
+    if ((e = hipMemsetAsync(cursor, 0, sizeof(int32_t) * (size_t)g.n, st)) != hipSuccess) return e;
+    if (g.nnz > 0)
+        hipLaunchKernelGGL(k_sp_count, dim3((unsigned)((g.nnz + 255) / 256)), dim3(256), 0, st, g.ci, g.nnz, cursor);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sp_scan, dim3(1), dim3(1024), 0, st, cursor, g.n, rpt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(cursor, rpt, sizeof(int32_t) * (size_t)g.n, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sp_scatter, dim3((g.m + 255) / 256), dim3(256), 0, st, g.rp, g.ci, g.va, g.m, cursor, cit, vat);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sp_sortseg, dim3((g.n + 255) / 256), dim3(256), 0, st, rpt, g.n, cit, vat);
+    return hipGetLastError();
+}
+
+// out = alpha * (M v) + beta * w for a CSR matrix M with `rows` rows (w may be null)
+__global__ void k_sp_spmv(const int32_t* rp, const int32_t* ci, const double* va, int32_t rows, const double* v,
+                          double alpha, const double* w, double beta, double* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    double s = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) s = fma(va[e], v[ci[e]], s);
+    out[i] = alpha * s + (w ? beta * w[i] : 0.0);
+}
+hipError_t sp_spmv(const int32_t* rp, const int32_t* ci, const double* va, int32_t rows, const double* v,
+                   double alpha, const double* w, double beta, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_spmv, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, va, rows, v, alpha, w, beta, out);
+    return hipGetLastError();
+}
+
+__global__ void k_sp_rowsq(const int32_t* rp, const double* va, int32_t m, double* dG) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double s = 1.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) s = fma(va[e], va[e], s);
+    dG[i] = s;
+}
+hipError_t sp_rowsq(const SpArgs& g, double* dG, hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_rowsq, dim3((g.m + 255) / 256), dim3(256), 0, st, g.rp, g.va, g.m, dG);
+    return hipGetLastError();
+}
+
+// partial dot products x . ys[k] per block (nblk blocks, fixed order inside);
+// partial[k * nblk + blk]; the host adds the blocks in order
+__global__ void k_sp_dots(const double* x, const double* const* ys, int ny, int64_t len, double* partial) {
+    __shared__ double sb[8 * 4];
+    for (int k = 0; k < ny; ++k) {
+        double v[1] = {0.0};
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+            v[0] = fma(x[i], ys[k][i], v[0]);
+        block_sum_n<1>(v, sb);
+        if (threadIdx.x == 0) partial[(int64_t)k * gridDim.x + blockIdx.x] = v[0];
+    }
+}
+hipError_t sp_dots(const double* x, const double* const* ys, int ny, int64_t len, double* partial, int nblk,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_dots, dim3(nblk), dim3(256), 0, st, x, ys, ny, len, partial);
+    return hipGetLastError();
+}
+
+int sp_max_blocks(int cu_count) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sp_solve, SP_THREADS, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int per_cu2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_sp_cg, SP_THREADS, 0) == hipSuccess &&
+        per_cu2 >= 1)
+        per_cu = std::min(per_cu, per_cu2);
+    return per_cu * cu_count;
+}
+
+hipError_t sp_cg_solve(SpArgs g, const double* rhs, double* out, double tol, int32_t maxit, int nb,
+                       int64_t* iters, hipStream_t st) {
+    void* args[] = {(void*)&g, (void*)&rhs, (void*)&tol, (void*)&maxit, (void*)&iters};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_sp_cg, dim3(nb), dim3(SP_THREADS), args, 0, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(out, g.a, sizeof(double) * (size_t)g.m, hipMemcpyDeviceToDevice, st);
+}
+
+hipError_t sp_solve(SpArgs g, int nb, hipStream_t st) {
+    void* args[] = {(void*)&g};
+    return hipLaunchCooperativeKernel((const void*)k_sp_solve, dim3(nb), dim3(SP_THREADS), args, 0, st);
+}
