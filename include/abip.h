@@ -91,12 +91,14 @@ typedef struct {
     int32_t engine;            /* ABIP_ENGINE_*; default auto */
     int64_t fp32_max_iters;    /* FP32 phase length cap before the FP64 polish
                                   starts regardless; default 1e6 */
-    double  cg_tol;            /* CG stops when ||r|| <= cg_tol ||rhs|| (sparse engine); default 1e-10 */
+    double  cg_tol;            /* CG stops when ||r|| <= cg_tol ||rhs|| (sparse engine); default 1e-7 */
     int32_t cg_max_iters;      /* per linear solve; default 500 */
     int32_t block_threads;     /* threads per workgroup for ENGINE_WG (256 or 512, honoured when
                                   the largest m <= 256; larger LPs always use 256); 0 = auto */
     double  adjoint_tol;       /* relative residual that stops the adjoint BiCGSTAB; default 1e-12 */
     int64_t adjoint_max_iters; /* default 2e5; 0 contracts one transposed step of dL/dz (testing) */
+    int32_t cg_rule;           /* sparse engine: 0 (default) stops CG at ||r|| <= max(cg_tol ||rhs||,
+                                  0.1 ||Q u - v|| / (1 + k)), k the ADMM count; 1: cg_tol alone */
 } abip_settings;
 
 /* Per-LP result summary (host struct). */
@@ -119,7 +121,10 @@ typedef struct {
     int64_t ticks_total;       /* (one-workgroup engine only; 0 otherwise) */
     int64_t ticks_check;       /* ... in the check sums and tests after each pass over A */
     int64_t ticks_update;      /* ... in the border solve and the y update after each pass over G^{-1} */
-                               /* (sparse engine: colpass_fp64 counts updates; ticks_total only) */
+                               /* sparse engine (workgroup 0): colpass_fp64 counts updates;
+                                  ticks_colpass = column passes (A^T gathers), ticks_ginv = row
+                                  passes (A gathers), ticks_check = grid barriers, ticks_update =
+                                  reductions of the per-workgroup sums */
 } abip_info;
 
 /* A matrix description.  All pointers are device pointers; abip_setup copies

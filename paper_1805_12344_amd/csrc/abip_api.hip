@@ -288,11 +288,12 @@ extern "C" int abip_default_settings(abip_settings* s) {
     s->lin_solver = ABIP_LIN_AUTO;
     s->engine = ABIP_ENGINE_AUTO;
     s->fp32_max_iters = 1000000;
-    s->cg_tol = 1e-10;
+    s->cg_tol = 1e-7;
     s->cg_max_iters = 500;
     s->block_threads = 0;
     s->adjoint_tol = 1e-12;
     s->adjoint_max_iters = 200000;
+    s->cg_rule = 0;
     return ABIP_OK;
 }
 
@@ -306,6 +307,7 @@ static int check_settings(const abip_settings& s) {
         return fail(ABIP_E_INVALID, "settings.restart_rule: unknown value %d", s.restart_rule);
     if (s.precision != ABIP_PREC_FP64 && s.precision != ABIP_PREC_FP32_POLISH)
         return fail(ABIP_E_INVALID, "settings.precision: unknown value %d", s.precision);
+    if (s.cg_rule != 0 && s.cg_rule != 1) return fail(ABIP_E_INVALID, "settings.cg_rule must be 0 or 1");
     if (s.block_threads != 0 && s.block_threads != 256 && s.block_threads != 512)
         return fail(ABIP_E_INVALID, "settings.block_threads must be 0, 256 or 512");
     return ABIP_OK;
@@ -533,9 +535,9 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
 // ---------------------------------------------------------------------------
 // sparse engine: setup and run
 // ---------------------------------------------------------------------------
-static int lanes_for(double avg) {           // lanes per CSR row: about 3 entries per lane
+static int lanes_for(double avg) {           // lanes per CSR row: about 4 entries per lane (one gather round)
     int L = 1;
-    while (L < 64 && 3.0 * L < avg) L *= 2;
+    while (L < 64 && 4.0 * L < avg) L *= 2;
     return L;
 }
 
@@ -585,7 +587,7 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
 #define SCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return bail(fail(ABIP_E_HIP, "%s: %s", #call, hipGetErrorString(e_))); } while (0)
     const int64_t nidx = (int64_t)(m + 1) + nnz + (n + 1) + nnz + n;
     const int NBLK = 64;
-    const int64_t nvec = 6 * (int64_t)d.ld + 5 * (int64_t)w->Ntot + (int64_t)SP_PS * 4 * w->cu_count;
+    const int64_t nvec = 7 * (int64_t)d.ld + 5 * (int64_t)w->Ntot + (int64_t)SP_PS * 4 * w->cu_count;
     SALLOC(w->ddesc, 1); SALLOC(w->dctrl, 1);
     SALLOC(w->Mv, (int64_t)NMF * w->Mtot); SALLOC(w->Nv, (int64_t)NNF * w->Ntot);
     SALLOC(w->errflag, 1); SALLOC(w->outp, 3);
@@ -608,6 +610,7 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     double* V = w->sp_vec;
     double* dG = V; V += d.ld;
     g.a = V; V += d.ld; g.r = V; V += d.ld; g.z = V; V += d.ld; g.p = V; V += d.ld; g.q = V; V += d.ld;
+    g.sv = V; V += d.ld;
     double* ATZy0 = V; V += w->Ntot;
     double* ATZy1 = V; V += w->Ntot;
     g.ATY = V; V += w->Ntot; g.ATA = V; V += w->Ntot; g.q1 = V; V += w->Ntot;
@@ -684,13 +687,11 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     // for H1 = (-b; c) and H2 = (bbar; -cbar), by CG to near machine precision
     const int maxb = std::min(sp_max_blocks(w->cu_count), 4 * w->cu_count);
     w->sp_nb = std::max(1, std::min<int>(maxb, (int)std::min<int64_t>(w->cu_count, (std::max<int64_t>(m, n) + 255) / 256)));
-    double* rhs = g.q;                                                         // m scratch until the solve
-    SCHK(sp_spmv(rp, ci, va, m, fC, -1.0, fb, -1.0, g.r, st));               // -b - A c  (into r, then copied)
-    SCHK(hipMemcpyAsync(rhs, g.r, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    double* rhs = g.Y;                                                         // scratch until the solve
     const int32_t bmax = std::max<int32_t>(5000, 20 * s.cg_max_iters);
+    SCHK(sp_spmv(rp, ci, va, m, fC, -1.0, fb, -1.0, rhs, st));               // -b - A c
     SCHK(sp_cg_solve(g, rhs, fZy0, 1e-14, bmax, w->sp_nb, w->sp_cgit, st));
-    SCHK(sp_spmv(rp, ci, va, m, fCB, 1.0, fbb, 1.0, g.r, st));               // bbar + A cbar
-    SCHK(hipMemcpyAsync(rhs, g.r, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    SCHK(sp_spmv(rp, ci, va, m, fCB, 1.0, fbb, 1.0, rhs, st));               // bbar + A cbar
     SCHK(sp_cg_solve(g, rhs, fZy1, 1e-14, bmax, w->sp_nb, w->sp_cgit, st));
     SCHK(sp_spmv(rpt, cit, vat, n, fZy0, 1.0, nullptr, 0.0, ATZy0, st));     // A^T Z_y0
     SCHK(sp_spmv(rpt, cit, vat, n, fZy1, 1.0, nullptr, 0.0, ATZy1, st));     // A^T Z_y1
@@ -743,6 +744,7 @@ static int sparse_run(abip_work* w, int64_t fixed) {
     g.prm = make_params(w->set);
     g.cg_tol = w->set.cg_tol;
     g.cg_max = w->set.cg_max_iters;
+    g.cg_rule = w->set.cg_rule;
     g.fixed_iters = fixed;
     if (fixed == 0) {          // a fresh solve starts CG from a = 0 (reproducible runs)
         HIPCHK(hipMemsetAsync(g.a, 0, sizeof(double) * (size_t)g.m, st));

@@ -47,20 +47,22 @@ __device__ __forceinline__ void grid_sync(unsigned* bar, int* err) {
     if (threadIdx.x == 0) {
         unsigned* cnt = bar;
         unsigned* gen = bar + 1;
-        __threadfence();
-        const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();                   // release this workgroup's writes
+        const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned arrived = atomicAdd(cnt, 1u);
         if (arrived == gridDim.x - 1) {
             __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
+            // relaxed polls (an acquire per poll would invalidate this XCD's L2
+            // under the workgroups still computing); one acquire fence after
             int polls = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++polls > (1 << 22)) { atomicExch(err, 1); break; }
             }
         }
-        __threadfence();
+        __threadfence();                   // acquire the other workgroups' writes
     }
     __syncthreads();
 }
@@ -96,6 +98,35 @@ __device__ __forceinline__ void get_parts(const double* part, int slot, double (
     __syncthreads();
 }
 
+// Sums over one CSR row of val[e] * f(idx[e]) (NV sums, f returns NV values)
+// for e = kb+sub, kb+sub+L, ... < ke, in that order, four entries per round so
+// that their index / value loads and the gathers behind them are in flight
+// together.  Entries past ke read index 0 with weight 0.
+template <int NV, typename F>
+__device__ __forceinline__ void row_sums(const int32_t* idx, const double* val, int kb, int ke, int sub, int L,
+                                         F f, double (&out)[NV]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+    for (int e = kb + sub; e < ke; e += 4 * L) {
+        int ii[4];
+        double ww[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int eu = e + u * L;
+            const bool ok = eu < ke;
+            ii[u] = ok ? idx[eu] : 0;
+            ww[u] = ok ? val[eu] : 0.0;
+        }
+        double fv[4][NV];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f(ii[u], fv[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v] = fma(ww[u], fv[u][v], out[v]);
+    }
+}
+
 struct Range { int lo, hi; };
 __device__ __forceinline__ Range my_range(int total) {
     const int per = (total + gridDim.x - 1) / gridDim.x;
@@ -104,92 +135,105 @@ __device__ __forceinline__ Range my_range(int total) {
 }
 
 // ---------------------------------------------------------------------------
-// CG on G a = t, G = I + A A^T, Jacobi preconditioned.  On entry r = t - G a,
-// z = r / diag(G), p = z (stored), and rz, rr, tt = ||t||^2 are the totals.
-// Leaves the border dots of the final a in bd.  Three grid barriers per
-// iteration: q1 = A^T p' (p' = z + beta p formed on the fly), q = p' + A q1
-// with p' stored, then the a / r / z update.
+// CG on G a = t, G = I + A A^T, Jacobi preconditioned, in the Chronopoulos-Gear
+// arrangement (both inner products of an iteration come out of one
+// reduction), with the vector recurrences folded into the gathers so that an
+// iteration needs two grid barriers:
+//   P1 (columns):  u' = (r - al (w + be s)) / diag(G) formed on the fly,
+//                  q1 = A^T u'                                   -> barrier
+//   P2 (rows):     p = u + be p, s = w + be s, a += al p, r -= al s,
+//                  u = r / diag(G), w = u + A q1 (= G u),
+//                  partial (r,u), (w,u), (r,r), border dots of a  -> barrier
+//   then every workgroup forms be = g'/g, al = g' / (d - be g' / al).
+// On entry (set by the caller) r = t - G a, u = 0, w = 0, s = 0, p = 0, and
+// al = be = 0, so the first P1/P2 pair computes u0 = r / diag(G), w0 = G u0.
+// Returns the number of updates of a.
 // ---------------------------------------------------------------------------
-__device__ int cg_loop(const SpArgs& g, double rz, double rr, double tt, double (&bd)[4], double* sbuf,
-                       bool want_bd, int maxit, double tol) {
+__device__ int cg_loop(const SpArgs& g, double rr, double tol2, double (&bd)[4], double* sbuf, bool want_bd,
+                       int maxit, int64_t (&tk)[4]) {
     const Range R = my_range(g.m), Cc = my_range(g.n);
     const int tid = threadIdx.x;
-    const double tol2 = tol * tol * tt;
-    double beta = 0.0;
-    int k = 0;
-    while (k < maxit && rr > tol2 && !grid_failed(g.err)) {
-        // q1_j = sum_i A_ij (z_i + beta p_i) over this workgroup's columns
+    double al = 0.0, be = 0.0, gam_old = 1.0;
+    int k = -1;                     // -1: the start-up pair (no update of a yet)
+    while (k < maxit && (k < 0 || rr > tol2) && !grid_failed(g.err)) {
+        int64_t t0 = wall_clock64();
+        // P1: q1_j = sum_i A_ij u'_i
         {
             const int L = g.LT, per = SP_THREADS / L;
             for (int j0 = Cc.lo; j0 < Cc.hi; j0 += per) {
                 const int j = j0 + tid / L, sub = tid % L;
                 double d = 0.0;
                 if (j < Cc.hi) {
-                    const int kb = g.rpt[j], ke = g.rpt[j + 1];
-                    for (int e = kb + sub; e < ke; e += L) {
-                        const int i = g.cit[e];
-                        d = fma(g.vat[e], fma(beta, g.p[i], g.z[i]), d);
-                    }
+                    // u' with the same arithmetic as P2, so q1 = A^T u exactly for the stored u
+                    double o[1];
+                    row_sums<1>(g.cit, g.vat, g.rpt[j], g.rpt[j + 1], sub, L,
+                                [&](int i, double* fv) {
+                                    fv[0] = fma(-al, fma(be, g.sv[i], g.q[i]), g.r[i]) / g.dG[i];
+                                }, o);
+                    d = o[0];
                 }
                 d = group_sum(d, L);
                 if (j < Cc.hi && sub == 0) g.q1[j] = d;
             }
         }
+        int64_t t1 = wall_clock64();
+        tk[0] += t1 - t0;
         grid_sync(g.bar, g.err);
-        // p_i = z_i + beta p_i, q_i = p_i + (A q1)_i, partial p^T q
-        double pq[1] = {0.0};
+        t0 = wall_clock64();
+        tk[2] += t0 - t1;
+        // P2: this workgroup's rows
+        double v[7] = {0, 0, 0, 0, 0, 0, 0};
         {
             const int L = g.LA, per = SP_THREADS / L;
             for (int i0 = R.lo; i0 < R.hi; i0 += per) {
                 const int i = i0 + tid / L, sub = tid % L;
                 double d = 0.0;
                 if (i < R.hi) {
-                    const int kb = g.rp[i], ke = g.rp[i + 1];
-                    for (int e = kb + sub; e < ke; e += L) d = fma(g.va[e], g.q1[g.ci[e]], d);
+                    double o[1];
+                    row_sums<1>(g.ci, g.va, g.rp[i], g.rp[i + 1], sub, L,
+                                [&](int jj, double* fv) { fv[0] = g.q1[jj]; }, o);
+                    d = o[0];
                 }
                 d = group_sum(d, L);
                 if (i < R.hi && sub == 0) {
-                    const double pn = fma(beta, g.p[i], g.z[i]);
-                    const double qi = pn + d;
-                    g.p[i] = pn;
-                    g.q[i] = qi;
-                    pq[0] = fma(pn, qi, pq[0]);
+                    const double pi = fma(be, g.p[i], g.z[i]);
+                    const double si = fma(be, g.sv[i], g.q[i]);
+                    const double ai = fma(al, pi, g.a[i]);
+                    const double ri = fma(-al, si, g.r[i]);
+                    const double ui = ri / g.dG[i];
+                    const double wi = ui + d;
+                    g.p[i] = pi; g.sv[i] = si; g.a[i] = ai; g.r[i] = ri; g.z[i] = ui; g.q[i] = wi;
+                    v[0] = fma(ri, ui, v[0]);
+                    v[1] = fma(wi, ui, v[1]);
+                    v[2] = fma(ri, ri, v[2]);
+                    if (want_bd) {
+                        v[3] = fma(g.b[i], ai, v[3]);
+                        v[4] = fma(g.bbar[i], ai, v[4]);
+                        v[5] = fma(g.Ac[i], ai, v[5]);
+                        v[6] = fma(g.Acb[i], ai, v[6]);
+                    }
                 }
             }
         }
-        put_parts<1>(pq, g.part, SP_PQ, sbuf);
+        put_parts<3>(*reinterpret_cast<double(*)[3]>(v), g.part, SP_CG, sbuf);
+        if (want_bd) put_parts<4>(*reinterpret_cast<double(*)[4]>(v + 3), g.part, SP_BD, sbuf);
+        t1 = wall_clock64();
+        tk[1] += t1 - t0;
         grid_sync(g.bar, g.err);
-        double tpq[1];
-        get_parts<1>(g.part, SP_PQ, tpq, sbuf);
-        const double al = rz / tpq[0];
-        // a += al p, r -= al q, z = r / diag(G); partial r^T z, r^T r, border dots of a
-        double v[6] = {0, 0, 0, 0, 0, 0};
-        for (int i = R.lo + tid; i < R.hi; i += SP_THREADS) {
-            const double ai = fma(al, g.p[i], g.a[i]);
-            const double ri = fma(-al, g.q[i], g.r[i]);
-            const double zi = ri / g.dG[i];
-            g.a[i] = ai; g.r[i] = ri; g.z[i] = zi;
-            v[0] = fma(ri, zi, v[0]);
-            v[1] = fma(ri, ri, v[1]);
-            if (want_bd) {
-                v[2] = fma(g.b[i], ai, v[2]);
-                v[3] = fma(g.bbar[i], ai, v[3]);
-                v[4] = fma(g.Ac[i], ai, v[4]);
-                v[5] = fma(g.Acb[i], ai, v[5]);
-            }
-        }
-        put_parts<2>(*reinterpret_cast<double(*)[2]>(v), g.part, SP_CG, sbuf);
-        if (want_bd) put_parts<4>(*reinterpret_cast<double(*)[4]>(v + 2), g.part, SP_BD, sbuf);
-        grid_sync(g.bar, g.err);
-        double t2[2];
-        get_parts<2>(g.part, SP_CG, t2, sbuf);
+        t0 = wall_clock64();
+        tk[2] += t0 - t1;
+        double t3[3];
+        get_parts<3>(g.part, SP_CG, t3, sbuf);
         if (want_bd) get_parts<4>(g.part, SP_BD, bd, sbuf);
-        beta = t2[0] / rz;
-        rz = t2[0];
-        rr = t2[1];
+        tk[3] += wall_clock64() - t0;
+        const double gam = t3[0], del = t3[1];
+        rr = t3[2];
+        if (k < 0) { be = 0.0; al = gam / del; }
+        else { be = gam / gam_old; al = gam / (del - be * gam / al); }
+        gam_old = gam;
         ++k;
     }
-    return k;
+    return k < 0 ? 0 : k;
 }
 
 // ---------------------------------------------------------------------------
@@ -215,11 +259,13 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
     double l_ms2 = 0.0, l_cs4 = 0.0, l_tau = 0.0, l_by = cl.by, l_cx = cl.cx;
     bool l_have = false;
     const int64_t t_start = wall_clock64();
+    int64_t tk[4] = {0, 0, 0, 0};      // ticks: column passes, row passes, barriers, reductions
 
     while (true) {
         if (grid_failed(g.err)) { status = -1; break; }
         const double tmu = mu / beta;
         // ---- column pass: x, s per op; A^T y of the state; 7 column sums
+        int64_t ta = wall_clock64();
         double cs[7] = {0, 0, 0, 0, 0, 0, 0};
         {
             const int L = g.LT, per = SP_THREADS / L;
@@ -228,8 +274,10 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
                 const int j = j0 + tid / L, sub = tid % L;
                 double d = 0.0;
                 if (j < Cc.hi) {
-                    const int kb = g.rpt[j], ke = g.rpt[j + 1];
-                    for (int e = kb + sub; e < ke; e += L) d = fma(g.vat[e], V[g.cit[e]], d);
+                    double o[1];
+                    row_sums<1>(g.cit, g.vat, g.rpt[j], g.rpt[j + 1], sub, L,
+                                [&](int i, double* fv) { fv[0] = V[i]; }, o);
+                    d = o[0];
                 }
                 d = group_sum(d, L);
                 if (j < Cc.hi && sub == 0) {
@@ -279,7 +327,11 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
         put_parts<7>(cs, g.part, SP_COL, sbuf);
         const bool was_update = (op == OP_PROX);
         if (was_update) { ++iters; ++done; }
+        int64_t tb = wall_clock64();
+        tk[0] += tb - ta;
         grid_sync(g.bar, g.err);
+        ta = wall_clock64();
+        tk[2] += ta - tb;
 
         // ---- row pass: A x, A s, A (A^T a); row sums; CG right-hand side and start
         double rs[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -289,14 +341,10 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
                 const int i = i0 + tid / L, sub = tid % L;
                 double ax = 0.0, as = 0.0, aa = 0.0;
                 if (i < R.hi) {
-                    const int kb = g.rp[i], ke = g.rp[i + 1];
-                    for (int e = kb + sub; e < ke; e += L) {
-                        const int j = g.ci[e];
-                        const double v = g.va[e];
-                        ax = fma(v, g.X[j], ax);
-                        as = fma(v, g.S[j], as);
-                        aa = fma(v, g.ATA[j], aa);
-                    }
+                    double o[3];
+                    row_sums<3>(g.ci, g.va, g.rp[i], g.rp[i + 1], sub, L,
+                                [&](int j, double* fv) { fv[0] = g.X[j]; fv[1] = g.S[j]; fv[2] = g.ATA[j]; }, o);
+                    ax = o[0]; as = o[1]; aa = o[2];
                 }
                 ax = group_sum(ax, L);
                 as = group_sum(as, L);
@@ -316,9 +364,8 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
                     const double ti = yi - (ax + as);
                     const double ai = g.a[i];
                     const double ri = ti - ai - aa;
-                    const double zi = ri / g.dG[i];
-                    g.r[i] = ri; g.z[i] = zi; g.p[i] = zi;
-                    rs[5] = fma(ri, zi, rs[5]);
+                    g.r[i] = ri; g.z[i] = 0.0; g.q[i] = 0.0; g.sv[i] = 0.0; g.p[i] = 0.0;
+                    rs[5] = 0.0;
                     rs[6] = fma(ri, ri, rs[6]);
                     rs[7] = fma(ti, ti, rs[7]);
                     rs[8] = fma(bi, ai, rs[8]);
@@ -329,10 +376,15 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
             }
         }
         put_parts<12>(rs, g.part, SP_ROW, sbuf);
+        tb = wall_clock64();
+        tk[1] += tb - ta;
         grid_sync(g.bar, g.err);
+        ta = wall_clock64();
+        tk[2] += ta - tb;
         double tc[7], tr[12];
         get_parts<7>(g.part, SP_COL, tc, sbuf);
         get_parts<12>(g.part, SP_ROW, tr, sbuf);
+        tk[3] += wall_clock64() - ta;
         const double cx = tc[0], cbx = tc[1], by = tr[0], bby = tr[1];
 
         if (g.fixed_iters > 0) {
@@ -373,8 +425,18 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
         }
 
         // ---- the linear step: G a = t by CG from the previous a
+        // stop at ||r|| <= max(cg_tol ||t||, 0.1 ||Q u - v|| / (1 + k)) (rule 0) or at the
+        // relative floor alone (rule 1)
+        double tol2 = g.cg_tol * g.cg_tol * tr[7];
+        if (g.cg_rule == 0 && g.fixed_iters == 0) {
+            const double rt = by - cx + zbar * theta - kappa;
+            const double rth = -bby + cbx - zbar * tau + np1;
+            const double inner = tr[4] + tc[6] + rt * rt + rth * rth;
+            const double sched = 0.01 * inner / ((1.0 + (double)iters) * (1.0 + (double)iters));
+            tol2 = fmax(tol2, sched);
+        }
         double bd[4] = {tr[8], tr[9], tr[10], tr[11]};
-        cgit += cg_loop(g, tr[5], tr[6], tr[7], bd, sbuf, true, g.cg_max, g.cg_tol);
+        cgit += cg_loop(g, tr[6], tol2, bd, sbuf, true, g.cg_max, tk);
         if (grid_failed(g.err)) { status = -1; break; }
         // ---- border (Section 4.4, rank 2) and the tau / kappa / theta update
         const double cs_f = cx + tc[2];
@@ -412,6 +474,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
         o.mode = OP_REFRESH;
         o.flags = ((g.fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);
         o.clk[2] += wall_clock64() - t_start;
+        o.clk[0] += tk[0]; o.clk[1] += tk[1]; o.clk[3] += tk[2]; o.clk[4] += tk[3];
     }
 }
 
@@ -420,21 +483,20 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_cg(SpArgs g, const double* rh
                                                      int64_t* iters) {
     __shared__ double sbuf[64];
     const Range R = my_range(g.m);
-    double v[3] = {0, 0, 0};
+    double v[2] = {0, 0};
     for (int i = R.lo + threadIdx.x; i < R.hi; i += SP_THREADS) {
         const double ri = rhs[i];
-        const double zi = ri / g.dG[i];
-        g.a[i] = 0.0; g.r[i] = ri; g.z[i] = zi; g.p[i] = zi;
-        v[0] = fma(ri, zi, v[0]);
-        v[1] = fma(ri, ri, v[1]);
-        v[2] = v[1];
+        g.a[i] = 0.0; g.r[i] = ri; g.z[i] = 0.0; g.q[i] = 0.0; g.sv[i] = 0.0; g.p[i] = 0.0;
+        v[0] = fma(ri, ri, v[0]);
     }
-    put_parts<3>(v, g.part, SP_CG, sbuf);
+    v[1] = v[0];
+    put_parts<2>(v, g.part, SP_CG, sbuf);
     grid_sync(g.bar, g.err);
-    double t[3];
-    get_parts<3>(g.part, SP_CG, t, sbuf);
+    double t[2];
+    get_parts<2>(g.part, SP_CG, t, sbuf);
     double bd[4];
-    const int k = cg_loop(g, t[0], t[1], t[2], bd, sbuf, false, maxit, tol);
+    int64_t tk[4] = {0, 0, 0, 0};
+    const int k = cg_loop(g, t[0], tol * tol * t[1], bd, sbuf, false, maxit, tk);
     if (blockIdx.x == 0 && threadIdx.x == 0) *iters = k;
 }
 

@@ -26,15 +26,17 @@ struct SpArgs {
     // state and work vectors (written during the solve)
     double *Y, *X, *S;                   // iterate (Y: m, X, S: n)
     double *ATY, *ATA;                   // n: A^T y of the current iterate, A^T a of the last solve
-    double *a, *r, *z, *p, *q;           // m: CG solution (warm start) and work vectors
+    double *a, *r, *z, *p, *q, *sv;      // m: CG solution (warm start) and work vectors
+                                         //    (z = u, q = w = G u, sv = s = G p)
     double *q1;                          // n: A^T p
     double* part;                        // gridDim.x * SP_PS partial sums
     unsigned* bar;                       // grid barrier: counter, generation
     int* err;                            // set when a grid barrier times out
     LPCtrl* lc;                          // scalars in / out
     SolveParams prm;
-    double cg_tol;                       // stop CG when ||r|| <= cg_tol ||t||
+    double cg_tol;                       // relative floor: stop CG when ||r|| <= cg_tol ||t||
     int32_t cg_max;
+    int32_t cg_rule;                     // 0: also stop at 0.1 ||Q u - v|| / (1 + k); 1: floor only
     int64_t fixed_iters;                 // > 0: exactly this many updates, no tests or restarts
 };
 

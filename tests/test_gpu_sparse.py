@@ -21,7 +21,7 @@ def _csr(lp):
 
 
 def _tight(**kw):
-    return abip.abip_default_settings(cg_tol=1e-13, cg_max_iters=2000, **kw)
+    return abip.abip_default_settings(cg_tol=1e-13, cg_max_iters=2000, cg_rule=1, **kw)
 
 
 @pytest.mark.parametrize("m,n,seed,density", [(40, 90, 1, 0.08), (150, 420, 2, 0.02), (600, 1700, 3, 0.004)])
