@@ -99,6 +99,10 @@ typedef struct {
     int64_t adjoint_max_iters; /* default 2e5; 0 contracts one transposed step of dL/dz (testing) */
     int32_t cg_rule;           /* sparse engine: 0 (default) stops CG at ||r|| <= max(cg_tol ||rhs||,
                                   0.1 ||Q u - v|| / (1 + k)), k the ADMM count; 1: cg_tol alone */
+    int32_t use_graph;         /* 1 (default): the dense engines replay hipGraphs (the batched
+                                  solve's launches; chunks of 16 iterations of the grid engine),
+                                  captured at the first solve of a handle and kept with it;
+                                  0: plain stream launches.  Results are bitwise the same. */
 } abip_settings;
 
 /* Per-LP result summary (host struct). */

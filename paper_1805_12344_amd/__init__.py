@@ -38,7 +38,7 @@ class abip_settings(ctypes.Structure):
         ("fp32_max_iters", ctypes.c_int64), ("cg_tol", ctypes.c_double),
         ("cg_max_iters", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("adjoint_tol", ctypes.c_double), ("adjoint_max_iters", ctypes.c_int64),
-        ("cg_rule", ctypes.c_int32),
+        ("cg_rule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
     ]
 
 

@@ -258,6 +258,13 @@ struct abip_work {
     unsigned* sp_bar = nullptr;      // grid barrier words
     int* sp_err = nullptr;
     int64_t* sp_cgit = nullptr;
+    // hipGraphs (captured on a private stream joined to the caller's by events)
+    hipStream_t gstream = nullptr;
+    hipEvent_t gjoin0 = nullptr, gjoin1 = nullptr;
+    hipGraph_t ggraph = nullptr; hipGraphExec_t gexec = nullptr;    // grid engine: 16 iterations
+    std::vector<char> gkey;
+    hipGraph_t wgraph = nullptr; hipGraphExec_t wexec = nullptr;    // batched solve launch
+    std::vector<char> wkey;
 };
 
 static void release(abip_work* w) {
@@ -271,6 +278,13 @@ static void release(abip_work* w) {
     (void)hipFree(w->gbuf); (void)hipFree(w->gctl);
     (void)hipFree(w->sp_idx); (void)hipFree(w->sp_val); (void)hipFree(w->sp_vec);
     (void)hipFree(w->sp_bar); (void)hipFree(w->sp_err); (void)hipFree(w->sp_cgit);
+    if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
+    if (w->ggraph) (void)hipGraphDestroy(w->ggraph);
+    if (w->wexec) (void)hipGraphExecDestroy(w->wexec);
+    if (w->wgraph) (void)hipGraphDestroy(w->wgraph);
+    if (w->gjoin0) (void)hipEventDestroy(w->gjoin0);
+    if (w->gjoin1) (void)hipEventDestroy(w->gjoin1);
+    if (w->gstream) (void)hipStreamDestroy(w->gstream);
     if (w->ev0) (void)hipEventDestroy(w->ev0);
     if (w->ev1) (void)hipEventDestroy(w->ev1);
 }
@@ -294,6 +308,7 @@ extern "C" int abip_default_settings(abip_settings* s) {
     s->adjoint_tol = 1e-12;
     s->adjoint_max_iters = 200000;
     s->cg_rule = 0;
+    s->use_graph = 1;
     return ABIP_OK;
 }
 
@@ -308,6 +323,7 @@ static int check_settings(const abip_settings& s) {
     if (s.precision != ABIP_PREC_FP64 && s.precision != ABIP_PREC_FP32_POLISH)
         return fail(ABIP_E_INVALID, "settings.precision: unknown value %d", s.precision);
     if (s.cg_rule != 0 && s.cg_rule != 1) return fail(ABIP_E_INVALID, "settings.cg_rule must be 0 or 1");
+    if (s.use_graph != 0 && s.use_graph != 1) return fail(ABIP_E_INVALID, "settings.use_graph must be 0 or 1");
     if (s.block_threads != 0 && s.block_threads != 256 && s.block_threads != 512)
         return fail(ABIP_E_INVALID, "settings.block_threads must be 0, 256 or 512");
     return ABIP_OK;
@@ -371,10 +387,51 @@ static int grid_prepare(abip_work* w) {
     return ABIP_OK;
 }
 
+// Private capture stream (default priority) and the events that join it to
+// the caller's stream, created on first use.
+static int graph_stream(abip_work* w) {
+    if (!w->gstream) HIPCHK(hipStreamCreateWithFlags(&w->gstream, hipStreamNonBlocking));
+    if (!w->gjoin0) HIPCHK(hipEventCreateWithFlags(&w->gjoin0, hipEventDisableTiming));
+    if (!w->gjoin1) HIPCHK(hipEventCreateWithFlags(&w->gjoin1, hipEventDisableTiming));
+    return ABIP_OK;
+}
+
+template <typename T>
+static std::vector<char> key_bytes(const T& v, int extra) {
+    std::vector<char> k(sizeof(T) + sizeof(int));
+    memcpy(k.data(), &v, sizeof(T));
+    memcpy(k.data() + sizeof(T), &extra, sizeof(int));
+    return k;
+}
+
+// Capture `body` (stream launches only: no memsets, no host copies) into *graph /
+// *exec on the private stream, unless the key matches the cached capture.
+template <typename F>
+static int capture_graph(abip_work* w, hipGraph_t* graph, hipGraphExec_t* exec, std::vector<char>* cached,
+                         const std::vector<char>& key, F body) {
+    if (*exec && *cached == key) return ABIP_OK;
+    if (*exec) { (void)hipGraphExecDestroy(*exec); *exec = nullptr; }
+    if (*graph) { (void)hipGraphDestroy(*graph); *graph = nullptr; }
+    HIPCHK(hipStreamBeginCapture(w->gstream, hipStreamCaptureModeThreadLocal));
+    const hipError_t eb = body(w->gstream);
+    hipGraph_t gr = nullptr;
+    const hipError_t ee = hipStreamEndCapture(w->gstream, &gr);
+    if (eb != hipSuccess) { if (gr) (void)hipGraphDestroy(gr); return fail(ABIP_E_HIP, "graph capture: %s", hipGetErrorString(eb)); }
+    if (ee != hipSuccess) return fail(ABIP_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    *graph = gr;
+    HIPCHK(hipGraphInstantiate(exec, gr, nullptr, nullptr, 0));
+    *cached = key;
+    return ABIP_OK;
+}
+
+static const int GRAPH_ITERS = 16;   // grid-engine iterations per captured graph
+
 // Drive the grid engine: chunks of iterations, then a look at the status.
 static int grid_run(abip_work* w, int64_t fixed, int phase) {
     hipStream_t st = w->stream;
-    GridArgs g = w->ga;
+    GridArgs g;
+    memset(&g, 0, sizeof g);                  // padding bytes take part in the graph key
+    g = w->ga;
     g.prm = make_params(w->set);
     if (fixed > 0) {
         const LPDesc& d0 = w->hdesc[0];
@@ -388,13 +445,41 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
     if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
     HIPCHK(hipEventRecord(w->ev0, st));
     GridCtl hc;
-    int chunk = 16;
-    while (true) {
-        for (int i = 0; i < chunk; ++i) HIPCHK(grid_launch_iteration(w->grid_nchw, g, st));
-        HIPCHK(hipMemcpyAsync(&hc, w->gctl, sizeof hc, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (hc.status != 0) break;
-        if (chunk < 256) chunk *= 2;
+    if (w->set.use_graph) {
+        // the iteration kernels take the same arguments every time (state lives in
+        // the device control block): 16 iterations as one graph, replayed
+        int rc = graph_stream(w);
+        if (rc) return rc;
+        const int nchw = w->grid_nchw;
+        rc = capture_graph(w, &w->ggraph, &w->gexec, &w->gkey, key_bytes(g, nchw), [&](hipStream_t cs) {
+            for (int i = 0; i < GRAPH_ITERS; ++i) {
+                const hipError_t e = grid_launch_iteration(nchw, g, cs);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        });
+        if (rc) return rc;
+        int reps = 1;
+        while (true) {
+            HIPCHK(hipEventRecord(w->gjoin0, st));
+            HIPCHK(hipStreamWaitEvent(w->gstream, w->gjoin0, 0));
+            for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(w->gexec, w->gstream));
+            HIPCHK(hipEventRecord(w->gjoin1, w->gstream));
+            HIPCHK(hipStreamWaitEvent(st, w->gjoin1, 0));
+            HIPCHK(hipMemcpyAsync(&hc, w->gctl, sizeof hc, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (hc.status != 0) break;
+            if (reps < 16) reps *= 2;
+        }
+    } else {
+        int chunk = 16;
+        while (true) {
+            for (int i = 0; i < chunk; ++i) HIPCHK(grid_launch_iteration(w->grid_nchw, g, st));
+            HIPCHK(hipMemcpyAsync(&hc, w->gctl, sizeof hc, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (hc.status != 0) break;
+            if (chunk < 256) chunk *= 2;
+        }
     }
     HIPCHK(hipEventRecord(w->ev1, st));
     const LPDesc& d = w->hdesc[0];
@@ -790,10 +875,35 @@ static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParam
     hipStream_t st = w->stream;
     const int per_cu = (wg_smem_bytes(w->ldmax, w->threads / 64) <= 76 * 1024 && w->threads <= 512) ? 2 : 1;
     const int grid = std::max(1, std::min<int>(B, w->cu_count * per_cu));
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, w->queue);
-    HIPCHK(hipGetLastError());
     if (!w->ev0) HIPCHK(hipEventCreate(&w->ev0));
     if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
+    if (w->set.use_graph && fixed_iters == 0 && B == w->B) {
+        // queue reset + the persistent launch as one graph, kept with the handle
+        int rc = graph_stream(w);
+        if (rc) return rc;
+        struct Key { SolveParams p; int threads, grid; } key;
+        memset(&key, 0, sizeof key);          // padding bytes take part in the comparison
+        key.p = prm; key.threads = w->threads; key.grid = grid;
+        const PoolPtrs P = pools(w);
+        rc = capture_graph(w, &w->wgraph, &w->wexec, &w->wkey, key_bytes(key, B), [&](hipStream_t cs) {
+            hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, cs, w->queue);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return launch_solve_wg(w->nch, grid, w->threads, cs, w->ddesc, w->dctrl, P, prm, w->order, B, w->queue,
+                                   0, w->ldmax);
+        });
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(w->gjoin0, st));
+        HIPCHK(hipStreamWaitEvent(w->gstream, w->gjoin0, 0));
+        HIPCHK(hipEventRecord(w->ev0, w->gstream));
+        HIPCHK(hipGraphLaunch(w->wexec, w->gstream));
+        HIPCHK(hipEventRecord(w->ev1, w->gstream));
+        HIPCHK(hipEventRecord(w->gjoin1, w->gstream));
+        HIPCHK(hipStreamWaitEvent(st, w->gjoin1, 0));
+        return ABIP_OK;
+    }
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, w->queue);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(w->ev0, st));
     HIPCHK(launch_solve_wg(w->nch, grid, w->threads, st, w->ddesc, w->dctrl, pools(w), prm, w->order, B, w->queue,
                            fixed_iters, w->ldmax));
