@@ -234,6 +234,21 @@ int abip_get_state(abip_work* w, int32_t k, double* y, double* x, double* s, dou
  * on LP k, without tests or restarts (FP64 data unless use_fp32 != 0). */
 int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_fp32);
 
+/* Launch-configuration autotuner (project extension).  Runs `iters` ADMM
+ * updates from Algorithm 2's start point with each candidate configuration of
+ * the handle's engine, timed with HIP events on the work stream, and keeps the
+ * fastest for later solves: one-workgroup engine 256 or 512 threads (LPs with
+ * m <= 256; larger ones have the single 256 candidate), grid engine about
+ * 0.5 / 1 / 2 / 4 workgroups per CU, sparse engine 32 / 64 / 128 / 256
+ * workgroups (up to what can be co-resident).  ms (host, may be NULL) receives
+ * the time of each candidate (up to max_cand), *ncand their number, *chosen
+ * the kept value (threads or workgroups); both may be NULL.  The iterate is
+ * reset to the start point.  A configuration change can change the last bits
+ * of later results (sums are reduced in a different fixed order), not their
+ * correctness. */
+int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t max_cand, int32_t* ncand,
+                  int32_t* chosen);
+
 /* Release everything owned by the handle.  NULL is accepted. */
 int abip_free(abip_work* w);
 

@@ -73,6 +73,7 @@ EXPORTS = [
     "abip_default_settings", "abip_setup", "abip_setup_batch", "abip_solve", "abip_solve_batch",
     "abip_backward", "abip_backward_batch", "abip_apply_iq", "abip_set_state", "abip_get_state",
     "abip_iterate", "abip_free", "abip_last_error", "abip_version", "abip_backward_stats",
+    "abip_autotune",
 ]
 
 
@@ -106,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.abip_free.argtypes = [P]
     lib.abip_backward_stats.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
+    lib.abip_autotune.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.abip_last_error.restype = ctypes.c_char_p
     lib.abip_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -322,6 +325,16 @@ def abip_get_state(w: Work, k: int):
 
 def abip_iterate(w: Work, k: int, iters: int, use_fp32: bool = False):
     _check(lib().abip_iterate(w.handle, k, int(iters), int(use_fp32)))
+
+
+def abip_autotune(w: Work, iters: int = 50):
+    """Try the engine's launch configurations for `iters` updates each; keep the fastest.
+    Returns dict(chosen=threads-or-workgroups, ms=[time per candidate])."""
+    ms = (ctypes.c_double * 8)()
+    nc = ctypes.c_int32()
+    ch = ctypes.c_int32()
+    _check(lib().abip_autotune(w.handle, int(iters), ms, 8, ctypes.byref(nc), ctypes.byref(ch)))
+    return dict(chosen=ch.value, ms=[ms[i] for i in range(min(8, nc.value))])
 
 
 def abip_free(w: Work):

@@ -244,6 +244,7 @@ struct abip_work {
     // grid engine (one LP over the whole GPU)
     bool grid = false;
     int grid_nchw = 1;
+    int grid_wgs = 0;                // workgroups per grid kernel (autotuned)
     GridArgs ga{};
     double* gbuf = nullptr;          // Y2, Pf, Px, pcol, prow, pa, t, a
     GridCtl* gctl = nullptr;         // 2 control blocks
@@ -347,33 +348,46 @@ static const int MAX_WG_M = 1024;   // largest m the one-workgroup engine holds 
 static const int MAX_GRID_M = 8192; // 4 row chunks of 256 per wave, 8 waves
 static const int64_t GRID_AUTO_MN = 4 * 1024 * 1024;   // one LP this large goes to the grid engine
 
-static int grid_prepare(abip_work* w) {
+// Column / row split of the grid engine for about `wgs` workgroups per kernel
+// (columns per workgroup a multiple of 8); the partial buffers are sized for
+// up to 4 workgroups per CU.
+static void grid_config(abip_work* w, int wgs) {
     const LPDesc& d = w->hdesc[0];
     GridArgs& g = w->ga;
-    g.m = d.m; g.n = d.n; g.ld = d.ld;
-    int cw = (d.n + w->cu_count - 1) / w->cu_count;
+    const int cap = 4 * w->cu_count;
+    wgs = std::max(1, std::min(wgs, cap));
+    int cw = (d.n + wgs - 1) / wgs;
     cw = ((cw + 7) / 8) * 8;
     g.cw = cw;
     g.NB = (d.n + cw - 1) / cw;
     g.NR = (d.ld + 255) / 256;
-    int gw = (d.m + w->cu_count - 1) / w->cu_count;
+    int gw = (d.m + wgs - 1) / wgs;
     gw = ((gw + 7) / 8) * 8;
     g.gw = gw;
     g.NG = (d.m + gw - 1) / gw;
-    w->grid_nchw = grid_nchw(d.ld);
-    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * (int64_t)g.NB * d.ld + 8 * (int64_t)g.NB + 8 * (int64_t)g.NR +
-                         4 * (int64_t)g.NG + 2 * (int64_t)d.ld;
-    HIPCHK(hipMalloc((void**)&w->gbuf, sizeof(double) * nbuf));
-    HIPCHK(hipMalloc((void**)&w->gctl, sizeof(GridCtl) * 2));
     double* p = w->gbuf;
     g.Y2 = p; p += 2 * d.ld;
-    g.Pf = p; p += (int64_t)g.NB * d.ld;
-    g.Px = p; p += (int64_t)g.NB * d.ld;
-    g.pcol = p; p += 8 * g.NB;
-    g.prow = p; p += 8 * g.NR;
-    g.pa = p; p += 4 * g.NG;
+    g.Pf = p; p += (int64_t)cap * d.ld;
+    g.Px = p; p += (int64_t)cap * d.ld;
+    g.pcol = p; p += 8 * (int64_t)cap;
+    g.prow = p; p += 8 * (int64_t)g.NR;
+    g.pa = p; p += 4 * (int64_t)cap;
     g.t = p; p += d.ld;
     g.a = p; p += d.ld;
+    w->grid_wgs = wgs;
+}
+
+static int grid_prepare(abip_work* w) {
+    const LPDesc& d = w->hdesc[0];
+    GridArgs& g = w->ga;
+    g.m = d.m; g.n = d.n; g.ld = d.ld;
+    w->grid_nchw = grid_nchw(d.ld);
+    const int64_t cap = 4 * (int64_t)w->cu_count;
+    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * cap * d.ld + 8 * cap + 8 * (int64_t)((d.ld + 255) / 256) +
+                         4 * cap + 2 * (int64_t)d.ld;
+    HIPCHK(hipMalloc((void**)&w->gbuf, sizeof(double) * nbuf));
+    HIPCHK(hipMalloc((void**)&w->gctl, sizeof(GridCtl) * 2));
+    grid_config(w, w->cu_count);
     g.A64 = w->A64 + d.oA; g.A32 = w->A32 + d.oA;
     g.G64 = w->G64 + d.oG; g.G32 = w->G32 + d.oG;
     g.b = w->Mv + MF_B * w->Mtot + d.om; g.bbar = w->Mv + MF_BBAR * w->Mtot + d.om;
@@ -1154,6 +1168,68 @@ extern "C" int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_
     (void)hipFree(ord1);
     if (e != hipSuccess) return fail(ABIP_E_HIP, "abip_iterate launch: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(ABIP_E_HIP, "abip_iterate: %s", hipGetErrorString(e2));
+    return ABIP_OK;
+}
+
+// Launch-configuration autotuner: every candidate runs `iters` updates from
+// Algorithm 2's start point (fixed-iteration mode, no tests), timed with HIP
+// events on the work stream; the fastest is kept and the iterate is reset.
+extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t max_cand, int32_t* ncand,
+                             int32_t* chosen) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_autotune: null handle");
+    if (iters < 1) return fail(ABIP_E_INVALID, "abip_autotune: iters must be >= 1");
+    std::vector<int> cand;
+    if (w->sparse) {
+        const int maxb = std::min(sp_max_blocks(w->cu_count), 4 * w->cu_count);
+        for (int nb : {32, 64, 128, 256})
+            if (nb <= maxb) cand.push_back(nb);
+        if (cand.empty()) cand.push_back(maxb);
+    } else if (w->grid) {
+        for (int f : {1, 2, 4, 8}) cand.push_back(w->cu_count * f / 2);
+    } else {
+        cand.push_back(256);
+        if (w->nch == 1) cand.push_back(512);
+    }
+    const int phase = (w->set.precision == ABIP_PREC_FP32_POLISH && !w->sparse) ? 0 : 1;
+    const SolveParams prm = make_params(w->set);
+    hipStream_t st = w->stream;
+    auto configure = [&](int c) -> int {
+        if (w->sparse) { w->sp_nb = c; return ABIP_OK; }
+        if (w->grid) { grid_config(w, c); return ABIP_OK; }
+        w->threads = c;
+        const hipError_t e = set_solve_wg_smem_limit(wg_smem_bytes(w->ldmax, w->threads / 64));
+        if (e != hipSuccess) return fail(ABIP_E_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+        return ABIP_OK;
+    };
+    auto reset = [&]() -> int {
+        hipLaunchKernelGGL(k_init_state, dim3(w->B), dim3(256), 0, st, w->ddesc, w->dctrl, w->Mv, w->Nv, w->Mtot,
+                           w->Ntot, w->set.beta, phase);
+        HIPCHK(hipGetLastError());
+        return ABIP_OK;
+    };
+    double best = 1e300;
+    int bi = 0;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        int rc = configure(cand[i]);
+        if (rc) return rc;
+        rc = reset();
+        if (rc) return rc;
+        rc = w->sparse ? sparse_run(w, iters) : w->grid ? grid_run(w, iters, phase) : run_wg(w, w->B, iters, prm);
+        if (rc) return rc;
+        HIPCHK(hipStreamSynchronize(st));
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, w->ev0, w->ev1));
+        if (ms && (int32_t)i < max_cand) ms[i] = t;
+        if (t < best) { best = t; bi = (int)i; }
+    }
+    int rc = configure(cand[bi]);
+    if (rc) return rc;
+    rc = reset();
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    w->solved = false;
+    if (ncand) *ncand = (int32_t)cand.size();
+    if (chosen) *chosen = cand[bi];
     return ABIP_OK;
 }
 
