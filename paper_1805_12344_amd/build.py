@@ -32,7 +32,7 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source into libabip.so (always recompiles)."""
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *sources(), "-o", tmp]
+           *sources(), "-o", tmp, "-lrocblas", "-lrocsolver"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

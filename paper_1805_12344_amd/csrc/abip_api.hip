@@ -20,6 +20,8 @@ hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const
                            const PoolPtrs& P, const SolveParams& prm, const int32_t* order, int32_t B,
                            int32_t* queue, int64_t fixed_iters, int32_t ldmax);
 size_t wg_smem_bytes(int ldmax, int W);
+int lib_setup_one(const LPDesc& d, const LPDesc* ddesc, const double* A64, double* G64, float* G32, double* Mv,
+                  double* Nv, int64_t Mtot, int64_t Ntot, LPCtrl* dctrl, hipStream_t st);
 struct AdjArgs {
     double* ws;
     const int64_t* ows;
@@ -360,7 +362,7 @@ static void grid_config(abip_work* w, int wgs) {
     cw = ((cw + 7) / 8) * 8;
     g.cw = cw;
     g.NB = (d.n + cw - 1) / cw;
-    g.NR = (d.ld + 255) / 256;
+    g.NR = (d.ld + 31) / 32;       // rows per workgroup of k_grid_red
     int gw = (d.m + wgs - 1) / wgs;
     gw = ((gw + 7) / 8) * 8;
     g.gw = gw;
@@ -383,7 +385,7 @@ static int grid_prepare(abip_work* w) {
     g.m = d.m; g.n = d.n; g.ld = d.ld;
     w->grid_nchw = grid_nchw(d.ld);
     const int64_t cap = 4 * (int64_t)w->cu_count;
-    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * cap * d.ld + 8 * cap + 8 * (int64_t)((d.ld + 255) / 256) +
+    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * cap * d.ld + 8 * cap + 8 * (int64_t)((d.ld + 31) / 32) +
                          4 * cap + 2 * (int64_t)d.ld;
     HIPCHK(hipMalloc((void**)&w->gbuf, sizeof(double) * nbuf));
     HIPCHK(hipMalloc((void**)&w->gctl, sizeof(GridCtl) * 2));
@@ -603,14 +605,22 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     hipLaunchKernelGGL(k_setup_rows, dim3(maxrowblk, B), dim3(256), 0, st, w->ddesc, dbp, dcp, w->A64, w->Mv, w->Nv,
                        w->Mtot, w->Ntot, w->errflag);
     SCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_syrk, dim3(maxsyrk, B), dim3(256), 0, st, w->ddesc, w->A64, w->G64);
-    SCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_chol_inv, dim3(B), dim3(256), 0, st, w->ddesc, w->G64, w->G32, Wp, doW, w->errflag);
-    SCHK(hipGetLastError());
-    for (int sgn = 1; sgn >= -1; sgn -= 2) {
-        hipLaunchKernelGGL(k_setup_border, dim3(B), dim3(512), sizeof(double) * 2 * w->ldmax, st, w->ddesc, w->A64,
-                           w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, w->dctrl, sgn);
+    if (w->grid) {
+        // one large LP: library SYRK / POTRF / POTRI and GEMV border
+        const int lrc = lib_setup_one(w->hdesc[0], w->ddesc, w->A64, w->G64, w->G32, w->Mv, w->Nv, w->Mtot,
+                                      w->Ntot, w->dctrl, st);
+        if (lrc == 2) return bail(fail(ABIP_E_HIP, "Cholesky of I + A A^T met a non-positive pivot"));
+        if (lrc) return bail(fail(ABIP_E_HIP, "rocBLAS / rocSOLVER setup of G = I + A A^T failed"));
+    } else {
+        hipLaunchKernelGGL(k_syrk, dim3(maxsyrk, B), dim3(256), 0, st, w->ddesc, w->A64, w->G64);
         SCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_chol_inv, dim3(B), dim3(256), 0, st, w->ddesc, w->G64, w->G32, Wp, doW, w->errflag);
+        SCHK(hipGetLastError());
+        for (int sgn = 1; sgn >= -1; sgn -= 2) {
+            hipLaunchKernelGGL(k_setup_border, dim3(B), dim3(512), sizeof(double) * 2 * w->ldmax, st, w->ddesc,
+                               w->A64, w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, w->dctrl, sgn);
+            SCHK(hipGetLastError());
+        }
     }
     int hflag = 0;
     SCHK(hipMemcpyAsync(&hflag, w->errflag, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -23,6 +23,7 @@
 
 #define GRID_W 8               // waves per workgroup (512 threads)
 #define GRID_UNR 8             // columns per step in the column kernels
+#define GRID_RED_ROWS 32       // rows per workgroup of the partial-sum reduction
 
 // Border, scalars and y' of a pending update, computed identically by every
 // workgroup from the published partial dots.
@@ -252,27 +253,48 @@ __global__ __launch_bounds__(512) void k_grid_col(GridArgs g) {
 // ---------------------------------------------------------------------------
 // k_grid_red: rows
 // ---------------------------------------------------------------------------
+// 32 rows per workgroup, 8 thread groups per row sum every 8th partial (4 per
+// round so the loads overlap), then the 8 group sums are added in order.
 __global__ __launch_bounds__(256) void k_grid_red(GridArgs g) {
     __shared__ double sbuf[8 * 8];
+    __shared__ double sf[8][GRID_RED_ROWS], sx[8][GRID_RED_ROWS];
     const GridCtl c = *g.ctl;
     if (c.status != 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ld = g.ld, m = g.m;
+    const int r = threadIdx.x % GRID_RED_ROWS, grp = threadIdx.x / GRID_RED_ROWS;
+    const int i = blockIdx.x * GRID_RED_ROWS + r;
+    const int ld = g.ld, m = g.m, NB = g.NB;
+    double f = 0.0, x = 0.0;
+    if (i < ld) {
+        int q = grp;
+        for (; q + 24 < NB; q += 32) {
+            const double f0 = g.Pf[(int64_t)q * ld + i], f1 = g.Pf[(int64_t)(q + 8) * ld + i];
+            const double f2 = g.Pf[(int64_t)(q + 16) * ld + i], f3 = g.Pf[(int64_t)(q + 24) * ld + i];
+            const double x0 = g.Px[(int64_t)q * ld + i], x1 = g.Px[(int64_t)(q + 8) * ld + i];
+            const double x2 = g.Px[(int64_t)(q + 16) * ld + i], x3 = g.Px[(int64_t)(q + 24) * ld + i];
+            f += f0; f += f1; f += f2; f += f3;
+            x += x0; x += x1; x += x2; x += x3;
+        }
+        for (; q < NB; q += 8) { f += g.Pf[(int64_t)q * ld + i]; x += g.Px[(int64_t)q * ld + i]; }
+    }
+    sf[grp][r] = f;
+    sx[grp][r] = x;
+    __syncthreads();
     const double* y = g.Y2 + (int64_t)(1 - c.ybuf) * ld;    // y of the new state
     const double tau = c.tau_n, theta = c.theta_n;
     double ms[5] = {0, 0, 0, 0, 0};
-    if (i < ld) {
-        double f = 0.0, x = 0.0;
-        for (int q = 0; q < g.NB; ++q) { f += g.Pf[(int64_t)q * ld + i]; x += g.Px[(int64_t)q * ld + i]; }
-        g.t[i] = (i < m) ? y[i] - f : 0.0;
+    if (grp == 0 && i < ld) {
+        double F = 0.0, X = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) { F += sf[k][r]; X += sx[k][r]; }
+        g.t[i] = (i < m) ? y[i] - F : 0.0;
         if (i < m) {
             const double bi = g.b[i], bbi = g.bbar[i], yi = y[i];
-            const double r1 = x - bi * tau;
+            const double r1 = X - bi * tau;
             const double r3 = r1 + bbi * theta;
             ms[0] = bi * yi;
             ms[1] = bbi * yi;
             ms[2] = r1 * r1;
-            ms[3] = x * x;
+            ms[3] = X * X;
             ms[4] = r3 * r3;
         }
     }
