@@ -84,9 +84,17 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
     const int j_end = min(n, j_begin + g.cw);
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     T va[U][R], vb[U][R];
+    // per-column data of a group, loaded with it by lanes u < U (lane u: column
+    // col0 + u; the other lanes load a valid neighbour and ignore it)
+    struct ColData { double x, s, z0, z1, c, cb; };
+    ColData da_, db_;
     // unmasked loads from clamped addresses: rows past ld have zero weights,
     // columns past j_end are skipped with a uniform test in step()
     const int rl = min(lane * 4, ld - 4);
+    auto load_cols = [&](int col0, ColData& cd) {
+        const int j = min(col0 + (lane < U ? lane : 0), j_end - 1);
+        cd.x = g.X[j]; cd.s = g.S[j]; cd.z0 = g.Zx0[j]; cd.z1 = g.Zx1[j]; cd.c = g.C[j]; cd.cb = g.CB[j];
+    };
     auto load = [&](int col0, T (&v)[U][R]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -108,7 +116,7 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
             }
         }
     };
-    auto step = [&](int col0, T (&v)[U][R]) {
+    auto step = [&](int col0, T (&v)[U][R], const ColData& cd) {
         // partial dots over this wave's rows, reduced over the wave, then over waves
         double dots[2 * U];
 #pragma unroll
@@ -122,10 +130,15 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
             dots[2 * u] = da;
             dots[2 * u + 1] = dy;
         }
-        wave_sum_n<2 * U>(dots);
-#pragma unroll
-        for (int k = 0; k < 2 * U; ++k)
-            if (lane == k) sd[wave * 2 * U + k] = dots[k];
+        // reduce-scatter: lanes u*LPC .. u*LPC+LPC-1 end with column u's (A^T a, A^T y')
+        // over this wave's rows
+        constexpr int LPC = 64 / U;
+        wave_rs<2 * U, 2>(dots);
+        if ((lane % LPC) == 0) {
+            const int u = lane / LPC;
+            sd[wave * 2 * U + 2 * u] = dots[0];
+            sd[wave * 2 * U + 2 * u + 1] = dots[1];
+        }
         __syncthreads();
         if (threadIdx.x < U) {
             const int u = threadIdx.x;
@@ -134,10 +147,10 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
             for (int w = 0; w < GRID_W; ++w) { ata += sd[w * 2 * U + 2 * u]; aty += sd[w * 2 * U + 2 * u + 1]; }
             double x1 = 0.0, s1 = 0.0;
             if (j < j_end) {
-                const double x0 = g.X[j], s0 = g.S[j];
+                const double x0 = cd.x, s0 = cd.s;
                 x1 = x0; s1 = s0;
                 if (prox) {
-                    const double ut = (x0 + s0) + ata - g.Zx0[j] * p0 - g.Zx1[j] * p1;
+                    const double ut = (x0 + s0) + ata - cd.z0 * p0 - cd.z1 * p1;
                     const double uh = alpha * ut + (1.0 - alpha) * x0;
                     x1 = prox_root(uh - s0, tmu);
                     s1 = s0 - uh + x1;
@@ -150,7 +163,7 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
                     }
                 }
                 if (op != OP_REFRESH) { g.X[j] = x1; g.S[j] = s1; }
-                const double c0 = g.C[j], cb0 = g.CB[j];
+                const double c0 = cd.c, cb0 = cd.cb;
                 const double r1 = aty + s1 - c0 * tau;
                 const double r2 = aty + s1;
                 const double r3 = -aty + c0 * tau - cb0 * theta - s1;
@@ -178,15 +191,15 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
         }
     };
     int c0 = j_begin;
-    if (c0 < j_end) load(c0, va);
+    if (c0 < j_end) { load(c0, va); load_cols(c0, da_); }
     while (c0 < j_end) {
         const int c1 = c0 + U;
-        if (c1 < j_end) load(c1, vb);
-        step(c0, va);
+        if (c1 < j_end) { load(c1, vb); load_cols(c1, db_); }
+        step(c0, va, da_);
         if (c1 >= j_end) break;
         const int c2 = c1 + U;
-        if (c2 < j_end) load(c2, va);
-        step(c1, vb);
+        if (c2 < j_end) { load(c2, va); load_cols(c2, da_); }
+        step(c1, vb, db_);
         c0 = c2;
     }
     // partial m-vectors of this workgroup
@@ -340,10 +353,8 @@ __device__ void grid_ginv_body(const GridArgs& g, const T* __restrict__ G, doubl
             }
             dots[u] = s;
         }
-        wave_sum_n<U>(dots);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (lane == u) sd[wave * U + u] = dots[u];
+        wave_rs<U, 1>(dots);                          // lanes 8u..8u+7: column u of this wave
+        if ((lane & 7) == 0) sd[wave * U + (lane >> 3)] = dots[0];
         __syncthreads();
         if (threadIdx.x < U) {
             const int j = col0 + threadIdx.x;
