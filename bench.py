@@ -162,6 +162,106 @@ def cpu_baseline(lps, gpu_iters, sample_idx, iters_each=12000):
                       f"{wall:.1f} s of CPU work"}
 
 
+def extra_basis_pursuit(abip, torch):
+    """Basis pursuit LP, A = [A0, -A0] with A0 2000 x 8000 Gaussian/sqrt(2000), 5% sparse x_true,
+    seed 2: one LP on the whole GPU (grid engine), FP32 bulk + FP64 polish."""
+    import lpgen
+    lp = lpgen.basis_pursuit(2000, 8000, 400, 2)
+    A = torch.tensor(lp["A"], device="cuda")
+    b = torch.tensor(lp["b"], device="cuda")
+    c = torch.tensor(lp["c"], device="cuda")
+    torch.cuda.synchronize()
+    s = abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH)
+    t0 = time.perf_counter()
+    w = abip.abip_setup(A, b, c, s)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    tune = abip.abip_autotune(w, 30)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, y, sv, info = abip.abip_solve(w)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    xh, yh, sh = x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy()
+    pres = np.linalg.norm(lp["A"] @ xh - lp["b"]) / (1 + np.linalg.norm(lp["b"]))
+    dres = np.linalg.norm(lp["A"].T @ yh + sh - lp["c"]) / (1 + np.linalg.norm(lp["c"]))
+    po, do = float(lp["c"] @ xh), float(lp["b"] @ yh)
+    gap = abs(po - do) / (1 + abs(po) + abs(do))
+    m, n = 2000, 16000
+    it32 = info["admm_iters"] - info["admm_iters_fp64"]
+    it64 = info["admm_iters_fp64"]
+    # per update: A once (m n) and G^{-1} once (m^2), plus 8 doubles per column
+    byts = info["colpass_fp32"] * (4.0 * m * n + 64.0 * n) + info["colpass_fp64"] * (8.0 * m * n + 64.0 * n) \
+        + it32 * 4.0 * m * m + it64 * 8.0 * m * m
+    ach = byts / (info["kernel_ms"] / 1e3) / 1e9
+    w.free()
+    return {"workload": "basis pursuit LP 2000 x 16000 (A = [A0, -A0]), seed 2, eps 1e-6, fp32 bulk + fp64 polish",
+            "status": info["status_name"], "admm_iters": info["admm_iters"], "admm_iters_fp64": it64,
+            "setup_ms": setup_ms, "solve_s": solve_s, "admm_iters_per_s": info["admm_iters"] / solve_s,
+            "us_per_iter": info["kernel_ms"] * 1e3 / max(1, info["admm_iters"]),
+            "host_kkt": [pres, dres, gap], "pobj": po, "pstar": lp["pstar"],
+            "autotune": tune, "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                           "frac": ach / HBM_PEAK_GBS, "kernel": "grid engine (col + G^-1 + reductions)"}}
+
+
+def extra_sparse(abip, torch):
+    """Sparse NETLIB-sized LP 10000 x 30000, ~0.1% U(-1,1) plus a diagonal block, seed 1, CG path, FP64."""
+    import lpgen
+    import scipy.sparse as sp
+    lp = lpgen.sparse_planted(10000, 30000, 1, density=1e-3)
+    A = lp["A_csr"]
+    As = sp.csr_matrix((A["data"], A["indices"], A["indptr"]), shape=A["shape"])
+    s = abip.abip_default_settings()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w = abip.abip_setup(As, lp["b"], lp["c"], s)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    x, y, sv, info = abip.abip_solve(w)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    xh, yh, sh = x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy()
+    pres = np.linalg.norm(As @ xh - lp["b"]) / (1 + np.linalg.norm(lp["b"]))
+    dres = np.linalg.norm(As.T @ yh + sh - lp["c"]) / (1 + np.linalg.norm(lp["c"]))
+    po, do = float(lp["c"] @ xh), float(lp["b"] @ yh)
+    gap = abs(po - do) / (1 + abs(po) + abs(do))
+    it = max(1, info["admm_iters"])
+    w.free()
+    return {"workload": "sparse planted LP 10000 x 30000, nnz %d, seed 1, eps 1e-6, CG on I + A A^T, fp64" % lp["nnz"],
+            "status": info["status_name"], "admm_iters": info["admm_iters"], "cg_iters": info["cg_iters"],
+            "setup_ms": setup_ms, "solve_s": solve_s, "admm_iters_per_s": info["admm_iters"] / solve_s,
+            "us_per_iter": info["kernel_ms"] * 1e3 / it, "us_per_cg_iter": info["kernel_ms"] * 1e3 / max(1, info["cg_iters"]),
+            "host_kkt": [pres, dres, gap], "pobj": po, "pstar": lp["pstar"]}
+
+
+def extra_differentiable(abip, torch):
+    """64 LPs 200 x 500, seed 4, FP32 forward; adjoint backward of L = w^T x* per LP."""
+    import lpgen
+    lps = lpgen.diff_batch(64, 200, 500, 4)
+    As = [torch.tensor(lp["A"], device="cuda") for lp in lps]
+    bs = [torch.tensor(lp["b"], device="cuda") for lp in lps]
+    cs = [torch.tensor(lp["c"], device="cuda") for lp in lps]
+    ws = [torch.tensor(lp["w"], device="cuda") for lp in lps]
+    s = abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w = abip.abip_setup_batch(As, bs, cs, s)
+    xs, ys, ss, infos = abip.abip_solve_batch(w)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dcs, dbs, _ = abip.abip_backward_batch(w, ws)
+    torch.cuda.synchronize()
+    bwd = time.perf_counter() - t0
+    ok = sum(1 for i in infos if i["status"] == abip.ABIP_SOLVED)
+    finite = sum(1 for dc, db in zip(dcs, dbs) if bool(torch.isfinite(dc).all()) and bool(torch.isfinite(db).all()))
+    w.free()
+    return {"workload": "64 LPs 200 x 500, seed 4, L = w^T x*, fp32 bulk + fp64 polish forward, adjoint backward",
+            "solved": ok, "finite_gradients": finite, "forward_s": fwd, "backward_s": bwd,
+            "backward_over_forward": bwd / fwd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +271,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the basis-pursuit, sparse and differentiable extra measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (PMC byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -277,6 +379,13 @@ def main():
         gpu_iters64 = it64
     else:
         gpu_iters64 = iters
+
+    if not args.no_extra:
+        for key, fn in [("basis_pursuit", extra_basis_pursuit), ("sparse_cg", extra_sparse),
+                        ("differentiable", extra_differentiable)]:
+            t0 = time.perf_counter()
+            line[key] = fn(abip, torch)
+            log(f"{key}: {time.perf_counter() - t0:.1f} s")
 
     if not args.no_cpu:
         rng = np.random.default_rng(1)

@@ -848,17 +848,32 @@ __device__ void adjoint_one(int k, const LPDesc& d, const LPCtrl* __restrict__ c
     __threadfence_block();
     __syncthreads();
     const double gnorm = sqrt(adj_dot(Rv, Rv, Nz, sh));
-    double rho = 1.0, al = 1.0, om = 1.0, rel = 0.0;
+    double rho = 1.0, al = 1.0, om = 1.0, rel = 1.0;
+    double rr = gnorm * gnorm;                  // ||r||^2
     int64_t it = 0;
+    bool restart = false;
     if (gnorm > 0.0) {
         for (it = 1; it <= aa.max_iters; ++it) {
-            const double rho1 = adj_dot(R0, Rv, Nz, sh);
+            double rho1 = adj_dot(R0, Rv, Nz, sh);
+            // breakdown of the two-sided recurrence (r0^ orthogonal to r, or a zero /
+            // non-finite step): restart with the current residual as the shadow
+            if (restart || !(fabs(rho1) > 0.0) || !isfinite(rho1)) {
+                restart = false;
+                for (int i = tid; i < Nz; i += blockDim.x) { R0[i] = Rv[i]; Pv[i] = 0.0; V[i] = 0.0; }
+                __threadfence_block();
+                __syncthreads();
+                rho1 = rr;
+                rho = 1.0; al = 1.0; om = 1.0;
+            }
             const double beta = (rho1 / rho) * (al / om);
             for (int i = tid; i < Nz; i += blockDim.x) Pv[i] = Rv[i] + beta * (Pv[i] - om * V[i]);
             __threadfence_block();
             __syncthreads();
             adj_op(d, cl, P, sh, Pv, V, WX, Dv, WB, alpha);
-            al = rho1 / adj_dot(R0, V, Nz, sh);
+            const double rv = adj_dot(R0, V, Nz, sh);
+            if (!(fabs(rv) > 0.0) || !isfinite(rv)) { restart = true; continue; }
+            al = rho1 / rv;
+            if (!isfinite(al)) { restart = true; continue; }
             for (int i = tid; i < Nz; i += blockDim.x) Sv[i] = Rv[i] - al * V[i];
             __threadfence_block();
             __syncthreads();
@@ -871,16 +886,18 @@ __device__ void adjoint_one(int k, const LPDesc& d, const LPCtrl* __restrict__ c
             adj_op(d, cl, P, sh, Sv, Tv, WX, Dv, WB, alpha);
             const double tt = adj_dot(Tv, Tv, Nz, sh);
             const double ts = adj_dot(Tv, Sv, Nz, sh);
-            om = (tt > 0.0) ? ts / tt : 0.0;
+            om = (tt > 0.0 && isfinite(ts / tt)) ? ts / tt : 0.0;     // 0: half step, then restart
             for (int i = tid; i < Nz; i += blockDim.x) {
                 LAM[i] += al * Pv[i] + om * Sv[i];
                 Rv[i] = Sv[i] - om * Tv[i];
             }
             __threadfence_block();
             __syncthreads();
-            rel = sqrt(adj_dot(Rv, Rv, Nz, sh)) / gnorm;
-            if (rel <= aa.tol || om == 0.0) break;
+            rr = adj_dot(Rv, Rv, Nz, sh);
+            rel = sqrt(rr) / gnorm;
+            if (rel <= aa.tol) break;
             rho = rho1;
+            if (om == 0.0) restart = true;         // stagnation
         }
     }
     __threadfence_block();
