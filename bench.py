@@ -36,7 +36,8 @@ PMC_TRAFFIC = {
     "6066efb0078a615a": {"fetch_kib": 1022203647.4, "write_kib": 20961532.4,
                          "fetch_scale": 1048576.0 / 524315.4, "write_scale": 1.0},
 }
-KERNEL_SOURCES = ["paper_1805_12344_amd/csrc/abip_solve_wg.hip", "paper_1805_12344_amd/csrc/abip_internal.h"]
+KERNEL_SOURCES = ["paper_1805_12344_amd/csrc/abip_solve_wg.hip", "paper_1805_12344_amd/csrc/abip_small.h",
+                  "paper_1805_12344_amd/csrc/abip_internal.h"]
 
 
 def kernel_hash():

@@ -103,6 +103,12 @@ typedef struct {
                                   solve's launches; chunks of 16 iterations of the grid engine),
                                   captured at the first solve of a handle and kept with it;
                                   0: plain stream launches.  Results are bitwise the same. */
+    int32_t lds_resident;      /* 1 (default): in the batched engine, an LP whose A and G^{-1} fit
+                                  in one workgroup's LDS (in the precision of the current phase;
+                                  m <= threads, n <= 2 threads) is solved from LDS, with no global
+                                  memory traffic per iteration; 0: every LP streams A and G^{-1}
+                                  from HBM.  Same iteration and tests; the sums are formed in a
+                                  different order, so results agree to rounding, not bitwise. */
 } abip_settings;
 
 /* Per-LP result summary (host struct). */

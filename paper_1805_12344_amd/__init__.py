@@ -39,6 +39,7 @@ class abip_settings(ctypes.Structure):
         ("cg_max_iters", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("adjoint_tol", ctypes.c_double), ("adjoint_max_iters", ctypes.c_int64),
         ("cg_rule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+        ("lds_resident", ctypes.c_int32),
     ]
 
 

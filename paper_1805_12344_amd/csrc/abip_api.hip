@@ -18,7 +18,7 @@
 // defined in abip_solve_wg.hip
 hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const LPDesc* desc, LPCtrl* ctrl,
                            const PoolPtrs& P, const SolveParams& prm, const int32_t* order, int32_t B,
-                           int32_t* queue, int64_t fixed_iters, int32_t ldmax);
+                           int32_t* queue, int64_t fixed_iters, int32_t ldmax, size_t smem);
 size_t wg_smem_bytes(int ldmax, int W);
 int lib_setup_one(const LPDesc& d, const LPDesc* ddesc, const double* A64, double* G64, float* G32, double* Mv,
                   double* Nv, int64_t Mtot, int64_t Ntot, LPCtrl* dctrl, hipStream_t st);
@@ -234,6 +234,8 @@ struct abip_work {
     int* errflag = nullptr;
     double** outp = nullptr;     // 3*B device pointer table
     int ldmax = 0, nch = 1, threads = 512;
+    size_t wg_smem = 0;              // LDS bytes of the batched launch (streamed or LDS-resident)
+    int lds_cap = 0;                 // the device's largest LDS allocation per workgroup
     int cu_count = 256;
     bool solved = false;
     double setup_ms = 0.0;
@@ -312,6 +314,7 @@ extern "C" int abip_default_settings(abip_settings* s) {
     s->adjoint_max_iters = 200000;
     s->cg_rule = 0;
     s->use_graph = 1;
+    s->lds_resident = 1;
     return ABIP_OK;
 }
 
@@ -327,6 +330,7 @@ static int check_settings(const abip_settings& s) {
         return fail(ABIP_E_INVALID, "settings.precision: unknown value %d", s.precision);
     if (s.cg_rule != 0 && s.cg_rule != 1) return fail(ABIP_E_INVALID, "settings.cg_rule must be 0 or 1");
     if (s.use_graph != 0 && s.use_graph != 1) return fail(ABIP_E_INVALID, "settings.use_graph must be 0 or 1");
+    if (s.lds_resident != 0 && s.lds_resident != 1) return fail(ABIP_E_INVALID, "settings.lds_resident must be 0 or 1");
     if (s.block_threads != 0 && s.block_threads != 256 && s.block_threads != 512)
         return fail(ABIP_E_INVALID, "settings.block_threads must be 0, 256 or 512");
     return ABIP_OK;
@@ -504,6 +508,26 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
     return ABIP_OK;
 }
 
+// Which phases of which LPs run LDS-resident, and the LDS bytes of the batched
+// launch: with 256 threads per workgroup an LP qualifies when m <= 256,
+// n <= 512 and its A and G^{-1} fit in one workgroup's LDS in that phase's
+// precision.  The launch then reserves the largest such footprint.
+static void assign_lds(abip_work* w) {
+    const int W = w->threads / 64;
+    size_t smem = wg_smem_bytes(w->ldmax, W);
+    const size_t cap = (w->lds_cap > 1024) ? (size_t)w->lds_cap - 1024 : 0;   // static LDS of the kernel
+    for (LPDesc& d : w->hdesc) {
+        d.lds = 0;
+        if (!w->set.lds_resident || w->grid || w->sparse || w->threads != 256) continue;
+        if (d.m > w->threads || d.n > 2 * w->threads) continue;
+        const size_t b32 = (size_t)small_layout(d.m, d.n, 4, W).total;
+        const size_t b64 = (size_t)small_layout(d.m, d.n, 8, W).total;
+        if (b32 <= cap) { d.lds |= DESC_LDS32; smem = std::max(smem, b32); }
+        if (b64 <= cap) { d.lds |= DESC_LDS64; smem = std::max(smem, b64); }
+    }
+    w->wg_smem = smem;
+}
+
 static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const double* const* b,
                        const double* const* c, const abip_settings* settings, void* stream) {
     if (!out) return fail(ABIP_E_INVALID, "abip_setup: null output handle");
@@ -533,7 +557,7 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
         if (!want_grid && M.m > MAX_WG_M) { delete w; return fail(ABIP_E_DIM, "LP %d: m=%d exceeds the one-workgroup engine limit %d (use abip_setup for one large LP)", k, M.m, MAX_WG_M); }
         if (!M.val || !b[k] || !c[k]) { delete w; return fail(ABIP_E_INVALID, "LP %d: null data pointer", k); }
         LPDesc& d = w->hdesc[k];
-        d.m = M.m; d.n = M.n; d.ld = (M.m + 3) & ~3; d.pad = 0;
+        d.m = M.m; d.n = M.n; d.ld = (M.m + 3) & ~3; d.lds = 0;
         d.oA = oA; d.oG = oG; d.om = om; d.on = on;
         oA += (int64_t)d.ld * d.n;
         oG += (int64_t)d.ld * d.m;
@@ -548,6 +572,8 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&w->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&w->lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    assign_lds(w);
 #define ALLOC(ptr, count) do { hipError_t e_ = hipMalloc((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count)); \
         if (e_ != hipSuccess) { release(w); delete w; return fail(e_ == hipErrorOutOfMemory ? ABIP_E_OOM : ABIP_E_HIP, "hipMalloc(%s, %lld elements): %s", #ptr, (long long)(count), hipGetErrorString(e_)); } } while (0)
     ALLOC(w->ddesc, B);
@@ -629,7 +655,7 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     cleanup_scratch();
     if (hflag & 3) { release(w); delete w; return fail(ABIP_E_NONFINITE, "NaN or Inf in %s", (hflag & 1) ? "A" : "b or c"); }
     if (hflag & 4) { release(w); delete w; return fail(ABIP_E_HIP, "Cholesky of I + A A^T met a non-positive pivot"); }
-    hipError_t e = w->grid ? grid_set_smem(w->ldmax) : set_solve_wg_smem_limit(wg_smem_bytes(w->ldmax, w->threads / 64));
+    hipError_t e = w->grid ? grid_set_smem(w->ldmax) : set_solve_wg_smem_limit(w->wg_smem);
     if (e != hipSuccess) { release(w); delete w; return fail(ABIP_E_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e)); }
     if (w->grid) {
         int rc2 = grid_prepare(w);
@@ -679,7 +705,7 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     w->sparse = true;
     w->hdesc.resize(1);
     LPDesc& d = w->hdesc[0];
-    d.m = m; d.n = n; d.ld = (m + 3) & ~3; d.pad = 0; d.oA = 0; d.oG = 0; d.om = 0; d.on = 0;
+    d.m = m; d.n = n; d.ld = (m + 3) & ~3; d.lds = 0; d.oA = 0; d.oG = 0; d.om = 0; d.on = 0;
     w->ldmax = d.ld;
     w->Mtot = d.ld;
     w->Ntot = (n + 4) & ~3;
@@ -897,7 +923,7 @@ static PoolPtrs pools(abip_work* w) {
 
 static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParams& prm) {
     hipStream_t st = w->stream;
-    const int per_cu = (wg_smem_bytes(w->ldmax, w->threads / 64) <= 76 * 1024 && w->threads <= 512) ? 2 : 1;
+    const int per_cu = (w->wg_smem <= 76 * 1024 && w->threads <= 512) ? 2 : 1;
     const int grid = std::max(1, std::min<int>(B, w->cu_count * per_cu));
     if (!w->ev0) HIPCHK(hipEventCreate(&w->ev0));
     if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
@@ -914,7 +940,7 @@ static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParam
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             return launch_solve_wg(w->nch, grid, w->threads, cs, w->ddesc, w->dctrl, P, prm, w->order, B, w->queue,
-                                   0, w->ldmax);
+                                   0, w->ldmax, w->wg_smem);
         });
         if (rc) return rc;
         HIPCHK(hipEventRecord(w->gjoin0, st));
@@ -930,7 +956,7 @@ static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParam
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(w->ev0, st));
     HIPCHK(launch_solve_wg(w->nch, grid, w->threads, st, w->ddesc, w->dctrl, pools(w), prm, w->order, B, w->queue,
-                           fixed_iters, w->ldmax));
+                           fixed_iters, w->ldmax, w->wg_smem));
     HIPCHK(hipEventRecord(w->ev1, st));
     return ABIP_OK;
 }
@@ -1173,7 +1199,7 @@ extern "C" int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_
     SolveParams prm = make_params(w->set);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, w->stream, w->queue);
     hipError_t e = launch_solve_wg(w->nch, 1, w->threads, w->stream, w->ddesc, w->dctrl, pools(w), prm, ord1, 1,
-                                   w->queue, iters, w->ldmax);
+                                   w->queue, iters, w->ldmax, w->wg_smem);
     hipError_t e2 = hipStreamSynchronize(w->stream);
     (void)hipFree(ord1);
     if (e != hipSuccess) return fail(ABIP_E_HIP, "abip_iterate launch: %s", hipGetErrorString(e));
@@ -1207,7 +1233,10 @@ extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t ma
         if (w->sparse) { w->sp_nb = c; return ABIP_OK; }
         if (w->grid) { grid_config(w, c); return ABIP_OK; }
         w->threads = c;
-        const hipError_t e = set_solve_wg_smem_limit(wg_smem_bytes(w->ldmax, w->threads / 64));
+        assign_lds(w);
+        HIPCHK(hipMemcpyAsync(w->ddesc, w->hdesc.data(), sizeof(LPDesc) * w->B, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const hipError_t e = set_solve_wg_smem_limit(w->wg_smem);
         if (e != hipSuccess) return fail(ABIP_E_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
         return ABIP_OK;
     };

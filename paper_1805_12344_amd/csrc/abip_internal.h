@@ -23,7 +23,8 @@ enum { NF_C = 0, NF_CBAR, NF_ZX0, NF_ZX1, NF_X, NF_S, NF_ZX0A, NF_ZX1A, NNF };
 enum { OP_REFRESH = 0, OP_PROX = 1, OP_RESTART = 2 };
 
 struct LPDesc {
-    int32_t m, n, ld, pad;
+    int32_t m, n, ld;
+    int32_t lds;    // DESC_LDS32 | DESC_LDS64: phases that run LDS-resident
     int64_t oA;     // element offset of column-major A (ld*n)
     int64_t oG;     // element offset of G^{-1} (ld*m)
     int64_t om;     // offset in each m-field (slice length ld)
@@ -59,6 +60,44 @@ struct PoolPtrs {
     double* Mv; double* Nv;
     int64_t Mtot, Ntot;
 };
+
+// LDS layout of the LDS-resident variant of the one-workgroup solve (byte
+// offsets, 16-byte aligned) for an m x n LP with esize-byte matrix entries and
+// W waves.  A is column-major with leading dimension lda: lda/4 odd for FP32 and
+// lda/2 odd for FP64, so the 16-byte column reads of 16 consecutive lanes
+// (lanes own columns) start in 16 different bank quads.  Rows m..lda-1 are zero.
+//   A    T[lda * n]          G^{-1}  T[ldg * m] (ldg = m rounded up to 4)
+//   av   double[m4]          a = G^{-1} t for updates, y for refresh / restart
+//   fx   double2[n]          (x_j + s_j, x_j) of the new iterate
+//   tv   double[m4]          t = y - A f
+//   pf   double[2 W m4]      per-wave partial A f, A x
+//   pg   double[W m4]        per-wave partial G^{-1} t
+//   red  double[16 W]        per-wave partial sums
+struct SmallLayout {
+    int lda, ldg, m4;
+    int64_t oA, oG, oav, ofx, otv, opf, opg, ored, total;
+};
+__host__ __device__ inline int64_t small_align16(int64_t x) { return (x + 15) & ~(int64_t)15; }
+__host__ __device__ inline SmallLayout small_layout(int m, int n, int esize, int W) {
+    SmallLayout L;
+    L.m4 = (m + 3) & ~3;
+    if (esize == 4) L.lda = (((L.m4 >> 2) & 1) != 0) ? L.m4 : L.m4 + 4;
+    else L.lda = L.m4 + 2;
+    L.ldg = L.m4;
+    int64_t o = 0;
+    L.oA = o;  o = small_align16(o + (int64_t)L.lda * n * esize);
+    L.oG = o;  o = small_align16(o + (int64_t)L.ldg * m * esize);
+    L.oav = o; o = small_align16(o + 8 * (int64_t)L.m4);
+    L.ofx = o; o = small_align16(o + 16 * (int64_t)n);
+    L.otv = o; o = small_align16(o + 8 * (int64_t)L.m4);
+    L.opf = o; o = small_align16(o + 16 * (int64_t)W * L.m4);
+    L.opg = o; o = small_align16(o + 8 * (int64_t)W * L.m4);
+    L.ored = o; o = small_align16(o + 8 * 16 * (int64_t)W);
+    L.total = o;
+    return L;
+}
+// LPDesc.lds bits: the FP32 / FP64 phase of this LP runs LDS-resident
+enum { DESC_LDS32 = 1, DESC_LDS64 = 2 };
 
 // Positive root of z^2 - w z - t = 0, cancellation free for w < 0
 // (closed form of the barrier prox, eqs. Simple-Update:Barrier-X/-tau).

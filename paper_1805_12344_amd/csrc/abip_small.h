@@ -1,0 +1,585 @@
+// LDS-resident variant of the one-workgroup solve, for LPs whose A and G^{-1}
+// fit in one workgroup's LDS in the precision of the current phase.  It runs
+// the same iteration as the streamed variant (Algorithm 2 with the Section 4.2
+// relaxation, the Section 4.1 tests on every update, the inner test
+// ||Qu - v||^2 <= mu, the Section 5 restart, the FP32 -> FP64 handover) and
+// takes the same decisions; what differs is where the data lives and how the
+// products are organised:
+//   * A and G^{-1} are copied into LDS once per precision phase, so an
+//     iteration touches no global memory.
+//   * thread j owns column j: x_j, s_j, c_j, cbar_j, the border entries and
+//     (A^T y)_j stay in its registers; (A^T a)_j is one LDS dot product and the
+//     prox root and dual update of x_j, s_j need no lane exchange.
+//   * thread i owns row i: y_i and the m-vectors of the border stay in its
+//     registers.  A f, A x and G^{-1} t come from sweeps in which wave w takes
+//     the w-th slice of the columns with lanes over rows; the row owner adds
+//     the W partial vectors in a fixed order (deterministic).
+//   * (A^T y)_j of the relaxed y update y' = alpha (a - Zy p) + (1 - alpha) y
+//     (Section 4.2 applied to the y block) is carried by
+//         A^T y' = alpha (A^T a - p0 A^T Zy0 - p1 A^T Zy1) + (1 - alpha) A^T y,
+//     so an update needs one dot product per column instead of two.  It is
+//     recomputed exactly by every refresh and restart pass, and old rounding
+//     errors are multiplied by |1 - alpha| < 1 at every step, so they stay
+//     bounded.
+// Five workgroup barriers per update: after the column pass, after the A f
+// sweep, in the check's sums, after the G^{-1} sweep and in the border sums.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "abip_internal.h"
+
+struct SmallCol {
+    double x, s, c, cb, z0, z1;     // iterate, c, cbar, border columns of x
+    double aty, atz0, atz1;         // (A^T y)_j, (A^T Zy0)_j, (A^T Zy1)_j
+};
+
+// dot of one LDS column with an LDS vector (rows past m are zero in both)
+__device__ __forceinline__ double small_dot(const float* __restrict__ col, const double* __restrict__ v, int m4) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 2
+    for (int i = 0; i < m4; i += 4) {
+        const float4 a = *reinterpret_cast<const float4*>(col + i);
+        const double2 v0 = *reinterpret_cast<const double2*>(v + i);
+        const double2 v1 = *reinterpret_cast<const double2*>(v + i + 2);
+        s0 = fma((double)a.x, v0.x, s0);
+        s1 = fma((double)a.y, v0.y, s1);
+        s2 = fma((double)a.z, v1.x, s2);
+        s3 = fma((double)a.w, v1.y, s3);
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+__device__ __forceinline__ double small_dot(const double* __restrict__ col, const double* __restrict__ v, int m4) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 2
+    for (int i = 0; i < m4; i += 4) {
+        const double2 a0 = *reinterpret_cast<const double2*>(col + i);
+        const double2 a1 = *reinterpret_cast<const double2*>(col + i + 2);
+        const double2 v0 = *reinterpret_cast<const double2*>(v + i);
+        const double2 v1 = *reinterpret_cast<const double2*>(v + i + 2);
+        s0 = fma(a0.x, v0.x, s0);
+        s1 = fma(a0.y, v0.y, s1);
+        s2 = fma(a1.x, v1.x, s2);
+        s3 = fma(a1.y, v1.y, s3);
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
+// Copy this phase's A and G^{-1} from the pools into LDS (zero rows m..lda-1).
+template <typename T>
+__device__ __forceinline__ void small_fill(T* __restrict__ As, int lda, T* __restrict__ Gs, int ldg,
+                                           const T* __restrict__ Ag, const T* __restrict__ Gg, int m, int n,
+                                           int ld) {
+    const int NT = blockDim.x;
+    for (int e = threadIdx.x; e < lda * n; e += NT) {
+        const int j = e / lda, i = e - j * lda;
+        As[e] = (i < m) ? Ag[(int64_t)j * ld + i] : T(0);
+    }
+    for (int e = threadIdx.x; e < ldg * m; e += NT) {
+        const int j = e / ldg, i = e - j * ldg;
+        Gs[e] = (i < m) ? Gg[(int64_t)j * ld + i] : T(0);
+    }
+}
+
+// The LDS-resident variant runs with 256 threads: four waves.
+#define SMALL_W 4
+
+// Block sum of K values (K = 4 or 12); every thread gets the totals, added in
+// a fixed order.  A reduce-scatter leaves lane group g (16 lanes) of each wave
+// with values K/4*g .. K/4*g + K/4 - 1; red holds them as [value][wave], read
+// back with 16-byte loads.  One barrier; red is not written again before the
+// caller's next barrier.
+template <int K>
+__device__ __forceinline__ void small_bsum(double (&v)[K], double* __restrict__ red) {
+    static_assert(K % 4 == 0 && K <= 16, "small_bsum: K = 4, 8, 12 or 16");
+    constexpr int V = K / 4;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    wave_rs<K, V>(v);
+    if ((lane & 15) == 0) {
+        const int g = lane >> 4;
+#pragma unroll
+        for (int q = 0; q < V; ++q) red[(V * g + q) * SMALL_W + wave] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double2 r0 = *reinterpret_cast<const double2*>(red + k * SMALL_W);
+        const double2 r1 = *reinterpret_cast<const double2*>(red + k * SMALL_W + 2);
+        v[k] = (r0.x + r0.y) + (r1.x + r1.y);
+    }
+}
+
+// Column pass: op OP_PROX (av = a: the update of x_j, s_j), OP_REFRESH or
+// OP_RESTART (av = y: exact A^T y; the restart rescales x_j, s_j).  Writes
+// (x'+s', x') to fx and adds the column-side sums of the check to acc:
+//   c^T x, cbar^T x, c^T s, cbar^T s, ||A^T y + s - c tau||^2, ||A^T y + s||^2,
+//   ||-A^T y + c tau - cbar theta - s||^2.
+template <typename T, int CPT>
+__device__ __forceinline__ void small_colpass(const T* __restrict__ As, int lda, int m4, int n,
+                                              const double* __restrict__ av, SmallCol (&col)[CPT],
+                                              double2* __restrict__ fx, int op, double p0, double p1, double tmu,
+                                              double alpha, double gamma, int rule, double tau, double theta,
+                                              double (&acc)[7]) {
+    const double sg = sqrt(gamma);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int j = threadIdx.x + q * blockDim.x;
+        if (j < n) {
+            SmallCol& C = col[q];
+            const double dv = small_dot(As + (int64_t)j * lda, av, m4);
+            double x1 = C.x, s1 = C.s, aty;
+            if (op == OP_PROX) {
+                const double dj = (C.x + C.s) + dv;                    // M^{-1} block, x part
+                const double ut = dj - C.z0 * p0 - C.z1 * p1;         // u~_x
+                const double uh = alpha * ut + (1.0 - alpha) * C.x;   // relaxation
+                x1 = prox_root(uh - C.s, tmu);                        // barrier prox
+                s1 = C.s - uh + x1;                                   // dual update
+                aty = alpha * (dv - p0 * C.atz0 - p1 * C.atz1) + (1.0 - alpha) * C.aty;
+            } else {
+                aty = dv;
+                if (op == OP_RESTART) {
+                    if (rule == 0) {
+                        if (C.x >= C.s) s1 = gamma * C.s;
+                        else x1 = gamma * C.x;
+                    } else {
+                        x1 = sg * C.x;
+                        s1 = sg * C.s;
+                    }
+                }
+            }
+            C.x = x1; C.s = s1; C.aty = aty;
+            const double r1 = aty + s1 - C.c * tau;
+            const double r2 = aty + s1;
+            const double r3 = -aty + C.c * tau - C.cb * theta - s1;
+            acc[0] = fma(C.c, x1, acc[0]);
+            acc[1] = fma(C.cb, x1, acc[1]);
+            acc[2] = fma(C.c, s1, acc[2]);
+            acc[3] = fma(C.cb, s1, acc[3]);
+            acc[4] = fma(r1, r1, acc[4]);
+            acc[5] = fma(r2, r2, acc[5]);
+            acc[6] = fma(r3, r3, acc[6]);
+            fx[j] = make_double2(x1 + s1, x1);
+        }
+    }
+}
+
+// Partial A f and A x over this wave's slice of the columns, lanes over rows
+// (RPL rows per lane, m <= 64 RPL): pf[(2w) m4 + i], pf[(2w+1) m4 + i].
+// Eight columns per step with every LDS read issued before the arithmetic;
+// the last step re-reads a valid column with zero weight (no branches).
+template <typename T, int RPL>
+__device__ __forceinline__ void small_rowpass(const T* __restrict__ As, int lda, int m, int n, int m4,
+                                              const double2* __restrict__ fx, double* __restrict__ pf) {
+    constexpr int U = 8;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int j0 = (n * wave) / SMALL_W, j1 = (n * (wave + 1)) / SMALL_W;
+    double af[RPL], ax[RPL];
+    int row[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        af[r] = 0.0; ax[r] = 0.0;
+        row[r] = min(lane + 64 * r, m - 1);
+    }
+    for (int jb = j0; jb < j1; jb += U) {
+        double2 f[U];
+        double a[U][RPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = min(jb + u, j1 - 1);
+            f[u] = fx[j];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) a[u][r] = (double)As[(int64_t)j * lda + row[r]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double wf = (jb + u < j1) ? f[u].x : 0.0, wx = (jb + u < j1) ? f[u].y : 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                af[r] = fma(a[u][r], wf, af[r]);
+                ax[r] = fma(a[u][r], wx, ax[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i < m) {
+            pf[(2 * wave) * m4 + i] = af[r];
+            pf[(2 * wave + 1) * m4 + i] = ax[r];
+        }
+    }
+}
+
+// Partial G^{-1} t over this wave's slice of the columns of the symmetric
+// G^{-1}, lanes over rows as in the row pass: pg[w m4 + i].
+template <typename T, int RPL>
+__device__ __forceinline__ void small_gpass(const T* __restrict__ Gs, int ldg, int m, int m4,
+                                            const double* __restrict__ tv, double* __restrict__ pg) {
+    constexpr int U = 8;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int k0 = (m * wave) / SMALL_W, k1 = (m * (wave + 1)) / SMALL_W;
+    double ag[RPL];
+    int row[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        ag[r] = 0.0;
+        row[r] = min(lane + 64 * r, m - 1);
+    }
+    for (int kb = k0; kb < k1; kb += U) {
+        double t[U];
+        double g[U][RPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = min(kb + u, k1 - 1);
+            t[u] = tv[k];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) g[u][r] = (double)Gs[(int64_t)k * ldg + row[r]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double wt = (kb + u < k1) ? t[u] : 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) ag[r] = fma(g[u][r], wt, ag[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i < m) pg[wave * m4 + i] = ag[r];
+    }
+}
+
+// Copy this phase's A and G^{-1} into LDS (layout L is set for the phase)
+// and form (A^T Zy0)_j, (A^T Zy1)_j for the owned columns.  Starts and ends
+// with a barrier.
+template <int CPT>
+__device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, const PoolPtrs& P,
+                                                 const double* __restrict__ Zy0, const double* __restrict__ Zy1,
+                                                 unsigned char* __restrict__ smem, SmallLayout& L,
+                                                 SmallCol (&col)[CPT]) {
+    const int m = d.m, n = d.n, tid = threadIdx.x;
+    L = small_layout(m, n, phase == 0 ? 4 : 8, num_waves());
+    double* av = reinterpret_cast<double*>(smem + L.oav);
+    double* tv = reinterpret_cast<double*>(smem + L.otv);
+    __syncthreads();                       // earlier readers of the LDS are done
+    if (phase == 0)
+        small_fill<float>(reinterpret_cast<float*>(smem + L.oA), L.lda, reinterpret_cast<float*>(smem + L.oG),
+                          L.ldg, P.A32 + d.oA, P.G32 + d.oG, m, n, d.ld);
+    else
+        small_fill<double>(reinterpret_cast<double*>(smem + L.oA), L.lda, reinterpret_cast<double*>(smem + L.oG),
+                           L.ldg, P.A64 + d.oA, P.G64 + d.oG, m, n, d.ld);
+    for (int i = tid; i < L.m4; i += blockDim.x) {
+        av[i] = (i < m) ? Zy0[i] : 0.0;
+        tv[i] = (i < m) ? Zy1[i] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int j = tid + q * blockDim.x;
+        if (j < n) {
+            if (phase == 0) {
+                const float* cp = reinterpret_cast<const float*>(smem + L.oA) + (int64_t)j * L.lda;
+                col[q].atz0 = small_dot(cp, av, L.m4);
+                col[q].atz1 = small_dot(cp, tv, L.m4);
+            } else {
+                const double* cp = reinterpret_cast<const double*>(smem + L.oA) + (int64_t)j * L.lda;
+                col[q].atz0 = small_dot(cp, av, L.m4);
+                col[q].atz1 = small_dot(cp, tv, L.m4);
+            }
+        }
+    }
+    __syncthreads();                       // av / tv are rewritten next
+}
+
+// Solve one LP LDS-resident from the state in ctrl[k] and the pools.  Returns
+// true when the LP is finished here; false when the current phase does not fit
+// (on entry, or at the handover to FP64 data): then ctrl[k] and the pools hold
+// the state, with a tested FP64 refresh as the next pass, for the streamed
+// variant.  Requires m <= blockDim.x and n <= CPT * blockDim.x.
+template <int CPT, int RPL>
+__device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __restrict__ ctrl, const PoolPtrs& P_in,
+                                         const SolveParams& prm_in, int64_t fixed_iters) {
+    // the launch's dynamic LDS, named here so that every access is an LDS access
+    extern __shared__ __align__(16) unsigned char small_lds[];
+    unsigned char* const smem = small_lds;
+    // private copies: the loop must not reload the caller's structs through
+    // generic pointers after every LDS store
+    const LPDesc d = d_in;
+    const PoolPtrs P = P_in;
+    const SolveParams prm = prm_in;
+    const int m = d.m, n = d.n, ld = d.ld;
+    const int tid = threadIdx.x;
+    constexpr int W = SMALL_W;
+    const LPCtrl cl = ctrl[k];
+    int phase = cl.phase;
+    if (num_waves() != W || !(d.lds & (phase == 0 ? DESC_LDS32 : DESC_LDS64))) return false;
+
+    const double* b = P.Mv + MF_B * P.Mtot + d.om;
+    const double* bbar = P.Mv + MF_BBAR * P.Mtot + d.om;
+    const double* Ac = P.Mv + MF_AC * P.Mtot + d.om;
+    const double* Acb = P.Mv + MF_ACBAR * P.Mtot + d.om;
+    const double* Zy0 = P.Mv + MF_ZY0 * P.Mtot + d.om;
+    const double* Zy1 = P.Mv + MF_ZY1 * P.Mtot + d.om;
+    double* Yg = P.Mv + MF_Y * P.Mtot + d.om;
+    const double* C = P.Nv + NF_C * P.Ntot + d.on;
+    const double* CBv = P.Nv + NF_CBAR * P.Ntot + d.on;
+    const double* ZX0 = P.Nv + NF_ZX0 * P.Ntot + d.on;
+    const double* ZX1 = P.Nv + NF_ZX1 * P.Ntot + d.on;
+    double* X = P.Nv + NF_X * P.Ntot + d.on;
+    double* S = P.Nv + NF_S * P.Ntot + d.on;
+
+    double tau = cl.tau, kappa = cl.kappa, theta = cl.theta, mu = cl.mu;
+    int64_t iters = cl.iters, iters64 = cl.iters64, ipm = cl.ipm;
+    int64_t cp32 = cl.cp32, cp64 = cl.cp64;
+    int status = cl.status;
+    const int check_final_first = cl.flags & 1;
+    double pres = cl.pres, dres = cl.dres, gap = cl.gap, pobj = cl.pobj, dobj = cl.dobj;
+    double l_ms2 = 0.0, l_cs4 = 0.0, l_tau = 0.0;
+    bool l_have = false;
+    double by_last = cl.by, cx_last = cl.cx;
+    const double zbar = cl.zbar, nb = cl.nb, nc = cl.nc;
+    const double alpha = prm.alpha, gamma = prm.gamma, beta = prm.beta, eps = prm.eps;
+    const double np1 = (double)n + 1.0;
+
+    // row owner registers (threads past m hold zeros and add nothing)
+    const bool rown = tid < m;
+    const int ri = rown ? tid : 0;
+    double y = rown ? Yg[ri] : 0.0;
+    const double rb = rown ? b[ri] : 0.0, rbb = rown ? bbar[ri] : 0.0;
+    const double rac = rown ? Ac[ri] : 0.0, racb = rown ? Acb[ri] : 0.0;
+    const double rz0 = rown ? Zy0[ri] : 0.0, rz1 = rown ? Zy1[ri] : 0.0;
+    // column owner registers
+    SmallCol col[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int j = tid + q * blockDim.x;
+        const int jj = (j < n) ? j : n - 1;
+        col[q].x = X[jj]; col[q].s = S[jj]; col[q].c = C[jj]; col[q].cb = CBv[jj];
+        col[q].z0 = ZX0[jj]; col[q].z1 = ZX1[jj];
+        col[q].aty = 0.0; col[q].atz0 = 0.0; col[q].atz1 = 0.0;
+    }
+
+    SmallLayout L = small_layout(m, n, phase == 0 ? 4 : 8, W);
+    double* av = reinterpret_cast<double*>(smem + L.oav);
+    double2* fx = reinterpret_cast<double2*>(smem + L.ofx);
+    double* tv = reinterpret_cast<double*>(smem + L.otv);
+    double* pf = reinterpret_cast<double*>(smem + L.opf);
+    double* pg = reinterpret_cast<double*>(smem + L.opg);
+    double* red = reinterpret_cast<double*>(smem + L.ored);
+    const int m4 = L.m4;                   // the same in both precisions
+
+    // this phase's matrices into LDS, and A^T Zy0, A^T Zy1 for the y recurrence
+    small_load_phase<CPT>(phase, d, P, Zy0, Zy1, smem, L, col);
+
+    double p0 = 0.0, p1 = 0.0;
+    int pass_kind = (cl.mode == OP_PROX) ? OP_REFRESH : cl.mode;   // a state enters with a refresh
+    bool first = true;
+    int64_t done_fixed = 0;
+    StallTrack stall;
+    stall_reset(stall);
+    int64_t passes = 0;
+    const int64_t pass_cap = prm.max_iters + 4096;
+    int64_t cyc_col = 0, cyc_ginv = 0, cyc_chk = 0, cyc_upd = 0;
+    const int64_t t_start = wall_clock64();
+    bool handover = false;
+    while (true) {
+        if (++passes > pass_cap && fixed_iters == 0) { status = 4; break; }
+        const double tmu = mu / beta;      // t = mu / beta, eq. (Simple-Update:Barrier-X)
+        const int64_t t0 = wall_clock64();
+        if (pass_kind != OP_PROX) {        // exact A^T y of the (rescaled) state
+            if (rown) av[tid] = y;
+            __syncthreads();
+        }
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (phase == 0)
+            small_colpass<float, CPT>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m4, n, av, col, fx,
+                                      pass_kind, p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, acc);
+        else
+            small_colpass<double, CPT>(reinterpret_cast<const double*>(smem + L.oA), L.lda, m4, n, av, col, fx,
+                                       pass_kind, p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, acc);
+        __syncthreads();
+        if (phase == 0) small_rowpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m, n, m4, fx, pf);
+        else small_rowpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oA), L.lda, m, n, m4, fx, pf);
+        __syncthreads();
+        // row owner: A f, A x of the new state, t = y - A f, m-side sums
+        double v12[12];
+        {
+            double Af = 0.0, Ax = 0.0;
+            if (rown) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    Af += pf[(2 * w) * m4 + tid];
+                    Ax += pf[(2 * w + 1) * m4 + tid];
+                }
+                tv[tid] = y - Af;
+            }
+            const double r1 = Ax - rb * tau;
+            const double r3 = r1 + rbb * theta;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) v12[q] = acc[q];
+            v12[7] = rb * y;
+            v12[8] = rbb * y;
+            v12[9] = r1 * r1;
+            v12[10] = Ax * Ax;
+            v12[11] = r3 * r3;
+        }
+        small_bsum<12>(v12, red);
+        cyc_col += wall_clock64() - t0;
+        if (phase == 0) ++cp32; else ++cp64;
+        const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
+                                 (pass_kind == OP_REFRESH && !first);
+        const bool was_update = (pass_kind == OP_PROX);
+        if (pass_kind == OP_PROX) {
+            ++iters;
+            if (phase == 1) ++iters64;
+            ++done_fixed;
+        }
+        first = false;
+        if (fixed_iters > 0 && done_fixed >= fixed_iters) break;
+
+        const int64_t tc = wall_clock64();
+        const double cx = v12[0], cbx = v12[1];
+        const double by = v12[7], bby = v12[8];
+        const double ms2 = v12[9], ms3 = v12[10], ms4 = v12[11];
+        const double cs4 = v12[4], cs5 = v12[5], cs6 = v12[6];
+        if (fixed_iters == 0) {
+            int to_phase1 = 0;
+            if (post_update) {
+                int st = 0;
+                // Section 4.1's tests multiplied through by tau (> 0) and squared
+                if (tau > 0.0) {
+                    const double ep = eps * (1.0 + nb) * tau, ed = eps * (1.0 + nc) * tau;
+                    if (ms2 <= ep * ep && cs4 <= ed * ed && fabs(cx - by) <= eps * (tau + fabs(cx) + fabs(by)))
+                        st = 1;
+                }
+                if (!st && nb > 0.0 && by > 0.0 && cs5 * (nb * nb) <= (eps * by) * (eps * by)) st = 2;
+                if (!st && nc > 0.0 && cx < 0.0 && ms3 * (nc * nc) <= (eps * cx) * (eps * cx)) st = 3;
+                l_ms2 = ms2; l_cs4 = cs4; l_tau = tau; l_have = true;
+                by_last = by;
+                cx_last = cx;
+                if (st) {
+                    if (phase == 0) to_phase1 = 1;     // FP32 verdict: confirm with FP64 data
+                    else { status = st; break; }
+                }
+            }
+            if (!to_phase1 && phase == 0 && iters >= prm.fp32_max_iters) to_phase1 = 1;
+            if (!to_phase1) {
+                // ---- inner test ||Q u - v||^2 <= mu (eq. inner-stop)
+                const double rt = by - cx + zbar * theta - kappa;
+                const double rth = -bby + cbx - zbar * tau + np1;
+                const double inner = ms4 + cs6 + rt * rt + rth * rth;
+                if (inner <= mu) {
+                    mu *= gamma;
+                    ++ipm;
+                    if (prm.restart_rule == 0) {
+                        if (tau >= kappa) kappa *= gamma;
+                        else tau *= gamma;
+                    } else {
+                        const double sg = sqrt(gamma);
+                        tau *= sg; kappa *= sg; theta *= sg;
+                        y *= sg;
+                    }
+                    stall_reset(stall);
+                    pass_kind = OP_RESTART;
+                    cyc_chk += wall_clock64() - tc;
+                    continue;
+                }
+                if (phase == 0 && was_update && stall_sample(stall, inner, mu)) to_phase1 = 1;
+            }
+            if (to_phase1) {                   // FP32 verdict or precision floor: FP64 data
+                phase = 1;
+                pass_kind = OP_REFRESH;
+                cyc_chk += wall_clock64() - tc;
+                if (!(d.lds & DESC_LDS64)) { handover = true; break; }
+                small_load_phase<CPT>(phase, d, P, Zy0, Zy1, smem, L, col);
+                av = reinterpret_cast<double*>(smem + L.oav);
+                fx = reinterpret_cast<double2*>(smem + L.ofx);
+                tv = reinterpret_cast<double*>(smem + L.otv);
+                pf = reinterpret_cast<double*>(smem + L.opf);
+                pg = reinterpret_cast<double*>(smem + L.opg);
+                red = reinterpret_cast<double*>(smem + L.ored);
+                continue;
+            }
+            if (iters >= prm.max_iters) { status = 4; break; }
+        }
+        cyc_chk += wall_clock64() - tc;
+
+        // ---- the inner update: a = G^{-1} t, border, scalars, y'
+        const int64_t t1 = wall_clock64();
+        if (phase == 0) small_gpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oG), L.ldg, m, m4, tv, pg);
+        else small_gpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oG), L.ldg, m, m4, tv, pg);
+        __syncthreads();
+        const int64_t t2 = wall_clock64();
+        cyc_ginv += t2 - t1;
+        double a = 0.0;
+        if (rown) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) a += pg[w * m4 + tid];
+            av[tid] = a;
+        }
+        double bs[4] = {rb * a, rbb * a, rac * a, racb * a};
+        small_bsum<4>(bs, red);
+        const double cs_f = cx + v12[2];        // c^T (x + s)
+        const double cbs_f = cbx + v12[3];      // cbar^T (x + s)
+        const double h1z = -bs[0] + cs_f + bs[2];      // h1^T z, c^T d = c^T f + (A c)^T a
+        const double h2z = bs[1] - cbs_f - bs[3];      // h2^T z
+        const double q0 = (tau + kappa) + h1z;
+        const double q1 = (theta - np1) + h2z;
+        p0 = cl.K00 * q0 + cl.K01 * q1;
+        p1 = cl.K10 * q0 + cl.K11 * q1;
+        const double uh_tau = alpha * p0 + (1.0 - alpha) * tau;
+        const double uh_theta = alpha * p1 + (1.0 - alpha) * theta;
+        const double tau1 = prox_root(uh_tau - kappa, tmu);
+        kappa = kappa - uh_tau + tau1;
+        tau = tau1;
+        theta = uh_theta;
+        if (rown) y = alpha * (a - rz0 * p0 - rz1 * p1) + (1.0 - alpha) * y;
+        cyc_upd += wall_clock64() - t2;
+        pass_kind = OP_PROX;
+    }
+
+    // state back to the pools
+    if (rown) Yg[tid] = y;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int j = tid + q * blockDim.x;
+        if (j < n) { X[j] = col[q].x; S[j] = col[q].s; }
+    }
+    if (handover) {
+        // the streamed variant continues with a tested refresh in FP64
+        if (tid == 0) {
+            LPCtrl& o = ctrl[k];
+            o.clk[0] += cyc_col; o.clk[1] += cyc_ginv; o.clk[2] += wall_clock64() - t_start;
+            o.clk[3] += cyc_chk; o.clk[4] += cyc_upd;
+            o.tau = tau; o.kappa = kappa; o.theta = theta; o.mu = mu;
+            o.by = by_last; o.cx = cx_last;
+            o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
+            o.cp32 = cp32; o.cp64 = cp64;
+            o.status = 0; o.phase = 1;
+            o.mode = OP_REFRESH;
+            o.flags = (cl.flags & 4) | 1;
+        }
+        __syncthreads();
+        return false;
+    }
+    if (l_have && l_tau > 0.0) {           // the relative residuals of the last test
+        pobj = cx_last / l_tau;
+        dobj = by_last / l_tau;
+        pres = sqrt(l_ms2) / l_tau / (1.0 + nb);
+        dres = sqrt(l_cs4) / l_tau / (1.0 + nc);
+        gap = fabs(pobj - dobj) / (1.0 + fabs(pobj) + fabs(dobj));
+    }
+    if (tid == 0) {
+        LPCtrl& o = ctrl[k];
+        o.clk[0] += cyc_col; o.clk[1] += cyc_ginv; o.clk[2] += wall_clock64() - t_start;
+        o.clk[3] += cyc_chk; o.clk[4] += cyc_upd;
+        o.tau = tau; o.kappa = kappa; o.theta = theta; o.mu = mu;
+        o.pres = pres; o.dres = dres; o.gap = gap; o.pobj = pobj; o.dobj = dobj;
+        o.by = by_last; o.cx = cx_last;
+        o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
+        o.cp32 = cp32; o.cp64 = cp64;
+        o.status = status; o.phase = phase;
+        o.mode = OP_REFRESH;
+        o.flags = ((fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);
+    }
+    __syncthreads();
+    return true;
+}

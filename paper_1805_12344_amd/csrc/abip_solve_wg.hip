@@ -17,6 +17,7 @@
 // iterate is therefore exact and costs no extra pass over A.
 #include <hip/hip_runtime.h>
 #include "abip_internal.h"
+#include "abip_small.h"
 
 struct WGShared {
     double* y;      // ld
@@ -376,7 +377,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     const double* G64 = P.G64 + d.oG;
     const float* G32 = P.G32 + d.oG;
 
-    LPCtrl cl = ctrl[k];
+    const LPCtrl cl = ctrl[k];
     double tau = cl.tau, kappa = cl.kappa, theta = cl.theta, mu = cl.mu;
     int64_t iters = cl.iters, iters64 = cl.iters64, ipm = cl.ipm;
     int64_t cp32 = cl.cp32, cp64 = cl.cp64;
@@ -614,6 +615,25 @@ __global__ __launch_bounds__(MAXT) void k_solve_wg(const LPDesc* __restrict__ de
         if (q >= B) break;
         const int k = order[q];
         const LPDesc d = desc[k];
+        // an LP whose current phase fits in LDS runs LDS-resident (256-thread
+        // builds); it comes back here (state in ctrl[k] and the pools) only to
+        // hand over to FP64 data that does not fit
+        if (MAXT == 256 && d.lds != 0) {
+            const int rpl = (d.m + 63) >> 6;
+            bool done;
+            if (d.n <= 256) {
+                done = (rpl == 1) ? solve_small<1, 1>(k, d, ctrl, P, prm, fixed_iters)
+                     : (rpl == 2) ? solve_small<1, 2>(k, d, ctrl, P, prm, fixed_iters)
+                     : (rpl == 3) ? solve_small<1, 3>(k, d, ctrl, P, prm, fixed_iters)
+                                  : solve_small<1, 4>(k, d, ctrl, P, prm, fixed_iters);
+            } else {
+                done = (rpl == 1) ? solve_small<2, 1>(k, d, ctrl, P, prm, fixed_iters)
+                     : (rpl == 2) ? solve_small<2, 2>(k, d, ctrl, P, prm, fixed_iters)
+                     : (rpl == 3) ? solve_small<2, 3>(k, d, ctrl, P, prm, fixed_iters)
+                                  : solve_small<2, 4>(k, d, ctrl, P, prm, fixed_iters);
+            }
+            if (done) continue;
+        }
         // each LP runs the variant for its own row count (the launch's NCH is
         // the batch maximum): a small LP in a mixed batch holds no idle rows
         const int nch = (d.ld + 255) >> 8;
@@ -629,10 +649,11 @@ size_t wg_smem_bytes(int ldmax, int W) {
     return sizeof(double) * ((size_t)5 * ldmax + (size_t)2 * W * ldmax + 16 * (size_t)W);
 }
 
+// smem: at least wg_smem_bytes(ldmax, threads / 64), and the LDS-resident
+// footprint of every LP whose descriptor asks for it
 hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const LPDesc* desc, LPCtrl* ctrl,
                            const PoolPtrs& P, const SolveParams& prm, const int32_t* order, int32_t B,
-                           int32_t* queue, int64_t fixed_iters, int32_t ldmax) {
-    const size_t smem = wg_smem_bytes(ldmax, threads / 64);
+                           int32_t* queue, int64_t fixed_iters, int32_t ldmax, size_t smem) {
     if (threads > 256 && nch != 1) return hipErrorInvalidValue;      // only NCH = 1 has a 512-thread build
     switch (nch * 1000 + threads) {
     case 1512: hipLaunchKernelGGL((k_solve_wg<1, 512>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
