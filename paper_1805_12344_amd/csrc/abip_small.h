@@ -64,18 +64,19 @@ __device__ __forceinline__ double small_dot(const double* __restrict__ col, cons
 }
 
 // Copy this phase's A and G^{-1} from the pools into LDS (zero rows m..lda-1).
-template <typename T>
-__device__ __forceinline__ void small_fill(T* __restrict__ As, int lda, T* __restrict__ Gs, int ldg,
-                                           const T* __restrict__ Ag, const T* __restrict__ Gg, int m, int n,
+// FP32 data may be held as doubles (the same values, no conversion per use).
+template <typename Td, typename Ts>
+__device__ __forceinline__ void small_fill(Td* __restrict__ As, int lda, Td* __restrict__ Gs, int ldg,
+                                           const Ts* __restrict__ Ag, const Ts* __restrict__ Gg, int m, int n,
                                            int ld) {
     const int NT = blockDim.x;
     for (int e = threadIdx.x; e < lda * n; e += NT) {
         const int j = e / lda, i = e - j * lda;
-        As[e] = (i < m) ? Ag[(int64_t)j * ld + i] : T(0);
+        As[e] = (i < m) ? (Td)Ag[(int64_t)j * ld + i] : Td(0);
     }
     for (int e = threadIdx.x; e < ldg * m; e += NT) {
         const int j = e / ldg, i = e - j * ldg;
-        Gs[e] = (i < m) ? Gg[(int64_t)j * ld + i] : T(0);
+        Gs[e] = (i < m) ? (Td)Gg[(int64_t)j * ld + i] : Td(0);
     }
 }
 
@@ -161,49 +162,66 @@ __device__ __forceinline__ void small_colpass(const T* __restrict__ As, int lda,
     }
 }
 
+// Wave-uniform copy of an integer (keeps sizes and loop bounds in scalar
+// registers inside this out-of-line function).
+__device__ __forceinline__ int small_uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Partial A f and A x over this wave's slice of the columns, lanes over rows
 // (RPL rows per lane, m <= 64 RPL): pf[(2w) m4 + i], pf[(2w+1) m4 + i].
-// Eight columns per step with every LDS read issued before the arithmetic;
-// the last step re-reads a valid column with zero weight (no branches).
+// Steps of eight columns issue every LDS read before the arithmetic; the
+// addresses advance by lda per column; two accumulator chains per output.
 template <typename T, int RPL>
 __device__ __forceinline__ void small_rowpass(const T* __restrict__ As, int lda, int m, int n, int m4,
                                               const double2* __restrict__ fx, double* __restrict__ pf) {
     constexpr int U = 8;
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const int j0 = (n * wave) / SMALL_W, j1 = (n * (wave + 1)) / SMALL_W;
-    double af[RPL], ax[RPL];
+    const int j0 = small_uni((n * wave) / SMALL_W), j1 = small_uni((n * (wave + 1)) / SMALL_W);
+    double af0[RPL], ax0[RPL], af1[RPL], ax1[RPL];
+    const T* cp = As + j0 * lda;
     int row[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
-        af[r] = 0.0; ax[r] = 0.0;
+        af0[r] = 0.0; ax0[r] = 0.0; af1[r] = 0.0; ax1[r] = 0.0;
         row[r] = min(lane + 64 * r, m - 1);
     }
-    for (int jb = j0; jb < j1; jb += U) {
+    int j = j0;
+    for (; j + U <= j1; j += U) {
         double2 f[U];
         double a[U][RPL];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int j = min(jb + u, j1 - 1);
-            f[u] = fx[j];
+            f[u] = fx[j + u];
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) a[u][r] = (double)As[(int64_t)j * lda + row[r]];
+            for (int r = 0; r < RPL; ++r) a[u][r] = (double)cp[u * lda + row[r]];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double wf = (jb + u < j1) ? f[u].x : 0.0, wx = (jb + u < j1) ? f[u].y : 0.0;
+        for (int u = 0; u < U; u += 2) {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
-                af[r] = fma(a[u][r], wf, af[r]);
-                ax[r] = fma(a[u][r], wx, ax[r]);
+                af0[r] = fma(a[u][r], f[u].x, af0[r]);
+                ax0[r] = fma(a[u][r], f[u].y, ax0[r]);
+                af1[r] = fma(a[u + 1][r], f[u + 1].x, af1[r]);
+                ax1[r] = fma(a[u + 1][r], f[u + 1].y, ax1[r]);
             }
         }
+        cp += U * lda;
+    }
+    for (; j < j1; ++j) {
+        const double2 f = fx[j];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const double a = (double)cp[row[r]];
+            af0[r] = fma(a, f.x, af0[r]);
+            ax0[r] = fma(a, f.y, ax0[r]);
+        }
+        cp += lda;
     }
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int i = lane + 64 * r;
         if (i < m) {
-            pf[(2 * wave) * m4 + i] = af[r];
-            pf[(2 * wave + 1) * m4 + i] = ax[r];
+            pf[(2 * wave) * m4 + i] = af0[r] + af1[r];
+            pf[(2 * wave + 1) * m4 + i] = ax0[r] + ax1[r];
         }
     }
 }
@@ -215,35 +233,45 @@ __device__ __forceinline__ void small_gpass(const T* __restrict__ Gs, int ldg, i
                                             const double* __restrict__ tv, double* __restrict__ pg) {
     constexpr int U = 8;
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const int k0 = (m * wave) / SMALL_W, k1 = (m * (wave + 1)) / SMALL_W;
-    double ag[RPL];
+    const int k0 = small_uni((m * wave) / SMALL_W), k1 = small_uni((m * (wave + 1)) / SMALL_W);
+    double ag0[RPL], ag1[RPL];
+    const T* cp = Gs + k0 * ldg;
     int row[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
-        ag[r] = 0.0;
+        ag0[r] = 0.0; ag1[r] = 0.0;
         row[r] = min(lane + 64 * r, m - 1);
     }
-    for (int kb = k0; kb < k1; kb += U) {
+    int k = k0;
+    for (; k + U <= k1; k += U) {
         double t[U];
         double g[U][RPL];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int k = min(kb + u, k1 - 1);
-            t[u] = tv[k];
+            t[u] = tv[k + u];
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) g[u][r] = (double)Gs[(int64_t)k * ldg + row[r]];
+            for (int r = 0; r < RPL; ++r) g[u][r] = (double)cp[u * ldg + row[r]];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double wt = (kb + u < k1) ? t[u] : 0.0;
+        for (int u = 0; u < U; u += 2) {
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) ag[r] = fma(g[u][r], wt, ag[r]);
+            for (int r = 0; r < RPL; ++r) {
+                ag0[r] = fma(g[u][r], t[u], ag0[r]);
+                ag1[r] = fma(g[u + 1][r], t[u + 1], ag1[r]);
+            }
         }
+        cp += U * ldg;
+    }
+    for (; k < k1; ++k) {
+        const double t = tv[k];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) ag0[r] = fma((double)cp[row[r]], t, ag0[r]);
+        cp += ldg;
     }
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int i = lane + 64 * r;
-        if (i < m) pg[wave * m4 + i] = ag[r];
+        if (i < m) pg[wave * m4 + i] = ag0[r] + ag1[r];
     }
 }
 
@@ -256,16 +284,24 @@ __device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, con
                                                  unsigned char* __restrict__ smem, SmallLayout& L,
                                                  SmallCol (&col)[CPT]) {
     const int m = d.m, n = d.n, tid = threadIdx.x;
-    L = small_layout(m, n, phase == 0 ? 4 : 8, num_waves());
+    // LDS entries are doubles in the FP64 phase, and in the FP32 phase too when
+    // the FP64 layout fits (FP32-rounded values held exactly as doubles)
+    const bool wide = (phase != 0) || (d.lds & DESC_LDS64);
+    L = small_layout(m, n, wide ? 8 : 4, num_waves());
     double* av = reinterpret_cast<double*>(smem + L.oav);
     double* tv = reinterpret_cast<double*>(smem + L.otv);
     __syncthreads();                       // earlier readers of the LDS are done
-    if (phase == 0)
-        small_fill<float>(reinterpret_cast<float*>(smem + L.oA), L.lda, reinterpret_cast<float*>(smem + L.oG),
-                          L.ldg, P.A32 + d.oA, P.G32 + d.oG, m, n, d.ld);
+    if (!wide)
+        small_fill<float, float>(reinterpret_cast<float*>(smem + L.oA), L.lda, reinterpret_cast<float*>(smem + L.oG),
+                                 L.ldg, P.A32 + d.oA, P.G32 + d.oG, m, n, d.ld);
+    else if (phase == 0)
+        small_fill<double, float>(reinterpret_cast<double*>(smem + L.oA), L.lda,
+                                  reinterpret_cast<double*>(smem + L.oG), L.ldg, P.A32 + d.oA, P.G32 + d.oG, m, n,
+                                  d.ld);
     else
-        small_fill<double>(reinterpret_cast<double*>(smem + L.oA), L.lda, reinterpret_cast<double*>(smem + L.oG),
-                           L.ldg, P.A64 + d.oA, P.G64 + d.oG, m, n, d.ld);
+        small_fill<double, double>(reinterpret_cast<double*>(smem + L.oA), L.lda,
+                                   reinterpret_cast<double*>(smem + L.oG), L.ldg, P.A64 + d.oA, P.G64 + d.oG, m, n,
+                                   d.ld);
     for (int i = tid; i < L.m4; i += blockDim.x) {
         av[i] = (i < m) ? Zy0[i] : 0.0;
         tv[i] = (i < m) ? Zy1[i] : 0.0;
@@ -275,7 +311,7 @@ __device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, con
     for (int q = 0; q < CPT; ++q) {
         const int j = tid + q * blockDim.x;
         if (j < n) {
-            if (phase == 0) {
+            if (!wide) {
                 const float* cp = reinterpret_cast<const float*>(smem + L.oA) + (int64_t)j * L.lda;
                 col[q].atz0 = small_dot(cp, av, L.m4);
                 col[q].atz1 = small_dot(cp, tv, L.m4);
@@ -305,7 +341,7 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     const LPDesc d = d_in;
     const PoolPtrs P = P_in;
     const SolveParams prm = prm_in;
-    const int m = d.m, n = d.n, ld = d.ld;
+    const int m = small_uni(d.m), n = small_uni(d.n), ld = small_uni(d.ld);
     const int tid = threadIdx.x;
     constexpr int W = SMALL_W;
     const LPCtrl cl = ctrl[k];
@@ -357,7 +393,8 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         col[q].aty = 0.0; col[q].atz0 = 0.0; col[q].atz1 = 0.0;
     }
 
-    SmallLayout L = small_layout(m, n, phase == 0 ? 4 : 8, W);
+    bool wide = (phase != 0) || (d.lds & DESC_LDS64);   // LDS entries are doubles
+    SmallLayout L = small_layout(m, n, wide ? 8 : 4, W);
     double* av = reinterpret_cast<double*>(smem + L.oav);
     double2* fx = reinterpret_cast<double2*>(smem + L.ofx);
     double* tv = reinterpret_cast<double*>(smem + L.otv);
@@ -389,14 +426,14 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
             __syncthreads();
         }
         double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-        if (phase == 0)
+        if (!wide)
             small_colpass<float, CPT>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m4, n, av, col, fx,
                                       pass_kind, p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, acc);
         else
             small_colpass<double, CPT>(reinterpret_cast<const double*>(smem + L.oA), L.lda, m4, n, av, col, fx,
                                        pass_kind, p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, acc);
         __syncthreads();
-        if (phase == 0) small_rowpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m, n, m4, fx, pf);
+        if (!wide) small_rowpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m, n, m4, fx, pf);
         else small_rowpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oA), L.lda, m, n, m4, fx, pf);
         __syncthreads();
         // row owner: A f, A x of the new state, t = y - A f, m-side sums
@@ -490,6 +527,7 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
                 cyc_chk += wall_clock64() - tc;
                 if (!(d.lds & DESC_LDS64)) { handover = true; break; }
                 small_load_phase<CPT>(phase, d, P, Zy0, Zy1, smem, L, col);
+                wide = true;
                 av = reinterpret_cast<double*>(smem + L.oav);
                 fx = reinterpret_cast<double2*>(smem + L.ofx);
                 tv = reinterpret_cast<double*>(smem + L.otv);
@@ -504,7 +542,7 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
 
         // ---- the inner update: a = G^{-1} t, border, scalars, y'
         const int64_t t1 = wall_clock64();
-        if (phase == 0) small_gpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oG), L.ldg, m, m4, tv, pg);
+        if (!wide) small_gpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oG), L.ldg, m, m4, tv, pg);
         else small_gpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oG), L.ldg, m, m4, tv, pg);
         __syncthreads();
         const int64_t t2 = wall_clock64();
