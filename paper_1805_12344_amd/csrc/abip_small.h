@@ -7,13 +7,17 @@
 // products are organised:
 //   * A and G^{-1} are copied into LDS once per precision phase, so an
 //     iteration touches no global memory.
-//   * thread j owns column j: x_j, s_j, c_j, cbar_j, the border entries and
-//     (A^T y)_j stay in its registers; (A^T a)_j is one LDS dot product and the
-//     prox root and dual update of x_j, s_j need no lane exchange.
-//   * thread i owns row i: y_i and the m-vectors of the border stay in its
-//     registers.  A f, A x and G^{-1} t come from sweeps in which wave w takes
-//     the w-th slice of the columns with lanes over rows; the row owner adds
-//     the W partial vectors in a fixed order (deterministic).
+//   * wave w owns a block of ceil(n/4) columns and a block of ceil(m/4) rows.
+//     A column's owner lane keeps x_j, s_j, c_j, cbar_j, the border entries
+//     and (A^T y)_j in registers: (A^T a)_j is one LDS dot product (split over
+//     a lane pair when n <= 128) and the prox root and dual update need no
+//     lane exchange.  A row's owner lane keeps y_i and the m-vectors of the
+//     border.
+//   * A f and A x: each wave sweeps its own columns with lanes over all rows
+//     and leaves a partial vector; G^{-1} t: each wave sweeps the columns of
+//     G^{-1} that match its own rows.  A wave only reads the f and t values
+//     its own lanes wrote, so neither sweep waits for the other waves; the row
+//     owners add the four partial vectors in a fixed order (deterministic).
 //   * (A^T y)_j of the relaxed y update y' = alpha (a - Zy p) + (1 - alpha) y
 //     (Section 4.2 applied to the y block) is carried by
 //         A^T y' = alpha (A^T a - p0 A^T Zy0 - p1 A^T Zy1) + (1 - alpha) A^T y,
@@ -21,11 +25,15 @@
 //     recomputed exactly by every refresh and restart pass, and old rounding
 //     errors are multiplied by |1 - alpha| < 1 at every step, so they stay
 //     bounded.
-// Five workgroup barriers per update: after the column pass, after the A f
-// sweep, in the check's sums, after the G^{-1} sweep and in the border sums.
+// Three workgroup barriers per update: after the A f sweep, in the check's
+// sums (which also publishes the G^{-1} t partials, computed before the tests
+// are taken) and in the border sums (which publishes a).
 #pragma once
 #include <hip/hip_runtime.h>
 #include "abip_internal.h"
+
+// four waves (256-thread launches)
+#define SMALL_W 4
 
 struct SmallCol {
     double x, s, c, cb, z0, z1;     // iterate, c, cbar, border columns of x
@@ -63,6 +71,40 @@ __device__ __forceinline__ double small_dot(const double* __restrict__ col, cons
     return (s0 + s1) + (s2 + s3);
 }
 
+// Wave-uniform copy of an integer (keeps sizes and loop bounds in scalar
+// registers inside this out-of-line function).
+__device__ __forceinline__ int small_uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Column ownership: wave w owns columns w*cb .. w*cb + cb - 1 (cb = ceil(n/4));
+// lane l owns column w*cb + l + 64 q (q < CPT), or, with PAIR (cb <= 32),
+// lanes 2l and 2l+1 share column w*cb + l: each takes every other group of
+// four rows and the halves are added across the lane pair (both lanes then
+// hold bitwise the same dot product).  Returns -1 for a lane with no column.
+template <int CPT, bool PAIR>
+__device__ __forceinline__ int small_col(int q, int cb, int n) {
+    const int lane = threadIdx.x & 63;
+    const int lo = PAIR ? (lane >> 1) : lane + 64 * q;
+    const int j = wave_id() * cb + lo;
+    return (lo < cb && j < n) ? j : -1;
+}
+template <typename T>
+__device__ __forceinline__ double small_dot_half(const T* __restrict__ col, const double* __restrict__ v, int m4,
+                                                 int h) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 2
+    for (int i = 4 * h; i < m4; i += 8) {
+        double a[4];
+        load4(col + i, a);
+        const double2 v0 = *reinterpret_cast<const double2*>(v + i);
+        const double2 v1 = *reinterpret_cast<const double2*>(v + i + 2);
+        s0 = fma(a[0], v0.x, s0);
+        s1 = fma(a[1], v0.y, s1);
+        s2 = fma(a[2], v1.x, s2);
+        s3 = fma(a[3], v1.y, s3);
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
 // Copy this phase's A and G^{-1} from the pools into LDS (zero rows m..lda-1).
 // FP32 data may be held as doubles (the same values, no conversion per use).
 template <typename Td, typename Ts>
@@ -80,14 +122,13 @@ __device__ __forceinline__ void small_fill(Td* __restrict__ As, int lda, Td* __r
     }
 }
 
-// The LDS-resident variant runs with 256 threads: four waves.
-#define SMALL_W 4
-
-// Block sum of K values (K = 4 or 12); every thread gets the totals, added in
-// a fixed order.  A reduce-scatter leaves lane group g (16 lanes) of each wave
-// with values K/4*g .. K/4*g + K/4 - 1; red holds them as [value][wave], read
-// back with 16-byte loads.  One barrier; red is not written again before the
-// caller's next barrier.
+// Block sum of K values (K = 4, 8, 12 or 16) over the four waves; every
+// thread gets the totals, added in a fixed order.  A reduce-scatter leaves lane
+// group g (16 lanes) of each wave with values K/4*g .. K/4*g + K/4 - 1; red
+// holds them as [value][wave], read back with 16-byte loads.  One barrier.
+// The two sums of an update use disjoint parts of red (the check's sums at 0,
+// the border's at 12 * 4), so neither overwrites what a slower wave may still
+// be reading.
 template <int K>
 __device__ __forceinline__ void small_bsum(double (&v)[K], double* __restrict__ red) {
     static_assert(K % 4 == 0 && K <= 16, "small_bsum: K = 4, 8, 12 or 16");
@@ -113,8 +154,8 @@ __device__ __forceinline__ void small_bsum(double (&v)[K], double* __restrict__ 
 // (x'+s', x') to fx and adds the column-side sums of the check to acc:
 //   c^T x, cbar^T x, c^T s, cbar^T s, ||A^T y + s - c tau||^2, ||A^T y + s||^2,
 //   ||-A^T y + c tau - cbar theta - s||^2.
-template <typename T, int CPT>
-__device__ __forceinline__ void small_colpass(const T* __restrict__ As, int lda, int m4, int n,
+template <typename T, int CPT, bool PAIR>
+__device__ __forceinline__ void small_colpass(const T* __restrict__ As, int lda, int m4, int n, int cb,
                                               const double* __restrict__ av, SmallCol (&col)[CPT],
                                               double2* __restrict__ fx, int op, double p0, double p1, double tmu,
                                               double alpha, double gamma, int rule, double tau, double theta,
@@ -122,10 +163,16 @@ __device__ __forceinline__ void small_colpass(const T* __restrict__ As, int lda,
     const double sg = sqrt(gamma);
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-        const int j = threadIdx.x + q * blockDim.x;
-        if (j < n) {
+        const int j = small_col<CPT, PAIR>(q, cb, n);
+        if (j >= 0) {
             SmallCol& C = col[q];
-            const double dv = small_dot(As + (int64_t)j * lda, av, m4);
+            double dv;
+            if constexpr (PAIR) {
+                const double hv = small_dot_half(As + (int64_t)j * lda, av, m4, (int)(threadIdx.x & 1));
+                dv = hv + dpp_partner<0xB1>(hv);                      // lane pair 2j, 2j+1
+            } else {
+                dv = small_dot(As + (int64_t)j * lda, av, m4);
+            }
             double x1 = C.x, s1 = C.s, aty;
             if (op == OP_PROX) {
                 const double dj = (C.x + C.s) + dv;                    // M^{-1} block, x part
@@ -147,35 +194,35 @@ __device__ __forceinline__ void small_colpass(const T* __restrict__ As, int lda,
                 }
             }
             C.x = x1; C.s = s1; C.aty = aty;
-            const double r1 = aty + s1 - C.c * tau;
-            const double r2 = aty + s1;
-            const double r3 = -aty + C.c * tau - C.cb * theta - s1;
-            acc[0] = fma(C.c, x1, acc[0]);
-            acc[1] = fma(C.cb, x1, acc[1]);
-            acc[2] = fma(C.c, s1, acc[2]);
-            acc[3] = fma(C.cb, s1, acc[3]);
+            const bool lead = !PAIR || (threadIdx.x & 1) == 0;        // one contribution per column
+            const double mk = lead ? 1.0 : 0.0;
+            const double r1 = (aty + s1 - C.c * tau) * mk;
+            const double r2 = (aty + s1) * mk;
+            const double r3 = (-aty + C.c * tau - C.cb * theta - s1) * mk;
+            const double cm = C.c * mk, cbm = C.cb * mk;
+            acc[0] = fma(cm, x1, acc[0]);
+            acc[1] = fma(cbm, x1, acc[1]);
+            acc[2] = fma(cm, s1, acc[2]);
+            acc[3] = fma(cbm, s1, acc[3]);
             acc[4] = fma(r1, r1, acc[4]);
             acc[5] = fma(r2, r2, acc[5]);
             acc[6] = fma(r3, r3, acc[6]);
-            fx[j] = make_double2(x1 + s1, x1);
+            if (lead) fx[j] = make_double2(x1 + s1, x1);
         }
     }
 }
 
-// Wave-uniform copy of an integer (keeps sizes and loop bounds in scalar
-// registers inside this out-of-line function).
-__device__ __forceinline__ int small_uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Partial A f and A x over this wave's slice of the columns, lanes over rows
+// Partial A f and A x over this wave's own column block (columns whose f the
+// wave's lanes wrote, so no barrier precedes the sweep), lanes over all rows
 // (RPL rows per lane, m <= 64 RPL): pf[(2w) m4 + i], pf[(2w+1) m4 + i].
 // Steps of eight columns issue every LDS read before the arithmetic; the
 // addresses advance by lda per column; two accumulator chains per output.
 template <typename T, int RPL>
-__device__ __forceinline__ void small_rowpass(const T* __restrict__ As, int lda, int m, int n, int m4,
+__device__ __forceinline__ void small_rowpass(const T* __restrict__ As, int lda, int m, int n, int m4, int cb,
                                               const double2* __restrict__ fx, double* __restrict__ pf) {
     constexpr int U = 8;
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const int j0 = small_uni((n * wave) / SMALL_W), j1 = small_uni((n * (wave + 1)) / SMALL_W);
+    const int j0 = small_uni(min(n, wave * cb)), j1 = small_uni(min(n, (wave + 1) * cb));
     double af0[RPL], ax0[RPL], af1[RPL], ax1[RPL];
     const T* cp = As + j0 * lda;
     int row[RPL];
@@ -226,14 +273,15 @@ __device__ __forceinline__ void small_rowpass(const T* __restrict__ As, int lda,
     }
 }
 
-// Partial G^{-1} t over this wave's slice of the columns of the symmetric
-// G^{-1}, lanes over rows as in the row pass: pg[w m4 + i].
+// Partial G^{-1} t over the columns of the symmetric G^{-1} that match this
+// wave's own row block (t values the wave's lanes wrote), lanes over all rows
+// as in the row pass: pg[w m4 + i].
 template <typename T, int RPL>
-__device__ __forceinline__ void small_gpass(const T* __restrict__ Gs, int ldg, int m, int m4,
+__device__ __forceinline__ void small_gpass(const T* __restrict__ Gs, int ldg, int m, int m4, int rb,
                                             const double* __restrict__ tv, double* __restrict__ pg) {
     constexpr int U = 8;
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const int k0 = small_uni((m * wave) / SMALL_W), k1 = small_uni((m * (wave + 1)) / SMALL_W);
+    const int k0 = small_uni(min(m, wave * rb)), k1 = small_uni(min(m, (wave + 1) * rb));
     double ag0[RPL], ag1[RPL];
     const T* cp = Gs + k0 * ldg;
     int row[RPL];
@@ -278,8 +326,8 @@ __device__ __forceinline__ void small_gpass(const T* __restrict__ Gs, int ldg, i
 // Copy this phase's A and G^{-1} into LDS (layout L is set for the phase)
 // and form (A^T Zy0)_j, (A^T Zy1)_j for the owned columns.  Starts and ends
 // with a barrier.
-template <int CPT>
-__device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, const PoolPtrs& P,
+template <int CPT, bool PAIR>
+__device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, int cb, const PoolPtrs& P,
                                                  const double* __restrict__ Zy0, const double* __restrict__ Zy1,
                                                  unsigned char* __restrict__ smem, SmallLayout& L,
                                                  SmallCol (&col)[CPT]) {
@@ -287,7 +335,7 @@ __device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, con
     // LDS entries are doubles in the FP64 phase, and in the FP32 phase too when
     // the FP64 layout fits (FP32-rounded values held exactly as doubles)
     const bool wide = (phase != 0) || (d.lds & DESC_LDS64);
-    L = small_layout(m, n, wide ? 8 : 4, num_waves());
+    L = small_layout(m, n, wide ? 8 : 4, SMALL_W);
     double* av = reinterpret_cast<double*>(smem + L.oav);
     double* tv = reinterpret_cast<double*>(smem + L.otv);
     __syncthreads();                       // earlier readers of the LDS are done
@@ -309,8 +357,8 @@ __device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, con
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-        const int j = tid + q * blockDim.x;
-        if (j < n) {
+        const int j = small_col<CPT, PAIR>(q, cb, n);
+        if (j >= 0) {
             if (!wide) {
                 const float* cp = reinterpret_cast<const float*>(smem + L.oA) + (int64_t)j * L.lda;
                 col[q].atz0 = small_dot(cp, av, L.m4);
@@ -329,10 +377,12 @@ __device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, con
 // true when the LP is finished here; false when the current phase does not fit
 // (on entry, or at the handover to FP64 data): then ctrl[k] and the pools hold
 // the state, with a tested FP64 refresh as the next pass, for the streamed
-// variant.  Requires m <= blockDim.x and n <= CPT * blockDim.x.
-template <int CPT, int RPL>
+// variant.  Requires four waves, m <= 64 RPL (and m <= 256) and
+// ceil(n/4) <= 64 CPT (<= 32 with PAIR).
+template <int CPT, int RPL, bool PAIR>
 __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __restrict__ ctrl, const PoolPtrs& P_in,
                                          const SolveParams& prm_in, int64_t fixed_iters) {
+    static_assert(!PAIR || CPT == 1, "column pairs own one column");
     // the launch's dynamic LDS, named here so that every access is an LDS access
     extern __shared__ __align__(16) unsigned char small_lds[];
     unsigned char* const smem = small_lds;
@@ -341,12 +391,13 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     const LPDesc d = d_in;
     const PoolPtrs P = P_in;
     const SolveParams prm = prm_in;
-    const int m = small_uni(d.m), n = small_uni(d.n), ld = small_uni(d.ld);
-    const int tid = threadIdx.x;
-    constexpr int W = SMALL_W;
+    const int m = small_uni(d.m), n = small_uni(d.n);
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const LPCtrl cl = ctrl[k];
     int phase = cl.phase;
-    if (num_waves() != W || !(d.lds & (phase == 0 ? DESC_LDS32 : DESC_LDS64))) return false;
+    if (num_waves() != SMALL_W || !(d.lds & (phase == 0 ? DESC_LDS32 : DESC_LDS64))) return false;
+    const int cb = small_uni((n + SMALL_W - 1) / SMALL_W);      // columns per wave
+    const int rb = small_uni((m + SMALL_W - 1) / SMALL_W);      // rows per wave
 
     const double* b = P.Mv + MF_B * P.Mtot + d.om;
     const double* bbar = P.Mv + MF_BBAR * P.Mtot + d.om;
@@ -367,7 +418,6 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     int64_t cp32 = cl.cp32, cp64 = cl.cp64;
     int status = cl.status;
     const int check_final_first = cl.flags & 1;
-    double pres = cl.pres, dres = cl.dres, gap = cl.gap, pobj = cl.pobj, dobj = cl.dobj;
     double l_ms2 = 0.0, l_cs4 = 0.0, l_tau = 0.0;
     bool l_have = false;
     double by_last = cl.by, cx_last = cl.cx;
@@ -375,36 +425,38 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     const double alpha = prm.alpha, gamma = prm.gamma, beta = prm.beta, eps = prm.eps;
     const double np1 = (double)n + 1.0;
 
-    // row owner registers (threads past m hold zeros and add nothing)
-    const bool rown = tid < m;
-    const int ri = rown ? tid : 0;
-    double y = rown ? Yg[ri] : 0.0;
-    const double rb = rown ? b[ri] : 0.0, rbb = rown ? bbar[ri] : 0.0;
-    const double rac = rown ? Ac[ri] : 0.0, racb = rown ? Acb[ri] : 0.0;
-    const double rz0 = rown ? Zy0[ri] : 0.0, rz1 = rown ? Zy1[ri] : 0.0;
+    // row owner registers: lane l of wave w owns row w*rb + l (lanes past the
+    // block or past m hold zeros and add nothing)
+    const int ri = wave * rb + lane;
+    const bool rown = lane < rb && ri < m;
+    const int rr = rown ? ri : 0;
+    double y = rown ? Yg[rr] : 0.0;
+    const double rbv = rown ? b[rr] : 0.0, rbb = rown ? bbar[rr] : 0.0;
+    const double rac = rown ? Ac[rr] : 0.0, racb = rown ? Acb[rr] : 0.0;
+    const double rz0 = rown ? Zy0[rr] : 0.0, rz1 = rown ? Zy1[rr] : 0.0;
     // column owner registers
     SmallCol col[CPT];
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-        const int j = tid + q * blockDim.x;
-        const int jj = (j < n) ? j : n - 1;
+        const int j = small_col<CPT, PAIR>(q, cb, n);
+        const int jj = (j >= 0) ? j : 0;
         col[q].x = X[jj]; col[q].s = S[jj]; col[q].c = C[jj]; col[q].cb = CBv[jj];
         col[q].z0 = ZX0[jj]; col[q].z1 = ZX1[jj];
         col[q].aty = 0.0; col[q].atz0 = 0.0; col[q].atz1 = 0.0;
     }
 
     bool wide = (phase != 0) || (d.lds & DESC_LDS64);   // LDS entries are doubles
-    SmallLayout L = small_layout(m, n, wide ? 8 : 4, W);
+    SmallLayout L = small_layout(m, n, wide ? 8 : 4, SMALL_W);
+    const int m4 = L.m4;                   // the same in both precisions
     double* av = reinterpret_cast<double*>(smem + L.oav);
     double2* fx = reinterpret_cast<double2*>(smem + L.ofx);
     double* tv = reinterpret_cast<double*>(smem + L.otv);
     double* pf = reinterpret_cast<double*>(smem + L.opf);
     double* pg = reinterpret_cast<double*>(smem + L.opg);
     double* red = reinterpret_cast<double*>(smem + L.ored);
-    const int m4 = L.m4;                   // the same in both precisions
 
     // this phase's matrices into LDS, and A^T Zy0, A^T Zy1 for the y recurrence
-    small_load_phase<CPT>(phase, d, P, Zy0, Zy1, smem, L, col);
+    small_load_phase<CPT, PAIR>(phase, d, cb, P, Zy0, Zy1, smem, L, col);
 
     double p0 = 0.0, p1 = 0.0;
     int pass_kind = (cl.mode == OP_PROX) ? OP_REFRESH : cl.mode;   // a state enters with a refresh
@@ -422,44 +474,54 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         const double tmu = mu / beta;      // t = mu / beta, eq. (Simple-Update:Barrier-X)
         const int64_t t0 = wall_clock64();
         if (pass_kind != OP_PROX) {        // exact A^T y of the (rescaled) state
-            if (rown) av[tid] = y;
+            if (rown) av[ri] = y;
             __syncthreads();
         }
+        // ---- column pass (own columns), then A f, A x over the own columns
         double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-        if (!wide)
-            small_colpass<float, CPT>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m4, n, av, col, fx,
-                                      pass_kind, p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, acc);
-        else
-            small_colpass<double, CPT>(reinterpret_cast<const double*>(smem + L.oA), L.lda, m4, n, av, col, fx,
-                                       pass_kind, p0, p1, tmu, alpha, gamma, prm.restart_rule, tau, theta, acc);
+        if (!wide) {
+            small_colpass<float, CPT, PAIR>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m4, n, cb, av, col,
+                                            fx, pass_kind, p0, p1, tmu, alpha, gamma, prm.restart_rule, tau,
+                                            theta, acc);
+            small_rowpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m, n, m4, cb, fx, pf);
+        } else {
+            small_colpass<double, CPT, PAIR>(reinterpret_cast<const double*>(smem + L.oA), L.lda, m4, n, cb, av,
+                                             col, fx, pass_kind, p0, p1, tmu, alpha, gamma, prm.restart_rule, tau,
+                                             theta, acc);
+            small_rowpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oA), L.lda, m, n, m4, cb, fx, pf);
+        }
         __syncthreads();
-        if (!wide) small_rowpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oA), L.lda, m, n, m4, fx, pf);
-        else small_rowpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oA), L.lda, m, n, m4, fx, pf);
-        __syncthreads();
-        // row owner: A f, A x of the new state, t = y - A f, m-side sums
+        // ---- row owner: A f, A x of the new state, t = y - A f, m-side sums
         double v12[12];
         {
             double Af = 0.0, Ax = 0.0;
             if (rown) {
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    Af += pf[(2 * w) * m4 + tid];
-                    Ax += pf[(2 * w + 1) * m4 + tid];
+                for (int w = 0; w < SMALL_W; ++w) {
+                    Af += pf[(2 * w) * m4 + ri];
+                    Ax += pf[(2 * w + 1) * m4 + ri];
                 }
-                tv[tid] = y - Af;
+                tv[ri] = y - Af;
             }
-            const double r1 = Ax - rb * tau;
+            const double r1 = Ax - rbv * tau;
             const double r3 = r1 + rbb * theta;
 #pragma unroll
             for (int q = 0; q < 7; ++q) v12[q] = acc[q];
-            v12[7] = rb * y;
+            v12[7] = rbv * y;
             v12[8] = rbb * y;
             v12[9] = r1 * r1;
             v12[10] = Ax * Ax;
             v12[11] = r3 * r3;
         }
-        small_bsum<12>(v12, red);
         cyc_col += wall_clock64() - t0;
+        // ---- G^{-1} t over the own rows, before the tests (a restart or a
+        // verdict leaves it unused); the sums' barrier publishes its partials
+        const int64_t t1 = wall_clock64();
+        if (!wide) small_gpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oG), L.ldg, m, m4, rb, tv, pg);
+        else small_gpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oG), L.ldg, m, m4, rb, tv, pg);
+        cyc_ginv += wall_clock64() - t1;
+        const int64_t tc = wall_clock64();
+        small_bsum<12>(v12, red);
         if (phase == 0) ++cp32; else ++cp64;
         const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
                                  (pass_kind == OP_REFRESH && !first);
@@ -472,7 +534,6 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         first = false;
         if (fixed_iters > 0 && done_fixed >= fixed_iters) break;
 
-        const int64_t tc = wall_clock64();
         const double cx = v12[0], cbx = v12[1];
         const double by = v12[7], bby = v12[8];
         const double ms2 = v12[9], ms3 = v12[10], ms4 = v12[11];
@@ -526,7 +587,7 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
                 pass_kind = OP_REFRESH;
                 cyc_chk += wall_clock64() - tc;
                 if (!(d.lds & DESC_LDS64)) { handover = true; break; }
-                small_load_phase<CPT>(phase, d, P, Zy0, Zy1, smem, L, col);
+                small_load_phase<CPT, PAIR>(phase, d, cb, P, Zy0, Zy1, smem, L, col);
                 wide = true;
                 av = reinterpret_cast<double*>(smem + L.oav);
                 fx = reinterpret_cast<double2*>(smem + L.ofx);
@@ -541,20 +602,15 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         cyc_chk += wall_clock64() - tc;
 
         // ---- the inner update: a = G^{-1} t, border, scalars, y'
-        const int64_t t1 = wall_clock64();
-        if (!wide) small_gpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oG), L.ldg, m, m4, tv, pg);
-        else small_gpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oG), L.ldg, m, m4, tv, pg);
-        __syncthreads();
         const int64_t t2 = wall_clock64();
-        cyc_ginv += t2 - t1;
         double a = 0.0;
         if (rown) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) a += pg[w * m4 + tid];
-            av[tid] = a;
+            for (int w = 0; w < SMALL_W; ++w) a += pg[w * m4 + ri];
+            av[ri] = a;
         }
-        double bs[4] = {rb * a, rbb * a, rac * a, racb * a};
-        small_bsum<4>(bs, red);
+        double bs[4] = {rbv * a, rbb * a, rac * a, racb * a};
+        small_bsum<4>(bs, red + 12 * SMALL_W);
         const double cs_f = cx + v12[2];        // c^T (x + s)
         const double cbs_f = cbx + v12[3];      // cbar^T (x + s)
         const double h1z = -bs[0] + cs_f + bs[2];      // h1^T z, c^T d = c^T f + (A c)^T a
@@ -575,11 +631,11 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     }
 
     // state back to the pools
-    if (rown) Yg[tid] = y;
+    if (rown) Yg[ri] = y;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-        const int j = tid + q * blockDim.x;
-        if (j < n) { X[j] = col[q].x; S[j] = col[q].s; }
+        const int j = small_col<CPT, PAIR>(q, cb, n);
+        if (j >= 0 && (!PAIR || (tid & 1) == 0)) { X[j] = col[q].x; S[j] = col[q].s; }
     }
     if (handover) {
         // the streamed variant continues with a tested refresh in FP64
@@ -598,19 +654,18 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         __syncthreads();
         return false;
     }
-    if (l_have && l_tau > 0.0) {           // the relative residuals of the last test
-        pobj = cx_last / l_tau;
-        dobj = by_last / l_tau;
-        pres = sqrt(l_ms2) / l_tau / (1.0 + nb);
-        dres = sqrt(l_cs4) / l_tau / (1.0 + nc);
-        gap = fabs(pobj - dobj) / (1.0 + fabs(pobj) + fabs(dobj));
-    }
     if (tid == 0) {
         LPCtrl& o = ctrl[k];
+        if (l_have && l_tau > 0.0) {       // the relative residuals of the last test
+            o.pobj = cx_last / l_tau;
+            o.dobj = by_last / l_tau;
+            o.pres = sqrt(l_ms2) / l_tau / (1.0 + nb);
+            o.dres = sqrt(l_cs4) / l_tau / (1.0 + nc);
+            o.gap = fabs(o.pobj - o.dobj) / (1.0 + fabs(o.pobj) + fabs(o.dobj));
+        }
         o.clk[0] += cyc_col; o.clk[1] += cyc_ginv; o.clk[2] += wall_clock64() - t_start;
         o.clk[3] += cyc_chk; o.clk[4] += cyc_upd;
         o.tau = tau; o.kappa = kappa; o.theta = theta; o.mu = mu;
-        o.pres = pres; o.dres = dres; o.gap = gap; o.pobj = pobj; o.dobj = dobj;
         o.by = by_last; o.cx = cx_last;
         o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
         o.cp32 = cp32; o.cp64 = cp64;
@@ -620,4 +675,34 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     }
     __syncthreads();
     return true;
+}
+
+// Pick the variant for this LP: rows per lane from m, column pairs when a
+// wave owns at most 32 columns, one or two columns per lane otherwise.
+__device__ inline bool solve_small_any(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
+                                       const SolveParams& prm, int64_t fixed_iters) {
+    const int rpl = (d.m + 63) >> 6;
+    const int cb = (d.n + SMALL_W - 1) / SMALL_W;
+    if (cb <= 32) {
+        switch (rpl) {
+        case 1: return solve_small<1, 1, true>(k, d, ctrl, P, prm, fixed_iters);
+        case 2: return solve_small<1, 2, true>(k, d, ctrl, P, prm, fixed_iters);
+        case 3: return solve_small<1, 3, true>(k, d, ctrl, P, prm, fixed_iters);
+        default: return solve_small<1, 4, true>(k, d, ctrl, P, prm, fixed_iters);
+        }
+    }
+    if (cb <= 64) {
+        switch (rpl) {
+        case 1: return solve_small<1, 1, false>(k, d, ctrl, P, prm, fixed_iters);
+        case 2: return solve_small<1, 2, false>(k, d, ctrl, P, prm, fixed_iters);
+        case 3: return solve_small<1, 3, false>(k, d, ctrl, P, prm, fixed_iters);
+        default: return solve_small<1, 4, false>(k, d, ctrl, P, prm, fixed_iters);
+        }
+    }
+    switch (rpl) {
+    case 1: return solve_small<2, 1, false>(k, d, ctrl, P, prm, fixed_iters);
+    case 2: return solve_small<2, 2, false>(k, d, ctrl, P, prm, fixed_iters);
+    case 3: return solve_small<2, 3, false>(k, d, ctrl, P, prm, fixed_iters);
+    default: return solve_small<2, 4, false>(k, d, ctrl, P, prm, fixed_iters);
+    }
 }

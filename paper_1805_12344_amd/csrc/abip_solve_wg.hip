@@ -615,24 +615,11 @@ __global__ __launch_bounds__(MAXT) void k_solve_wg(const LPDesc* __restrict__ de
         if (q >= B) break;
         const int k = order[q];
         const LPDesc d = desc[k];
-        // an LP whose current phase fits in LDS runs LDS-resident (256-thread
-        // builds); it comes back here (state in ctrl[k] and the pools) only to
-        // hand over to FP64 data that does not fit
+        // an LP whose current phase fits in LDS runs LDS-resident; it comes
+        // back here (state in ctrl[k] and the pools) only to hand over to FP64
+        // data that does not fit
         if (MAXT == 256 && d.lds != 0) {
-            const int rpl = (d.m + 63) >> 6;
-            bool done;
-            if (d.n <= 256) {
-                done = (rpl == 1) ? solve_small<1, 1>(k, d, ctrl, P, prm, fixed_iters)
-                     : (rpl == 2) ? solve_small<1, 2>(k, d, ctrl, P, prm, fixed_iters)
-                     : (rpl == 3) ? solve_small<1, 3>(k, d, ctrl, P, prm, fixed_iters)
-                                  : solve_small<1, 4>(k, d, ctrl, P, prm, fixed_iters);
-            } else {
-                done = (rpl == 1) ? solve_small<2, 1>(k, d, ctrl, P, prm, fixed_iters)
-                     : (rpl == 2) ? solve_small<2, 2>(k, d, ctrl, P, prm, fixed_iters)
-                     : (rpl == 3) ? solve_small<2, 3>(k, d, ctrl, P, prm, fixed_iters)
-                                  : solve_small<2, 4>(k, d, ctrl, P, prm, fixed_iters);
-            }
-            if (done) continue;
+            if (solve_small_any(k, d, ctrl, P, prm, fixed_iters)) continue;
         }
         // each LP runs the variant for its own row count (the launch's NCH is
         // the batch maximum): a small LP in a mixed batch holds no idle rows
