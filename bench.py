@@ -263,6 +263,68 @@ def extra_differentiable(abip, torch):
             "backward_over_forward": bwd / fwd}
 
 
+def extra_paper_random(abip, torch):
+    """The paper's random-LP recipe (lpgen.paper_random, seed 1) at three of its
+    Table 1 sizes and its tolerance 1e-3: one LP on the whole GPU (grid engine),
+    FP32 bulk + FP64 polish.  The paper's own ABIP times (a laptop CPU, other
+    instances drawn from the same recipe) are context, not a target."""
+    import lpgen
+    paper_s = {(500, 5000): 10.6, (1000, 10000): 56.0, (2000, 10000): 889.0}
+    out = []
+    for (m, n), ps in paper_s.items():
+        lp = lpgen.paper_random(m, n, 1)
+        A = torch.tensor(lp["A"], device="cuda")
+        b = torch.tensor(lp["b"], device="cuda")
+        c = torch.tensor(lp["c"], device="cuda")
+        torch.cuda.synchronize()
+        s = abip.abip_default_settings(eps=1e-3, engine=abip.ABIP_ENGINE_GRID, precision=abip.ABIP_PREC_FP32_POLISH)
+        t0 = time.perf_counter()
+        w = abip.abip_setup(A, b, c, s)
+        x, y, sv, info = abip.abip_solve(w)
+        torch.cuda.synchronize()
+        total_s = time.perf_counter() - t0
+        xh, yh, sh = x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy()
+        pres = np.linalg.norm(lp["A"] @ xh - lp["b"]) / (1 + np.linalg.norm(lp["b"]))
+        dres = np.linalg.norm(lp["A"].T @ yh + sh - lp["c"]) / (1 + np.linalg.norm(lp["c"]))
+        po, do = float(lp["c"] @ xh), float(lp["b"] @ yh)
+        gap = abs(po - do) / (1 + abs(po) + abs(do))
+        w.free()
+        out.append({"m": m, "n": n, "status": info["status_name"], "admm_iters": info["admm_iters"],
+                    "setup_plus_solve_s": total_s, "solve_kernel_s": info["kernel_ms"] / 1e3,
+                    "host_kkt": [pres, dres, gap], "pobj": po, "pstar": lp["pstar"],
+                    "paper_abip_s_laptop_cpu": ps})
+    return {"workload": "paper's random-LP recipe, seed 1, eps 1e-3, fp32 bulk + fp64 polish, grid engine",
+            "instances": out}
+
+
+def extra_sice(abip, torch, d=64, N=1000):
+    """Sparse inverse covariance estimation (lpgen.sice: synthetic Sigma, d
+    variables, N samples, lambda = 1.5 sqrt(log d / N)): the d column LPs
+    (2d x 4d each) in one batched launch, FP32 bulk + FP64 polish."""
+    import lpgen
+    S = lpgen.sice(d, N, 1)
+    A = torch.tensor(S["A"], device="cuda")
+    c = torch.tensor(S["c"], device="cuda")
+    bs = [torch.tensor(b, device="cuda") for b in S["bs"]]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w = abip.abip_setup_batch([A] * d, bs, [c] * d, abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH))
+    xs, ys, ss, infos = abip.abip_solve_batch(w)
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    X = torch.stack(xs).cpu().numpy()
+    B = X[:, :d] - X[:, d:2 * d]
+    viol = float(np.abs(S["Sigma"] @ B.T - np.eye(d)).max() / S["lam"])
+    its = [i["admm_iters"] for i in infos]
+    st = np.bincount([i["status"] for i in infos], minlength=5).tolist()
+    w.free()
+    return {"workload": f"SICE d={d} (N={N} samples, lambda={S['lam']:.4f}): {d} LPs of {2 * d} x {4 * d}, "
+                        "one batched launch, fp32 bulk + fp64 polish, eps 1e-6",
+            "statuses": st, "setup_plus_solve_s": total_s, "solve_kernel_s": infos[0]["kernel_ms"] / 1e3,
+            "admm_iters_mean": float(np.mean(its)), "admm_iters_max": int(np.max(its)),
+            "max_constraint_over_lambda": viol, "l1_norm_of_omega": float(np.abs(B).sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,7 +445,8 @@ def main():
 
     if not args.no_extra:
         for key, fn in [("basis_pursuit", extra_basis_pursuit), ("sparse_cg", extra_sparse),
-                        ("differentiable", extra_differentiable)]:
+                        ("differentiable", extra_differentiable), ("paper_random", extra_paper_random),
+                        ("sice", extra_sice)]:
             t0 = time.perf_counter()
             line[key] = fn(abip, torch)
             log(f"{key}: {time.perf_counter() - t0:.1f} s")

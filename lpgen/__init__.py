@@ -21,6 +21,15 @@ these synthetic shapes stand in for them):
 * ``batch``              -- many dense planted LPs of uneven size, a fraction
                             of them made primal infeasible by a planted
                             Farkas vector.
+* ``paper_random``       -- the random dense LP recipe of the paper's random-LP
+                            experiments (Section 5): A = U^T D V with sparse
+                            Gaussian factors, a planted x split 60/10/30 into
+                            zero / ten times larger / ten times smaller entries,
+                            complementary s, Gaussian y.
+* ``sice``               -- the sparse inverse covariance estimation LPs of
+                            Section 5 (one LP per column of Omega) with a
+                            synthetic sample covariance standing in for the UCI
+                            data.
 * toy LPs with closed-form answers.
 """
 from __future__ import annotations
@@ -39,6 +48,8 @@ __all__ = [
     "toy_primal_infeasible",
     "toy_dual_infeasible",
     "config0",
+    "paper_random",
+    "sice",
 ]
 
 
@@ -240,3 +251,75 @@ def toy_dual_infeasible():
     """min -x1 s.t. x1 - x2 = 0: unbounded along the ray (1, 1)."""
     return dict(A=np.array([[1.0, -1.0]]), b=np.array([0.0]), c=np.array([-1.0, 0.0]),
                 ray=np.array([1.0, 1.0]) / np.sqrt(2.0), status="dual_infeasible", m=1, n=2)
+
+
+def _sprandn(rng, rows, cols, density):
+    """Dense array with a uniform random pattern of about density*rows*cols
+    standard normal entries (the rest zero)."""
+    mask = rng.random((rows, cols)) < density
+    return np.where(mask, rng.standard_normal((rows, cols)), 0.0)
+
+
+def paper_random(m, n, seed):
+    """The random dense LP recipe of the paper's random-LP experiments (Section 5).
+
+    x: Gaussian, split at random into 60% zeros, 10% scaled by 10 and 30%
+    scaled by 1/10; s: standard normal on the zero set of x, zero elsewhere, so
+    x o s = 0.  The paper's text leaves the signs of x and s free, which would
+    break x, s >= 0; absolute values are taken.  A = U^T D V with
+    D = diag(N(0,1)), U an m x m and V an m x n sparse Gaussian matrix of
+    density 0.2; y ~ N(0,1); b = A x, c = A^T y + s, so (x, y, s) is a planted
+    optimal pair (the optimum need not be unique; the optimal value
+    c^T x = b^T y is).
+    """
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n)
+    perm = rng.permutation(n)
+    n0, n1 = int(round(0.6 * n)), int(round(0.1 * n))
+    zero, big, small = perm[:n0], perm[n0:n0 + n1], perm[n0 + n1:]
+    x[zero] = 0.0
+    x[big] *= 10.0
+    x[small] *= 0.1
+    x = np.abs(x)
+    s = np.zeros(n)
+    s[zero] = np.abs(rng.standard_normal(zero.size))
+    D = rng.standard_normal(m)
+    U = _sprandn(rng, m, m, 0.2)
+    V = _sprandn(rng, m, n, 0.2)
+    A = U.T @ (D[:, None] * V)
+    y = rng.standard_normal(m)
+    b = A @ x
+    c = A.T @ y + s
+    return dict(A=A, b=b, c=c, x0=x, y0=y, s0=s, pstar=float(c @ x), status="solved", m=m, n=n,
+                groups=dict(zero=np.sort(zero), big=np.sort(big), small=np.sort(small)))
+
+
+def sice(d, N, seed, cols=None):
+    """Sparse inverse covariance estimation LPs (Section 5), one per column j
+    of Omega: min e^T (beta+ + beta-) s.t. Sigma beta+ - Sigma beta- + w+ =
+    lambda e + e_j, w+ + w- = 2 lambda e, all variables >= 0; m = 2d, n = 4d.
+
+    Sigma is the sample covariance of N draws of a d-variate Gaussian with a
+    random well-conditioned covariance (a stand-in for the UCI data sets, which
+    are not available); lambda = (3/2) sqrt(log(d) / N) as in the paper.
+    Returns the shared A (2d x 4d, rows [Sigma, -Sigma, I, 0] and [0, 0, I, I]),
+    c, and one b per requested column (all d by default).
+    """
+    rng = np.random.default_rng(seed)
+    L = rng.standard_normal((d, d)) / np.sqrt(d)
+    cov = L @ L.T + 0.5 * np.eye(d)
+    X = rng.standard_normal((N, d)) @ np.linalg.cholesky(cov).T
+    X -= X.mean(axis=0)
+    Sigma = X.T @ X / N
+    lam = 1.5 * np.sqrt(np.log(d) / N)
+    I = np.eye(d)
+    Z = np.zeros((d, d))
+    A = np.block([[Sigma, -Sigma, I, Z], [Z, Z, I, I]])
+    c = np.concatenate([np.ones(2 * d), np.zeros(2 * d)])
+    cols = list(range(d)) if cols is None else list(cols)
+    bs = []
+    for j in cols:
+        e = np.zeros(d)
+        e[j] = 1.0
+        bs.append(np.concatenate([lam * np.ones(d) + e, 2.0 * lam * np.ones(d)]))
+    return dict(A=A, c=c, bs=bs, cols=cols, Sigma=Sigma, lam=lam, d=d, N=N, m=2 * d, n=4 * d)
