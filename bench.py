@@ -335,7 +335,11 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the basis-pursuit, sparse and differentiable extra measurements")
+                    help="skip the extra measurements (basis pursuit, sparse CG, differentiable batch, "
+                         "the paper's random LPs, SICE)")
+    ap.add_argument("--extra-only", default=None,
+                    choices=["basis_pursuit", "sparse_cg", "differentiable", "paper_random", "sice"],
+                    help="run one extra measurement alone, print its JSON object and exit (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (PMC byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -351,6 +355,11 @@ def main():
     import paper_1805_12344_amd as abip
 
     torch.cuda.set_device(0)
+    extras = {"basis_pursuit": extra_basis_pursuit, "sparse_cg": extra_sparse,
+              "differentiable": extra_differentiable, "paper_random": extra_paper_random, "sice": extra_sice}
+    if args.extra_only:
+        print(json.dumps({args.extra_only: extras[args.extra_only](abip, torch)}), flush=True)
+        return
     lps = make_workload(args.batch, args.seed)
     As, bs, cs = to_device(lps)
     s32 = abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH)
@@ -444,9 +453,7 @@ def main():
         gpu_iters64 = iters
 
     if not args.no_extra:
-        for key, fn in [("basis_pursuit", extra_basis_pursuit), ("sparse_cg", extra_sparse),
-                        ("differentiable", extra_differentiable), ("paper_random", extra_paper_random),
-                        ("sice", extra_sice)]:
+        for key, fn in extras.items():
             t0 = time.perf_counter()
             line[key] = fn(abip, torch)
             log(f"{key}: {time.perf_counter() - t0:.1f} s")
