@@ -116,3 +116,45 @@ def test_lds_batch_matches_streamed_and_kkt():
         for k, lp in enumerate(lps):
             _check_solution(lp, xs[k], ys[k], ss[k], infos[k])
         w.free()
+
+
+# edge shapes of the LDS-resident layout: one row, one column, the column-pair
+# boundary (ceil(n/4) = 32 / 33), two columns per lane (n > 256), rows per lane
+# 2 and 3, FP64 data that does and does not fit
+EDGE = [(1, 1, 31), (1, 7, 32), (3, 3, 33), (4, 128, 34), (4, 129, 35), (5, 300, 40), (64, 100, 45),
+        (65, 70, 38), (129, 140, 42)]
+
+
+@pytest.mark.parametrize("m,n,seed", EDGE)
+def test_lds_edge_shapes_match_oracle_and_streamed(m, n, seed):
+    print(f"lds edge m={m} n={n} seed={seed}", flush=True)
+    lp = lpgen.dense_planted(m, n, seed)
+    prob = Problem(lp["A"], lp["b"], lp["c"])
+    s = Settings(alpha=1.8, gamma=0.5, restart_rule="heuristic")
+    st0 = oracle.restart(oracle.initial_state(prob, s), s.gamma, "heuristic")
+    solver = oracle.SchurIQSolver(prob)
+    N = 30
+    st = st0.copy()
+    for _ in range(N):
+        st = oracle.admm_iteration(prob, solver, st, s)
+    scale = 1.0 + np.abs(st.u()).max()
+    got = {}
+    for lds in (1, 0):
+        for fp32 in (False, True):
+            got[(lds, fp32)] = _iterate(lp, st0, N, lds, fp32, "heuristic")
+    for lds in (1, 0):
+        y, x, sv, sc = got[(lds, False)]
+        for g, ref in [(y, st.y), (x, st.x), (sv, st.s)]:
+            assert np.abs(g - ref).max() <= 1e-10 * scale, (lds, m, n)
+        assert abs(sc["tau"] - st.tau) <= 1e-10 * scale
+    a, b = got[(1, True)], got[(0, True)]
+    for ga, gb in zip(a[:3], b[:3]):
+        assert np.abs(ga - gb).max() <= 1e-9 * scale
+    # full solve, default settings (LDS-resident where it fits), against the oracle's status
+    ref = oracle.solve(lp["A"], lp["b"], lp["c"])
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"], abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH))
+    x, y, sv, info = abip.abip_solve(w)
+    assert info["status_name"] == ref["status_name"]
+    if ref["status_name"] == "solved":
+        k = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(sv))
+        assert max(k["pres"], k["dres"], k["gap"]) <= 1e-6, k
