@@ -107,8 +107,11 @@ typedef struct {
                                   in one workgroup's LDS (in the precision of the current phase;
                                   m <= threads, n <= 2 threads) is solved from LDS, with no global
                                   memory traffic per iteration; 0: every LP streams A and G^{-1}
-                                  from HBM.  Same iteration and tests; the sums are formed in a
-                                  different order, so results agree to rounding, not bitwise. */
+                                  from HBM.  In the sparse engine, 1 lets each workgroup keep its
+                                  rows of CSR(A) and CSR(A^T) in LDS for the CG passes when they
+                                  fit; 0: the CG passes read them from global memory.  Same
+                                  iteration and tests; the sums are formed in a different order,
+                                  so results agree to rounding, not bitwise. */
 } abip_settings;
 
 /* Per-LP result summary (host struct). */

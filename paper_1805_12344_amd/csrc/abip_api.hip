@@ -259,7 +259,9 @@ struct abip_work {
     int sp_nb = 1;
     int32_t* sp_idx = nullptr;       // rp (m+1), ci (nnz), rpt (n+1), cit (nnz), cursor (n)
     double* sp_val = nullptr;        // va (nnz), vat (nnz)
-    double* sp_vec = nullptr;        // dG, a, r, z, p, q (m); ATZy0, ATZy1, ATY, ATA, q1 (n); part
+    double* sp_vec = nullptr;        // dG, a, z, p (m); CG records (4 m); ATZy0, ATZy1, ATY, ATA, q1 (n); part
+    std::vector<int32_t> sp_hrp, sp_hrpt;   // host copies of the row pointers of CSR(A), CSR(A^T)
+    int sp_lds_cap = 0;              // dynamic LDS the cooperative kernels may use
     unsigned* sp_bar = nullptr;      // grid barrier words
     int* sp_err = nullptr;
     int64_t* sp_cgit = nullptr;
@@ -676,6 +678,27 @@ static int lanes_for(double avg) {           // lanes per CSR row: about 4 entri
     return L;
 }
 
+// Dynamic LDS of a launch of nb workgroups: enough for the largest slices
+// that fit (a workgroup whose slices do not fit runs the global-memory
+// passes); 0 when none fits or the launch would not be co-resident with it.
+static int sp_lds_for(const abip_work* w, int nb) {
+    const SpArgs& g = w->sa;
+    if (w->sp_lds_cap <= 0 || w->sp_hrp.empty() || w->sp_hrpt.empty()) return 0;
+    int64_t need = 0;
+    for (int b = 0; b < nb; ++b) {
+        int rlo, rhi, clo, chi;
+        sp_share(g.m, b, nb, &rlo, &rhi);
+        sp_share(g.n, b, nb, &clo, &chi);
+        const int64_t by = sp_slice_bytes(chi - clo, w->sp_hrpt[chi] - w->sp_hrpt[clo], rhi - rlo,
+                                          w->sp_hrp[rhi] - w->sp_hrp[rlo]);
+        if (by <= w->sp_lds_cap) need = std::max(need, by);
+    }
+    if (need == 0) return 0;
+    const int bytes = (int)std::min<int64_t>(w->sp_lds_cap, (need + 255) & ~(int64_t)255);
+    if (nb > sp_max_blocks(w->cu_count, bytes)) return 0;
+    return bytes;
+}
+
 static double host_sum(const std::vector<double>& v, int k, int nblk) {
     double s = 0.0;
     for (int i = 0; i < nblk; ++i) s += v[(size_t)k * nblk + i];
@@ -722,7 +745,7 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
 #define SCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return bail(fail(ABIP_E_HIP, "%s: %s", #call, hipGetErrorString(e_))); } while (0)
     const int64_t nidx = (int64_t)(m + 1) + nnz + (n + 1) + nnz + n;
     const int NBLK = 64;
-    const int64_t nvec = 7 * (int64_t)d.ld + 5 * (int64_t)w->Ntot + (int64_t)SP_PS * 4 * w->cu_count;
+    const int64_t nvec = 8 * (int64_t)d.ld + 5 * (int64_t)w->Ntot + (int64_t)SP_PS * 4 * w->cu_count;
     SALLOC(w->ddesc, 1); SALLOC(w->dctrl, 1);
     SALLOC(w->Mv, (int64_t)NMF * w->Mtot); SALLOC(w->Nv, (int64_t)NNF * w->Ntot);
     SALLOC(w->errflag, 1); SALLOC(w->outp, 3);
@@ -744,12 +767,14 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     g.rp = rp; g.ci = ci; g.va = va; g.rpt = rpt; g.cit = cit; g.vat = vat;
     double* V = w->sp_vec;
     double* dG = V; V += d.ld;
-    g.a = V; V += d.ld; g.r = V; V += d.ld; g.z = V; V += d.ld; g.p = V; V += d.ld; g.q = V; V += d.ld;
-    g.sv = V; V += d.ld;
+    g.a = V; V += d.ld; g.z = V; V += d.ld; g.p = V; V += d.ld;
+    g.rw = reinterpret_cast<SpRow*>(V); V += 4 * (int64_t)d.ld;     // 32-byte records (ld is a multiple of 4)
     double* ATZy0 = V; V += w->Ntot;
     double* ATZy1 = V; V += w->Ntot;
     g.ATY = V; V += w->Ntot; g.ATA = V; V += w->Ntot; g.q1 = V; V += w->Ntot;
     g.part = V; V += (int64_t)SP_PS * 4 * w->cu_count;          // partial sums of up to 4 workgroups per CU
+    g.nbp = 4 * w->cu_count;
+    g.lds_bytes = 0;
     g.dG = dG; g.ATZy0 = ATZy0; g.ATZy1 = ATZy1;
     double* Mv = w->Mv;
     double* Nv = w->Nv;
@@ -796,6 +821,15 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     // CSR(A^T), Jacobi diagonal, HSD constants (eq. bar-b-c-z-re)
     SCHK(sp_transpose(g, rpt, cit, vat, cursor, st));
     SCHK(sp_rowsq(g, dG, st));
+    // row pointers on the host, to size each launch's LDS-resident slices
+    w->sp_hrp.resize((size_t)m + 1);
+    w->sp_hrpt.resize((size_t)n + 1);
+    SCHK(hipMemcpyAsync(w->sp_hrp.data(), rp, sizeof(int32_t) * ((size_t)m + 1), hipMemcpyDeviceToHost, st));
+    SCHK(hipMemcpyAsync(w->sp_hrpt.data(), rpt, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, st));
+    SCHK(hipStreamSynchronize(st));
+    (void)hipDeviceGetAttribute(&w->lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    w->sp_lds_cap = (w->lds_cap > 1024) ? w->lds_cap - 1024 : 0;      // the kernels' static LDS stays free
+    if (w->sp_lds_cap > 0) SCHK(sp_set_lds_limit(w->sp_lds_cap));
     SCHK(sp_affine(fC, 0.0, 1.0, n, g.q1, st));                               // e (scratch)
     SCHK(sp_spmv(rp, ci, va, m, g.q1, -1.0, fb, 1.0, fbb, st));              // bbar = b - A e
     SCHK(sp_affine(fC, 1.0, -1.0, n, fCB, st));                               // cbar = c - e
@@ -820,8 +854,9 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     const double nb = std::sqrt(host_sum(hp, 0, NBLK));
     // the border Z = M^{-1} H (Section 4.4, rank 2): Z_y = G^{-1}(e - A f), Z_x = f + A^T Z_y
     // for H1 = (-b; c) and H2 = (bbar; -cbar), by CG to near machine precision
-    const int maxb = std::min(sp_max_blocks(w->cu_count), 4 * w->cu_count);
+    const int maxb = std::min(sp_max_blocks(w->cu_count, 0), 4 * w->cu_count);
     w->sp_nb = std::max(1, std::min<int>(maxb, (int)std::min<int64_t>(w->cu_count, (std::max<int64_t>(m, n) + 255) / 256)));
+    g.lds_bytes = s.lds_resident ? sp_lds_for(w, w->sp_nb) : 0;
     double* rhs = g.Y;                                                         // scratch until the solve
     const int32_t bmax = std::max<int32_t>(5000, 20 * s.cg_max_iters);
     SCHK(sp_spmv(rp, ci, va, m, fC, -1.0, fb, -1.0, rhs, st));               // -b - A c
@@ -876,6 +911,7 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
 static int sparse_run(abip_work* w, int64_t fixed) {
     hipStream_t st = w->stream;
     SpArgs g = w->sa;
+    g.lds_bytes = w->set.lds_resident ? sp_lds_for(w, w->sp_nb) : 0;
     g.prm = make_params(w->set);
     g.cg_tol = w->set.cg_tol;
     g.cg_max = w->set.cg_max_iters;
@@ -1216,7 +1252,7 @@ extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t ma
     if (iters < 1) return fail(ABIP_E_INVALID, "abip_autotune: iters must be >= 1");
     std::vector<int> cand;
     if (w->sparse) {
-        const int maxb = std::min(sp_max_blocks(w->cu_count), 4 * w->cu_count);
+        const int maxb = std::min(sp_max_blocks(w->cu_count, 0), 4 * w->cu_count);
         for (int nb : {32, 64, 128, 256})
             if (nb <= maxb) cand.push_back(nb);
         if (cand.empty()) cand.push_back(maxb);

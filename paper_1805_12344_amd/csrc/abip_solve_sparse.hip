@@ -11,8 +11,9 @@
 // partial sums in the same fixed order and takes the same decisions, so runs
 // are bitwise reproducible.  Per update: the column pass (prox, dual update,
 // A^T y of the new iterate, column sums of the check), the row pass (A x, A s,
-// the row sums of the check, the CG right-hand side and start), then 3
-// barriers per CG iteration.
+// the row sums of the check, the CG right-hand side and start), then 2
+// barriers per CG iteration.  A workgroup whose rows of CSR(A) and CSR(A^T)
+// fit in the launch's LDS keeps them there for the CG passes.
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <cmath>
@@ -73,23 +74,34 @@ __device__ __forceinline__ bool grid_failed(int* err) {
 
 // Block sum of K per-thread values written to this workgroup's partial slots.
 template <int K>
-__device__ __forceinline__ void put_parts(double (&v)[K], double* part, int slot, double* sbuf) {
+__device__ __forceinline__ void put_parts(double (&v)[K], double* part, int nbp, int slot, double* sbuf) {
     block_sum_n<K>(v, sbuf);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) part[(int64_t)blockIdx.x * SP_PS + slot + k] = v[k];
+        for (int k = 0; k < K; ++k) part[(int64_t)(slot + k) * nbp + blockIdx.x] = v[k];
     }
 }
 
 // Totals of K partial slots over all workgroups, in a fixed order (lane l
-// takes workgroups l, l+64, ...; then the wave sum).  Every thread gets them.
+// adds workgroups l, l+64, l+128, l+192 as two pairs, then every 256th; then
+// the wave sum); one value per wave at a time, every load of a value issued
+// together.  Every thread gets the totals.
 template <int K>
-__device__ __forceinline__ void get_parts(const double* part, int slot, double (&out)[K], double* sbuf) {
+__device__ __forceinline__ void get_parts(const double* part, int nbp, int slot, double (&out)[K], double* sbuf) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int nb = gridDim.x;
     for (int k = wave; k < K; k += W) {
-        double s = 0.0;
-        for (int bb = lane; bb < (int)gridDim.x; bb += 64) s += part[(int64_t)bb * SP_PS + slot + k];
-        s = wave_sum(s);
+        const double* pk = part + (int64_t)(slot + k) * nbp;
+        double s0 = 0.0, s1 = 0.0;
+        for (int b0 = lane; b0 < nb; b0 += 256) {
+            const double v0 = pk[b0];
+            const double v1 = (b0 + 64 < nb) ? pk[b0 + 64] : 0.0;
+            const double v2 = (b0 + 128 < nb) ? pk[b0 + 128] : 0.0;
+            const double v3 = (b0 + 192 < nb) ? pk[b0 + 192] : 0.0;
+            s0 += v0 + v1;
+            s1 += v2 + v3;
+        }
+        double s = wave_sum(s0 + s1);
         if (lane == 0) sbuf[k] = s;
     }
     __syncthreads();
@@ -129,9 +141,101 @@ __device__ __forceinline__ void row_sums(const int32_t* idx, const double* val, 
 
 struct Range { int lo, hi; };
 __device__ __forceinline__ Range my_range(int total) {
-    const int per = (total + gridDim.x - 1) / gridDim.x;
-    const int lo = min(total, (int)blockIdx.x * per);
-    return {lo, min(total, lo + per)};
+    Range r;
+    sp_share(total, (int)blockIdx.x, (int)gridDim.x, &r.lo, &r.hi);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident slices.  A workgroup owns the same columns (rows of CSR(A^T))
+// and rows of CSR(A) for the whole launch, so it copies those rows of both
+// matrices into LDS once; the CG passes then read no matrix entry from global
+// memory (a grid barrier's acquire leaves the L2 cold for them otherwise).
+// A pass forms every product val[e] * f(idx[e]) of the slice with all the
+// gathers of a round in flight, stores them in LDS, and the owner of each row
+// adds its products in entry order (deterministic).
+// ---------------------------------------------------------------------------
+struct SpSlice {
+    int n, ne;                 // rows, entries
+    const int32_t* ptr;        // n + 1 offsets (LDS)
+    const int32_t* idx;        // ne column indices (LDS)
+    const double* val;         // ne values (LDS)
+};
+struct SpLds {
+    bool on;
+    SpSlice t, a;              // CSR(A^T) rows of the workgroup's columns, CSR(A) rows of its rows
+    double* prod;              // max(t.ne, a.ne) products
+};
+
+// Copy the slices when they fit in the launch's dynamic LDS (the decision is
+// the workgroup's own; the others may run the global-memory passes).  Ends
+// with a workgroup barrier when it copies.
+__device__ SpLds sp_lds_init(const SpArgs& g, Range R, Range Cc, unsigned char* lds) {
+    SpLds L;
+    L.on = false;
+    if (g.lds_bytes <= 0) return L;
+    const int tid = threadIdx.x;
+    const int tb = g.rpt[Cc.lo], te = g.rpt[Cc.hi], ab = g.rp[R.lo], ae = g.rp[R.hi];
+    const int tnc = Cc.hi - Cc.lo, tne = te - tb, anr = R.hi - R.lo, ane = ae - ab;
+    if (sp_slice_bytes(tnc, tne, anr, ane) > (int64_t)g.lds_bytes) return L;
+    double* tval = reinterpret_cast<double*>(lds);
+    double* aval = tval + tne;
+    double* prod = aval + ane;
+    int32_t* tidx = reinterpret_cast<int32_t*>(prod + max(tne, ane));
+    int32_t* aidx = tidx + tne;
+    int32_t* tptr = aidx + ane;
+    int32_t* aptr = tptr + (tnc + 1);
+    for (int e = tid; e < tne; e += SP_THREADS) { tidx[e] = g.cit[tb + e]; tval[e] = g.vat[tb + e]; }
+    for (int e = tid; e < ane; e += SP_THREADS) { aidx[e] = g.ci[ab + e]; aval[e] = g.va[ab + e]; }
+    for (int c = tid; c <= tnc; c += SP_THREADS) tptr[c] = g.rpt[Cc.lo + c] - tb;
+    for (int r = tid; r <= anr; r += SP_THREADS) aptr[r] = g.rp[R.lo + r] - ab;
+    __syncthreads();
+    L.on = true;
+    L.t = {tnc, tne, tptr, tidx, tval};
+    L.a = {anr, ane, aptr, aidx, aval};
+    L.prod = prod;
+    return L;
+}
+
+// prod[e] = val[e] * f(idx[e]) for every entry of the slice, eight entries per
+// thread and round with their gathers issued together; ends with a workgroup
+// barrier.
+template <typename F>
+__device__ __forceinline__ void slice_products(const SpSlice& S, double* __restrict__ prod, F f) {
+    constexpr int U = 8;
+    const int tid = threadIdx.x;
+    for (int e0 = 0; e0 < S.ne; e0 += U * SP_THREADS) {
+        int ii[U];
+        double vv[U], fv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * SP_THREADS + tid;
+            const bool ok = e < S.ne;
+            ii[u] = ok ? S.idx[e] : 0;
+            vv[u] = ok ? S.val[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) fv[u] = f(ii[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * SP_THREADS + tid;
+            if (e < S.ne) prod[e] = vv[u] * fv[u];
+        }
+    }
+    __syncthreads();
+}
+
+// Sum of row r's products, in entry order.
+__device__ __forceinline__ double slice_row_sum(const SpSlice& S, const double* __restrict__ prod, int r) {
+    const int kb = S.ptr[r], ke = S.ptr[r + 1];
+    double s0 = 0.0, s1 = 0.0;
+    int e = kb;
+    for (; e + 1 < ke; e += 2) {
+        s0 += prod[e];
+        s1 += prod[e + 1];
+    }
+    if (e < ke) s0 += prod[e];
+    return s0 + s1;
 }
 
 // ---------------------------------------------------------------------------
@@ -145,11 +249,18 @@ __device__ __forceinline__ Range my_range(int total) {
 //                  u = r / diag(G), w = u + A q1 (= G u),
 //                  partial (r,u), (w,u), (r,r), border dots of a  -> barrier
 //   then every workgroup forms be = g'/g, al = g' / (d - be g' / al).
+// r, w, s of a row sit in one record (SpRow) with 1 / diag(G), so the gather
+// of P1 is one 32-byte load; the division by diag(G) is a product with that
+// reciprocal on both sides, so q1 = A^T u exactly for the stored u.
 // On entry (set by the caller) r = t - G a, u = 0, w = 0, s = 0, p = 0, and
 // al = be = 0, so the first P1/P2 pair computes u0 = r / diag(G), w0 = G u0.
 // Returns the number of updates of a.
 // ---------------------------------------------------------------------------
-__device__ int cg_loop(const SpArgs& g, double rr, double tol2, double (&bd)[4], double* sbuf, bool want_bd,
+__device__ __forceinline__ double sp_u_next(const SpRow& q, double al, double be) {
+    return fma(-al, fma(be, q.s, q.w), q.r) * q.idg;
+}
+
+__device__ int cg_loop(const SpArgs& g, const SpLds& L, double rr, double tol2, double (&bd)[4], double* sbuf,
                        int maxit, int64_t (&tk)[4]) {
     const Range R = my_range(g.m), Cc = my_range(g.n);
     const int tid = threadIdx.x;
@@ -158,21 +269,21 @@ __device__ int cg_loop(const SpArgs& g, double rr, double tol2, double (&bd)[4],
     while (k < maxit && (k < 0 || rr > tol2) && !grid_failed(g.err)) {
         int64_t t0 = wall_clock64();
         // P1: q1_j = sum_i A_ij u'_i
-        {
-            const int L = g.LT, per = SP_THREADS / L;
+        if (L.on) {
+            slice_products(L.t, L.prod, [&](int i) { return sp_u_next(g.rw[i], al, be); });
+            for (int c = tid; c < L.t.n; c += SP_THREADS) g.q1[Cc.lo + c] = slice_row_sum(L.t, L.prod, c);
+        } else {
+            const int Lt = g.LT, per = SP_THREADS / Lt;
             for (int j0 = Cc.lo; j0 < Cc.hi; j0 += per) {
-                const int j = j0 + tid / L, sub = tid % L;
+                const int j = j0 + tid / Lt, sub = tid % Lt;
                 double d = 0.0;
                 if (j < Cc.hi) {
-                    // u' with the same arithmetic as P2, so q1 = A^T u exactly for the stored u
                     double o[1];
-                    row_sums<1>(g.cit, g.vat, g.rpt[j], g.rpt[j + 1], sub, L,
-                                [&](int i, double* fv) {
-                                    fv[0] = fma(-al, fma(be, g.sv[i], g.q[i]), g.r[i]) / g.dG[i];
-                                }, o);
+                    row_sums<1>(g.cit, g.vat, g.rpt[j], g.rpt[j + 1], sub, Lt,
+                                [&](int i, double* fv) { fv[0] = sp_u_next(g.rw[i], al, be); }, o);
                     d = o[0];
                 }
-                d = group_sum(d, L);
+                d = group_sum(d, Lt);
                 if (j < Cc.hi && sub == 0) g.q1[j] = d;
             }
         }
@@ -183,51 +294,54 @@ __device__ int cg_loop(const SpArgs& g, double rr, double tol2, double (&bd)[4],
         tk[2] += t0 - t1;
         // P2: this workgroup's rows
         double v[7] = {0, 0, 0, 0, 0, 0, 0};
-        {
-            const int L = g.LA, per = SP_THREADS / L;
+        auto row_update = [&](int i, double d) {
+            const double pi = fma(be, g.p[i], g.z[i]);
+            const SpRow o = g.rw[i];
+            const double si = fma(be, o.s, o.w);
+            const double ai = fma(al, pi, g.a[i]);
+            const double ri = fma(-al, si, o.r);
+            const double ui = ri * o.idg;
+            const double wi = ui + d;
+            g.p[i] = pi; g.a[i] = ai; g.z[i] = ui;
+            g.rw[i] = SpRow{ri, wi, si, o.idg};
+            v[0] = fma(ri, ui, v[0]);
+            v[1] = fma(wi, ui, v[1]);
+            v[2] = fma(ri, ri, v[2]);
+            v[3] = fma(g.b[i], ai, v[3]);
+            v[4] = fma(g.bbar[i], ai, v[4]);
+            v[5] = fma(g.Ac[i], ai, v[5]);
+            v[6] = fma(g.Acb[i], ai, v[6]);
+        };
+        if (L.on) {
+            slice_products(L.a, L.prod, [&](int j) { return g.q1[j]; });
+            for (int r = tid; r < L.a.n; r += SP_THREADS) row_update(R.lo + r, slice_row_sum(L.a, L.prod, r));
+        } else {
+            const int La = g.LA, per = SP_THREADS / La;
             for (int i0 = R.lo; i0 < R.hi; i0 += per) {
-                const int i = i0 + tid / L, sub = tid % L;
+                const int i = i0 + tid / La, sub = tid % La;
                 double d = 0.0;
                 if (i < R.hi) {
                     double o[1];
-                    row_sums<1>(g.ci, g.va, g.rp[i], g.rp[i + 1], sub, L,
+                    row_sums<1>(g.ci, g.va, g.rp[i], g.rp[i + 1], sub, La,
                                 [&](int jj, double* fv) { fv[0] = g.q1[jj]; }, o);
                     d = o[0];
                 }
-                d = group_sum(d, L);
-                if (i < R.hi && sub == 0) {
-                    const double pi = fma(be, g.p[i], g.z[i]);
-                    const double si = fma(be, g.sv[i], g.q[i]);
-                    const double ai = fma(al, pi, g.a[i]);
-                    const double ri = fma(-al, si, g.r[i]);
-                    const double ui = ri / g.dG[i];
-                    const double wi = ui + d;
-                    g.p[i] = pi; g.sv[i] = si; g.a[i] = ai; g.r[i] = ri; g.z[i] = ui; g.q[i] = wi;
-                    v[0] = fma(ri, ui, v[0]);
-                    v[1] = fma(wi, ui, v[1]);
-                    v[2] = fma(ri, ri, v[2]);
-                    if (want_bd) {
-                        v[3] = fma(g.b[i], ai, v[3]);
-                        v[4] = fma(g.bbar[i], ai, v[4]);
-                        v[5] = fma(g.Ac[i], ai, v[5]);
-                        v[6] = fma(g.Acb[i], ai, v[6]);
-                    }
-                }
+                d = group_sum(d, La);
+                if (i < R.hi && sub == 0) row_update(i, d);
             }
         }
-        put_parts<3>(*reinterpret_cast<double(*)[3]>(v), g.part, SP_CG, sbuf);
-        if (want_bd) put_parts<4>(*reinterpret_cast<double(*)[4]>(v + 3), g.part, SP_BD, sbuf);
+        put_parts<7>(v, g.part, g.nbp, SP_CG, sbuf);
         t1 = wall_clock64();
         tk[1] += t1 - t0;
         grid_sync(g.bar, g.err);
         t0 = wall_clock64();
         tk[2] += t0 - t1;
-        double t3[3];
-        get_parts<3>(g.part, SP_CG, t3, sbuf);
-        if (want_bd) get_parts<4>(g.part, SP_BD, bd, sbuf);
+        double t7[7];
+        get_parts<7>(g.part, g.nbp, SP_CG, t7, sbuf);
         tk[3] += wall_clock64() - t0;
-        const double gam = t3[0], del = t3[1];
-        rr = t3[2];
+        bd[0] = t7[3]; bd[1] = t7[4]; bd[2] = t7[5]; bd[3] = t7[6];
+        const double gam = t7[0], del = t7[1];
+        rr = t7[2];
         if (k < 0) { be = 0.0; al = gam / del; }
         else { be = gam / gam_old; al = gam / (del - be * gam / al); }
         gam_old = gam;
@@ -241,9 +355,11 @@ __device__ int cg_loop(const SpArgs& g, double rr, double tol2, double (&bd)[4],
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
     __shared__ double sbuf[64];
+    extern __shared__ __align__(16) unsigned char sp_lds[];
     const int tid = threadIdx.x;
     const int m = g.m, n = g.n;
     const Range R = my_range(m), Cc = my_range(n);
+    const SpLds L = sp_lds_init(g, R, Cc, sp_lds);
     const LPCtrl cl = *g.lc;
     const SolveParams& prm = g.prm;
     const double alpha = prm.alpha, gamma = prm.gamma, beta = prm.beta, eps = prm.eps;
@@ -324,7 +440,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
             for (int i = R.lo + tid; i < R.hi; i += SP_THREADS)
                 g.Y[i] = alpha * (g.a[i] - g.Zy0[i] * p0 - g.Zy1[i] * p1) + (1.0 - alpha) * g.Y[i];
         }
-        put_parts<7>(cs, g.part, SP_COL, sbuf);
+        put_parts<7>(cs, g.part, g.nbp, SP_COL, sbuf);
         const bool was_update = (op == OP_PROX);
         if (was_update) { ++iters; ++done; }
         int64_t tb = wall_clock64();
@@ -364,7 +480,9 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
                     const double ti = yi - (ax + as);
                     const double ai = g.a[i];
                     const double ri = ti - ai - aa;
-                    g.r[i] = ri; g.z[i] = 0.0; g.q[i] = 0.0; g.sv[i] = 0.0; g.p[i] = 0.0;
+                    SpRow* o = g.rw + i;
+                    o->r = ri; o->w = 0.0; o->s = 0.0;
+                    g.z[i] = 0.0; g.p[i] = 0.0;
                     rs[5] = 0.0;
                     rs[6] = fma(ri, ri, rs[6]);
                     rs[7] = fma(ti, ti, rs[7]);
@@ -375,15 +493,16 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
                 }
             }
         }
-        put_parts<12>(rs, g.part, SP_ROW, sbuf);
+        put_parts<12>(rs, g.part, g.nbp, SP_ROW, sbuf);
         tb = wall_clock64();
         tk[1] += tb - ta;
         grid_sync(g.bar, g.err);
         ta = wall_clock64();
         tk[2] += ta - tb;
-        double tc[7], tr[12];
-        get_parts<7>(g.part, SP_COL, tc, sbuf);
-        get_parts<12>(g.part, SP_ROW, tr, sbuf);
+        double tcr[19];                 // SP_COL and SP_ROW are adjacent: one reduction
+        get_parts<19>(g.part, g.nbp, SP_COL, tcr, sbuf);
+        const double* tc = tcr;
+        const double* tr = tcr + 7;
         tk[3] += wall_clock64() - ta;
         const double cx = tc[0], cbx = tc[1], by = tr[0], bby = tr[1];
 
@@ -436,7 +555,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
             tol2 = fmax(tol2, sched);
         }
         double bd[4] = {tr[8], tr[9], tr[10], tr[11]};
-        cgit += cg_loop(g, tr[6], tol2, bd, sbuf, true, g.cg_max, tk);
+        cgit += cg_loop(g, L, tr[6], tol2, bd, sbuf, g.cg_max, tk);
         if (grid_failed(g.err)) { status = -1; break; }
         // ---- border (Section 4.4, rank 2) and the tau / kappa / theta update
         const double cs_f = cx + tc[2];
@@ -482,21 +601,25 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
 __global__ __launch_bounds__(SP_THREADS) void k_sp_cg(SpArgs g, const double* rhs, double tol, int32_t maxit,
                                                      int64_t* iters) {
     __shared__ double sbuf[64];
-    const Range R = my_range(g.m);
+    extern __shared__ __align__(16) unsigned char sp_lds[];
+    const Range R = my_range(g.m), Cc = my_range(g.n);
+    const SpLds L = sp_lds_init(g, R, Cc, sp_lds);
     double v[2] = {0, 0};
     for (int i = R.lo + threadIdx.x; i < R.hi; i += SP_THREADS) {
         const double ri = rhs[i];
-        g.a[i] = 0.0; g.r[i] = ri; g.z[i] = 0.0; g.q[i] = 0.0; g.sv[i] = 0.0; g.p[i] = 0.0;
+        SpRow* o = g.rw + i;
+        o->r = ri; o->w = 0.0; o->s = 0.0;
+        g.a[i] = 0.0; g.z[i] = 0.0; g.p[i] = 0.0;
         v[0] = fma(ri, ri, v[0]);
     }
     v[1] = v[0];
-    put_parts<2>(v, g.part, SP_CG, sbuf);
+    put_parts<2>(v, g.part, g.nbp, SP_CG, sbuf);
     grid_sync(g.bar, g.err);
     double t[2];
-    get_parts<2>(g.part, SP_CG, t, sbuf);
+    get_parts<2>(g.part, g.nbp, SP_CG, t, sbuf);
     double bd[4];
     int64_t tk[4] = {0, 0, 0, 0};
-    const int k = cg_loop(g, t[0], tol * tol * t[1], bd, sbuf, false, maxit, tk);
+    const int k = cg_loop(g, L, t[0], tol * tol * t[1], bd, sbuf, maxit, tk);
     if (blockIdx.x == 0 && threadIdx.x == 0) *iters = k;
 }
 
@@ -631,15 +754,17 @@ hipError_t sp_spmv(const int32_t* rp, const int32_t* ci, const double* va, int32
     return hipGetLastError();
 }
 
-__global__ void k_sp_rowsq(const int32_t* rp, const double* va, int32_t m, double* dG) {
+// diag(G)_i = 1 + ||A_{i,:}||^2, and the CG record of row i (1 / diag(G)_i, r = w = s = 0)
+__global__ void k_sp_rowsq(const int32_t* rp, const double* va, int32_t m, double* dG, SpRow* rw) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     double s = 1.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) s = fma(va[e], va[e], s);
     dG[i] = s;
+    rw[i] = SpRow{0.0, 0.0, 0.0, 1.0 / s};
 }
 hipError_t sp_rowsq(const SpArgs& g, double* dG, hipStream_t st) {
-    hipLaunchKernelGGL(k_sp_rowsq, dim3((g.m + 255) / 256), dim3(256), 0, st, g.rp, g.va, g.m, dG);
+    hipLaunchKernelGGL(k_sp_rowsq, dim3((g.m + 255) / 256), dim3(256), 0, st, g.rp, g.va, g.m, dG, g.rw);
     return hipGetLastError();
 }
 
@@ -661,27 +786,36 @@ hipError_t sp_dots(const double* x, const double* const* ys, int ny, int64_t len
     return hipGetLastError();
 }
 
-int sp_max_blocks(int cu_count) {
+// Co-resident workgroups of the cooperative kernels with `lds_bytes` of dynamic LDS.
+int sp_max_blocks(int cu_count, int lds_bytes) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sp_solve, SP_THREADS, 0) != hipSuccess ||
-        per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sp_solve, SP_THREADS, lds_bytes) !=
+            hipSuccess || per_cu < 1)
         per_cu = 1;
     int per_cu2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_sp_cg, SP_THREADS, 0) == hipSuccess &&
-        per_cu2 >= 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_sp_cg, SP_THREADS, lds_bytes) ==
+            hipSuccess && per_cu2 >= 1)
         per_cu = std::min(per_cu, per_cu2);
     return per_cu * cu_count;
+}
+
+hipError_t sp_set_lds_limit(int bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_sp_solve, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_sp_cg, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t sp_cg_solve(SpArgs g, const double* rhs, double* out, double tol, int32_t maxit, int nb,
                        int64_t* iters, hipStream_t st) {
     void* args[] = {(void*)&g, (void*)&rhs, (void*)&tol, (void*)&maxit, (void*)&iters};
-    hipError_t e = hipLaunchCooperativeKernel((const void*)k_sp_cg, dim3(nb), dim3(SP_THREADS), args, 0, st);
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_sp_cg, dim3(nb), dim3(SP_THREADS), args,
+                                              (size_t)g.lds_bytes, st);
     if (e != hipSuccess) return e;
     return hipMemcpyAsync(out, g.a, sizeof(double) * (size_t)g.m, hipMemcpyDeviceToDevice, st);
 }
 
 hipError_t sp_solve(SpArgs g, int nb, hipStream_t st) {
     void* args[] = {(void*)&g};
-    return hipLaunchCooperativeKernel((const void*)k_sp_solve, dim3(nb), dim3(SP_THREADS), args, 0, st);
+    return hipLaunchCooperativeKernel((const void*)k_sp_solve, dim3(nb), dim3(SP_THREADS), args,
+                                      (size_t)g.lds_bytes, st);
 }

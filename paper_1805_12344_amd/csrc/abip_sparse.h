@@ -5,18 +5,25 @@
 #include <cstdint>
 #include "abip_internal.h"
 
-// per-workgroup partial sums (slots of SP_PS doubles per workgroup)
+// per-workgroup partial sums: slot k of workgroup b at part[k * nbp + b]
+// (one value's partials are contiguous, so the reduction reads them coalesced)
 #define SP_PS 32
 #define SP_COL 0       // 7 column-side sums of the check
-#define SP_ROW 8       // 5 row-side sums of the check
-#define SP_CG 13       // r^T z, r^T r, t^T t
-#define SP_BD 16       // b^T a, bbar^T a, (A c)^T a, (A cbar)^T a
-#define SP_PQ 20       // p^T G p
+#define SP_ROW 7       // 12 row-side sums: 5 of the check, one unused, r^T r and t^T t of the CG start,
+                       // 4 border dots of a
+#define SP_CG 19       // per CG iteration: r^T u, w^T u, r^T r, then b^T a, bbar^T a, (A c)^T a, (A cbar)^T a
+
+// CG state of one row i of G a = t, read together by the column pass of every
+// workgroup (one 32-byte record instead of four scattered loads):
+// r = residual, w = G u, s = G p, idg = 1 / diag(G)_i.
+struct __align__(32) SpRow {
+    double r, w, s, idg;
+};
 
 struct SpArgs {
     int32_t m, n;
     int64_t nnz;
-    int32_t LA, LT;                      // lanes per row of CSR(A), of CSR(A^T)
+    int32_t LA, LT;                      // lanes per row of CSR(A), of CSR(A^T) (global-memory passes)
     const int32_t* rp; const int32_t* ci; const double* va;     // CSR(A)
     const int32_t* rpt; const int32_t* cit; const double* vat;  // CSR(A^T)
     const double* dG;                    // 1 + ||A_{i,:}||^2 (Jacobi preconditioner of G)
@@ -26,10 +33,12 @@ struct SpArgs {
     // state and work vectors (written during the solve)
     double *Y, *X, *S;                   // iterate (Y: m, X, S: n)
     double *ATY, *ATA;                   // n: A^T y of the current iterate, A^T a of the last solve
-    double *a, *r, *z, *p, *q, *sv;      // m: CG solution (warm start) and work vectors
-                                         //    (z = u, q = w = G u, sv = s = G p)
-    double *q1;                          // n: A^T p
-    double* part;                        // gridDim.x * SP_PS partial sums
+    double *a, *z, *p;                   // m: CG solution (warm start), u = D^{-1} r, search direction
+    SpRow* rw;                           // m: r, G u, G p, 1 / diag(G)
+    double *q1;                          // n: A^T u of the next CG iterate
+    double* part;                        // SP_PS * nbp partial sums
+    int32_t nbp;                         // workgroup capacity of part (>= gridDim.x)
+    int32_t lds_bytes;                   // dynamic LDS of the launch (0: no LDS-resident slices)
     unsigned* bar;                       // grid barrier: counter, generation
     int* err;                            // set when a grid barrier times out
     LPCtrl* lc;                          // scalars in / out
@@ -39,6 +48,23 @@ struct SpArgs {
     int32_t cg_rule;                     // 0: also stop at 0.1 ||Q u - v|| / (1 + k); 1: floor only
     int64_t fixed_iters;                 // > 0: exactly this many updates, no tests or restarts
 };
+
+// Contiguous share [lo, hi) of `total` items for workgroup `b` of `nb`
+// (the same split on the host and on the device).
+__host__ __device__ inline void sp_share(int total, int b, int nb, int* lo, int* hi) {
+    const int per = (total + nb - 1) / nb;
+    const int l = (int)((int64_t)b * per < total ? (int64_t)b * per : total);
+    *lo = l;
+    *hi = (l + per < total) ? l + per : total;
+}
+
+// LDS bytes of one workgroup's slices: CSR(A^T) rows of its columns (tnc rows,
+// tne entries) and CSR(A) rows of its rows (anr rows, ane entries), with a
+// product buffer for the larger of the two.
+__host__ __device__ inline int64_t sp_slice_bytes(int tnc, int tne, int anr, int ane) {
+    const int pe = tne > ane ? tne : ane;
+    return 8 * ((int64_t)tne + ane + pe) + 4 * ((int64_t)tne + ane + tnc + 1 + anr + 1);
+}
 
 // setup helpers (abip_solve_sparse.hip)
 hipError_t sp_validate_rows(const SpArgs& g, int* flag, hipStream_t st);
@@ -54,4 +80,5 @@ hipError_t sp_dots(const double* x, const double* const* ys, int ny, int64_t len
 hipError_t sp_cg_solve(SpArgs g, const double* rhs, double* out, double tol, int32_t maxit, int nb,
                        int64_t* iters, hipStream_t st);
 hipError_t sp_solve(SpArgs g, int nb, hipStream_t st);
-int sp_max_blocks(int cu_count);
+hipError_t sp_set_lds_limit(int bytes);
+int sp_max_blocks(int cu_count, int lds_bytes);

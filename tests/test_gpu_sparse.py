@@ -26,16 +26,18 @@ def _tight(**kw):
 
 @pytest.mark.parametrize("m,n,seed,density", [(40, 90, 1, 0.08), (150, 420, 2, 0.02), (600, 1700, 3, 0.004)])
 @pytest.mark.parametrize("rule", ["heuristic", "sqrt"])
-def test_sparse_iterations_match_oracle(m, n, seed, density, rule):
-    """Fixed updates from the same restarted iterate: the CG-based step equals the exact one."""
-    print(f"sparse iterate m={m} n={n} seed={seed} rule={rule}", flush=True)
+@pytest.mark.parametrize("lds", [1, 0])
+def test_sparse_iterations_match_oracle(m, n, seed, density, rule, lds):
+    """Fixed updates from the same restarted iterate: the CG-based step equals the exact one,
+    with the CSR rows held in LDS (lds=1) and read from global memory (lds=0)."""
+    print(f"sparse iterate m={m} n={n} seed={seed} rule={rule} lds={lds}", flush=True)
     lp = lpgen.sparse_planted(m, n, seed, density=density)
     A = _csr(lp)
     prob = Problem(A.toarray(), lp["b"], lp["c"])
     s = Settings(restart_rule=rule)
     st = oracle.initial_state(prob, s)
     st = oracle.restart(st, s.gamma, rule)
-    w = abip.abip_setup(A, lp["b"], lp["c"], _tight(restart_rule=0 if rule == "heuristic" else 1))
+    w = abip.abip_setup(A, lp["b"], lp["c"], _tight(restart_rule=0 if rule == "heuristic" else 1, lds_resident=lds))
     abip.abip_set_state(w, 0, st.y, st.x, st.s, st.tau, st.kappa, st.theta, st.mu)
     solver = oracle.SchurIQSolver(prob)
     N = 25
@@ -53,11 +55,12 @@ def test_sparse_iterations_match_oracle(m, n, seed, density, rule):
 
 
 @pytest.mark.parametrize("seed", [1, 2])
-def test_sparse_solve_matches_oracle(seed):
+@pytest.mark.parametrize("lds", [1, 0])
+def test_sparse_solve_matches_oracle(seed, lds):
     lp = lpgen.sparse_planted(60, 150, seed, density=0.05)
     A = _csr(lp)
     ref = oracle.solve(A.toarray(), lp["b"], lp["c"], Settings())
-    w = abip.abip_setup(A, lp["b"], lp["c"], _tight())
+    w = abip.abip_setup(A, lp["b"], lp["c"], _tight(lds_resident=lds))
     x, y, s, info = abip.abip_solve(w)
     print(info, ref["admm_iters"], flush=True)
     assert info["status"] == abip.ABIP_SOLVED == ref["status"]
@@ -120,3 +123,25 @@ def test_sparse_boundary_errors():
     with pytest.raises(abip.ABIPError) as e:
         abip.abip_backward(w, np.ones(60))
     assert e.value.code == abip.ABIP_E_STATE
+
+
+def test_sparse_lds_and_global_passes_agree():
+    """A CSR LP spread over many workgroups (several CG passes per update, default CG
+    schedule): the LDS-resident and global-memory passes reach the same status, KKT
+    tolerance and objective, with iteration counts within a few percent."""
+    lp = lpgen.sparse_planted(3000, 9000, 11, density=3e-3)
+    A = _csr(lp)
+    res = {}
+    for lds in (1, 0):
+        w = abip.abip_setup(A, lp["b"], lp["c"], abip.abip_default_settings(lds_resident=lds))
+        x, y, s, info = abip.abip_solve(w)
+        print("lds", lds, info["admm_iters"], info["cg_iters"], info["kernel_ms"], flush=True)
+        assert info["status"] == abip.ABIP_SOLVED
+        xh, yh, sh = _np(x), _np(y), _np(s)
+        pres = np.linalg.norm(A @ xh - lp["b"]) / (1 + np.linalg.norm(lp["b"]))
+        dres = np.linalg.norm(A.T @ yh + sh - lp["c"]) / (1 + np.linalg.norm(lp["c"]))
+        assert max(pres, dres) <= 1e-6 * 1.01, (pres, dres)
+        assert abs(lp["c"] @ xh - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
+        res[lds] = info["admm_iters"]
+        w.free()
+    assert abs(res[1] - res[0]) <= max(5, 0.05 * res[0]), res
