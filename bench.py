@@ -348,7 +348,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch would shard "
-              f"LP-by-LP across GPUs, which this build does not run.", file=sys.stderr)
+              f"LP-by-LP across GPUs, which this library does not implement.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -54,7 +54,8 @@ def test_backward_after_solve_matches_oracle_and_basis_formula():
         assert np.abs(_np(got) - want).max() <= 1e-7 * (1 + np.abs(want).max())
     lam = oracle.kkt_adjoint(A, b, c, st, g)
     assert np.abs(_np(dc) - ref["dc"]).max() <= 1e-9 * np.abs(lam).max() * (1.0 + np.abs(st.u()).max())
-    # the LP derivative at the nondegenerate planted vertex (survey reading c18)
+    # as mu -> 0 the central point tends to the planted nondegenerate vertex, whose derivative is
+    # dL/db = A_B^{-T} w_B and dL/dc = 0 (the fixed point of Algorithm 2 read as a map of (b, c))
     bg = oracle.basis_gradients(A, b, lp["basis"], g)
     assert np.abs(_np(db) - bg["db"]).max() <= 1e-3 * (1 + np.abs(bg["db"]).max())
     assert np.abs(_np(dc)).max() <= 1e-3 * np.linalg.norm(g)
