@@ -190,15 +190,19 @@ __device__ void grid_col_body(const GridArgs& g, const GridCtl& c, int op, const
             }
         }
     };
+    // The next group's loads are issued without a condition (past j_end they
+    // re-read the last column, which step() ignores): with a fixed number of
+    // loads in flight the waits for one group leave the next group's loads
+    // outstanding, so they overlap the reductions and the prox of this one.
     int c0 = j_begin;
     if (c0 < j_end) { load(c0, va); load_cols(c0, da_); }
     while (c0 < j_end) {
         const int c1 = c0 + U;
-        if (c1 < j_end) { load(c1, vb); load_cols(c1, db_); }
+        load(c1, vb); load_cols(c1, db_);
         step(c0, va, da_);
         if (c1 >= j_end) break;
         const int c2 = c1 + U;
-        if (c2 < j_end) { load(c2, va); load_cols(c2, da_); }
+        load(c2, va); load_cols(c2, da_);
         step(c1, vb, db_);
         c0 = c2;
     }
