@@ -188,17 +188,20 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ A, int m, int 
             }
         }
     };
+    // the next group's loads are issued without a condition (past n they
+    // re-read column n-1 and are not used), so the number of loads in flight
+    // is fixed and the waits for one group leave the next group outstanding
     Grp ga, gb;
     int g = 0;
     int c0 = group_col(0);
     if (c0 < n) load(c0, ga);
     while (c0 < n) {
         const int c1 = group_col(g + 1);
-        if (c1 < n) load(c1, gb);
+        load(c1, gb);
         compute(c0, ga);
         if (c1 >= n) break;
         const int c2 = group_col(g + 2);
-        if (c2 < n) load(c2, ga);
+        load(c2, ga);
         compute(c1, gb);
         c0 = c2;
         g += 2;
@@ -297,17 +300,18 @@ __device__ __forceinline__ void ginv_pass(const T* __restrict__ G, int m, int ld
         const int j = col0 + lane / LPC;
         if ((lane % LPC) == 0 && j < m) sh.a[j] = dots[0];
     };
+    // next group issued without a condition, as in the column pass
     Grp ga, gb;
     int g = 0;
     int c0 = group_col(0);
     if (c0 < m) load(c0, ga);
     while (c0 < m) {
         const int c1 = group_col(g + 1);
-        if (c1 < m) load(c1, gb);
+        load(c1, gb);
         compute(c0, ga);
         if (c1 >= m) break;
         const int c2 = group_col(g + 2);
-        if (c2 < m) load(c2, ga);
+        load(c2, ga);
         compute(c1, gb);
         c0 = c2;
         g += 2;
