@@ -323,8 +323,46 @@ __global__ __launch_bounds__(256) void k_grid_red(GridArgs g) {
 // ---------------------------------------------------------------------------
 // k_grid_ginv: decision + slice of a = G^{-1} t
 // ---------------------------------------------------------------------------
+// One group of GRID_UNR columns of G^{-1}: this lane's four rows of every
+// 256-row chunk of this wave, in the precision of the phase.
 template <int NCHW, typename T>
-__device__ void grid_ginv_body(const GridArgs& g, const T* __restrict__ G, double* st, double* sd) {
+struct GinvGroup {
+    T v[GRID_UNR][NCHW * 4];
+};
+
+// Load the group starting at column col0 (columns clamped to j_end - 1, rows
+// past ld to a valid row: their weights are 0).
+template <int NCHW, typename T>
+__device__ __forceinline__ void ginv_load(const T* __restrict__ G, int col0, int j_end, int ld,
+                                          GinvGroup<NCHW, T>& P) {
+    const int lane = threadIdx.x & 63, wave = wave_id();
+#pragma unroll
+    for (int u = 0; u < GRID_UNR; ++u) {
+        const int col = min(col0 + u, j_end - 1);
+#pragma unroll
+        for (int ch = 0; ch < NCHW; ++ch) {
+            const int r0 = (ch * GRID_W + wave) * 256 + lane * 4;
+            const int rr = (r0 < ld) ? r0 : min(lane * 4, ld - 4);
+            if constexpr (sizeof(T) == 4) {
+                const float4 q4 = *reinterpret_cast<const float4*>(G + (int64_t)col * ld + rr);
+                P.v[u][ch * 4 + 0] = q4.x; P.v[u][ch * 4 + 1] = q4.y;
+                P.v[u][ch * 4 + 2] = q4.z; P.v[u][ch * 4 + 3] = q4.w;
+            } else {
+                const double2 q0 = reinterpret_cast<const double2*>(G + (int64_t)col * ld + rr)[0];
+                const double2 q1 = reinterpret_cast<const double2*>(G + (int64_t)col * ld + rr)[1];
+                P.v[u][ch * 4 + 0] = q0.x; P.v[u][ch * 4 + 1] = q0.y;
+                P.v[u][ch * 4 + 2] = q1.x; P.v[u][ch * 4 + 3] = q1.y;
+            }
+        }
+    }
+}
+
+// a = G^{-1} t on this workgroup's columns.  With PRE, `first` holds its first
+// group, loaded by the caller before the decision so that its latency overlaps
+// it (for NCHW <= 2: the larger groups would not stay in registers).
+template <int NCHW, typename T, bool PRE>
+__device__ __forceinline__ void grid_ginv_body(const GridArgs& g, const T* __restrict__ G,
+                                               const GinvGroup<NCHW, T>& first, double* st, double* sd) {
     const int lane = threadIdx.x & 63, wave = wave_id();
     constexpr int R = NCHW * 4;
     constexpr int U = GRID_UNR;
@@ -340,21 +378,13 @@ __device__ void grid_ginv_body(const GridArgs& g, const T* __restrict__ G, doubl
     const int j_begin = blockIdx.x * g.gw;
     const int j_end = min(m, j_begin + g.gw);
     double bs[4] = {0, 0, 0, 0};
-    for (int col0 = j_begin; col0 < j_end; col0 += U) {
+    auto process = [&](const GinvGroup<NCHW, T>& P, int col0) {
         double dots[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int col = col0 + u;
             double s = 0.0;
 #pragma unroll
-            for (int ch = 0; ch < NCHW; ++ch) {
-                const int r0 = (ch * GRID_W + wave) * 256 + lane * 4;
-                const int rr = (r0 < ld) ? r0 : min(lane * 4, ld - 4);
-                double v4[4];
-                load4(G + (int64_t)min(col, j_end - 1) * ld + rr, v4);     // weights are 0 past ld
-#pragma unroll
-                for (int q = 0; q < 4; ++q) s = fma(v4[q], rt[ch * 4 + q], s);
-            }
+            for (int r = 0; r < R; ++r) s = fma((double)P.v[u][r], rt[r], s);
             dots[u] = s;
         }
         wave_rs<U, 1>(dots);                          // lanes 8u..8u+7: column u of this wave
@@ -373,18 +403,23 @@ __device__ void grid_ginv_body(const GridArgs& g, const T* __restrict__ G, doubl
             }
         }
         __syncthreads();
+    };
+    if constexpr (PRE) {
+        if (j_begin < j_end) process(first, j_begin);
+    }
+    for (int col0 = PRE ? j_begin + U : j_begin; col0 < j_end; col0 += U) {
+        GinvGroup<NCHW, T> P;
+        ginv_load<NCHW, T>(G, col0, j_end, ld, P);
+        process(P, col0);
     }
     block_sum_n<4>(bs, sd);
     if (threadIdx.x == 0)
         for (int q = 0; q < 4; ++q) g.pa[blockIdx.x * 4 + q] = bs[q];
 }
 
-template <int NCHW>
-__global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
-    extern __shared__ double smem[];
-    __shared__ double sd[GRID_W * GRID_UNR + 64];
-    GridCtl c = *g.ctl;
-    if (c.status != 0) return;
+template <int NCHW, typename T>
+__device__ __forceinline__ void grid_ginv_step(const GridArgs& g, GridCtl c, const T* __restrict__ G, double* smem,
+                                               double* sd) {
     const int ld = g.ld, n = g.n;
     // ---- sums of the state the last column pass produced, reduced in a fixed
     // order by the whole block: every workgroup gets bitwise the same totals
@@ -397,6 +432,16 @@ __global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
     for (int q = threadIdx.x; q < g.NR; q += blockDim.x)
 #pragma unroll
         for (int k = 0; k < 5; ++k) sums[7 + k] += g.prow[q * 8 + k];
+    // this workgroup's first group of G^{-1} columns, issued after the partial
+    // sums and without a condition (every launched workgroup has a column; a
+    // pass that does not update leaves it unused): the waits for the sums
+    // leave these loads in flight through the decision below
+    constexpr bool PRE = NCHW <= 2;
+    GinvGroup<NCHW, T> first;
+    if constexpr (PRE) {
+        const int j0 = blockIdx.x * g.gw;
+        ginv_load<NCHW, T>(G, j0, min(g.m, j0 + g.gw), ld, first);
+    }
     block_sum_n<12>(sums, sd);
     const double* cs = sums;          // c^T x, cbar^T x, c^T s, cbar^T s, D1, D2, Rx
     const double* ms = sums + 7;      // b^T y, bbar^T y, P1, P2, Ry
@@ -472,14 +517,23 @@ __global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
     }
     c.first = 0;
     c.mode = next;
-    if (c.status == 0 && next == OP_PROX) {
+    if (c.status == 0 && next == OP_PROX) {    // the phase is unchanged on this path
         double* st = smem;
         for (int i = threadIdx.x; i < ld; i += blockDim.x) st[i] = g.t[i];
         __syncthreads();
-        if (c.phase == 0) grid_ginv_body<NCHW, float>(g, g.G32, st, sd);
-        else grid_ginv_body<NCHW, double>(g, g.G64, st, sd);
+        grid_ginv_body<NCHW, T, PRE>(g, G, first, st, sd);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *g.ctl_next = c;
+}
+
+template <int NCHW>
+__global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
+    extern __shared__ double smem[];
+    __shared__ double sd[GRID_W * GRID_UNR + 64];
+    const GridCtl c = *g.ctl;
+    if (c.status != 0) return;
+    if (c.phase == 0) grid_ginv_step<NCHW, float>(g, c, g.G32, smem, sd);
+    else grid_ginv_step<NCHW, double>(g, c, g.G64, smem, sd);
 }
 
 // After every slice of a exists: the 2x2 border, the new scalars, and the
