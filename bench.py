@@ -229,11 +229,23 @@ def extra_sparse(abip, torch):
     gap = abs(po - do) / (1 + abs(po) + abs(do))
     it = max(1, info["admm_iters"])
     w.free()
+    # algorithmic bytes of one CG iteration (the dominant work): CSR(A^T) and CSR(A) once each
+    # (8-byte value + 4-byte index per entry, 4-byte row pointers), the 32-byte CG record of
+    # every row read by the column pass, q1 written and read (8 bytes per column), and the
+    # row update's reads and writes of r, G u, G p (record) and p, a, u (56 + 32 bytes per row)
+    m, n, nnz = 10000, 30000, lp["nnz"]
+    cg_bytes = 24.0 * nnz + 4.0 * (m + n + 2) + 32.0 * m + 16.0 * n + 88.0 * m
+    us_cg = info["kernel_ms"] * 1e3 / max(1, info["cg_iters"])
+    achieved = cg_bytes / (us_cg * 1e-6) / 1e9
     return {"workload": "sparse planted LP 10000 x 30000, nnz %d, seed 1, eps 1e-6, CG on I + A A^T, fp64" % lp["nnz"],
             "status": info["status_name"], "admm_iters": info["admm_iters"], "cg_iters": info["cg_iters"],
             "setup_ms": setup_ms, "solve_s": solve_s, "admm_iters_per_s": info["admm_iters"] / solve_s,
             "us_per_iter": info["kernel_ms"] * 1e3 / it, "us_per_cg_iter": info["kernel_ms"] * 1e3 / max(1, info["cg_iters"]),
-            "host_kkt": [pres, dres, gap], "pobj": po, "pstar": lp["pstar"]}
+            "host_kkt": [pres, dres, gap], "pobj": po, "pstar": lp["pstar"],
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_sp_solve (per CG iteration)",
+                         "algorithmic_bytes_per_cg_iteration": cg_bytes,
+                         "note": "bound in practice by two grid barriers per CG iteration, not by HBM"}}
 
 
 def extra_differentiable(abip, torch):
