@@ -14,8 +14,11 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
+# up to 2048 rows every lane holds one four-row group per wave; 2100, 4200 and 6200
+# rows take the variants with two, three and four such chunks per lane
 @pytest.mark.parametrize("m,n,seed,engine", [(50, 100, 1, "grid"), (300, 700, 2, "grid"),
-                                             (1100, 2600, 3, "auto")])
+                                             (1100, 2600, 3, "auto"), (2100, 2300, 7, "grid"),
+                                             (4200, 4400, 8, "grid"), (6200, 6400, 9, "grid")])
 def test_grid_iterations_match_oracle(m, n, seed, engine):
     print(f"grid iterate m={m} n={n}", flush=True)
     lp = lpgen.dense_planted(m, n, seed)
@@ -63,3 +66,19 @@ def test_grid_basis_pursuit_fp32_polish():
     kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s))
     assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
     assert abs(kk["pobj"] - lp["pstar"]) <= 1e-5 * (1 + lp["pstar"])
+
+
+@pytest.mark.parametrize("m,n,seed", [(2100, 2300, 7), (4200, 4400, 8)])
+def test_grid_multichunk_fp32_polish_solve(m, n, seed):
+    """FP32-streamed A and G^{-1} with two and three row chunks per lane: the solve
+    reaches the planted optimum at the KKT tolerance (FP64 recheck on the host)."""
+    lp = lpgen.dense_planted(m, n, seed)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"],
+                        abip.abip_default_settings(engine=abip.ABIP_ENGINE_GRID,
+                                                   precision=abip.ABIP_PREC_FP32_POLISH))
+    x, y, s, info = abip.abip_solve(w)
+    print(m, n, info["status_name"], info["admm_iters"], info["admm_iters_fp64"], flush=True)
+    assert info["status"] == abip.ABIP_SOLVED
+    kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s))
+    assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
+    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
