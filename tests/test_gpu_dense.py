@@ -23,7 +23,9 @@ def _settings(**kw):
     return abip.abip_default_settings(**kw)
 
 
-SHAPES = [(7, 13, 0), (50, 100, 1), (130, 301, 2), (300, 650, 3), (20, 1000, 4)]
+# one to four 256-row chunks per lane in the one-workgroup engine (m <= 256, 512, 768, 1024)
+SHAPES = [(7, 13, 0), (50, 100, 1), (130, 301, 2), (300, 650, 3), (20, 1000, 4), (600, 1300, 5),
+          (1000, 2100, 6)]
 
 
 @pytest.mark.parametrize("m,n,seed", SHAPES)
@@ -193,3 +195,17 @@ def test_fp32_floor_hands_over_to_fp64(engine):
         assert abs(lp["b"] @ y - 1.0) < 1e-9
         assert np.linalg.norm(lp["A"].T @ y + _np(s)) <= 1e-6 / np.linalg.norm(lp["b"]) * 1.001
         assert info["admm_iters"] - info["admm_iters_fp64"] > 0      # the bulk ran in FP32
+
+
+@pytest.mark.parametrize("m,n,seed", [(600, 1300, 5), (1000, 2100, 6)])
+def test_fp32_polish_solve_three_and_four_chunks(m, n, seed):
+    """FP32-streamed A and G^{-1} with three and four 256-row chunks per lane (one
+    workgroup): the solve reaches the planted optimum at the KKT tolerance."""
+    lp = lpgen.dense_planted(m, n, seed)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"], _settings(precision=abip.ABIP_PREC_FP32_POLISH))
+    x, y, s, info = abip.abip_solve(w)
+    print(m, n, info["status_name"], info["admm_iters"], info["admm_iters_fp64"], flush=True)
+    assert info["status"] == abip.ABIP_SOLVED
+    kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s))
+    assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
+    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
