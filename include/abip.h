@@ -248,8 +248,10 @@ int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_fp32);
  * the handle's engine, timed with HIP events on the work stream, and keeps the
  * fastest for later solves: one-workgroup engine 256 or 512 threads (LPs with
  * m <= 256; larger ones have the single 256 candidate), grid engine about
- * 0.5 / 1 / 2 / 4 workgroups per CU, sparse engine 32 / 64 / 128 / 256
- * workgroups (up to what can be co-resident).  ms (host, may be NULL) receives
+ * 0.5 / 1 / 2 / 4 workgroups per CU, sparse engine the setup's workgroup count
+ * (one per 256 rows or columns, at most one per CU) then 32 / 64 / 128 / 256
+ * workgroups (up to what can be co-resident; its updates use the solve's CG
+ * stopping rule).  ms (host, may be NULL) receives
  * the time of each candidate (up to max_cand), *ncand their number, *chosen
  * the kept value (threads or workgroups); both may be NULL.  The iterate is
  * reset to the start point.  A configuration change can change the last bits

@@ -257,6 +257,7 @@ struct abip_work {
     bool sparse = false;
     SpArgs sa{};
     int sp_nb = 1;
+    int sp_nb_default = 1;          // the setup's choice (one workgroup per 256 rows or columns)
     int32_t* sp_idx = nullptr;       // rp (m+1), ci (nnz), rpt (n+1), cit (nnz), cursor (n)
     double* sp_val = nullptr;        // va (nnz), vat (nnz)
     double* sp_vec = nullptr;        // dG, a, z, p (m); CG records (4 m); ATZy0, ATZy1, ATY, ATA, q1 (n); part
@@ -856,6 +857,7 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     // for H1 = (-b; c) and H2 = (bbar; -cbar), by CG to near machine precision
     const int maxb = std::min(sp_max_blocks(w->cu_count, 0), 4 * w->cu_count);
     w->sp_nb = std::max(1, std::min<int>(maxb, (int)std::min<int64_t>(w->cu_count, (std::max<int64_t>(m, n) + 255) / 256)));
+    w->sp_nb_default = w->sp_nb;
     g.lds_bytes = s.lds_resident ? sp_lds_for(w, w->sp_nb) : 0;
     double* rhs = g.Y;                                                         // scratch until the solve
     const int32_t bmax = std::max<int32_t>(5000, 20 * s.cg_max_iters);
@@ -1253,9 +1255,9 @@ extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t ma
     std::vector<int> cand;
     if (w->sparse) {
         const int maxb = std::min(sp_max_blocks(w->cu_count, 0), 4 * w->cu_count);
+        cand.push_back(std::min(w->sp_nb_default, maxb));
         for (int nb : {32, 64, 128, 256})
-            if (nb <= maxb) cand.push_back(nb);
-        if (cand.empty()) cand.push_back(maxb);
+            if (nb <= maxb && nb != cand[0]) cand.push_back(nb);
     } else if (w->grid) {
         for (int f : {1, 2, 4, 8}) cand.push_back(w->cu_count * f / 2);
     } else {

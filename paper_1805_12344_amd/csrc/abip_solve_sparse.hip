@@ -547,7 +547,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
         // stop at ||r|| <= max(cg_tol ||t||, 0.1 ||Q u - v|| / (1 + k)) (rule 0) or at the
         // relative floor alone (rule 1)
         double tol2 = g.cg_tol * g.cg_tol * tr[7];
-        if (g.cg_rule == 0 && g.fixed_iters == 0) {
+        if (g.cg_rule == 0) {           // also in fixed-update runs, so they time a solve's CG work
             const double rt = by - cx + zbar * theta - kappa;
             const double rth = -bby + cbx - zbar * tau + np1;
             const double inner = tr[4] + tc[6] + rt * rt + rth * rth;
