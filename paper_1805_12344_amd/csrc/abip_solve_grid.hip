@@ -1,11 +1,12 @@
-// Grid engine: one LP spread over the whole GPU, three kernels per inner
+// Grid engine: one LP spread over the whole GPU, four kernels per inner
 // iteration of Algorithm 2 (Section 4.2 relaxation, Section 4.1 tests,
-// Section 5 restart), driven from the host in chunks of iterations.
+// Section 5 restart), replayed as hipGraphs of 16 iterations and driven from
+// the host in chunks of iterations.
 //
-//   k_grid_col   columns split over NB workgroups.  Each workgroup first
-//                finishes the previous step's small work redundantly (the 2x2
-//                border p, tau/kappa/theta, y' = alpha (a - Z_y p) + (1-alpha) y),
-//                then streams its columns of A once: (A^T a)_j, (A^T y')_j, the
+//   k_grid_col   columns split over NB workgroups.  Each workgroup first forms
+//                y' = alpha (a - Z_y p) + (1-alpha) y redundantly from the
+//                border p of the pending update, then streams its columns of A
+//                once: (A^T a)_j, (A^T y')_j, the
 //                relaxed prox / dual update of x_j, s_j, and the accumulation of
 //                A[:,j](x'_j + s'_j) and A[:,j] x'_j into per-workgroup partial
 //                m-vectors (waves own disjoint row ranges, so no cross-wave
@@ -16,6 +17,9 @@
 //                same decision (final test, inner test, restart, phase switch);
 //                for an update it computes its slice of a = G^{-1} t and the
 //                partial border dots; workgroup 0 publishes the decision.
+//   k_grid_border one workgroup: the 2x2 border (Section 4.4) and the relaxed
+//                tau, kappa, theta of the update, published as the control
+//                block of the next column pass.
 // All sums are reduced in a fixed order, so runs are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include "abip_internal.h"
