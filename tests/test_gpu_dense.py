@@ -209,3 +209,32 @@ def test_fp32_polish_solve_three_and_four_chunks(m, n, seed):
     kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s))
     assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
     assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
+
+
+def test_zero_row_and_empty_column_every_engine():
+    """A planted LP extended by a zero row (b_i = 0: A loses full row rank, G = I + A A^T
+    stays nonsingular) and an empty column with cost 1 (its x_j is 0 at the optimum, the
+    planted pair stays optimal): the oracle and every engine reach the planted value."""
+    import scipy.sparse as sp
+    lp = lpgen.dense_planted(40, 90, 12)
+    m, n = lp["A"].shape
+    A = np.zeros((m + 1, n + 1))
+    A[:m, :n] = lp["A"]
+    b = np.concatenate([lp["b"], [0.0]])
+    c = np.concatenate([lp["c"], [1.0]])
+    ref = oracle.solve(A, b, c)
+    assert ref["status_name"] == "solved"
+    assert abs(c @ ref["x"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
+    cases = [("wg", A, _settings()), ("grid", A, _settings(engine=abip.ABIP_ENGINE_GRID)),
+             ("sparse lds", sp.csr_matrix(A), _settings(lds_resident=1)),
+             ("sparse global", sp.csr_matrix(A), _settings(lds_resident=0))]
+    for name, Ain, st in cases:
+        w = abip.abip_setup(Ain, b, c, st)
+        x, y, s, info = abip.abip_solve(w)
+        print(name, info["status_name"], info["admm_iters"], "oracle", ref["admm_iters"], flush=True)
+        assert info["status"] == abip.ABIP_SOLVED, name
+        kk = oracle.kkt_relative(A, b, c, _np(x), _np(y), _np(s))
+        assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, (name, kk)
+        assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"])), name
+        assert abs(_np(x)[n]) <= 1e-4 * (1 + np.abs(_np(x)).max()), name
+        w.free()
