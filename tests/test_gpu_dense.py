@@ -238,3 +238,32 @@ def test_zero_row_and_empty_column_every_engine():
         assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"])), name
         assert abs(_np(x)[n]) <= 1e-4 * (1 + np.abs(_np(x)).max()), name
         w.free()
+
+
+def test_more_rows_than_columns_every_engine():
+    """m > n: a planted 6 x 12 LP whose rows are repeated as 12 random combinations
+    (18 x 12, rank 6, consistent b).  The feasible set and the optimum are the planted
+    LP's; G = I + A A^T is nonsingular regardless of rank.  Every engine reaches the
+    oracle's iteration count and the planted value."""
+    import scipy.sparse as sp
+    lp = lpgen.dense_planted(6, 12, 13)
+    R = np.random.default_rng(5).standard_normal((12, 6))
+    A = np.vstack([lp["A"], R @ lp["A"]])
+    b = np.concatenate([lp["b"], R @ lp["b"]])
+    c = lp["c"]
+    ref = oracle.solve(A, b, c)
+    assert ref["status_name"] == "solved"
+    cases = [("wg", A, _settings()), ("wg streamed", A, _settings(lds_resident=0)),
+             ("grid", A, _settings(engine=abip.ABIP_ENGINE_GRID)),
+             # CG to the relative floor, so the step is the exact one the oracle takes
+             ("sparse", sp.csr_matrix(A), _settings(cg_tol=1e-13, cg_max_iters=2000, cg_rule=1))]
+    for name, Ain, st in cases:
+        w = abip.abip_setup(Ain, b, c, st)
+        x, y, s, info = abip.abip_solve(w)
+        print(name, info["status_name"], info["admm_iters"], "oracle", ref["admm_iters"], flush=True)
+        assert info["status"] == abip.ABIP_SOLVED, name
+        kk = oracle.kkt_relative(A, b, c, _np(x), _np(y), _np(s))
+        assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, (name, kk)
+        assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"])), name
+        assert abs(info["admm_iters"] - ref["admm_iters"]) <= max(5, ref["admm_iters"] // 50), name
+        w.free()
