@@ -101,11 +101,23 @@ def test_solve_config0_matches_oracle(seed):
     np.testing.assert_allclose(x, ref["x"], atol=1e-6 * (1 + np.abs(ref["x"]).max()))
 
 
-def test_toys_and_certificates():
+CERT_CFG = {"wg": {}, "wg_streamed": {"lds_resident": 0}, "grid": {"engine": 2},
+            "wg_fp32": {"precision": 1}, "grid_fp32": {"engine": 2, "precision": 1}}
+
+
+@pytest.mark.parametrize("cfg", list(CERT_CFG))
+def test_toys_and_certificates(cfg):
+    """Toy LPs and Farkas certificates (Section 4.1) on every dense configuration:
+    one workgroup LDS-resident / streamed, grid engine, FP32 bulk + FP64 confirmation."""
+    kw = dict(CERT_CFG[cfg])
+    if "engine" in kw:
+        kw["engine"] = abip.ABIP_ENGINE_GRID
+    if "precision" in kw:
+        kw["precision"] = abip.ABIP_PREC_FP32_POLISH
     for lp in [lpgen.toy_two_var(), lpgen.toy_primal_infeasible(), lpgen.toy_dual_infeasible(),
                lpgen.dense_farkas_infeasible(20, 50, 3)]:
         ref = oracle.solve(lp["A"], lp["b"], lp["c"], Settings())
-        w = abip.abip_setup(lp["A"], lp["b"], lp["c"])
+        w = abip.abip_setup(lp["A"], lp["b"], lp["c"], _settings(**kw))
         x, y, s, info = abip.abip_solve(w)
         print(lp["status"], info["status_name"], info["admm_iters"], ref["admm_iters"], flush=True)
         assert info["status"] == ref["status"]
