@@ -525,8 +525,12 @@ static void assign_lds(abip_work* w) {
         if (d.m > w->threads || d.n > 2 * w->threads) continue;
         const size_t b32 = (size_t)small_layout(d.m, d.n, 4, W).total;
         const size_t b64 = (size_t)small_layout(d.m, d.n, 8, W).total;
+        const size_t a32 = (size_t)small_layout(d.m, d.n, 4, W, true).total;
+        const size_t a64 = (size_t)small_layout(d.m, d.n, 8, W, true).total;
         if (b32 <= cap) { d.lds |= DESC_LDS32; smem = std::max(smem, b32); }
+        else if (a32 <= cap) { d.lds |= DESC_LDSA32; smem = std::max(smem, a32); }
         if (b64 <= cap) { d.lds |= DESC_LDS64; smem = std::max(smem, b64); }
+        else if (a64 <= cap) { d.lds |= DESC_LDSA64; smem = std::max(smem, a64); }
     }
     w->wg_smem = smem;
 }

@@ -78,7 +78,8 @@ struct SmallLayout {
     int64_t oA, oG, oav, ofx, otv, opf, opg, ored, total;
 };
 __host__ __device__ inline int64_t small_align16(int64_t x) { return (x + 15) & ~(int64_t)15; }
-__host__ __device__ inline SmallLayout small_layout(int m, int n, int esize, int W) {
+// gs: G^{-1} is not held in LDS (the loop reads the pool's copy instead).
+__host__ __device__ inline SmallLayout small_layout(int m, int n, int esize, int W, bool gs = false) {
     SmallLayout L;
     L.m4 = (m + 3) & ~3;
     if (esize == 4) L.lda = (((L.m4 >> 2) & 1) != 0) ? L.m4 : L.m4 + 4;
@@ -86,7 +87,7 @@ __host__ __device__ inline SmallLayout small_layout(int m, int n, int esize, int
     L.ldg = L.m4;
     int64_t o = 0;
     L.oA = o;  o = small_align16(o + (int64_t)L.lda * n * esize);
-    L.oG = o;  o = small_align16(o + (int64_t)L.ldg * m * esize);
+    L.oG = o;  o = small_align16(o + (gs ? 0 : (int64_t)L.ldg * m * esize));
     L.oav = o; o = small_align16(o + 8 * (int64_t)L.m4);
     L.ofx = o; o = small_align16(o + 16 * (int64_t)n);
     L.otv = o; o = small_align16(o + 8 * (int64_t)L.m4);
@@ -96,8 +97,10 @@ __host__ __device__ inline SmallLayout small_layout(int m, int n, int esize, int
     L.total = o;
     return L;
 }
-// LPDesc.lds bits: the FP32 / FP64 phase of this LP runs LDS-resident
-enum { DESC_LDS32 = 1, DESC_LDS64 = 2 };
+// LPDesc.lds bits: the FP32 / FP64 phase of this LP runs LDS-resident with A
+// and G^{-1} in LDS (DESC_LDS32 / 64), or with A alone in LDS and G^{-1} read
+// from the pool (DESC_LDSA32 / 64)
+enum { DESC_LDS32 = 1, DESC_LDS64 = 2, DESC_LDSA32 = 4, DESC_LDSA64 = 8 };
 
 // Positive root of z^2 - w z - t = 0, cancellation free for w < 0
 // (closed form of the barrier prox, eqs. Simple-Update:Barrier-X/-tau).

@@ -6,7 +6,9 @@
 // takes the same decisions; what differs is where the data lives and how the
 // products are organised:
 //   * A and G^{-1} are copied into LDS once per precision phase, so an
-//     iteration touches no global memory.
+//     iteration touches no global memory.  When A fits but A and G^{-1}
+//     together do not, G^{-1} stays in the pool and the G^{-1} t sweep reads
+//     its columns from global memory (L2 / MALL); the rest is unchanged.
 //   * wave w owns a block of ceil(n/4) columns and a block of ceil(m/4) rows.
 //     A column's owner lane keeps x_j, s_j, c_j, cbar_j, the border entries
 //     and (A^T y)_j in registers: (A^T a)_j is one LDS dot product (split over
@@ -34,6 +36,18 @@
 
 // four waves (256-thread launches)
 #define SMALL_W 4
+
+// For a phase that runs LDS-resident: G^{-1} is read from the pool (only A
+// fits in LDS), and A is held as doubles (always in the FP64 phase; in the FP32
+// phase when the FP64 layout of the same kind fits: the same values, no
+// conversion per use).
+__device__ __forceinline__ bool small_gs(int lds, int phase) {
+    return phase == 0 ? (lds & DESC_LDS32) == 0 : (lds & DESC_LDS64) == 0;
+}
+__device__ __forceinline__ bool small_wide(int lds, int phase) {
+    if (phase != 0) return true;
+    return small_gs(lds, 0) ? (lds & DESC_LDSA64) != 0 : (lds & DESC_LDS64) != 0;
+}
 
 struct SmallCol {
     double x, s, c, cb, z0, z1;     // iterate, c, cbar, border columns of x
@@ -105,18 +119,19 @@ __device__ __forceinline__ double small_dot_half(const T* __restrict__ col, cons
     return (s0 + s1) + (s2 + s3);
 }
 
-// Copy this phase's A and G^{-1} from the pools into LDS (zero rows m..lda-1).
-// FP32 data may be held as doubles (the same values, no conversion per use).
+// Copy this phase's A and (unless gs) G^{-1} from the pools into LDS (zero
+// rows m..lda-1).  FP32 data may be held as doubles (the same values, no
+// conversion per use).
 template <typename Td, typename Ts>
 __device__ __forceinline__ void small_fill(Td* __restrict__ As, int lda, Td* __restrict__ Gs, int ldg,
                                            const Ts* __restrict__ Ag, const Ts* __restrict__ Gg, int m, int n,
-                                           int ld) {
+                                           int ld, bool gs) {
     const int NT = blockDim.x;
     for (int e = threadIdx.x; e < lda * n; e += NT) {
         const int j = e / lda, i = e - j * lda;
         As[e] = (i < m) ? (Td)Ag[(int64_t)j * ld + i] : Td(0);
     }
-    for (int e = threadIdx.x; e < ldg * m; e += NT) {
+    for (int e = threadIdx.x; e < (gs ? 0 : ldg * m); e += NT) {
         const int j = e / ldg, i = e - j * ldg;
         Gs[e] = (i < m) ? (Td)Gg[(int64_t)j * ld + i] : Td(0);
     }
@@ -334,22 +349,22 @@ __device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, int
     const int m = d.m, n = d.n, tid = threadIdx.x;
     // LDS entries are doubles in the FP64 phase, and in the FP32 phase too when
     // the FP64 layout fits (FP32-rounded values held exactly as doubles)
-    const bool wide = (phase != 0) || (d.lds & DESC_LDS64);
-    L = small_layout(m, n, wide ? 8 : 4, SMALL_W);
+    const bool wide = small_wide(d.lds, phase), gs = small_gs(d.lds, phase);
+    L = small_layout(m, n, wide ? 8 : 4, SMALL_W, gs);
     double* av = reinterpret_cast<double*>(smem + L.oav);
     double* tv = reinterpret_cast<double*>(smem + L.otv);
     __syncthreads();                       // earlier readers of the LDS are done
     if (!wide)
         small_fill<float, float>(reinterpret_cast<float*>(smem + L.oA), L.lda, reinterpret_cast<float*>(smem + L.oG),
-                                 L.ldg, P.A32 + d.oA, P.G32 + d.oG, m, n, d.ld);
+                                 L.ldg, P.A32 + d.oA, P.G32 + d.oG, m, n, d.ld, gs);
     else if (phase == 0)
         small_fill<double, float>(reinterpret_cast<double*>(smem + L.oA), L.lda,
                                   reinterpret_cast<double*>(smem + L.oG), L.ldg, P.A32 + d.oA, P.G32 + d.oG, m, n,
-                                  d.ld);
+                                  d.ld, gs);
     else
         small_fill<double, double>(reinterpret_cast<double*>(smem + L.oA), L.lda,
                                    reinterpret_cast<double*>(smem + L.oG), L.ldg, P.A64 + d.oA, P.G64 + d.oG, m, n,
-                                   d.ld);
+                                   d.ld, gs);
     for (int i = tid; i < L.m4; i += blockDim.x) {
         av[i] = (i < m) ? Zy0[i] : 0.0;
         tv[i] = (i < m) ? Zy1[i] : 0.0;
@@ -379,7 +394,7 @@ __device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, int
 // the state, with a tested FP64 refresh as the next pass, for the streamed
 // variant.  Requires four waves, m <= 64 RPL (and m <= 256) and
 // ceil(n/4) <= 64 CPT (<= 32 with PAIR).
-template <int CPT, int RPL, bool PAIR>
+template <int CPT, int RPL, bool PAIR, bool GS>
 __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __restrict__ ctrl, const PoolPtrs& P_in,
                                          const SolveParams& prm_in, int64_t fixed_iters) {
     static_assert(!PAIR || CPT == 1, "column pairs own one column");
@@ -395,7 +410,12 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const LPCtrl cl = ctrl[k];
     int phase = cl.phase;
-    if (num_waves() != SMALL_W || !(d.lds & (phase == 0 ? DESC_LDS32 : DESC_LDS64))) return false;
+    // this variant runs a phase held in LDS with (GS false) or without (GS true) G^{-1}
+    auto runs_here = [&](int ph) {
+        const int full = ph == 0 ? DESC_LDS32 : DESC_LDS64, aonly = ph == 0 ? DESC_LDSA32 : DESC_LDSA64;
+        return GS ? ((d.lds & full) == 0 && (d.lds & aonly) != 0) : (d.lds & full) != 0;
+    };
+    if (num_waves() != SMALL_W || !runs_here(phase)) return false;
     const int cb = small_uni((n + SMALL_W - 1) / SMALL_W);      // columns per wave
     const int rb = small_uni((m + SMALL_W - 1) / SMALL_W);      // rows per wave
 
@@ -445,8 +465,8 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         col[q].aty = 0.0; col[q].atz0 = 0.0; col[q].atz1 = 0.0;
     }
 
-    bool wide = (phase != 0) || (d.lds & DESC_LDS64);   // LDS entries are doubles
-    SmallLayout L = small_layout(m, n, wide ? 8 : 4, SMALL_W);
+    bool wide = small_wide(d.lds, phase);    // LDS entries are doubles
+    SmallLayout L = small_layout(m, n, wide ? 8 : 4, SMALL_W, GS);
     const int m4 = L.m4;                   // the same in both precisions
     double* av = reinterpret_cast<double*>(smem + L.oav);
     double2* fx = reinterpret_cast<double2*>(smem + L.ofx);
@@ -517,8 +537,13 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         // ---- G^{-1} t over the own rows, before the tests (a restart or a
         // verdict leaves it unused); the sums' barrier publishes its partials
         const int64_t t1 = wall_clock64();
-        if (!wide) small_gpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oG), L.ldg, m, m4, rb, tv, pg);
-        else small_gpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oG), L.ldg, m, m4, rb, tv, pg);
+        if constexpr (GS) {            // G^{-1} columns from the pool (L2 / MALL)
+            if (phase == 0) small_gpass<float, RPL>(P.G32 + d.oG, d.ld, m, m4, rb, tv, pg);
+            else small_gpass<double, RPL>(P.G64 + d.oG, d.ld, m, m4, rb, tv, pg);
+        } else {
+            if (!wide) small_gpass<float, RPL>(reinterpret_cast<const float*>(smem + L.oG), L.ldg, m, m4, rb, tv, pg);
+            else small_gpass<double, RPL>(reinterpret_cast<const double*>(smem + L.oG), L.ldg, m, m4, rb, tv, pg);
+        }
         cyc_ginv += wall_clock64() - t1;
         const int64_t tc = wall_clock64();
         small_bsum<12>(v12, red);
@@ -586,7 +611,9 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
                 phase = 1;
                 pass_kind = OP_REFRESH;
                 cyc_chk += wall_clock64() - tc;
-                if (!(d.lds & DESC_LDS64)) { handover = true; break; }
+                // FP64 data held the other way (or not at all): hand over; the
+                // caller continues with the matching variant or streams
+                if (!runs_here(1)) { handover = true; break; }
                 small_load_phase<CPT, PAIR>(phase, d, cb, P, Zy0, Zy1, smem, L, col);
                 wide = true;
                 av = reinterpret_cast<double*>(smem + L.oav);
@@ -679,30 +706,41 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
 
 // Pick the variant for this LP: rows per lane from m, column pairs when a
 // wave owns at most 32 columns, one or two columns per lane otherwise.
-__device__ inline bool solve_small_any(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
-                                       const SolveParams& prm, int64_t fixed_iters) {
+template <bool GS>
+__device__ inline bool solve_small_shape(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
+                                         const SolveParams& prm, int64_t fixed_iters) {
     const int rpl = (d.m + 63) >> 6;
     const int cb = (d.n + SMALL_W - 1) / SMALL_W;
     if (cb <= 32) {
         switch (rpl) {
-        case 1: return solve_small<1, 1, true>(k, d, ctrl, P, prm, fixed_iters);
-        case 2: return solve_small<1, 2, true>(k, d, ctrl, P, prm, fixed_iters);
-        case 3: return solve_small<1, 3, true>(k, d, ctrl, P, prm, fixed_iters);
-        default: return solve_small<1, 4, true>(k, d, ctrl, P, prm, fixed_iters);
+        case 1: return solve_small<1, 1, true, GS>(k, d, ctrl, P, prm, fixed_iters);
+        case 2: return solve_small<1, 2, true, GS>(k, d, ctrl, P, prm, fixed_iters);
+        case 3: return solve_small<1, 3, true, GS>(k, d, ctrl, P, prm, fixed_iters);
+        default: return solve_small<1, 4, true, GS>(k, d, ctrl, P, prm, fixed_iters);
         }
     }
     if (cb <= 64) {
         switch (rpl) {
-        case 1: return solve_small<1, 1, false>(k, d, ctrl, P, prm, fixed_iters);
-        case 2: return solve_small<1, 2, false>(k, d, ctrl, P, prm, fixed_iters);
-        case 3: return solve_small<1, 3, false>(k, d, ctrl, P, prm, fixed_iters);
-        default: return solve_small<1, 4, false>(k, d, ctrl, P, prm, fixed_iters);
+        case 1: return solve_small<1, 1, false, GS>(k, d, ctrl, P, prm, fixed_iters);
+        case 2: return solve_small<1, 2, false, GS>(k, d, ctrl, P, prm, fixed_iters);
+        case 3: return solve_small<1, 3, false, GS>(k, d, ctrl, P, prm, fixed_iters);
+        default: return solve_small<1, 4, false, GS>(k, d, ctrl, P, prm, fixed_iters);
         }
     }
     switch (rpl) {
-    case 1: return solve_small<2, 1, false>(k, d, ctrl, P, prm, fixed_iters);
-    case 2: return solve_small<2, 2, false>(k, d, ctrl, P, prm, fixed_iters);
-    case 3: return solve_small<2, 3, false>(k, d, ctrl, P, prm, fixed_iters);
-    default: return solve_small<2, 4, false>(k, d, ctrl, P, prm, fixed_iters);
+    case 1: return solve_small<2, 1, false, GS>(k, d, ctrl, P, prm, fixed_iters);
+    case 2: return solve_small<2, 2, false, GS>(k, d, ctrl, P, prm, fixed_iters);
+    case 3: return solve_small<2, 3, false, GS>(k, d, ctrl, P, prm, fixed_iters);
+    default: return solve_small<2, 4, false, GS>(k, d, ctrl, P, prm, fixed_iters);
     }
+}
+
+// A and G^{-1} in LDS first; then A alone (the current phase may be held that
+// way from the start, or the FP32 -> FP64 handover of the first variant may
+// have left a phase that is).  false: the streamed variant continues from the
+// state in ctrl[k] and the pools.
+__device__ inline bool solve_small_any(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
+                                       const SolveParams& prm, int64_t fixed_iters) {
+    if (solve_small_shape<false>(k, d, ctrl, P, prm, fixed_iters)) return true;
+    return solve_small_shape<true>(k, d, ctrl, P, prm, fixed_iters);
 }

@@ -23,8 +23,10 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-# (m, n, seed, FP64 data fits in LDS)
-SHAPES = [(39, 97, 21, True), (76, 159, 23, True), (23, 400, 13, True), (100, 200, 14, False)]
+# (m, n, seed, FP64 data fits in LDS); 90 x 180: the FP64 phase holds only A in LDS
+# (G^{-1} read from the pool); 128 x 256: the FP32 phase does, and FP64 data does not fit
+SHAPES = [(39, 97, 21, True), (76, 159, 23, True), (23, 400, 13, True), (100, 200, 14, False),
+          (90, 180, 17, True), (128, 256, 16, False)]
 
 
 def _iterate(lp, st, N, lds, fp32, rule):
