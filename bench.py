@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # (bench.py --copy-calibration).  Keyed by a hash of the kernel's sources: any
 # change to them voids the figure (reported as null until measured again).
 PMC_TRAFFIC = {
-    "9cfeebb4c7b2915a": {"fetch_kib": 1011606163.7, "write_kib": 19752660.2,
+    "20c6498551e51a87": {"fetch_kib": 1011746727.5, "write_kib": 19438547.3,
                          "fetch_scale": 1048576.0 / 524315.1, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ["paper_1805_12344_amd/csrc/abip_solve_wg.hip", "paper_1805_12344_amd/csrc/abip_small.h",
