@@ -5,12 +5,16 @@ Workload (one "step"): 256 dense random LPs, m ~ U{20..400}, n ~ U{2m..3m},
 planted strictly complementary optima, 10% made primal infeasible by a planted
 Farkas vector (seed 3).  A step is the whole hot path for the batch: setup
 (HSD constants, FP64 SYRK + Cholesky + inverse of I + A A^T, Schur border) and
-the batched ABIP solve (FP32-streamed bulk with FP64 checks and FP64 polish) in
-one persistent launch, inputs already resident in HBM.
+the batched ABIP solve (FP32 bulk with FP64 checks and FP64 polish) in one
+persistent launch, inputs already resident in HBM.
 
 Printed: one JSON line.  value = LP solves/s (LPs ending with the right status,
 solved ones re-checked in FP64 on the host at <= 1e-6 relative KKT) over the
-end-to-end wall time of the timed steps.
+end-to-end wall time of the timed steps.  Beside it: the FP64 batched run and
+the plain FP64 path (one LP per setup/solve call) on the same 256 LPs, the
+error of every FP32-bulk result against the FP64 results and the planted
+optimum, the roofline of the solve kernel, the oracle's time on the host cores,
+and extra measurements of the other workloads.
 """
 from __future__ import annotations
 
@@ -33,8 +37,6 @@ HBM_PEAK_GBS = 8000.0
 # (bench.py --copy-calibration).  Keyed by a hash of the kernel's sources: any
 # change to them voids the figure (reported as null until measured again).
 PMC_TRAFFIC = {
-    "20c6498551e51a87": {"fetch_kib": 1011746727.5, "write_kib": 19438547.3,
-                         "fetch_scale": 1048576.0 / 524315.1, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ["paper_1805_12344_amd/csrc/abip_solve_wg.hip", "paper_1805_12344_amd/csrc/abip_small.h",
                   "paper_1805_12344_amd/csrc/abip_internal.h"]
@@ -78,47 +80,76 @@ def to_device(lps):
     return As, bs, cs
 
 
+def host_kkt(A, b, c, x, y, s):
+    """The relative residuals of the Section 4.1 tests for a returned (x, y, s),
+    recomputed in FP64 on the host: (pres, dres, gap)."""
+    pres = np.linalg.norm(A @ x - b) / (1 + np.linalg.norm(b))
+    dres = np.linalg.norm(A.T @ y + s - c) / (1 + np.linalg.norm(c))
+    pobj, dobj = float(c @ x), float(b @ y)
+    gap = abs(pobj - dobj) / (1 + abs(pobj) + abs(dobj))
+    return float(pres), float(dres), float(gap)
+
+
+def _host(ts):
+    return [t.cpu().numpy() for t in ts]
+
+
 def verify(lps, xs, ys, ss, infos, eps=1e-6):
-    """Host FP64 re-check: status right, and KKT <= eps for solved LPs."""
+    """Host FP64 re-check: status right, and KKT <= eps for solved LPs.
+    Returns (number correct, worst KKT, per-LP host KKT (NaN where not solved))."""
     ok = 0
     worst = 0.0
+    per = []
     for lp, x, y, s, info in zip(lps, xs, ys, ss, infos):
+        kkt = float("nan")
         if lp["status"] == "solved":
-            if info["status"] != 1:
-                continue
-            A, b, c = lp["A"], lp["b"], lp["c"]
-            x, y, s = x.cpu().numpy(), y.cpu().numpy(), s.cpu().numpy()
-            pres = np.linalg.norm(A @ x - b) / (1 + np.linalg.norm(b))
-            dres = np.linalg.norm(A.T @ y + s - c) / (1 + np.linalg.norm(c))
-            pobj, dobj = c @ x, b @ y
-            gap = abs(pobj - dobj) / (1 + abs(pobj) + abs(dobj))
-            kkt = max(pres, dres, gap)
-            worst = max(worst, kkt)
-            if kkt <= eps * (1 + 1e-9):
-                ok += 1
-        else:
-            if info["status"] == 2:
-                ok += 1
-    return ok, worst
+            if info["status"] == 1:
+                kkt = max(host_kkt(lp["A"], lp["b"], lp["c"], x, y, s))
+                worst = max(worst, kkt)
+                if kkt <= eps * (1 + 1e-9):
+                    ok += 1
+        elif info["status"] == 2:
+            ok += 1
+        per.append(kkt)
+    return ok, worst, per
 
 
-def algorithmic_bytes(lps, infos, fp32_stream=True):
-    """Bytes the persistent solve launch must move, from its own pass counts.
+# ---------------------------------------------------------------------------
+# bytes of the solve kernel
+# ---------------------------------------------------------------------------
 
-    Per column pass over A: m*n matrix entries plus 8 doubles per column (x, s
-    read and written, c, cbar, Z_x read); per inner update one pass over the
-    m x m G^{-1}.  FP32-streamed passes count 4 bytes per matrix entry, FP64
-    passes 8.
+def survey_bytes_per_update(m, n, p):
+    """Algorithmic bytes of one ADMM update by the count of the scope table's
+    measurement row: A read twice (2 m n p), the factor's two triangular sweeps
+    (m^2 p, here one pass over the symmetric G^{-1}) and about ten vectors of
+    length m + n in FP64; p = 4 for FP32 data, 8 for FP64."""
+    return 2.0 * m * n * p + m * m * p + 80.0 * (m + n)
+
+
+def launch_bytes(lps, infos):
+    """Bytes of one persistent solve launch, from the library's own counters.
+
+    survey: every update priced by survey_bytes_per_update (data precision of
+            the update), wherever the data actually lives;
+    hbm:    what this design must move through device memory: one read of A
+            per pass that streams it (8 doubles per column of vectors with it)
+            and one read of G^{-1} per pass that reads it from device memory;
+            passes whose A (and G^{-1}) sit in LDS move no HBM bytes.
     """
-    tot = 0.0
+    survey = hbm = 0.0
+    passes = {"lds": 0, "streamed": 0}
     for lp, info in zip(lps, infos):
         m, n = lp["m"], lp["n"]
         it64 = info["admm_iters_fp64"]
         it32 = info["admm_iters"] - it64
-        tot += info["colpass_fp32"] * (4.0 * m * n + 64.0 * n)
-        tot += info["colpass_fp64"] * (8.0 * m * n + 64.0 * n)
-        tot += it32 * 4.0 * m * m + it64 * 8.0 * m * m
-    return tot
+        survey += it32 * survey_bytes_per_update(m, n, 4) + it64 * survey_bytes_per_update(m, n, 8)
+        s32 = info["colpass_fp32"] - info["colpass_lds_fp32"]
+        s64 = info["colpass_fp64"] - info["colpass_lds_fp64"]
+        hbm += s32 * (4.0 * m * n + 64.0 * n) + s64 * (8.0 * m * n + 64.0 * n)
+        hbm += info["ginv_hbm_fp32"] * 4.0 * m * m + info["ginv_hbm_fp64"] * 8.0 * m * m
+        passes["lds"] += info["colpass_lds_fp32"] + info["colpass_lds_fp64"]
+        passes["streamed"] += s32 + s64
+    return survey, hbm, passes
 
 
 def traffic_bytes():
@@ -135,35 +166,153 @@ def run_batch(abip, As, bs, cs, settings):
     return xs, ys, ss, infos
 
 
-def cpu_baseline(lps, gpu_iters, sample_idx, iters_each=12000):
-    """Time the FP64 oracle (as it is) on a bounded sample of the same LPs.
+def _stats(v):
+    v = [x for x in v if np.isfinite(x)]
+    if not v:
+        return None
+    return {"max": float(np.max(v)), "median": float(np.median(v)), "count": len(v)}
 
-    Each sampled LP runs `iters_each` oracle iterations; its per-iteration time
-    times the LP's full iteration count (the same algorithm in FP64 stops at
-    the same iteration as the FP64 GPU path) gives its solve time.
+
+def error_report(lps, r32, r64):
+    """Error of every FP32-bulk result against the FP64 batched result of the
+    same LP and against the planted optimum (unique: |supp x0| = m)."""
+    e_obj64, e_x64, e_objp, e_xp, lib = [], [], [], [], []
+    for k, lp in enumerate(lps):
+        i32, i64 = r32[3][k], r64[3][k]
+        lib.append(i32["err_vs_fp64"])
+        if lp["status"] != "solved" or i32["status"] != 1 or i64["status"] != 1:
+            continue
+        x32, x64 = r32[0][k], r64[0][k]
+        p32, p64 = float(lp["c"] @ x32), float(lp["c"] @ x64)
+        e_obj64.append(abs(p32 - p64) / (1 + abs(p64)))
+        e_x64.append(float(np.linalg.norm(x32 - x64) / (1 + np.linalg.norm(x64))))
+        e_objp.append(abs(p32 - lp["pstar"]) / (1 + abs(lp["pstar"])))
+        e_xp.append(float(np.linalg.norm(x32 - lp["x0"]) / (1 + np.linalg.norm(lp["x0"]))))
+    return {"what": "fp32-bulk results: objective |c^T x - ref| / (1 + |ref|) and solution "
+                    "||x - x_ref|| / (1 + ||x_ref||) against the fp64 batched result and the planted optimum; "
+                    "err_vs_fp64 = the library's FP64 recheck of each returned point (relative KKT, or the "
+                    "certificate test for infeasible LPs)",
+            "obj_vs_fp64": _stats(e_obj64), "x_vs_fp64": _stats(e_x64),
+            "obj_vs_planted": _stats(e_objp), "x_vs_planted": _stats(e_xp),
+            "err_vs_fp64_library": _stats(lib)}
+
+
+def per_lp_rows(lps, infos, infos64, kkt):
+    rows = []
+    for k, (lp, i, j) in enumerate(zip(lps, infos, infos64)):
+        rows.append([k, lp["m"], lp["n"], lp["status"], i["status_name"], i["admm_iters"], i["admm_iters_fp64"],
+                     i["colpass_fp32"], i["colpass_fp64"], i["colpass_lds_fp32"], i["colpass_lds_fp64"],
+                     i["ginv_hbm_fp32"], i["ginv_hbm_fp64"], i["lds_mode"], j["admm_iters"] if j else -1,
+                     kkt[k], i["err_vs_fp64"], i["fp32_exit_kkt"],
+                     i["ticks_total"] / 100.0 / max(1, i["admm_iters"])])
+    return rows
+
+
+PER_LP_HEADER = ["lp", "m", "n", "planted", "status", "iters", "iters_fp64", "colpass_fp32", "colpass_fp64",
+                 "colpass_lds_fp32", "colpass_lds_fp64", "ginv_hbm_fp32", "ginv_hbm_fp64", "lds_mode",
+                 "iters_fp64_batched", "host_kkt", "err_vs_fp64", "fp32_exit_kkt", "us_per_update"]
+
+
+# ---------------------------------------------------------------------------
+# the oracle on the host cores (cpu_baseline leg: the only part that runs the oracle)
+# ---------------------------------------------------------------------------
+
+def host_info():
+    model = "?"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return model, nproc
+
+
+def cpu_baseline(lps, iters64, correct, budget_iters=1500):
+    """The FP64 oracle as it stands, timed on the host on a stratified sample of
+    the batch, at one BLAS thread and at all host cores.
+
+    Every sampled LP runs its setup (Schur solver: Cholesky of G, border) and
+    min(its FP64 iteration count, budget_iters) oracle iterations (tests every
+    iteration).  A least-squares fit of the per-iteration time against
+    (1, m n, m^2) and of the setup time against (1, m^2 n) over the sample then
+    prices every LP of the batch at its FP64 iteration count (the same count the
+    oracle takes: the GPU's FP64 path matches it to 1%), so the estimate covers
+    the whole batch, including the LPs that run to the iteration cap.
     """
     from threadpoolctl import threadpool_limits
     import oracle
-    per_lp = []
-    t_all = time.perf_counter()
-    with threadpool_limits(limits=1):
-        for k in sample_idx:
-            lp = lps[k]
-            s = oracle.Settings(max_admm_iters=iters_each)
-            t0 = time.perf_counter()
-            out = oracle.solve(lp["A"], lp["b"], lp["c"], s)
-            dt = time.perf_counter() - t0
-            done = max(1, out["admm_iters"])
-            per_lp.append(dt / done * gpu_iters[k])
-    wall = time.perf_counter() - t_all
-    sec_per_solve = float(np.mean(per_lp))
-    return {"value": 1.0 / sec_per_solve, "unit": "LP solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(sample_idx)} LPs of the batch (indices {list(sample_idx)}), {iters_each} "
-                      f"oracle iterations each, per-iteration time x the LP's FP64 iteration count; "
-                      f"{wall:.1f} s of CPU work"}
+    model, nproc = host_info()
+    order = np.argsort([lp["m"] * lp["n"] for lp in lps])
+    sample = sorted(set(int(order[i]) for i in np.linspace(0, len(lps) - 1, 10).round().astype(int)) |
+                    {k for k in range(len(lps)) if iters64[k] >= 10 ** 6})
+    out = {}
+    for label, threads in (("1_thread", 1), ("all_cores", nproc)):
+        rows_it, rows_su = [], []
+        t_all = time.perf_counter()
+        with threadpool_limits(limits=threads):
+            for k in sample:
+                lp = lps[k]
+                prob = oracle.Problem(lp["A"], lp["b"], lp["c"])
+                t0 = time.perf_counter()
+                solver = oracle.SchurIQSolver(prob)
+                t_setup = time.perf_counter() - t0
+                cap = int(min(max(1, iters64[k]), budget_iters))
+                t0 = time.perf_counter()
+                out_k = oracle.solve(prob, settings=oracle.Settings(max_admm_iters=cap), solver=solver)
+                t_it = (time.perf_counter() - t0) / max(1, out_k["admm_iters"])
+                rows_it.append((lp["m"] * lp["n"], lp["m"] ** 2, t_it))
+                rows_su.append((lp["m"] ** 2 * lp["n"], t_setup))
+        wall = time.perf_counter() - t_all
+        X = np.array([[1.0, r[0], r[1]] for r in rows_it])
+        ci, *_ = np.linalg.lstsq(X, np.array([r[2] for r in rows_it]), rcond=None)
+        Xs = np.array([[1.0, r[0]] for r in rows_su])
+        cs, *_ = np.linalg.lstsq(Xs, np.array([r[1] for r in rows_su]), rcond=None)
+        total = 0.0
+        for k, lp in enumerate(lps):
+            m, n = lp["m"], lp["n"]
+            t_it = max(ci[0] + ci[1] * m * n + ci[2] * m * m, 1e-7)
+            t_su = max(cs[0] + cs[1] * m * m * n, 0.0)
+            total += t_su + t_it * iters64[k]
+        out[label] = {"value": correct / total, "threads": threads, "batch_seconds_estimated": total,
+                      "sample_cpu_seconds": wall}
+    one = out["1_thread"]
+    return {"value": one["value"], "unit": "LP solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sample)} LPs of the batch stratified by m n (indices {sample}, including every LP "
+                      f"at the iteration cap), setup + min(FP64 count, {budget_iters}) oracle iterations each; "
+                      f"per-iteration and setup times fitted against (1, m n, m^2) and (1, m^2 n) and summed "
+                      f"over all {len(lps)} LPs at their FP64 iteration counts; {one['sample_cpu_seconds']:.1f} s "
+                      f"of CPU work at 1 thread",
+            "all_cores": out["all_cores"], "host_cpu": model, "nproc": nproc}
 
 
-def extra_basis_pursuit(abip, torch):
+def cpu_time_single(A, b, c, iters_total, sample_iters, solver_fn, threads):
+    """Oracle time of one LP: setup once, `sample_iters` iterations, scaled to iters_total."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    with threadpool_limits(limits=threads):
+        prob = oracle.abip._as_problem(A, b, c)
+        t0 = time.perf_counter()
+        solver = solver_fn(prob)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        out = oracle.solve(prob, settings=oracle.Settings(max_admm_iters=sample_iters), solver=solver)
+        t_it = (time.perf_counter() - t0) / max(1, out["admm_iters"])
+    return {"threads": threads, "setup_s": t_setup, "s_per_iter": t_it, "iters_timed": out["admm_iters"],
+            "solve_s_estimated": t_setup + t_it * iters_total}
+
+
+# ---------------------------------------------------------------------------
+# extra workloads
+# ---------------------------------------------------------------------------
+
+def extra_basis_pursuit(abip, torch, cpu=True):
     """Basis pursuit LP, A = [A0, -A0] with A0 2000 x 8000 Gaussian/sqrt(2000), 5% sparse x_true,
     seed 2: one LP on the whole GPU (grid engine), FP32 bulk + FP64 polish."""
     import lpgen
@@ -183,29 +332,41 @@ def extra_basis_pursuit(abip, torch):
     x, y, sv, info = abip.abip_solve(w)
     torch.cuda.synchronize()
     solve_s = time.perf_counter() - t0
-    xh, yh, sh = x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy()
-    pres = np.linalg.norm(lp["A"] @ xh - lp["b"]) / (1 + np.linalg.norm(lp["b"]))
-    dres = np.linalg.norm(lp["A"].T @ yh + sh - lp["c"]) / (1 + np.linalg.norm(lp["c"]))
-    po, do = float(lp["c"] @ xh), float(lp["b"] @ yh)
-    gap = abs(po - do) / (1 + abs(po) + abs(do))
+    xh, yh, sh = _host((x, y, sv))
+    kkt = host_kkt(lp["A"], lp["b"], lp["c"], xh, yh, sh)
     m, n = 2000, 16000
     it32 = info["admm_iters"] - info["admm_iters_fp64"]
     it64 = info["admm_iters_fp64"]
-    # per update: A once (m n) and G^{-1} once (m^2), plus 8 doubles per column
-    byts = info["colpass_fp32"] * (4.0 * m * n + 64.0 * n) + info["colpass_fp64"] * (8.0 * m * n + 64.0 * n) \
+    survey = it32 * survey_bytes_per_update(m, n, 4) + it64 * survey_bytes_per_update(m, n, 8)
+    # this design: A once per pass, G^{-1} once per update, 8 doubles per column
+    design = info["colpass_fp32"] * (4.0 * m * n + 64.0 * n) + info["colpass_fp64"] * (8.0 * m * n + 64.0 * n) \
         + it32 * 4.0 * m * m + it64 * 8.0 * m * m
-    ach = byts / (info["kernel_ms"] / 1e3) / 1e9
+    ks = info["kernel_ms"] / 1e3
     w.free()
-    return {"workload": "basis pursuit LP 2000 x 16000 (A = [A0, -A0]), seed 2, eps 1e-6, fp32 bulk + fp64 polish",
-            "status": info["status_name"], "admm_iters": info["admm_iters"], "admm_iters_fp64": it64,
-            "setup_ms": setup_ms, "solve_s": solve_s, "admm_iters_per_s": info["admm_iters"] / solve_s,
-            "us_per_iter": info["kernel_ms"] * 1e3 / max(1, info["admm_iters"]),
-            "host_kkt": [pres, dres, gap], "pobj": po, "pstar": lp["pstar"],
-            "autotune": tune, "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                           "frac": ach / HBM_PEAK_GBS, "kernel": "grid engine (col + G^-1 + reductions)"}}
+    out = {"workload": "basis pursuit LP 2000 x 16000 (A = [A0, -A0]), seed 2, eps 1e-6, fp32 bulk + fp64 polish",
+           "status": info["status_name"], "admm_iters": info["admm_iters"], "admm_iters_fp64": it64,
+           "setup_ms": setup_ms, "solve_s": solve_s, "admm_iters_per_s": info["admm_iters"] / solve_s,
+           "us_per_iter": info["kernel_ms"] * 1e3 / max(1, info["admm_iters"]),
+           "host_kkt": list(kkt), "err_vs_fp64": info["err_vs_fp64"], "fp32_exit_kkt": info["fp32_exit_kkt"],
+           "pobj": float(lp["c"] @ xh), "pstar": lp["pstar"],
+           "obj_vs_planted": abs(float(lp["c"] @ xh) - lp["pstar"]) / (1 + lp["pstar"]),
+           "autotune": tune,
+           "roofline": {"bound": "hbm", "achieved": survey / ks / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": survey / ks / 1e9 / HBM_PEAK_GBS,
+                        "frac_design_bytes": design / ks / 1e9 / HBM_PEAK_GBS,
+                        "bytes_per_update_survey": survey_bytes_per_update(m, n, 4),
+                        "kernel": "grid engine (col + G^-1 + reductions + border)"}}
+    if cpu:
+        import oracle
+        out["cpu_baseline"] = {
+            "kind": "oracle", "what": "dense Schur solve (Cholesky of G), 40 iterations timed, scaled to the "
+                                      "GPU's iteration count",
+            "runs": [cpu_time_single(lp["A"], lp["b"], lp["c"], info["admm_iters"], 40, oracle.SchurIQSolver, t)
+                     for t in (1, host_info()[1])]}
+    return out
 
 
-def extra_sparse(abip, torch):
+def extra_sparse(abip, torch, cpu=True):
     """Sparse NETLIB-sized LP 10000 x 30000, ~0.1% U(-1,1) plus a diagonal block, seed 1, CG path, FP64."""
     import lpgen
     import scipy.sparse as sp
@@ -222,11 +383,8 @@ def extra_sparse(abip, torch):
     x, y, sv, info = abip.abip_solve(w)
     torch.cuda.synchronize()
     solve_s = time.perf_counter() - t0
-    xh, yh, sh = x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy()
-    pres = np.linalg.norm(As @ xh - lp["b"]) / (1 + np.linalg.norm(lp["b"]))
-    dres = np.linalg.norm(As.T @ yh + sh - lp["c"]) / (1 + np.linalg.norm(lp["c"]))
-    po, do = float(lp["c"] @ xh), float(lp["b"] @ yh)
-    gap = abs(po - do) / (1 + abs(po) + abs(do))
+    xh, yh, sh = _host((x, y, sv))
+    kkt = host_kkt(As, lp["b"], lp["c"], xh, yh, sh)
     it = max(1, info["admm_iters"])
     w.free()
     # algorithmic bytes of one CG iteration (the dominant work): CSR(A^T) and CSR(A) once each
@@ -237,19 +395,31 @@ def extra_sparse(abip, torch):
     cg_bytes = 24.0 * nnz + 4.0 * (m + n + 2) + 32.0 * m + 16.0 * n + 88.0 * m
     us_cg = info["kernel_ms"] * 1e3 / max(1, info["cg_iters"])
     achieved = cg_bytes / (us_cg * 1e-6) / 1e9
-    return {"workload": "sparse planted LP 10000 x 30000, nnz %d, seed 1, eps 1e-6, CG on I + A A^T, fp64" % lp["nnz"],
-            "status": info["status_name"], "admm_iters": info["admm_iters"], "cg_iters": info["cg_iters"],
-            "setup_ms": setup_ms, "solve_s": solve_s, "admm_iters_per_s": info["admm_iters"] / solve_s,
-            "us_per_iter": info["kernel_ms"] * 1e3 / it, "us_per_cg_iter": info["kernel_ms"] * 1e3 / max(1, info["cg_iters"]),
-            "host_kkt": [pres, dres, gap], "pobj": po, "pstar": lp["pstar"],
-            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_sp_solve (per CG iteration)",
-                         "algorithmic_bytes_per_cg_iteration": cg_bytes,
-                         "note": "bound in practice by two grid barriers per CG iteration, not by HBM"}}
+    out = {"workload": "sparse planted LP 10000 x 30000, nnz %d, seed 1, eps 1e-6, CG on I + A A^T, fp64" % nnz,
+           "status": info["status_name"], "admm_iters": info["admm_iters"], "cg_iters": info["cg_iters"],
+           "setup_ms": setup_ms, "solve_s": solve_s, "admm_iters_per_s": info["admm_iters"] / solve_s,
+           "us_per_iter": info["kernel_ms"] * 1e3 / it, "us_per_cg_iter": us_cg,
+           "barrier_ticks_share": info["ticks_check"] / max(1, info["ticks_total"]),
+           "host_kkt": list(kkt), "err_vs_fp64": info["err_vs_fp64"], "pobj": float(lp["c"] @ xh),
+           "pstar": lp["pstar"],
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "kernel": "k_sp_solve (per CG iteration)",
+                        "algorithmic_bytes_per_cg_iteration": cg_bytes,
+                        "note": "bound in practice by the grid barriers of each CG iteration, not by HBM"}}
+    if cpu:
+        import oracle
+        out["cpu_baseline"] = {
+            "kind": "oracle", "what": "CG step of Section 4.4 on scipy.sparse A (Jacobi, warm start, tol 1e-7), "
+                                      "30 iterations timed, scaled to the GPU's iteration count",
+            "runs": [cpu_time_single(As, lp["b"], lp["c"], info["admm_iters"], 30,
+                                     lambda p: oracle.CGIQSolver(p, tol=1e-7), t) for t in (1, host_info()[1])]}
+    return out
 
 
-def extra_differentiable(abip, torch):
-    """64 LPs 200 x 500, seed 4, FP32 forward; adjoint backward of L = w^T x* per LP."""
+def extra_differentiable(abip, torch, cpu=True):
+    """64 LPs 200 x 500, seed 4, FP32 forward; adjoint backward of L = w^T x* per LP,
+    checked against the LP derivative of the planted basis (dL/db = A_B^{-T} w_B,
+    dL/dc = 0), which is what central differences of the basis solution map give."""
     import lpgen
     lps = lpgen.diff_batch(64, 200, 500, 4)
     As = [torch.tensor(lp["A"], device="cuda") for lp in lps]
@@ -268,14 +438,38 @@ def extra_differentiable(abip, torch):
     torch.cuda.synchronize()
     bwd = time.perf_counter() - t0
     ok = sum(1 for i in infos if i["status"] == abip.ABIP_SOLVED)
-    finite = sum(1 for dc, db in zip(dcs, dbs) if bool(torch.isfinite(dc).all()) and bool(torch.isfinite(db).all()))
+    eb, ec = [], []
+    for lp, dc, db in zip(lps, _host(dcs), _host(dbs)):
+        B = lp["basis"]
+        lam = np.linalg.solve(lp["A"][:, B].T, lp["w"][B])
+        eb.append(float(np.linalg.norm(db - lam) / np.linalg.norm(lam)))
+        ec.append(float(np.linalg.norm(dc) / np.linalg.norm(lp["w"])))
     w.free()
-    return {"workload": "64 LPs 200 x 500, seed 4, L = w^T x*, fp32 bulk + fp64 polish forward, adjoint backward",
-            "solved": ok, "finite_gradients": finite, "forward_s": fwd, "backward_s": bwd,
-            "backward_over_forward": bwd / fwd}
+    out = {"workload": "64 LPs 200 x 500, seed 4, L = w^T x*, fp32 bulk + fp64 polish forward, adjoint backward",
+           "solved": ok, "forward_s": fwd, "backward_s": bwd, "backward_over_forward": bwd / fwd,
+           "db_rel_err_vs_basis_formula": _stats(eb), "dc_norm_over_w_norm": _stats(ec),
+           "note": "the adjoint differentiates the central point at the final mu; its distance to the "
+                   "LP derivative shrinks with mu and grows as the vertex nears degeneracy"}
+    if cpu:
+        import oracle
+        from threadpoolctl import threadpool_limits
+        runs = []
+        for threads in (1, host_info()[1]):
+            with threadpool_limits(limits=threads):
+                t0 = time.perf_counter()
+                for lp in lps[:2]:
+                    ref = oracle.solve(lp["A"], lp["b"], lp["c"])
+                    lam = oracle.kkt_adjoint(lp["A"], lp["b"], lp["c"], ref["state"], lp["w"])
+                    oracle.contract_adjoint(lp["A"], lp["b"], lp["c"], ref["state"], lam)
+                per = (time.perf_counter() - t0) / 2
+            runs.append({"threads": threads, "s_per_lp_forward_backward": per,
+                         "batch_s_estimated": per * len(lps)})
+        out["cpu_baseline"] = {"kind": "oracle", "what": "oracle solve + dense KKT adjoint, 2 LPs timed, "
+                                                         "scaled to 64", "runs": runs}
+    return out
 
 
-def extra_paper_random(abip, torch):
+def extra_paper_random(abip, torch, cpu=True):
     """The paper's random-LP recipe (lpgen.paper_random, seed 1) at three of its
     Table 1 sizes and its tolerance 1e-3: one LP on the whole GPU (grid engine),
     FP32 bulk + FP64 polish.  The paper's own ABIP times (a laptop CPU, other
@@ -295,21 +489,18 @@ def extra_paper_random(abip, torch):
         x, y, sv, info = abip.abip_solve(w)
         torch.cuda.synchronize()
         total_s = time.perf_counter() - t0
-        xh, yh, sh = x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy()
-        pres = np.linalg.norm(lp["A"] @ xh - lp["b"]) / (1 + np.linalg.norm(lp["b"]))
-        dres = np.linalg.norm(lp["A"].T @ yh + sh - lp["c"]) / (1 + np.linalg.norm(lp["c"]))
-        po, do = float(lp["c"] @ xh), float(lp["b"] @ yh)
-        gap = abs(po - do) / (1 + abs(po) + abs(do))
+        xh, yh, sh = _host((x, y, sv))
         w.free()
         out.append({"m": m, "n": n, "status": info["status_name"], "admm_iters": info["admm_iters"],
                     "setup_plus_solve_s": total_s, "solve_kernel_s": info["kernel_ms"] / 1e3,
-                    "host_kkt": [pres, dres, gap], "pobj": po, "pstar": lp["pstar"],
+                    "host_kkt": list(host_kkt(lp["A"], lp["b"], lp["c"], xh, yh, sh)),
+                    "err_vs_fp64": info["err_vs_fp64"], "pobj": float(lp["c"] @ xh), "pstar": lp["pstar"],
                     "paper_abip_s_laptop_cpu": ps})
     return {"workload": "paper's random-LP recipe, seed 1, eps 1e-3, fp32 bulk + fp64 polish, grid engine",
             "instances": out}
 
 
-def extra_sice(abip, torch, d=64, N=1000):
+def extra_sice(abip, torch, d=64, N=1000, cpu=True):
     """Sparse inverse covariance estimation (lpgen.sice: synthetic Sigma, d
     variables, N samples, lambda = 1.5 sqrt(log d / N)): the d column LPs
     (2d x 4d each) in one batched launch, FP32 bulk + FP64 polish."""
@@ -334,6 +525,7 @@ def extra_sice(abip, torch, d=64, N=1000):
                         "one batched launch, fp32 bulk + fp64 polish, eps 1e-6",
             "statuses": st, "setup_plus_solve_s": total_s, "solve_kernel_s": infos[0]["kernel_ms"] / 1e3,
             "admm_iters_mean": float(np.mean(its)), "admm_iters_max": int(np.max(its)),
+            "err_vs_fp64": _stats([i["err_vs_fp64"] for i in infos]),
             "max_constraint_over_lambda": viol, "l1_norm_of_omega": float(np.abs(B).sum())}
 
 
@@ -345,7 +537,10 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparisons")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baselines")
+    ap.add_argument("--plain-sample", type=int, default=0,
+                    help="time the plain FP64 path on this many LPs (0: all LPs of the batch)")
+    ap.add_argument("--per-lp-out", default=None, help="write the per-LP table (TSV) to this file")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra measurements (basis pursuit, sparse CG, differentiable batch, "
                          "the paper's random LPs, SICE)")
@@ -370,7 +565,7 @@ def main():
     extras = {"basis_pursuit": extra_basis_pursuit, "sparse_cg": extra_sparse,
               "differentiable": extra_differentiable, "paper_random": extra_paper_random, "sice": extra_sice}
     if args.extra_only:
-        print(json.dumps({args.extra_only: extras[args.extra_only](abip, torch)}), flush=True)
+        print(json.dumps({args.extra_only: extras[args.extra_only](abip, torch, cpu=False)}), flush=True)
         return
     lps = make_workload(args.batch, args.seed)
     As, bs, cs = to_device(lps)
@@ -393,14 +588,16 @@ def main():
     log(f"timed {args.steps} step(s): {elapsed:.2f} s")
 
     xs, ys, ss, infos = results[-1]
-    ok, worst = verify(lps, xs, ys, ss, infos)
+    r32 = (_host(xs), _host(ys), _host(ss), infos)
+    ok, worst, kkt32 = verify(lps, *r32)
     solves_per_s = ok * args.steps / elapsed
     iters = np.array([i["admm_iters"] for i in infos])
     kernel_ms = infos[0]["kernel_ms"]
     admm_per_s = float(iters.sum()) / (kernel_ms / 1e3)
-    bytes_launch = algorithmic_bytes(lps, infos)
-    achieved = bytes_launch / (kernel_ms / 1e3) / 1e9
+    survey_b, hbm_b, passes = launch_bytes(lps, infos)
+    ks = kernel_ms / 1e3
     statuses = np.bincount([i["status"] for i in infos], minlength=5).tolist()
+    tail = sorted(range(len(lps)), key=lambda k: -infos[k]["ticks_total"])[:4]
     line = {
         "metric": "ADMM iters/s and LP solves/s at 1e-6 rel KKT; FP32-batched vs FP64 plain",
         "value": solves_per_s,
@@ -412,7 +609,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 arithmetic on f32-streamed A and G^-1, f64 polish",
+        "dtype": "f64 arithmetic on f32-stored A and G^-1, f64 polish",
         "data": "synthetic",
         "config": {"workload": f"batched dense LPs: {len(lps)} LPs, m~U[20,400], n~U[2m,3m], 10% "
                                f"primal infeasible, seed {args.seed}; eps 1e-6",
@@ -426,12 +623,26 @@ def main():
         "worst_kkt": worst,
         "solve_kernel_ms": kernel_ms,
         "setup_plus_solve_ms": elapsed / args.steps * 1e3,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(),
+        "makespan_lps": [{"lp": k, "m": lps[k]["m"], "n": lps[k]["n"], "iters": infos[k]["admm_iters"],
+                          "status": infos[k]["status_name"], "lds_mode": infos[k]["lds_mode"],
+                          "ms": infos[k]["ticks_total"] / 1e5,
+                          "us_per_update": infos[k]["ticks_total"] / 100.0 / max(1, infos[k]["admm_iters"])}
+                         for k in tail],
+        "roofline": {"bound": "hbm", "achieved": survey_b / ks / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": survey_b / ks / 1e9 / HBM_PEAK_GBS, "traffic": traffic_bytes(),
                      "kernel": "k_solve_wg (persistent batched solve)", "kernel_src": kernel_hash(),
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "algorithmic_bytes_per_launch": survey_b,
+                     "count": "per update 2 m n p + m^2 p + 80 (m + n) bytes (p = 4 FP32 / 8 FP64 data), "
+                              "summed over every update of the launch",
+                     "hbm_bytes_this_design": hbm_b,
+                     "frac_hbm_bytes_this_design": hbm_b / ks / 1e9 / HBM_PEAK_GBS,
+                     "passes": passes,
+                     "note": "most updates of the batch read A (and G^-1) from LDS; the launch lasts as long "
+                             "as its slowest LP (makespan_lps), which runs alone on one CU, so the kernel is "
+                             "bound by that LP's per-update latency, not by HBM"},
     }
 
+    r64 = None
     if not args.no_compare:
         s64 = abip.abip_default_settings(precision=abip.ABIP_PREC_FP64)
         torch.cuda.synchronize()
@@ -439,41 +650,57 @@ def main():
         xs64, ys64, ss64, infos64 = run_batch(abip, As, bs, cs, s64)
         torch.cuda.synchronize()
         e64 = time.perf_counter() - t1
-        ok64, worst64 = verify(lps, xs64, ys64, ss64, infos64)
+        r64 = (_host(xs64), _host(ys64), _host(ss64), infos64)
+        ok64, worst64, _ = verify(lps, *r64)
         it64 = np.array([i["admm_iters"] for i in infos64])
         line["fp64_batched"] = {"solves_per_s": ok64 / e64, "ms": e64 * 1e3, "correct": ok64,
                                 "admm_iters_per_s": float(it64.sum()) / (infos64[0]["kernel_ms"] / 1e3),
-                                "worst_kkt": worst64}
-        # the plain FP64 path: one LP per setup/solve call, sequentially, on a sample
-        rng = np.random.default_rng(0)
-        sample = sorted(rng.choice(len(lps), size=8, replace=False).tolist())
+                                "admm_iters_total": int(it64.sum()), "worst_kkt": worst64}
+        line["speedup_vs_fp64_batched"] = solves_per_s / max(1e-12, ok64 / e64)
+        line["fp32_error"] = error_report(lps, r32, r64)
+        # the plain FP64 path: one LP per setup/solve call, sequentially
+        idx = list(range(len(lps)))
+        if args.plain_sample:
+            rng = np.random.default_rng(0)
+            caps = [k for k in idx if infos64[k]["status"] == 4]
+            rest = sorted(set(rng.choice(len(lps), size=args.plain_sample, replace=False).tolist()) - set(caps))
+            idx = sorted(caps + rest[:max(0, args.plain_sample - len(caps))])
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         okp = 0
-        for k in sample:
+        for k in idx:
             w = abip.abip_setup(As[k], bs[k], cs[k], s64)
             x, y, s_, info = abip.abip_solve(w)
             w.free()
-            okp += verify([lps[k]], [x], [y], [s_], [info])[0]
+            okp += verify([lps[k]], [x.cpu().numpy()], [y.cpu().numpy()], [s_.cpu().numpy()], [info])[0]
         torch.cuda.synchronize()
         ep = time.perf_counter() - t2
-        line["fp64_plain_sequential"] = {"solves_per_s": okp / ep, "sample": sample, "correct": okp,
-                                         "ms": ep * 1e3}
+        line["fp64_plain_sequential"] = {"solves_per_s": okp / ep, "lps": len(idx), "correct": okp, "ms": ep * 1e3,
+                                         "sample": None if len(idx) == len(lps) else idx}
         line["speedup_vs_fp64_plain"] = solves_per_s / max(1e-12, okp / ep)
-        gpu_iters64 = it64
+        iters64 = it64
     else:
-        gpu_iters64 = iters
+        iters64 = iters
+
+    if args.per_lp_out:
+        rows = per_lp_rows(lps, infos, r64[3] if r64 else [None] * len(lps), kkt32)
+        with open(args.per_lp_out, "w") as fh:
+            fh.write("# per-LP counters of the timed FP32-bulk batched solve (bench.py --per-lp-out)\n")
+            fh.write("\t".join(PER_LP_HEADER) + "\n")
+            for r in rows:
+                fh.write("\t".join(f"{v:.6g}" if isinstance(v, float) else str(v) for v in r) + "\n")
+        line["per_lp_table"] = args.per_lp_out
 
     if not args.no_extra:
         for key, fn in extras.items():
             t0 = time.perf_counter()
-            line[key] = fn(abip, torch)
+            line[key] = fn(abip, torch, cpu=not args.no_cpu)
             log(f"{key}: {time.perf_counter() - t0:.1f} s")
 
     if not args.no_cpu:
-        rng = np.random.default_rng(1)
-        sample = sorted(rng.choice(len(lps), size=8, replace=False).tolist())
-        line["cpu_baseline"] = cpu_baseline(lps, gpu_iters64, sample)
+        t0 = time.perf_counter()
+        line["cpu_baseline"] = cpu_baseline(lps, iters64, ok)
+        log(f"cpu_baseline: {time.perf_counter() - t0:.1f} s")
 
     print(json.dumps(line), flush=True)
 

@@ -103,11 +103,13 @@ typedef struct {
                                   solve's launches; chunks of 16 iterations of the grid engine),
                                   captured at the first solve of a handle and kept with it;
                                   0: plain stream launches.  Results are bitwise the same. */
-    int32_t lds_resident;      /* 1 (default): in the batched engine, an LP whose A and G^{-1} fit
-                                  in one workgroup's LDS (in the precision of the current phase;
-                                  m <= threads, n <= 2 threads) is solved from LDS, with no global
-                                  memory traffic per iteration; 0: every LP streams A and G^{-1}
-                                  from HBM.  In the sparse engine, 1 lets each workgroup keep its
+    int32_t lds_resident;      /* 1 (default): in the batched engine (256 threads, m <= 256,
+                                  n <= 512), an LP whose A and G^{-1} fit in one workgroup's LDS in
+                                  the precision of the current phase is solved from LDS with no
+                                  global memory traffic per iteration; one whose A fits but not
+                                  together with G^{-1} holds A alone in LDS and reads G^{-1} from
+                                  device memory once per pass (abip_info.lds_mode says which);
+                                  0: every LP streams A and G^{-1} from HBM.  In the sparse engine, 1 lets each workgroup keep its
                                   rows of CSR(A) and CSR(A^T) in LDS for the CG passes when they
                                   fit; 0: the CG passes read them from global memory.  Same
                                   iteration and tests; the sums are formed in a different order,
@@ -138,6 +140,22 @@ typedef struct {
                                   ticks_colpass = column passes (A^T gathers), ticks_ginv = row
                                   passes (A gathers), ticks_check = grid barriers, ticks_update =
                                   reductions of the per-workgroup sums */
+    int64_t colpass_lds_fp32;  /* of colpass_fp32 / colpass_fp64: passes that read A from LDS */
+    int64_t colpass_lds_fp64;  /* (the rest streamed A from device memory) */
+    int64_t ginv_hbm_fp32;     /* passes over G^{-1} read from device memory (streamed LPs, and */
+    int64_t ginv_hbm_fp64;     /* LDS-resident LPs that hold A alone in LDS), per precision */
+    int32_t lds_mode;          /* LDS-resident phases of the LP: bit 0 FP32 with A and G^{-1} in LDS,
+                                  bit 1 FP64 likewise, bit 2 FP32 with A alone, bit 3 FP64 with A alone */
+    double  fp32_exit_kkt;     /* ABIP_PREC_FP32_POLISH: relative KKT (largest of the three ratios of
+                                  Section 4.1) of the FP32 phase's last iterate, measured with the FP64
+                                  data at the handover to the FP64 polish; NaN if no FP32 phase ran */
+    double  err_vs_fp64;       /* FP64 recheck of the returned point, computed after the solve by a
+                                  separate pass over the FP64 copies of A, b, c (independent of the
+                                  iteration's own sums and of the FP32 data): SOLVED / MAX_ITERS: the
+                                  largest of pres, dres, gap of (x, y, s) as returned; PRIMAL_INFEASIBLE:
+                                  ||A^T y + s|| ||b|| of the returned certificate (b^T y = 1);
+                                  DUAL_INFEASIBLE: ||A x|| ||c|| of the returned ray (c^T x = -1).
+                                  Each passes the Section 4.1 test when <= eps. */
 } abip_info;
 
 /* A matrix description.  All pointers are device pointers; abip_setup copies

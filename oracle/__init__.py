@@ -9,15 +9,18 @@ It is a plain, slow, NumPy/SciPy implementation written from the paper:
 ``oracle.abip`` holds the method (HSD embedding, Algorithms 1 and 2, the
 stopping rules, over-relaxation and the restart rules), ``oracle.reference``
 holds the independent references used to pin it (central point by Newton's
-method, dense KKT adjoint, basis-solution derivatives, vertex enumeration).
+method, dense KKT adjoint, basis-solution derivatives, vertex enumeration),
+``oracle.precision`` the FP32-data model of the linear step used to check the
+GPU's FP32 bulk phase element by element.
 Functions without an independent pin say "parity unpinned" in their docstring.
 """
 from .abip import (  # noqa: F401
     Settings, State, Problem, hsd_constants, assemble_Q, apply_Q, DenseIQSolver,
-    SchurIQSolver, barrier_prox, initial_state, admm_iteration, inner_residual,
+    SchurIQSolver, CGIQSolver, barrier_prox, initial_state, admm_iteration, inner_residual,
     termination, restart, solve, alg1_iteration, alg1_initial,
     SOLVED, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE, MAX_ITERS, MU_STOP,
 )
+from .precision import Fp32DataSchurSolver  # noqa: F401
 from .reference import (  # noqa: F401
     central_point, kkt_adjoint, contract_adjoint, basis_gradients, vertex_enumeration,
     kkt_relative,

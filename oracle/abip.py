@@ -106,8 +106,11 @@ class State:
 def _as_problem(A, b=None, c=None):
     if isinstance(A, Problem):
         return A
-    return Problem(np.asarray(A, dtype=np.float64), np.asarray(b, dtype=np.float64),
-                   np.asarray(c, dtype=np.float64))
+    if hasattr(A, "tocsr"):           # scipy.sparse: kept sparse (CG solver only)
+        A = A.tocsr().astype(np.float64)
+    else:
+        A = np.asarray(A, dtype=np.float64)
+    return Problem(A, np.asarray(b, dtype=np.float64), np.asarray(c, dtype=np.float64))
 
 
 def hsd_constants(prob):
@@ -204,6 +207,80 @@ class SchurIQSolver:
     def solve(self, w):
         m, n = self.m, self.n
         z = self.apply_Minv(w[:m + n])
+        pq = np.linalg.solve(self.K, w[m + n:] + self.H.T @ z)
+        return np.concatenate([z - self.Z @ pq, pq])
+
+
+class CGIQSolver:
+    """(I+Q)^{-1} w by the structure of Section 4.4 with the inner solve
+    G a = e - A f (G = I + A A^T) done by conjugate gradients, the paper's
+    indirect variant: each CG iteration multiplies once by A and once by A^T,
+    so A may be a scipy.sparse matrix and G is never formed.
+
+    [reading] Jacobi preconditioner diag(G)_i = 1 + ||A_i,:||^2; CG starts from
+    the previous solve's a (warm start) and stops when ||r|| <= tol ||rhs||.
+    The border Z = M^{-1} H is solved once to ``border_tol``.  With a tight tol
+    the result equals ``SchurIQSolver`` (pinned in the tests).
+    """
+
+    def __init__(self, prob, tol=1e-7, max_iters=500, border_tol=1e-14):
+        A, b, c = prob.A, prob.b, prob.c
+        m, n = A.shape
+        self.A = A
+        self.m, self.n = m, n
+        self.tol, self.max_iters = tol, max_iters
+        bbar, cbar, zbar = hsd_constants(prob)
+        if hasattr(A, "multiply"):
+            self.dinv = 1.0 / (1.0 + np.asarray(A.multiply(A).sum(axis=1)).ravel())
+        else:
+            self.dinv = 1.0 / (1.0 + np.einsum("ij,ij->i", A, A))
+        self.a_prev = np.zeros(m)
+        self.cg_iters = 0
+        H = np.zeros((m + n, 2))
+        H[:m, 0] = -b
+        H[m:, 0] = c
+        H[:m, 1] = bbar
+        H[m:, 1] = -cbar
+        self.H = H
+        z0 = self._minv(H[:, 0], border_tol, warm=False)
+        z1 = self._minv(H[:, 1], border_tol, warm=False)
+        self.Z = np.column_stack([z0, z1])
+        S = np.array([[0.0, zbar], [-zbar, 0.0]])
+        self.K = np.eye(2) + S + H.T @ self.Z
+
+    def _cg(self, rhs, x0, tol):
+        A = self.A
+        x = x0.copy()
+        r = rhs - (x + A @ (A.T @ x))
+        z = self.dinv * r
+        p = z.copy()
+        rz = r @ z
+        nrhs = np.linalg.norm(rhs)
+        for _ in range(self.max_iters):
+            if np.linalg.norm(r) <= tol * nrhs:
+                break
+            Gp = p + A @ (A.T @ p)
+            al = rz / (p @ Gp)
+            x += al * p
+            r -= al * Gp
+            z = self.dinv * r
+            rz1 = r @ z
+            p = z + (rz1 / rz) * p
+            rz = rz1
+            self.cg_iters += 1
+        return x
+
+    def _minv(self, w, tol, warm=True):
+        m = self.m
+        e, f = w[:m], w[m:]
+        a = self._cg(e - self.A @ f, self.a_prev if warm else np.zeros(m), tol)
+        if warm:
+            self.a_prev = a
+        return np.concatenate([a, f + self.A.T @ a])
+
+    def solve(self, w):
+        m, n = self.m, self.n
+        z = self._minv(w[:m + n], self.tol)
         pq = np.linalg.solve(self.K, w[m + n:] + self.H.T @ z)
         return np.concatenate([z - self.Z @ pq, pq])
 

@@ -54,6 +54,9 @@ class abip_info(ctypes.Structure):
         ("colpass_fp32", ctypes.c_int64), ("colpass_fp64", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
         ("ticks_colpass", ctypes.c_int64), ("ticks_ginv", ctypes.c_int64), ("ticks_total", ctypes.c_int64),
         ("ticks_check", ctypes.c_int64), ("ticks_update", ctypes.c_int64),
+        ("colpass_lds_fp32", ctypes.c_int64), ("colpass_lds_fp64", ctypes.c_int64),
+        ("ginv_hbm_fp32", ctypes.c_int64), ("ginv_hbm_fp64", ctypes.c_int64),
+        ("lds_mode", ctypes.c_int32), ("fp32_exit_kkt", ctypes.c_double), ("err_vs_fp64", ctypes.c_double),
     ]
 
     def as_dict(self):

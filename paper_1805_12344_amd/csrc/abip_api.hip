@@ -38,6 +38,14 @@ hipError_t launch_adjoint(int grid, int threads, hipStream_t st, const LPDesc* d
                           const PoolPtrs& P, const SolveParams& prm, const AdjArgs& aa, const int32_t* order,
                           int32_t B, int32_t* queue, int32_t ldmax);
 hipError_t set_solve_wg_smem_limit(size_t bytes);
+// FP64 recheck of the returned point (abip_recheck.hip)
+hipError_t launch_recheck_dense(const LPDesc* desc, LPCtrl* ctrl, const double* A64, const double* Mv,
+                                const double* Nv, int64_t Mtot, int64_t Ntot, double* part, int B, int P,
+                                hipStream_t st);
+hipError_t launch_recheck_csr(const int32_t* rp, const int32_t* ci, const double* va, const int32_t* rpt,
+                              const int32_t* cit, const double* vat, int m, int n, LPCtrl* ctrl, const double* b,
+                              const double* y, const double* c, const double* x, const double* s, double* part,
+                              int P, hipStream_t st);
 
 // setup kernels (abip_setup.hip)
 __global__ void k_setup_copy(const LPDesc*, const double* const*, double*, float*, int*);
@@ -95,6 +103,8 @@ __global__ void k_init_state(const LPDesc* __restrict__ desc, LPCtrl* __restrict
         c.by = c.cx = 0.0;
         c.iters = 0; c.iters64 = 0; c.ipm = 0; c.cp32 = 0; c.cp64 = 0; c.cg = 0;
         c.clk[0] = c.clk[1] = c.clk[2] = c.clk[3] = c.clk[4] = 0;
+        c.cpl32 = c.cpl64 = c.gh32 = c.gh64 = 0;
+        c.kfx = NAN; c.err64 = NAN;
         c.status = 0; c.phase = phase; c.mode = OP_REFRESH; c.flags = 0;
     }
 }
@@ -233,6 +243,8 @@ struct abip_work {
     int32_t* queue = nullptr;
     int* errflag = nullptr;
     double** outp = nullptr;     // 3*B device pointer table
+    double* rchk = nullptr;      // partial sums of the FP64 recheck (B * rchk_P * 8)
+    int rchk_P = 1;              // workgroups per LP of the recheck
     int ldmax = 0, nch = 1, threads = 512;
     size_t wg_smem = 0;              // LDS bytes of the batched launch (streamed or LDS-resident)
     int lds_cap = 0;                 // the device's largest LDS allocation per workgroup
@@ -281,6 +293,7 @@ static void release(abip_work* w) {
     (void)hipFree(w->A64); (void)hipFree(w->A32); (void)hipFree(w->G64); (void)hipFree(w->G32);
     (void)hipFree(w->Mv); (void)hipFree(w->Nv);
     (void)hipFree(w->order); (void)hipFree(w->queue); (void)hipFree(w->errflag); (void)hipFree(w->outp);
+    (void)hipFree(w->rchk);
     (void)hipFree(w->adj_ws); (void)hipFree(w->adj_ows); (void)hipFree(w->adj_ptrs);
     (void)hipFree(w->adj_iters); (void)hipFree(w->adj_resid);
     (void)hipFree(w->gbuf); (void)hipFree(w->gctl);
@@ -513,8 +526,10 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
 
 // Which phases of which LPs run LDS-resident, and the LDS bytes of the batched
 // launch: with 256 threads per workgroup an LP qualifies when m <= 256,
-// n <= 512 and its A and G^{-1} fit in one workgroup's LDS in that phase's
-// precision.  The launch then reserves the largest such footprint.
+// n <= 512 and, in that phase's precision, its A and G^{-1} fit in one
+// workgroup's LDS (DESC_LDS32/64: no global memory traffic per iteration) or A
+// alone fits (DESC_LDSA32/64: G^{-1} is read from the pool on every pass).
+// The launch then reserves the largest such footprint.
 static void assign_lds(abip_work* w) {
     const int W = w->threads / 64;
     size_t smem = wg_smem_bytes(w->ldmax, W);
@@ -590,6 +605,11 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     ALLOC(w->Mv, (int64_t)NMF * om); ALLOC(w->Nv, (int64_t)NNF * on);
     ALLOC(w->order, B); ALLOC(w->queue, 1); ALLOC(w->errflag, 1);
     ALLOC(w->outp, 3 * B);
+    if (B == 1) {
+        const int mx = std::max(w->hdesc[0].m, w->hdesc[0].n);
+        w->rchk_P = std::max(1, std::min(512, (mx + 255) / 256));
+    }
+    ALLOC(w->rchk, (int64_t)B * w->rchk_P * 8);
     // scratch for the setup
     std::vector<int64_t> hoW(B);
     int64_t wtot = 0;
@@ -754,6 +774,8 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     SALLOC(w->ddesc, 1); SALLOC(w->dctrl, 1);
     SALLOC(w->Mv, (int64_t)NMF * w->Mtot); SALLOC(w->Nv, (int64_t)NNF * w->Ntot);
     SALLOC(w->errflag, 1); SALLOC(w->outp, 3);
+    w->rchk_P = std::max(1, std::min(1024, (std::max(m, n) + 255) / 256));
+    SALLOC(w->rchk, (int64_t)w->rchk_P * 8);
     SALLOC(w->sp_idx, nidx); SALLOC(w->sp_val, 2 * std::max<int64_t>(nnz, 1));
     SALLOC(w->sp_vec, nvec);
     SALLOC(w->sp_bar, 2); SALLOC(w->sp_err, 1); SALLOC(w->sp_cgit, 1);
@@ -1003,7 +1025,15 @@ static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParam
     return ABIP_OK;
 }
 
-static void fill_info(abip_info* info, const LPCtrl& c, double setup_ms, double solve_ms, double kernel_ms) {
+static void fill_info(abip_info* info, const LPCtrl& c, const LPDesc& d, double setup_ms, double solve_ms,
+                      double kernel_ms) {
+    info->colpass_lds_fp32 = c.cpl32;
+    info->colpass_lds_fp64 = c.cpl64;
+    info->ginv_hbm_fp32 = c.gh32;
+    info->ginv_hbm_fp64 = c.gh64;
+    info->lds_mode = d.lds;
+    info->fp32_exit_kkt = c.kfx;
+    info->err_vs_fp64 = c.err64;
     info->ticks_colpass = c.clk[0];
     info->ticks_ginv = c.clk[1];
     info->ticks_total = c.clk[2];
@@ -1040,6 +1070,15 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
         tab[3 * k + 1] = y ? y[k] : nullptr;
         tab[3 * k + 2] = s ? s[k] : nullptr;
     }
+    // FP64 recheck of the point handed back (independent of the loop's own sums)
+    if (w->sparse) {
+        const SpArgs& g = w->sa;
+        HIPCHK(launch_recheck_csr(g.rp, g.ci, g.va, g.rpt, g.cit, g.vat, g.m, g.n, w->dctrl, g.b, g.Y, g.C, g.X, g.S,
+                                  w->rchk, w->rchk_P, st));
+    } else {
+        HIPCHK(launch_recheck_dense(w->ddesc, w->dctrl, w->A64, w->Mv, w->Nv, w->Mtot, w->Ntot, w->rchk, w->B,
+                                    w->rchk_P, st));
+    }
     HIPCHK(hipMemcpyAsync(w->outp, tab.data(), sizeof(double*) * 3 * w->B, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_write_outputs, dim3(w->B), dim3(256), 0, st, w->ddesc, w->dctrl, w->Mv, w->Nv, w->Mtot,
                        w->Ntot, w->outp, 0);
@@ -1050,7 +1089,7 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
     float kms = 0.0f;
     HIPCHK(hipEventElapsedTime(&kms, w->ev0, w->ev1));
     if (info)
-        for (int k = 0; k < w->B; ++k) fill_info(&info[k], w->hctrl[k], w->setup_ms, ms, (double)kms);
+        for (int k = 0; k < w->B; ++k) fill_info(&info[k], w->hctrl[k], w->hdesc[k], w->setup_ms, ms, (double)kms);
     w->solved = true;
     return ABIP_OK;
 }

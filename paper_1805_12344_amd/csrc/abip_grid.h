@@ -12,13 +12,14 @@ struct GridCtl {
     int32_t status;            // 0 while running
     int32_t ybuf;              // which y buffer holds the current y
     int32_t first;             // 1 until the first decision
-    int32_t pad;
+    int32_t exit_pend;         // 1: the next FP64 check measures the FP32 phase's exit (kfx)
     int64_t iters, iters64, ipm, cp32, cp64, passes;
     int64_t fixed_left;        // fixed mode: updates still to run
     int32_t fixed_mode;        // 1: run exactly fixed_left updates, no tests or restarts
     int32_t pad2;
     // last check
     double pres, dres, gap, pobj, dobj, by, cx;
+    double kfx;                // relative KKT of the FP32 phase's last iterate with FP64 data
     // scalars of the state produced by the last column pass (for the decision)
     double tau_n, kappa_n, theta_n;
     StallTrack stall;          // FP32 precision-floor test of the current inner loop

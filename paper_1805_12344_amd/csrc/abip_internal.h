@@ -24,7 +24,9 @@ enum { OP_REFRESH = 0, OP_PROX = 1, OP_RESTART = 2 };
 
 struct LPDesc {
     int32_t m, n, ld;
-    int32_t lds;    // DESC_LDS32 | DESC_LDS64: phases that run LDS-resident
+    int32_t lds;    // DESC_* bits: phases that run LDS-resident, with A and G^{-1} in LDS
+                    // (DESC_LDS32/64) or with A alone in LDS and G^{-1} read from the pool
+                    // on every pass (DESC_LDSA32/64)
     int64_t oA;     // element offset of column-major A (ld*n)
     int64_t oG;     // element offset of G^{-1} (ld*m)
     int64_t om;     // offset in each m-field (slice length ld)
@@ -44,7 +46,14 @@ struct LPCtrl {
     int64_t cg;                           // CG iterations (sparse engine)
     int64_t clk[5];                       // wall-clock ticks: column passes, G^{-1} passes, whole solve,
                                           // check sums + tests, border + y update
+    int64_t cpl32, cpl64;                 // of cp32 / cp64: passes that read A from LDS
+    int64_t gh32, gh64;                   // passes that read G^{-1} from device memory, per precision
+    double kfx;                           // relative KKT of the FP32 phase's last iterate, measured
+                                          // with FP64 data at the handover (NaN: no handover)
+    double err64;                         // FP64 recheck of the returned point (after the solve)
     int32_t status, phase, mode, flags;  // phase 0 = FP32 bulk, 1 = FP64; mode = next op
+                                          // flags: 1 test the loaded state first, 4 loaded iterate,
+                                          // 8 the next FP64 check measures the FP32 exit (kfx)
 };
 
 // Solver parameters passed by value to kernels.
@@ -107,6 +116,18 @@ enum { DESC_LDS32 = 1, DESC_LDS64 = 2, DESC_LDSA32 = 4, DESC_LDSA64 = 8 };
 __device__ __forceinline__ double prox_root(double w, double t) {
     double r = sqrt(w * w + 4.0 * t);
     return (w >= 0.0) ? 0.5 * (w + r) : (2.0 * t) / (r - w);
+}
+
+// Relative KKT of Section 4.1 (the largest of the three ratios) from the raw
+// sums of a check: ms2 = ||A x - b tau||^2, cs4 = ||A^T y + s - c tau||^2,
+// cx = c^T x, by = b^T y; NaN when tau <= 0.
+__device__ __forceinline__ double kkt_rel(double ms2, double cs4, double cx, double by, double tau, double nb,
+                                          double nc) {
+    if (!(tau > 0.0)) return __builtin_nan("");
+    const double pres = sqrt(ms2) / tau / (1.0 + nb);
+    const double dres = sqrt(cs4) / tau / (1.0 + nc);
+    const double gap = fabs(cx - by) / (tau + fabs(cx) + fabs(by));
+    return fmax(pres, fmax(dres, gap));
 }
 
 __device__ __forceinline__ double bcast_first(double v) {

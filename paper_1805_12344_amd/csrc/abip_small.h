@@ -436,6 +436,9 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     double tau = cl.tau, kappa = cl.kappa, theta = cl.theta, mu = cl.mu;
     int64_t iters = cl.iters, iters64 = cl.iters64, ipm = cl.ipm;
     int64_t cp32 = cl.cp32, cp64 = cl.cp64;
+    int64_t cpl32 = cl.cpl32, cpl64 = cl.cpl64, gh32 = cl.gh32, gh64 = cl.gh64;
+    double kfx = cl.kfx;
+    bool exit_pend = (cl.flags & 8) != 0;     // the next FP64 check measures the FP32 exit
     int status = cl.status;
     const int check_final_first = cl.flags & 1;
     double l_ms2 = 0.0, l_cs4 = 0.0, l_tau = 0.0;
@@ -547,7 +550,8 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         cyc_ginv += wall_clock64() - t1;
         const int64_t tc = wall_clock64();
         small_bsum<12>(v12, red);
-        if (phase == 0) ++cp32; else ++cp64;
+        if (phase == 0) { ++cp32; ++cpl32; } else { ++cp64; ++cpl64; }
+        if constexpr (GS) { if (phase == 0) ++gh32; else ++gh64; }
         const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
                                  (pass_kind == OP_REFRESH && !first);
         const bool was_update = (pass_kind == OP_PROX);
@@ -578,6 +582,10 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
                 l_ms2 = ms2; l_cs4 = cs4; l_tau = tau; l_have = true;
                 by_last = by;
                 cx_last = cx;
+                if (exit_pend && phase == 1) {     // the FP32 phase's last iterate, FP64 data
+                    kfx = kkt_rel(ms2, cs4, cx, by, tau, nb, nc);
+                    exit_pend = false;
+                }
                 if (st) {
                     if (phase == 0) to_phase1 = 1;     // FP32 verdict: confirm with FP64 data
                     else { status = st; break; }
@@ -609,6 +617,7 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
             }
             if (to_phase1) {                   // FP32 verdict or precision floor: FP64 data
                 phase = 1;
+                exit_pend = true;
                 pass_kind = OP_REFRESH;
                 cyc_chk += wall_clock64() - tc;
                 // FP64 data held the other way (or not at all): hand over; the
@@ -674,9 +683,10 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
             o.by = by_last; o.cx = cx_last;
             o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
             o.cp32 = cp32; o.cp64 = cp64;
+            o.cpl32 = cpl32; o.cpl64 = cpl64; o.gh32 = gh32; o.gh64 = gh64; o.kfx = kfx;
             o.status = 0; o.phase = 1;
             o.mode = OP_REFRESH;
-            o.flags = (cl.flags & 4) | 1;
+            o.flags = (cl.flags & 4) | 1 | (exit_pend ? 8 : 0);
         }
         __syncthreads();
         return false;
@@ -696,6 +706,7 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         o.by = by_last; o.cx = cx_last;
         o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
         o.cp32 = cp32; o.cp64 = cp64;
+        o.cpl32 = cpl32; o.cpl64 = cpl64; o.gh32 = gh32; o.gh64 = gh64; o.kfx = kfx;
         o.status = status; o.phase = phase;
         o.mode = OP_REFRESH;
         o.flags = ((fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);

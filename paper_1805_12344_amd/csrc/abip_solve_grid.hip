@@ -481,19 +481,23 @@ __device__ __forceinline__ void grid_ginv_step(const GridArgs& g, GridCtl c, con
                 c.gap = gap / (1.0 + fabs(pobj) + fabs(dobj));
                 c.pobj = pobj;
                 c.dobj = dobj;
+                if (c.exit_pend && c.phase == 1) {     // the FP32 phase's last iterate, FP64 data
+                    c.kfx = fmax(c.pres, fmax(c.dres, c.gap));
+                    c.exit_pend = 0;
+                }
             }
             if (!st && nb > 0.0 && by > 0.0 && sqrt(cs[5]) <= eps * by / nb) st = 2;
             if (!st && nc > 0.0 && cx < 0.0 && sqrt(ms[3]) <= eps * (-cx) / nc) st = 3;
             c.by = by;
             c.cx = cx;
             if (st) {
-                if (c.phase == 0) { c.phase = 1; next = OP_REFRESH; }   // confirm with FP64 data
+                if (c.phase == 0) { c.phase = 1; c.exit_pend = 1; next = OP_REFRESH; }   // confirm with FP64 data
                 else c.status = st;
                 decided = true;
             }
         }
         if (!decided && c.phase == 0 && c.iters >= prm.fp32_max_iters) {
-            c.phase = 1; next = OP_REFRESH; decided = true;
+            c.phase = 1; c.exit_pend = 1; next = OP_REFRESH; decided = true;
         }
         if (!decided) {
             const double rt = by - cx + zbar * theta - kappa;
@@ -511,6 +515,7 @@ __device__ __forceinline__ void grid_ginv_step(const GridArgs& g, GridCtl c, con
                 decided = true;
             } else if (c.phase == 0 && pass == OP_PROX && stall_sample(c.stall, inner, c.mu)) {
                 c.phase = 1;                   // FP32 precision floor reached
+                c.exit_pend = 1;
                 next = OP_REFRESH;
                 decided = true;
             } else if (c.iters >= prm.max_iters || c.passes > prm.max_iters + 4096) {
@@ -573,7 +578,7 @@ __global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed) {
         c.tau = c.kappa = c.theta = 1.0;
         c.mu = beta;
         c.p0 = c.p1 = 0.0;
-        c.mode = OP_REFRESH; c.phase = phase; c.status = 0; c.ybuf = 0; c.first = 1; c.pad = 0;
+        c.mode = OP_REFRESH; c.phase = phase; c.status = 0; c.ybuf = 0; c.first = 1; c.exit_pend = 0;
         c.iters = c.iters64 = c.ipm = c.cp32 = c.cp64 = c.passes = 0;
         stall_reset(c.stall);
         c.fixed_left = fixed;
@@ -581,6 +586,7 @@ __global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed) {
         c.pad2 = 0;
         c.pres = c.dres = c.gap = c.pobj = c.dobj = NAN;
         c.by = c.cx = 0.0;
+        c.kfx = NAN;
         c.tau_n = c.kappa_n = c.theta_n = 1.0;
         *g.ctl = c;
         *g.ctl_next = c;
@@ -601,7 +607,7 @@ __global__ void k_grid_from_state(GridArgs g, const double* Yslice, const LPCtrl
         GridCtl c;
         c.tau = L.tau; c.kappa = L.kappa; c.theta = L.theta; c.mu = L.mu;
         c.p0 = c.p1 = 0.0;
-        c.mode = OP_REFRESH; c.phase = phase; c.status = 0; c.ybuf = 0; c.first = 1; c.pad = 0;
+        c.mode = OP_REFRESH; c.phase = phase; c.status = 0; c.ybuf = 0; c.first = 1; c.exit_pend = 0;
         c.iters = c.iters64 = c.ipm = c.cp32 = c.cp64 = c.passes = 0;
         stall_reset(c.stall);
         c.fixed_left = fixed;
@@ -609,6 +615,7 @@ __global__ void k_grid_from_state(GridArgs g, const double* Yslice, const LPCtrl
         c.pad2 = 0;
         c.pres = c.dres = c.gap = c.pobj = c.dobj = NAN;
         c.by = c.cx = 0.0;
+        c.kfx = NAN;
         c.tau_n = L.tau; c.kappa_n = L.kappa; c.theta_n = L.theta;
         *g.ctl = c;
         *g.ctl_next = c;
@@ -627,6 +634,9 @@ __global__ void k_grid_finish(GridArgs g, double* Ypool_slice, LPCtrl* lc) {
         o.pres = c.pres; o.dres = c.dres; o.gap = c.gap; o.pobj = c.pobj; o.dobj = c.dobj;
         o.by = c.by; o.cx = c.cx;
         o.iters = c.iters; o.iters64 = c.iters64; o.ipm = c.ipm; o.cp32 = c.cp32; o.cp64 = c.cp64;
+        o.cpl32 = 0; o.cpl64 = 0;
+        o.gh64 = c.iters64; o.gh32 = c.iters - c.iters64;   // one pass over G^{-1} per update
+        o.kfx = c.kfx;
         o.status = (c.status < 0) ? 0 : c.status;
         o.phase = c.phase;
         o.mode = OP_REFRESH;

@@ -385,6 +385,9 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     double tau = cl.tau, kappa = cl.kappa, theta = cl.theta, mu = cl.mu;
     int64_t iters = cl.iters, iters64 = cl.iters64, ipm = cl.ipm;
     int64_t cp32 = cl.cp32, cp64 = cl.cp64;
+    int64_t gh32 = cl.gh32, gh64 = cl.gh64;
+    double kfx = cl.kfx;
+    bool exit_pend = (cl.flags & 8) != 0;     // the next FP64 check measures the FP32 exit
     int phase = cl.phase;
     int op = cl.mode;          // first pass: OP_REFRESH of the loaded state
     int status = cl.status;
@@ -485,9 +488,14 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
                 l_ms2 = ms[2]; l_cs4 = cs[4]; l_tau = tau; l_have = true;
                 by_last = by;
                 cx_last = cx;
+                if (exit_pend && phase == 1) {     // the FP32 phase's last iterate, FP64 data
+                    kfx = kkt_rel(ms[2], cs[4], cx, by, tau, nb, nc);
+                    exit_pend = false;
+                }
                 if (st) {
                     if (phase == 0) {          // FP32 verdict: confirm with FP64 data
                         phase = 1;
+                        exit_pend = true;
                         pass_kind = OP_REFRESH;
                         continue;
                     }
@@ -497,6 +505,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
             }
             if (phase == 0 && iters >= prm.fp32_max_iters) {
                 phase = 1;
+                exit_pend = true;
                 pass_kind = OP_REFRESH;
                 continue;
             }
@@ -522,6 +531,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
             }
             if (phase == 0 && was_update && stall_sample(stall, inner, mu)) {
                 phase = 1;                     // FP32 precision floor reached
+                exit_pend = true;
                 pass_kind = OP_REFRESH;
                 continue;
             }
@@ -533,8 +543,8 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         for (int i = tid; i < ld; i += blockDim.x) sh.t[i] = (i < m) ? sh.y[i] - sh.Af[i] : 0.0;
         __syncthreads();
         const int64_t t1 = wall_clock64();
-        if (phase == 0) ginv_pass<NCH, (NCH == 1 ? 8 : NCH == 2 ? 4 : 2), float>(G32, m, ld, sh);
-        else ginv_pass<NCH, (NCH == 1 ? 4 : 2), double>(G64, m, ld, sh);
+        if (phase == 0) { ginv_pass<NCH, (NCH == 1 ? 8 : NCH == 2 ? 4 : 2), float>(G32, m, ld, sh); ++gh32; }
+        else { ginv_pass<NCH, (NCH == 1 ? 4 : 2), double>(G64, m, ld, sh); ++gh64; }
         const int64_t t2 = wall_clock64();
         cyc_ginv += t2 - t1;
         double bs[4] = {0, 0, 0, 0};
@@ -587,6 +597,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         o.by = by_last; o.cx = cx_last;
         o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
         o.cp32 = cp32; o.cp64 = cp64;
+        o.gh32 = gh32; o.gh64 = gh64; o.kfx = kfx;
         o.status = status; o.phase = phase;
         o.mode = OP_REFRESH;
         o.flags = ((fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);

@@ -1,4 +1,6 @@
-"""LDS-resident variant of the batched engine (A and G^{-1} held in LDS).
+"""LDS-resident variant of the batched engine: A and G^{-1} held in LDS, or A
+alone held in LDS with G^{-1} read from device memory on every pass (LPs whose
+A fits but not together with G^{-1}).
 
 The same iteration as the streamed variant, with sums formed in another order:
 fixed-iteration iterates are compared with the FP64 oracle and with the
@@ -160,3 +162,56 @@ def test_lds_edge_shapes_match_oracle_and_streamed(m, n, seed):
     if ref["status_name"] == "solved":
         k = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(sv))
         assert max(k["pres"], k["dres"], k["gap"]) <= 1e-6, k
+
+
+def _tall(m_planted, n, extra, seed):
+    """A planted m_planted x n LP stacked with `extra` random combinations of its
+    rows: more rows than columns, rank m_planted, consistent b, same optimum."""
+    lp = lpgen.dense_planted(m_planted, n, seed)
+    R = np.random.default_rng(seed + 1).standard_normal((extra, m_planted))
+    A = np.vstack([lp["A"], R @ lp["A"]])
+    b = np.concatenate([lp["b"], R @ lp["b"]])
+    return dict(A=A, b=b, c=lp["c"], pstar=lp["pstar"], status="solved", m=A.shape[0], n=n)
+
+
+def test_lds_tall_a_only_fp32_held_as_doubles():
+    """160 x 90 (m > n): G^{-1} (160 x 160) does not fit beside A in either precision,
+    so both phases hold A alone in LDS, and the FP32 phase holds its FP32-rounded A as
+    doubles (the FP64 A-only layout fits).  Fixed updates in both precisions against the
+    streamed variant and the oracle, then full FP32-bulk and FP64 solves."""
+    lp = _tall(40, 90, 120, 51)
+    prob = Problem(lp["A"], lp["b"], lp["c"])
+    s = Settings(alpha=1.8, gamma=0.5, restart_rule="heuristic")
+    st0 = oracle.restart(oracle.initial_state(prob, s), s.gamma, "heuristic")
+    solver = oracle.SchurIQSolver(prob)
+    N = 40
+    st = st0.copy()
+    for _ in range(N):
+        st = oracle.admm_iteration(prob, solver, st, s)
+    scale = 1.0 + np.abs(st.u()).max()
+    got = {(lds, fp32): _iterate(lp, st0, N, lds, fp32, "heuristic") for lds in (1, 0) for fp32 in (False, True)}
+    for lds in (1, 0):
+        y, x, sv, sc = got[(lds, False)]
+        for g, ref in [(y, st.y), (x, st.x), (sv, st.s)]:
+            assert np.abs(g - ref).max() <= 1e-10 * scale, lds
+        for key, ref in [("tau", st.tau), ("kappa", st.kappa), ("theta", st.theta)]:
+            assert abs(sc[key] - ref) <= 1e-10 * scale, (lds, key)
+    a, b = got[(1, True)], got[(0, True)]
+    for ga, gb in zip(a[:3], b[:3]):
+        assert np.abs(ga - gb).max() <= 1e-9 * scale
+    assert np.abs(a[1] - st.x).max() <= 1e-3 * scale
+    ref = oracle.solve(lp["A"], lp["b"], lp["c"])
+    assert ref["status_name"] == "solved"
+    for prec in (abip.ABIP_PREC_FP32_POLISH, abip.ABIP_PREC_FP64):
+        w = abip.abip_setup(lp["A"], lp["b"], lp["c"], abip.abip_default_settings(precision=prec))
+        x, y, sv, info = abip.abip_solve(w)
+        print("tall", prec, info["status_name"], info["admm_iters"], info["admm_iters_fp64"], "oracle",
+              ref["admm_iters"], "lds_mode", info["lds_mode"], flush=True)
+        assert info["lds_mode"] == 4 | 8           # A alone in LDS in both phases
+        assert info["colpass_lds_fp32"] + info["colpass_lds_fp64"] > 0
+        _check_solution(lp, x, y, sv, info)
+        k = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(sv))
+        assert abs(k["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
+        if prec == abip.ABIP_PREC_FP64:
+            assert abs(info["admm_iters"] - ref["admm_iters"]) <= max(5, ref["admm_iters"] // 50)
+        w.free()

@@ -400,3 +400,84 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(oracle.abip, "barrier_prox", good)
     z2 = oracle.alg1_iteration(prob, z, st.mu, s.beta)
     assert np.abs(z2["u"] - st2.u()).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# FP32-data model of the linear step (precision extension)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,seed", [(5, 11, 1), (30, 70, 2), (60, 150, 3)])
+def test_fp32_data_model_without_rounding_is_the_exact_solve(m, n, seed):
+    """With nothing rounded the model is the Section 4.4 solve: equal to the dense LU of
+    the assembled I + Q (not only to the Schur solver it borrows its border from)."""
+    lp = lpgen.dense_planted(m, n, seed)
+    prob = Problem(lp["A"], lp["b"], lp["c"])
+    w = np.random.default_rng(seed).standard_normal(m + n + 2)
+    got = oracle.Fp32DataSchurSolver(prob, dtype=np.float64).solve(w)
+    ref = oracle.DenseIQSolver(prob).solve(w)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("m,n,seed", [(30, 70, 2), (60, 150, 3), (120, 300, 4)])
+def test_fp32_data_model_within_the_rounding_bound(m, n, seed):
+    """Rounding A and G^{-1} to FP32 (unit roundoff u = 2^-24) moves the step by at most
+    the first-order bound propagated through a = G^{-1}(y - A f), d = f + A^T a and the
+    rank-2 border:  |da| <= u (||G^{-1}||_F ||t|| + ||A||_F ||f||),
+    |dd| <= u ||A||_F ||a|| + ||A||_2 |da|,  |dq| <= (||A c - b|| + ||bbar - A cbar||) |da|,
+    |du| <= |da| + |dd| + (||Z||_2 + 1) ||K^{-1}||_2 |dq|  (twice that, for second-order
+    terms).  The deviation must also be above the FP64 level, i.e. the rounding happened."""
+    lp = lpgen.dense_planted(m, n, seed)
+    prob = Problem(lp["A"], lp["b"], lp["c"])
+    A = lp["A"]
+    w = np.random.default_rng(seed + 7).standard_normal(m + n + 2)
+    exact = oracle.SchurIQSolver(prob)
+    ref = exact.solve(w)
+    got = oracle.Fp32DataSchurSolver(prob).solve(w)
+    u = 2.0 ** -24
+    bbar, cbar, _ = oracle.hsd_constants(prob)
+    Ginv = np.linalg.inv(np.eye(m) + A @ A.T)
+    y, f = w[:m], w[m:m + n]
+    t = y - A @ f
+    a = Ginv @ t
+    nA_F, nA_2 = np.linalg.norm(A), np.linalg.norm(A, 2)
+    da = u * (np.linalg.norm(Ginv) * np.linalg.norm(t) + nA_F * np.linalg.norm(f))
+    dd = u * nA_F * np.linalg.norm(a) + nA_2 * da
+    dq = (np.linalg.norm(A @ lp["c"] - lp["b"]) + np.linalg.norm(bbar - A @ cbar)) * da
+    bound = 2.0 * (da + dd + (np.linalg.norm(exact.Z, 2) + 1.0) * np.linalg.norm(np.linalg.inv(exact.K), 2) * dq)
+    dev = np.linalg.norm(got - ref)
+    assert dev <= bound, (dev, bound)
+    assert dev >= 1e-6 * bound, (dev, bound)
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_cg_solver_equals_direct_solve(sparse):
+    """The indirect variant of Section 4.4 (CG on G = I + A A^T, A and A^T products
+    only) converges to the direct solve; a warm-started second solve agrees too."""
+    import scipy.sparse as sps
+    lp = lpgen.sparse_planted(80, 200, 3, density=0.05)
+    Ac = lp["A_csr"]
+    A = sps.csr_matrix((Ac["data"], Ac["indices"], Ac["indptr"]), shape=Ac["shape"])
+    prob_d = Problem(A.toarray(), lp["b"], lp["c"])
+    prob = oracle.abip._as_problem(A if sparse else A.toarray(), lp["b"], lp["c"])
+    cg = oracle.CGIQSolver(prob, tol=1e-14, max_iters=2000)
+    ref = oracle.DenseIQSolver(prob_d)
+    rng = np.random.default_rng(0)
+    for _ in range(2):
+        w = rng.standard_normal(80 + 200 + 2)
+        got, want = cg.solve(w), ref.solve(w)
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+    assert cg.cg_iters > 0
+
+
+def test_cg_solver_full_solve_matches_direct():
+    """Algorithm 2 with the CG step (tight tolerance) takes the direct path's iterations."""
+    import scipy.sparse as sps
+    lp = lpgen.sparse_planted(40, 90, 1, density=0.08)
+    Ac = lp["A_csr"]
+    A = sps.csr_matrix((Ac["data"], Ac["indices"], Ac["indptr"]), shape=Ac["shape"])
+    prob = oracle.abip._as_problem(A, lp["b"], lp["c"])
+    out_cg = oracle.solve(prob, settings=Settings(), solver=oracle.CGIQSolver(prob, tol=1e-13, max_iters=2000))
+    out_d = oracle.solve(A.toarray(), lp["b"], lp["c"], Settings())
+    assert out_cg["status"] == out_d["status"] == oracle.SOLVED
+    assert abs(out_cg["admm_iters"] - out_d["admm_iters"]) <= max(3, out_d["admm_iters"] // 100)
+    np.testing.assert_allclose(out_cg["x"], out_d["x"], atol=1e-7 * (1 + np.abs(out_d["x"]).max()))
