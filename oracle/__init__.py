@@ -17,7 +17,7 @@ Functions without an independent pin say "parity unpinned" in their docstring.
 from .abip import (  # noqa: F401
     Settings, State, Problem, hsd_constants, assemble_Q, apply_Q, DenseIQSolver,
     SchurIQSolver, CGIQSolver, barrier_prox, initial_state, admm_iteration, inner_residual,
-    termination, restart, solve, alg1_iteration, alg1_initial,
+    termination, restart, solve, alg1_iteration, alg1_initial, bb_estimate, bb_rule, bb_select,
     SOLVED, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE, MAX_ITERS, MU_STOP,
 )
 from .precision import Fp32DataSchurSolver  # noqa: F401

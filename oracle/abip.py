@@ -63,6 +63,10 @@ class Settings:
     restart_rule: str = "heuristic"   # "heuristic" (Section 5) or "sqrt" (Algorithm 2)
     mu_stop: float | None = None      # if set: stop the outer loop once mu < mu_stop
     keep_history: bool = False
+    bb: bool = False                  # Barzilai-Borwein choice of beta per outer iteration (Section 4.3)
+    eps_cor: float = 0.2              # Section 5 defaults of the Section 4.3 rule
+    eps_penalty: float = 0.1
+    bb_max_redo: int = 10             # [reading] bound on the "redo" branch of Section 4.3
 
 
 @dataclasses.dataclass
@@ -305,16 +309,18 @@ def initial_state(prob, settings):
     return State(np.zeros(m), np.ones(n), 1.0, 1.0, np.ones(n), 1.0, settings.beta)
 
 
-def admm_iteration(prob, solver, st, settings, return_v=False):
+def admm_iteration(prob, solver, st, settings, return_v=False, beta=None, return_ut=False):
     """One relaxed inner iteration of Algorithm 2 (Section 4.2 form).
 
     With ``return_v`` the full updated v = (r, s, kappa, xi) is returned too, so
-    that Theorem 3.1's claims r = 0 and xi = -(n+1) can be checked.
+    that Theorem 3.1's claims r = 0 and xi = -(n+1) can be checked; with
+    ``return_ut`` also the affine step u~ (before relaxation).  ``beta``
+    overrides settings.beta (the outer iteration's beta of Section 4.3).
     """
     n = prob.n
     m = prob.m
     a = settings.alpha
-    t = st.mu / settings.beta
+    t = st.mu / (settings.beta if beta is None else beta)
     u = st.u()
     v = st.v()
     ut = solver.solve(u + v)                          # eq. (Simple-Update:Affine)
@@ -327,6 +333,8 @@ def admm_iteration(prob, solver, st, settings, return_v=False):
     v_new = v - uh + u_new                            # eq. (Simple-Update:Dual)
     out = State(y_new, x_new, tau_new, theta_new, v_new[m:m + n].copy(),
                 float(v_new[m + n]), st.mu)
+    if return_ut:
+        return out, v_new, ut
     return (out, v_new) if return_v else out
 
 
@@ -402,6 +410,87 @@ def restart(st, gamma, rule):
     return st
 
 
+def _hybrid(sd, mg):
+    """The hybrid spectral step of Section 4.3: MG when 2 MG > SD, else SD - MG/2."""
+    return mg if 2.0 * mg > sd else sd - 0.5 * mg
+
+
+def bb_estimate(u0, v0, ut1, u1, v1, ut2, u2, v2, alpha, beta, eps_cor):
+    """Spectral estimate of beta from the first three iterates of an outer
+    iteration (Section 4.3): curvature pairs, the steepest-descent and
+    minimum-gradient steps, their hybrid, and the correlation safeguard.
+
+    Returns (beta_hat, diagnostics); beta_hat == beta when neither curvature
+    estimate is reliable (both correlations <= eps_cor).
+    """
+    vh1 = v0 - alpha * ut1 - (1.0 - alpha) * u0 + alpha * u1
+    vh2 = v1 - alpha * ut2 - (1.0 - alpha) * u1 + alpha * u2
+    dvh = vh2 - vh1
+    dut = alpha * (ut2 - ut1) + (1.0 - alpha) * (u1 - u0)
+    du = -(u2 - u1)
+    vv, vt, tt = float(dvh @ dvh), float(dvh @ dut), float(dut @ dut)
+    vu, uu = float(dvh @ du), float(du @ du)
+    nv, nt, nu = np.sqrt(vv), np.sqrt(tt), np.sqrt(uu)
+    phi_cor = vt / (nv * nt) if nv > 0 and nt > 0 else 0.0
+    psi_cor = vu / (nv * nu) if nv > 0 and nu > 0 else 0.0
+    d = dict(phi_cor=phi_cor, psi_cor=psi_cor)
+    phi = psi = None
+    if phi_cor > eps_cor:
+        d["phi_sd"], d["phi_mg"] = vv / vt, vt / tt
+        phi = _hybrid(d["phi_sd"], d["phi_mg"])
+    if psi_cor > eps_cor:
+        d["psi_sd"], d["psi_mg"] = vv / vu, vu / uu
+        psi = _hybrid(d["psi_sd"], d["psi_mg"])
+    d["phi"], d["psi"] = phi, psi
+    if phi is not None and psi is not None:
+        return float(np.sqrt(phi * psi)), d
+    if phi is not None:
+        return float(phi), d
+    if psi is not None:
+        return float(psi), d
+    return beta, d
+
+
+def bb_rule(beta, beta_hat, eps_penalty):
+    """The heuristic selection of Section 4.3: ("keep", beta) when the estimate
+    equals beta, ("average", (beta + beta_hat)/2) when it is within eps_penalty,
+    ("redo", beta_hat) otherwise (estimate again from the same initial point)."""
+    if beta_hat == beta:
+        return "keep", beta
+    if abs(beta_hat - beta) <= eps_penalty:
+        return "average", 0.5 * (beta + beta_hat)
+    return "redo", beta_hat
+
+
+def bb_select(prob, solver, st0, settings, beta):
+    """Choose the beta of an outer iteration (Section 4.3) from its initial point.
+
+    [reading] Each estimate takes two probe iterations from st0 with the current
+    beta; the probes are then discarded and the outer iteration starts from st0
+    with the chosen beta; st0 is not rescaled (a redo uses the same initial
+    point).  At most settings.bb_max_redo redos.  Returns (beta, probe
+    iterations, list of (action, beta)).
+    """
+    probes = 0
+    trail = []
+    for _ in range(settings.bb_max_redo + 1):
+        u0, v0 = st0.u(), st0.v()
+        st1, v1, ut1 = admm_iteration(prob, solver, st0, settings, beta=beta, return_ut=True)
+        st2, v2, ut2 = admm_iteration(prob, solver, st1, settings, beta=beta, return_ut=True)
+        probes += 2
+        beta_hat, _ = bb_estimate(u0, v0, ut1, st1.u(), v1, ut2, st2.u(), v2, settings.alpha, beta,
+                                  settings.eps_cor)
+        action, nb = bb_rule(beta, beta_hat, settings.eps_penalty)
+        trail.append((action, nb))
+        if action != "redo" or not (nb > 0.0) or not np.isfinite(nb):
+            if action == "redo":                      # a non-positive estimate: keep beta
+                trail[-1] = ("keep", beta)
+                return beta, probes, trail
+            return nb, probes, trail
+        beta = nb
+    return beta, probes, trail
+
+
 def solve(A, b=None, c=None, settings=None, solver=None, state=None):
     """Algorithm 2 (with Section 4.1-4.2 and the Section 5 restart).
 
@@ -417,13 +506,19 @@ def solve(A, b=None, c=None, settings=None, solver=None, state=None):
     outer = 0
     inner_counts = []
     history = []
+    betas = []
     status = 0
     info = {}
+    beta = settings.beta
     while status == 0:
         if settings.mu_stop is not None and st.mu < settings.mu_stop:
             status = MU_STOP
             break
         i = 0
+        if settings.bb and inner_residual(prob, st) > st.mu:
+            beta, probes, trail = bb_select(prob, solver, st, settings, beta)   # Section 4.3
+            total += probes
+            betas.append((outer, beta, trail))
         while True:
             res = inner_residual(prob, st)
             if res <= st.mu:                          # eq. (inner-stop)
@@ -431,7 +526,7 @@ def solve(A, b=None, c=None, settings=None, solver=None, state=None):
             if total >= settings.max_admm_iters:
                 status = MAX_ITERS
                 break
-            st = admm_iteration(prob, solver, st, settings)
+            st = admm_iteration(prob, solver, st, settings, beta=beta)
             total += 1
             i += 1
             if settings.mu_stop is None:
@@ -447,7 +542,7 @@ def solve(A, b=None, c=None, settings=None, solver=None, state=None):
         outer += 1
     out = dict(status=status, status_name=STATUS_NAMES.get(status, "?"), state=st,
                admm_iters=total, ipm_iters=outer, inner_counts=inner_counts,
-               history=history, info=info)
+               history=history, info=info, betas=betas)
     if status in (SOLVED, MAX_ITERS, MU_STOP) and st.tau > 0:
         out.update(x=st.x / st.tau, y=st.y / st.tau, s=st.s / st.tau)
     elif status == PRIMAL_INFEASIBLE:

@@ -43,9 +43,13 @@ def _kw(engine, **extra):
 @pytest.mark.parametrize("m,n,seed,engine", [(50, 100, 1, "lds"), (50, 100, 1, "streamed"), (50, 100, 1, "grid"),
                                              (130, 301, 2, "streamed"), (300, 650, 3, "streamed"),
                                              (600, 1300, 5, "streamed"), (1100, 2600, 6, "grid"),
-                                             (2100, 2300, 7, "grid")])
+                                             (2100, 4600, 7, "grid")])
 @pytest.mark.parametrize("rule", ["heuristic", "sqrt"])
 def test_fp32_data_iterations_match_model(m, n, seed, engine, rule):
+    """The model rounds its own FP64 G^{-1} to FP32; the library rounds the one its
+    factorization produced.  The two FP64 inverses agree to about cond(G) times the
+    FP64 unit roundoff, so the FP32 copies agree entry for entry only when that is far
+    below the FP32 rounding step: the shapes keep cond(G) small (n well above m)."""
     print(f"fp32 iterate m={m} n={n} engine={engine} rule={rule}", flush=True)
     lp = lpgen.dense_planted(m, n, seed)
     prob = Problem(lp["A"], lp["b"], lp["c"])
@@ -77,12 +81,28 @@ def test_fp32_data_iterations_match_model(m, n, seed, engine, rule):
 
 
 def _recheck(A, b, c, x, y, s, status):
+    """(host recheck, bound on the FP64 rounding difference of two evaluations).
+
+    Two FP64 evaluations of a residual like A x - b, summed in different orders,
+    differ by at most about n u (|A| |x| + |b|) per entry (u = 2^-53); the bound
+    takes 4 n u (||A||_F ||x|| + ||b||) over the normaliser, and the same for the
+    other residuals."""
+    u = 2.0 ** -53
+    A = np.asarray(A.toarray() if hasattr(A, "toarray") else A)
+    m, n = A.shape
+    nA = np.linalg.norm(A)
     if status == abip.ABIP_PRIMAL_INFEASIBLE:
-        return np.linalg.norm(A.T @ y + s) * np.linalg.norm(b)
+        return (np.linalg.norm(A.T @ y + s) * np.linalg.norm(b),
+                4 * m * u * (nA * np.linalg.norm(y) + np.linalg.norm(s)) * np.linalg.norm(b))
     if status == abip.ABIP_DUAL_INFEASIBLE:
-        return np.linalg.norm(A @ x) * np.linalg.norm(c)
+        return np.linalg.norm(A @ x) * np.linalg.norm(c), 4 * n * u * nA * np.linalg.norm(x) * np.linalg.norm(c)
     kk = oracle.kkt_relative(A, b, c, x, y, s)
-    return max(kk["pres"], kk["dres"], kk["gap"])
+    nb, nc = np.linalg.norm(b), np.linalg.norm(c)
+    bound = 4 * max(m, n) * u * max((nA * np.linalg.norm(x) + nb) / (1 + nb),
+                                    (nA * np.linalg.norm(y) + np.linalg.norm(s) + nc) / (1 + nc),
+                                    (nc * np.linalg.norm(x) + nb * np.linalg.norm(y))
+                                    / (1 + abs(kk["pobj"]) + abs(kk["dobj"])))
+    return max(kk["pres"], kk["dres"], kk["gap"]), bound
 
 
 @pytest.mark.parametrize("engine", list(ENG))
@@ -93,11 +113,11 @@ def test_err_vs_fp64_is_the_fp64_recheck(engine, prec):
         w = abip.abip_setup(lp["A"], lp["b"], lp["c"], abip.abip_default_settings(**_kw(engine, precision=p)))
         x, y, s, info = abip.abip_solve(w)
         x, y, s = _np(x), _np(y), _np(s)
-        want = _recheck(lp["A"], lp["b"], lp["c"], x, y, s, info["status"])
+        want, tol = _recheck(lp["A"], lp["b"], lp["c"], x, y, s, info["status"])
         got = info["err_vs_fp64"]
-        print(engine, prec, info["status_name"], got, want, info["fp32_exit_kkt"], flush=True)
+        print(engine, prec, info["status_name"], got, want, tol, info["fp32_exit_kkt"], flush=True)
         assert math.isfinite(got)
-        assert abs(got - want) <= 1e-9 * max(want, 1e-12) + 1e-15, (got, want)
+        assert abs(got - want) <= tol, (got, want, tol)
         assert got <= 1e-6 * 1.001
         if prec == "fp64":
             assert math.isnan(info["fp32_exit_kkt"])
@@ -114,16 +134,16 @@ def test_err_vs_fp64_batch_and_sparse():
                               abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH))
     xs, ys, ss, infos = abip.abip_solve_batch(w)
     for lp, x, y, s, info in zip(lps, xs, ys, ss, infos):
-        want = _recheck(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s), info["status"])
-        assert abs(info["err_vs_fp64"] - want) <= 1e-9 * max(want, 1e-12) + 1e-15, (info["err_vs_fp64"], want)
+        want, tol = _recheck(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(s), info["status"])
+        assert abs(info["err_vs_fp64"] - want) <= tol, (info["err_vs_fp64"], want, tol)
     w.free()
     lp = lpgen.sparse_planted(60, 150, 2, density=0.05)
     Ac = lp["A_csr"]
     A = sp.csr_matrix((Ac["data"], Ac["indices"], Ac["indptr"]), shape=Ac["shape"])
     w = abip.abip_setup(A, lp["b"], lp["c"])
     x, y, s, info = abip.abip_solve(w)
-    want = _recheck(A.toarray(), lp["b"], lp["c"], _np(x), _np(y), _np(s), info["status"])
-    print("sparse", info["err_vs_fp64"], want, flush=True)
-    assert abs(info["err_vs_fp64"] - want) <= 1e-9 * max(want, 1e-12) + 1e-15
+    want, tol = _recheck(A.toarray(), lp["b"], lp["c"], _np(x), _np(y), _np(s), info["status"])
+    print("sparse", info["err_vs_fp64"], want, tol, flush=True)
+    assert abs(info["err_vs_fp64"] - want) <= tol
     assert math.isnan(info["fp32_exit_kkt"])
     w.free()

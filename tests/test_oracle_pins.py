@@ -481,3 +481,102 @@ def test_cg_solver_full_solve_matches_direct():
     assert out_cg["status"] == out_d["status"] == oracle.SOLVED
     assert abs(out_cg["admm_iters"] - out_d["admm_iters"]) <= max(3, out_d["admm_iters"] // 100)
     np.testing.assert_allclose(out_cg["x"], out_d["x"], atol=1e-7 * (1 + np.abs(out_d["x"]).max()))
+
+
+# ---------------------------------------------------------------------------
+# Barzilai-Borwein choice of beta (Section 4.3)
+# ---------------------------------------------------------------------------
+
+def _bb_from_pairs(rng, dvh, dut, du, alpha=1.8):
+    """Iterates (u0, v0, ut1, u1, v1, ut2, u2, v2) whose curvature pairs of Section 4.3
+    are the given (dvh, dut, du): u0, v0, ut1, u1, v2 are drawn, u2 follows from du,
+    ut2 from dut and v1 from dvh."""
+    N = dvh.size
+    u0, v0, ut1, u1, v2 = (rng.standard_normal(N) for _ in range(5))
+    u2 = u1 - du
+    ut2 = ut1 + (dut - (1 - alpha) * (u1 - u0)) / alpha
+    vh1 = v0 - alpha * ut1 - (1 - alpha) * u0 + alpha * u1
+    v1 = dvh + vh1 + alpha * ut2 + (1 - alpha) * u1 - alpha * u2
+    return [u0, v0, ut1, u1, v1, ut2, u2, v2]
+
+
+def test_bb_sd_at_least_mg_by_cauchy_schwarz():
+    rng = np.random.default_rng(0)
+    seen = 0
+    for _ in range(200):
+        dvh, dut, du = (rng.standard_normal(9) for _ in range(3))
+        dut = dut + rng.uniform(0.1, 3.0) * dvh            # positive correlations
+        du = du + rng.uniform(0.1, 3.0) * dvh
+        _, d = oracle.bb_estimate(*_bb_from_pairs(rng, dvh, dut, du), 1.8, 1.0, eps_cor=0.0)
+        for k in ("phi", "psi"):
+            assert d[k + "_cor"] <= 1 + 1e-12
+            if d[k + "_cor"] > 0:
+                assert d[k + "_sd"] >= d[k + "_mg"] * (1 - 1e-12)
+                seen += 1
+    assert seen > 300
+
+
+@pytest.mark.parametrize("cst", [0.3, 2.5])
+def test_bb_exact_curvature_gives_that_step(cst):
+    """dvh = c dut and dvh = d du exactly: SD = MG for both, correlations 1, the
+    hybrid picks MG, and the estimate is sqrt(c d)."""
+    rng = np.random.default_rng(1)
+    dvh = rng.standard_normal(9)
+    d2 = 1.7
+    vs = _bb_from_pairs(rng, dvh, dvh / cst, dvh / d2)
+    bh, d = oracle.bb_estimate(*vs, 1.8, 1.0, eps_cor=0.2)
+    assert abs(d["phi_cor"] - 1.0) < 1e-12 and abs(d["psi_cor"] - 1.0) < 1e-12
+    assert abs(d["phi_sd"] - cst) < 1e-10 * cst and abs(d["phi_mg"] - cst) < 1e-10 * cst
+    assert abs(d["phi"] - cst) < 1e-10 * cst and abs(d["psi"] - d2) < 1e-10 * d2
+    assert abs(bh - np.sqrt(cst * d2)) < 1e-10
+
+
+def test_bb_hybrid_branches():
+    assert oracle.abip._hybrid(3.0, 2.0) == 2.0            # 2 MG > SD: MG
+    assert oracle.abip._hybrid(5.0, 2.0) == 4.0            # otherwise SD - MG / 2
+    assert oracle.abip._hybrid(4.0, 2.0) == 3.0            # tie 2 MG == SD: the second branch
+
+
+def test_bb_safeguard_branches():
+    """Every branch of the correlation safeguard: both estimates reliable (geometric
+    mean), one of them (that one), neither (beta kept)."""
+    rng = np.random.default_rng(2)
+    beta = 1.7
+    dvh, e1, e2 = (rng.standard_normal(9) for _ in range(3))
+    dut = dvh + 0.3 * e1            # correlation near 0.96
+    du = dvh + 2.0 * e2             # correlation near 0.45
+    vs = _bb_from_pairs(rng, dvh, dut, du)
+    _, d0 = oracle.bb_estimate(*vs, 1.8, beta, 0.0)
+    pc, sc = d0["phi_cor"], d0["psi_cor"]
+    assert 0.0 < sc < pc < 1.0
+    bh, d = oracle.bb_estimate(*vs, 1.8, beta, 0.5 * sc)            # both reliable
+    assert abs(bh - np.sqrt(d["phi"] * d["psi"])) <= 1e-12 * bh
+    bh, d = oracle.bb_estimate(*vs, 1.8, beta, 0.5 * (sc + pc))     # phi only
+    assert d["psi"] is None and bh == d["phi"]
+    vs2 = _bb_from_pairs(rng, dvh, du, dut)                          # swapped: psi only
+    bh, d = oracle.bb_estimate(*vs2, 1.8, beta, 0.5 * (sc + pc))
+    assert d["phi"] is None and bh == d["psi"]
+    bh, d = oracle.bb_estimate(*vs, 1.8, beta, 0.5 * (pc + 1.0))    # neither: beta kept
+    assert d["phi"] is None and d["psi"] is None and bh == beta
+    # the Section 5 threshold on these iterates: both reliable
+    bh, d = oracle.bb_estimate(*vs, 1.8, beta, 0.2)
+    assert d["phi"] is not None and d["psi"] is not None
+
+
+def test_bb_selection_rule():
+    assert oracle.bb_rule(1.0, 1.0, 0.1) == ("keep", 1.0)
+    act, b = oracle.bb_rule(1.0, 1.08, 0.1)
+    assert act == "average" and abs(b - 1.04) < 1e-15
+    assert oracle.bb_rule(1.0, 1.5, 0.1) == ("redo", 1.5)
+    assert oracle.bb_rule(1.0, 0.5, 0.1) == ("redo", 0.5)
+
+
+def test_bb_solve_still_reaches_the_optimum():
+    """With the Section 4.3 beta the method still ends SOLVED at the planted optimum."""
+    lp = lpgen.config0(4)
+    out = oracle.solve(lp["A"], lp["b"], lp["c"], Settings(bb=True))
+    assert out["status"] == oracle.SOLVED
+    assert out["betas"] and all(b > 0 for _, b, _ in out["betas"])
+    kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], out["x"], out["y"], out["s"])
+    assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6
+    assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
