@@ -278,6 +278,29 @@ int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_fp32);
 int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t max_cand, int32_t* ncand,
                   int32_t* chosen);
 
+/* ---- allocation-free solve -------------------------------------------------
+ * For callers that cannot allocate device memory: tight serving loops that
+ * must not call hipMalloc, harnesses that forbid it.  (The call synchronises
+ * its stream, so it cannot itself be recorded into a graph capture.)
+ * Sets up and solves ONE dense LP (row-major A, m <= ABIP_NOALLOC_MAX_M,
+ * n <= ABIP_NOALLOC_MAX_N) exactly as abip_setup followed by abip_solve would
+ * (same kernels, same results), but every device buffer it needs is carved out
+ * of a fixed 5 MiB region of device memory built into the library (one per GPU,
+ * held until the process ends); it calls no hipMalloc / hipFree and creates no
+ * stream, event or graph (abip_info.kernel_ms is NaN).  Arguments as for
+ * abip_setup (device pointers A->val, b, c; settings and info host, may be
+ * NULL; stream as a hipStream_t or NULL) and abip_solve (device outputs x (n),
+ * y (m), s (n), each may be NULL).  The call synchronises the stream before it
+ * returns.  Errors: ABIP_E_DIM for sizes beyond the limits, ABIP_E_INVALID for
+ * CSR input or settings.engine = ABIP_ENGINE_GRID.  All calls on one GPU share
+ * the region: calls that overlap in time on the same GPU (other host threads,
+ * or other streams of the same process) race and must be serialised by the
+ * caller; sequential calls are independent (each clears what it uses). */
+#define ABIP_NOALLOC_MAX_M 256
+#define ABIP_NOALLOC_MAX_N 1024
+int abip_solve_noalloc(const abip_matrix* A, const double* b, const double* c, double* x, double* y, double* s,
+                       abip_info* info, const abip_settings* settings, void* stream);
+
 /* Release everything owned by the handle.  NULL is accepted. */
 int abip_free(abip_work* w);
 

@@ -77,7 +77,7 @@ EXPORTS = [
     "abip_default_settings", "abip_setup", "abip_setup_batch", "abip_solve", "abip_solve_batch",
     "abip_backward", "abip_backward_batch", "abip_apply_iq", "abip_set_state", "abip_get_state",
     "abip_iterate", "abip_free", "abip_last_error", "abip_version", "abip_backward_stats",
-    "abip_autotune",
+    "abip_autotune", "abip_solve_noalloc",
 ]
 
 
@@ -113,6 +113,8 @@ def load_library(path: str = LIB_PATH):
                                         ctypes.POINTER(ctypes.c_double)]
     lib.abip_autotune.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.abip_solve_noalloc.argtypes = [ctypes.POINTER(abip_matrix), P, P, P, P, P, ctypes.POINTER(abip_info),
+                                       ctypes.POINTER(abip_settings), P]
     lib.abip_last_error.restype = ctypes.c_char_p
     lib.abip_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -339,6 +341,26 @@ def abip_autotune(w: Work, iters: int = 50):
     ch = ctypes.c_int32()
     _check(lib().abip_autotune(w.handle, int(iters), ms, 8, ctypes.byref(nc), ctypes.byref(ch)))
     return dict(chosen=ch.value, ms=[ms[i] for i in range(min(8, nc.value))])
+
+
+def abip_solve_noalloc(A, b, c, settings: abip_settings | None = None, out=None):
+    """One dense LP set up and solved without device allocations inside the
+    library (abip_solve_noalloc).  Returns (x, y, s, info_dict); ``out`` may give
+    preallocated (x, y, s) CUDA float64 tensors to write into."""
+    A = _dev(A)
+    m, n = A.shape
+    b = _dev(b, (m,))
+    c = _dev(c, (n,))
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(m, dtype=torch.float64, device="cuda"),
+               torch.empty(n, dtype=torch.float64, device="cuda"))
+    x, y, s = out
+    mat = abip_matrix(m, n, ABIP_DENSE_ROWMAJOR, A.data_ptr(), None, None, 0)
+    info = abip_info()
+    st = settings or abip_default_settings()
+    _check(lib().abip_solve_noalloc(ctypes.byref(mat), _ptr(b), _ptr(c), _ptr(x), _ptr(y), _ptr(s),
+                                    ctypes.byref(info), ctypes.byref(st), _stream()))
+    return x, y, s, info.as_dict()
 
 
 def abip_free(w: Work):

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -285,10 +286,28 @@ struct abip_work {
     std::vector<char> gkey;
     hipGraph_t wgraph = nullptr; hipGraphExec_t wexec = nullptr;    // batched solve launch
     std::vector<char> wkey;
+    // device memory taken from a caller-provided region instead of hipMalloc
+    // (the allocation-free entry point): no buffer is freed, no event or graph
+    // is created, launches go straight to the stream
+    unsigned char* carve_base = nullptr;
+    size_t carve_off = 0, carve_cap = 0;
+    bool noalloc = false;
 };
+
+// Device buffer for a handle: hipMalloc, or the next 256-byte aligned slice of
+// the handle's carve region.
+static hipError_t dev_alloc(abip_work* w, void** p, size_t bytes) {
+    if (!w->noalloc) return hipMalloc(p, bytes);
+    const size_t off = (w->carve_off + 255) & ~(size_t)255;
+    if (off + bytes > w->carve_cap) return hipErrorOutOfMemory;
+    *p = w->carve_base + off;
+    w->carve_off = off + bytes;
+    return hipSuccess;
+}
 
 static void release(abip_work* w) {
     if (!w) return;
+    if (w->noalloc) return;        // carved buffers belong to the region; nothing else was created
     (void)hipFree(w->ddesc); (void)hipFree(w->dctrl);
     (void)hipFree(w->A64); (void)hipFree(w->A32); (void)hipFree(w->G64); (void)hipFree(w->G32);
     (void)hipFree(w->Mv); (void)hipFree(w->Nv);
@@ -550,8 +569,12 @@ static void assign_lds(abip_work* w) {
     w->wg_smem = smem;
 }
 
+// carve: when not null, every device buffer of the handle comes from this
+// region of carve_cap bytes (no hipMalloc) and the handle creates no events or
+// graphs (the allocation-free entry point).
 static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const double* const* b,
-                       const double* const* c, const abip_settings* settings, void* stream) {
+                       const double* const* c, const abip_settings* settings, void* stream,
+                       unsigned char* carve = nullptr, size_t carve_cap = 0) {
     if (!out) return fail(ABIP_E_INVALID, "abip_setup: null output handle");
     *out = nullptr;
     if (B < 1) return fail(ABIP_E_DIM, "abip_setup_batch: B must be >= 1 (got %d)", B);
@@ -562,6 +585,12 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     if (rc) return rc;
     const double t0 = now_ms();
     abip_work* w = new abip_work();
+    if (carve) {
+        w->noalloc = true;
+        w->carve_base = carve;
+        w->carve_cap = carve_cap;
+        s.use_graph = 0;
+    }
     w->B = B;
     w->set = s;
     w->stream = (hipStream_t)stream;
@@ -596,8 +625,8 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     (void)hipDeviceGetAttribute(&w->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipDeviceGetAttribute(&w->lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     assign_lds(w);
-#define ALLOC(ptr, count) do { hipError_t e_ = hipMalloc((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count)); \
-        if (e_ != hipSuccess) { release(w); delete w; return fail(e_ == hipErrorOutOfMemory ? ABIP_E_OOM : ABIP_E_HIP, "hipMalloc(%s, %lld elements): %s", #ptr, (long long)(count), hipGetErrorString(e_)); } } while (0)
+#define ALLOC(ptr, count) do { hipError_t e_ = dev_alloc(w, (void**)&(ptr), sizeof(*(ptr)) * (size_t)(count)); \
+        if (e_ != hipSuccess) { const bool nz_ = w->noalloc; release(w); delete w; return fail(e_ == hipErrorOutOfMemory ? (nz_ ? ABIP_E_DIM : ABIP_E_OOM) : ABIP_E_HIP, nz_ ? "%s (%lld elements) does not fit the scratch region" : "hipMalloc(%s, %lld elements): %s", #ptr, (long long)(count), hipGetErrorString(e_)); } } while (0)
     ALLOC(w->ddesc, B);
     ALLOC(w->dctrl, B);
     ALLOC(w->A64, oA); ALLOC(w->A32, oA);
@@ -619,7 +648,10 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     ALLOC(Wp, wtot); ALLOC(doW, B);
     ALLOC(dAp, B); ALLOC(dbp, B); ALLOC(dcp, B);
 #undef ALLOC
-    auto cleanup_scratch = [&]() { (void)hipFree(Wp); (void)hipFree(doW); (void)hipFree(dAp); (void)hipFree(dbp); (void)hipFree(dcp); };
+    auto cleanup_scratch = [&]() {
+        if (w->noalloc) return;
+        (void)hipFree(Wp); (void)hipFree(doW); (void)hipFree(dAp); (void)hipFree(dbp); (void)hipFree(dcp);
+    };
     auto bail = [&](int code) { cleanup_scratch(); release(w); delete w; return code; };
     hipStream_t st = w->stream;
 #define SCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return bail(fail(ABIP_E_HIP, "%s: %s", #call, hipGetErrorString(e_))); } while (0)
@@ -989,6 +1021,13 @@ static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParam
     hipStream_t st = w->stream;
     const int per_cu = (w->wg_smem <= 76 * 1024 && w->threads <= 512) ? 2 : 1;
     const int grid = std::max(1, std::min<int>(B, w->cu_count * per_cu));
+    if (w->noalloc) {                     // plain launches, no events
+        hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, w->queue);
+        HIPCHK(hipGetLastError());
+        HIPCHK(launch_solve_wg(w->nch, grid, w->threads, st, w->ddesc, w->dctrl, pools(w), prm, w->order, B,
+                               w->queue, fixed_iters, w->ldmax, w->wg_smem));
+        return ABIP_OK;
+    }
     if (!w->ev0) HIPCHK(hipEventCreate(&w->ev0));
     if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
     if (w->set.use_graph && fixed_iters == 0 && B == w->B) {
@@ -1086,8 +1125,8 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
     HIPCHK(hipMemcpyAsync(w->hctrl.data(), w->dctrl, sizeof(LPCtrl) * w->B, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const double ms = now_ms() - t0;
-    float kms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&kms, w->ev0, w->ev1));
+    float kms = NAN;
+    if (!w->noalloc) HIPCHK(hipEventElapsedTime(&kms, w->ev0, w->ev1));
     if (info)
         for (int k = 0; k < w->B; ++k) fill_info(&info[k], w->hctrl[k], w->hdesc[k], w->setup_ms, ms, (double)kms);
     w->solved = true;
@@ -1359,6 +1398,66 @@ extern "C" int abip_free(abip_work* w) {
     release(w);
     delete w;
     return ABIP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free solve of one small dense LP
+// ---------------------------------------------------------------------------
+// Every device buffer of the solve (the library's copies of A, b, c in both
+// precisions, G^{-1}, the border, the iterate, the control block, the setup's
+// Cholesky workspace, the recheck's partial sums) is carved out of this
+// file-scope array; each GPU the library runs on holds its own copy until the
+// process ends.  The largest LP (m = 256, n = 1024) takes about 4.4 MiB.
+static const size_t NOALLOC_BYTES = (size_t)5 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+static const int NOALLOC_MAX_DEV = 64;
+static unsigned char* g_scratch_ptr[NOALLOC_MAX_DEV];
+static std::mutex g_scratch_mu;
+
+// The device address of `scratch` on the current device (looked up once per
+// device; host code never uses the symbol's own name as a device address).
+static int scratch_address(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) return fail(ABIP_E_INVALID, "abip_solve_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ABIP_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ABIP_OK;
+}
+
+extern "C" int abip_solve_noalloc(const abip_matrix* A, const double* b, const double* c, double* x, double* y,
+                                  double* s, abip_info* info, const abip_settings* settings, void* stream) {
+    if (!A || !b || !c) return fail(ABIP_E_INVALID, "abip_solve_noalloc: null A, b or c");
+    if (A->format != ABIP_DENSE_ROWMAJOR) return fail(ABIP_E_INVALID, "abip_solve_noalloc: dense row-major A only");
+    if (A->m < 1 || A->n < 1 || A->m > ABIP_NOALLOC_MAX_M || A->n > ABIP_NOALLOC_MAX_N)
+        return fail(ABIP_E_DIM, "abip_solve_noalloc: m=%d n=%d outside 1..%d x 1..%d", A->m, A->n,
+                    ABIP_NOALLOC_MAX_M, ABIP_NOALLOC_MAX_N);
+    abip_settings st;
+    if (settings) st = *settings; else abip_default_settings(&st);
+    if (st.engine == ABIP_ENGINE_GRID) return fail(ABIP_E_INVALID, "abip_solve_noalloc: one-workgroup engine only");
+    st.engine = ABIP_ENGINE_WG;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    unsigned char* base = nullptr;
+    int rc = scratch_address(dev, &base);
+    if (rc) return rc;
+    const double* bb[1] = {b};
+    const double* cc[1] = {c};
+    abip_work* w = nullptr;
+    rc = setup_dense(&w, 1, A, bb, cc, &st, stream, base, NOALLOC_BYTES);
+    if (rc) return rc;
+    double* xs[1] = {x};
+    double* ys[1] = {y};
+    double* ss[1] = {s};
+    rc = solve_all(w, xs, ys, ss, info);
+    release(w);                 // nothing to free: the buffers are the scratch region's
+    delete w;
+    return rc;
 }
 
 extern "C" const char* abip_last_error(void) { return g_err.c_str(); }
