@@ -164,6 +164,23 @@ def test_lds_edge_shapes_match_oracle_and_streamed(m, n, seed):
         assert max(k["pres"], k["dres"], k["gap"]) <= 1e-6, k
 
 
+class _ExplicitInverseIQ(oracle.SchurIQSolver):
+    """The oracle's Schur linear step with G^{-1} formed once (numpy's inverse)
+    instead of a Cholesky solve per application: the same mathematics, another
+    FP64 rounding, used to measure how far FP64 arithmetic alone spreads an
+    iterate of an ill-conditioned LP."""
+
+    def __init__(self, prob):
+        A = prob.A
+        self.Gi = np.linalg.inv(np.eye(A.shape[0]) + A @ A.T)
+        super().__init__(prob)
+
+    def apply_Minv(self, w):
+        m, A = self.m, self.prob.A
+        a = self.Gi @ (w[:m] - A @ w[m:])
+        return np.concatenate([a, w[m:] + A.T @ a])
+
+
 def _tall(m_planted, n, extra, seed):
     """A planted m_planted x n LP stacked with `extra` random combinations of its
     rows: more rows than columns, rank m_planted, consistent b, same optimum."""
@@ -183,19 +200,31 @@ def test_lds_tall_a_only_fp32_held_as_doubles():
     prob = Problem(lp["A"], lp["b"], lp["c"])
     s = Settings(alpha=1.8, gamma=0.5, restart_rule="heuristic")
     st0 = oracle.restart(oracle.initial_state(prob, s), s.gamma, "heuristic")
-    solver = oracle.SchurIQSolver(prob)
     N = 40
-    st = st0.copy()
-    for _ in range(N):
-        st = oracle.admm_iteration(prob, solver, st, s)
+
+    def run(solver):
+        st = st0.copy()
+        for _ in range(N):
+            st = oracle.admm_iteration(prob, solver, st, s)
+        return st
+
+    st = run(oracle.SchurIQSolver(prob))
     scale = 1.0 + np.abs(st.u()).max()
+    # G = I + A A^T has condition number ~4e4 here, so FP64 rounding alone moves the
+    # 40-update iterate by ~1e-10 relative: the bar is 1e-10 plus four times the
+    # spread between the oracle's Cholesky-solve linear step and the same step through
+    # an explicitly formed G^{-1} (the form Section 4.4's cached inverse takes)
+    st_inv = run(_ExplicitInverseIQ(prob))
+    spread = max(np.abs(st_inv.u() - st.u()).max(), np.abs(st_inv.v() - st.v()).max())
+    tol = (1e-10 + 4 * spread / scale) * scale
+    print(f"tall: oracle FP64 spread {spread / scale:.2e} relative, bar {tol / scale:.2e}", flush=True)
     got = {(lds, fp32): _iterate(lp, st0, N, lds, fp32, "heuristic") for lds in (1, 0) for fp32 in (False, True)}
     for lds in (1, 0):
         y, x, sv, sc = got[(lds, False)]
         for g, ref in [(y, st.y), (x, st.x), (sv, st.s)]:
-            assert np.abs(g - ref).max() <= 1e-10 * scale, lds
+            assert np.abs(g - ref).max() <= tol, lds
         for key, ref in [("tau", st.tau), ("kappa", st.kappa), ("theta", st.theta)]:
-            assert abs(sc[key] - ref) <= 1e-10 * scale, (lds, key)
+            assert abs(sc[key] - ref) <= tol, (lds, key)
     a, b = got[(1, True)], got[(0, True)]
     for ga, gb in zip(a[:3], b[:3]):
         assert np.abs(ga - gb).max() <= 1e-9 * scale
