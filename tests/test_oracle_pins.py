@@ -580,3 +580,36 @@ def test_bb_solve_still_reaches_the_optimum():
     kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], out["x"], out["y"], out["s"])
     assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6
     assert abs(kk["pobj"] - lp["pstar"]) <= 1e-4 * (1 + abs(lp["pstar"]))
+
+
+def test_bb_differences_from_iterate_differences():
+    """The curvature differences of Section 4.3, formed as the paper defines them
+    (v-hat from v, u-tilde, u; the relaxed u-tilde difference), equal the forms
+    built from differences of consecutive iterates alone: with the dual update
+    v_k = v_{k-1} - uh_k + u_k and uh_k = alpha ut_k + (1 - alpha) u_{k-1},
+        dvh = dv2 - (1 - alpha) du2,  dut = du2 - dv2 + dv1,  du = -du2
+    (du2 = u2 - u1, dv2 = v2 - v1, dv1 = v1 - v0).  The GPU accumulates the
+    second form, so a wrong sign or a dropped term in either fails here."""
+    lp = lpgen.dense_planted(20, 45, 3)
+    prob = Problem(lp["A"], lp["b"], lp["c"])
+    for alpha in (1.0, 1.8, 0.7):
+        s = Settings(alpha=alpha)
+        st0 = oracle.restart(oracle.initial_state(prob, s), s.gamma, "heuristic")
+        solver = oracle.SchurIQSolver(prob)
+        for _ in range(5):                      # a point inside the outer iteration
+            st0 = oracle.admm_iteration(prob, solver, st0, s)
+        u0, v0 = st0.u(), st0.v()
+        st1, v1, ut1 = oracle.admm_iteration(prob, solver, st0, s, return_ut=True)
+        st2, v2, ut2 = oracle.admm_iteration(prob, solver, st1, s, return_ut=True)
+        u1, u2 = st1.u(), st2.u()
+        vh1 = v0 - alpha * ut1 - (1.0 - alpha) * u0 + alpha * u1
+        vh2 = v1 - alpha * ut2 - (1.0 - alpha) * u1 + alpha * u2
+        dvh, dut, du = vh2 - vh1, alpha * (ut2 - ut1) + (1.0 - alpha) * (u1 - u0), -(u2 - u1)
+        du2, dv2, dv1 = u2 - u1, v2 - v1, v1 - v0
+        scale = np.abs(u0).max() + np.abs(v0).max()
+        assert np.abs(dvh - (dv2 - (1.0 - alpha) * du2)).max() <= 1e-12 * scale
+        assert np.abs(dut - (du2 - dv2 + dv1)).max() <= 1e-12 * scale
+        assert np.abs(du + du2).max() == 0.0
+        # v's y block stays 0 and its theta entry -(n+1)
+        m, n = prob.m, prob.n
+        assert np.all(v1[:m] == 0.0) and v1[m + n + 1] == -(n + 1.0)
