@@ -176,10 +176,10 @@ def _stats(v):
 def error_report(lps, r32, r64):
     """Error of every FP32-bulk result against the FP64 batched result of the
     same LP and against the planted optimum (unique: |supp x0| = m)."""
-    e_obj64, e_x64, e_objp, e_xp, lib = [], [], [], [], []
+    e_obj64, e_x64, e_objp, e_xp, lib, lib_cap = [], [], [], [], [], []
     for k, lp in enumerate(lps):
         i32, i64 = r32[3][k], r64[3][k]
-        lib.append(i32["err_vs_fp64"])
+        (lib_cap if i32["status"] == 4 else lib).append(i32["err_vs_fp64"])
         if lp["status"] != "solved" or i32["status"] != 1 or i64["status"] != 1:
             continue
         x32, x64 = r32[0][k], r64[0][k]
@@ -194,7 +194,7 @@ def error_report(lps, r32, r64):
                     "certificate test for infeasible LPs)",
             "obj_vs_fp64": _stats(e_obj64), "x_vs_fp64": _stats(e_x64),
             "obj_vs_planted": _stats(e_objp), "x_vs_planted": _stats(e_xp),
-            "err_vs_fp64_library": _stats(lib)}
+            "err_vs_fp64_library": _stats(lib), "err_vs_fp64_library_at_iteration_cap": _stats(lib_cap)}
 
 
 def per_lp_rows(lps, infos, infos64, kkt):
@@ -439,17 +439,25 @@ def extra_differentiable(abip, torch, cpu=True):
     bwd = time.perf_counter() - t0
     ok = sum(1 for i in infos if i["status"] == abip.ABIP_SOLVED)
     eb, ec = [], []
-    for lp, dc, db in zip(lps, _host(dcs), _host(dbs)):
+    dch, dbh = _host(dcs), _host(dbs)
+    for lp, dc, db in zip(lps, dch, dbh):
         B = lp["basis"]
         lam = np.linalg.solve(lp["A"][:, B].T, lp["w"][B])
         eb.append(float(np.linalg.norm(db - lam) / np.linalg.norm(lam)))
         ec.append(float(np.linalg.norm(dc) / np.linalg.norm(lp["w"])))
+    adj = [abip.abip_backward_stats(w, k) for k in range(len(lps))]
+    # the final iterates of the LPs furthest from and nearest to the basis formula, for the host check
+    order = np.argsort(ec)
+    probe = [int(order[-1]), int(order[len(order) // 2])]
+    states = {k: [t.cpu().numpy() if hasattr(t, "cpu") else t for t in abip.abip_get_state(w, k)] for k in probe}
     w.free()
     out = {"workload": "64 LPs 200 x 500, seed 4, L = w^T x*, fp32 bulk + fp64 polish forward, adjoint backward",
            "solved": ok, "forward_s": fwd, "backward_s": bwd, "backward_over_forward": bwd / fwd,
+           "adjoint_iters": _stats([a[0] for a in adj]), "adjoint_rel_resid": _stats([a[1] for a in adj]),
            "db_rel_err_vs_basis_formula": _stats(eb), "dc_norm_over_w_norm": _stats(ec),
-           "note": "the adjoint differentiates the central point at the final mu; its distance to the "
-                   "LP derivative shrinks with mu and grows as the vertex nears degeneracy"}
+           "note": "the adjoint differentiates the central point at the final mu (checked against the dense "
+                   "KKT adjoint at the same iterate in cpu_baseline); its distance to the LP derivative of the "
+                   "basis shrinks with mu and grows as the vertex nears degeneracy (small reduced costs)"}
     if cpu:
         import oracle
         from threadpoolctl import threadpool_limits
@@ -464,8 +472,19 @@ def extra_differentiable(abip, torch, cpu=True):
                 per = (time.perf_counter() - t0) / 2
             runs.append({"threads": threads, "s_per_lp_forward_backward": per,
                          "batch_s_estimated": per * len(lps)})
+        # the GPU gradients against the oracle's dense KKT adjoint at the GPU's own final iterate
+        checks = []
+        for k in probe:
+            y, x, s_, sc = states[k]
+            lp = lps[k]
+            st = oracle.State(y, x, sc["tau"], sc["theta"], s_, sc["kappa"], sc["mu"])
+            lam = oracle.kkt_adjoint(lp["A"], lp["b"], lp["c"], st, lp["w"])
+            ref = oracle.contract_adjoint(lp["A"], lp["b"], lp["c"], st, lam)
+            checks.append({"lp": k, "dc_rel_err": float(np.linalg.norm(dch[k] - ref["dc"]) / np.linalg.norm(ref["dc"])),
+                           "db_rel_err": float(np.linalg.norm(dbh[k] - ref["db"]) / np.linalg.norm(ref["db"]))})
         out["cpu_baseline"] = {"kind": "oracle", "what": "oracle solve + dense KKT adjoint, 2 LPs timed, "
-                                                         "scaled to 64", "runs": runs}
+                                                         "scaled to 64", "runs": runs,
+                               "gpu_vs_kkt_adjoint_at_gpu_iterate": checks}
     return out
 
 
@@ -529,6 +548,30 @@ def extra_sice(abip, torch, d=64, N=1000, cpu=True):
             "max_constraint_over_lambda": viol, "l1_norm_of_omega": float(np.abs(B).sum())}
 
 
+def extra_trsv(abip, torch, cpu=True):
+    """The linear step by triangular solves with the cached factor L (ABIP_LIN_TRSV)
+    against the product with the cached G^{-1} (the default), streamed one-workgroup
+    engine, FP64, on dense planted LPs of growing m: time per update and the
+    iteration count of the same solve (capped at 3000 updates)."""
+    import lpgen
+    rows = []
+    for m in (100, 200, 400, 700, 1000):
+        lp = lpgen.dense_planted(m, int(2.2 * m), 40 + m)
+        row = {"m": m, "n": int(2.2 * m)}
+        for key, lin in (("inverse", abip.ABIP_LIN_AUTO), ("trsv", abip.ABIP_LIN_TRSV)):
+            st = abip.abip_default_settings(lin_solver=lin, lds_resident=0, max_admm_iters=3000)
+            w = abip.abip_setup(lp["A"], lp["b"], lp["c"], st)
+            x, y, sv, info = abip.abip_solve(w)
+            w.free()
+            it = max(1, info["admm_iters"])
+            row[key] = {"us_per_update": info["kernel_ms"] * 1e3 / it, "admm_iters": info["admm_iters"],
+                        "status": info["status_name"]}
+        row["trsv_over_inverse"] = row["trsv"]["us_per_update"] / row["inverse"]["us_per_update"]
+        rows.append(row)
+    return {"workload": "dense planted LPs m = 100 ... 1000, n = 2.2 m, FP64, streamed, one workgroup per LP, "
+                        "3000-update cap", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -543,10 +586,12 @@ def main():
     ap.add_argument("--per-lp-out", default=None, help="write the per-LP table (TSV) to this file")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra measurements (basis pursuit, sparse CG, differentiable batch, "
-                         "the paper's random LPs, SICE)")
+                         "the paper's random LPs, SICE, triangular solves vs the inverse)")
     ap.add_argument("--extra-only", default=None,
-                    choices=["basis_pursuit", "sparse_cg", "differentiable", "paper_random", "sice"],
+                    choices=["basis_pursuit", "sparse_cg", "differentiable", "paper_random", "sice", "trsv"],
                     help="run one extra measurement alone, print its JSON object and exit (for profiling)")
+    ap.add_argument("--tune-iters", type=int, default=200,
+                    help="updates per autotuner candidate on the batch handle (0: no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (PMC byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -562,7 +607,7 @@ def main():
     import paper_1805_12344_amd as abip
 
     torch.cuda.set_device(0)
-    extras = {"basis_pursuit": extra_basis_pursuit, "sparse_cg": extra_sparse,
+    extras = {"trsv": extra_trsv, "basis_pursuit": extra_basis_pursuit, "sparse_cg": extra_sparse,
               "differentiable": extra_differentiable, "paper_random": extra_paper_random, "sice": extra_sice}
     if args.extra_only:
         print(json.dumps({args.extra_only: extras[args.extra_only](abip, torch, cpu=False)}), flush=True)
@@ -572,9 +617,35 @@ def main():
     s32 = abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH)
     log(f"workload: {len(lps)} LPs, sum m*n = {sum(lp['m'] * lp['n'] for lp in lps):.3e}")
 
+    # one handle for every step: its buffers are allocated once, each step loads the
+    # batch into them (the whole setup: copies, the factorization, the border) and
+    # solves it, so the batched launch's captured graph is replayed from the second
+    # step on
+    t0 = time.perf_counter()
+    wb = abip.abip_setup_batch(As, bs, cs, s32)
+    torch.cuda.synchronize()
+    log(f"handle + first setup: {time.perf_counter() - t0:.2f} s")
+    tune = None
+    if args.tune_iters > 0:
+        t0 = time.perf_counter()
+        r = abip.abip_autotune(wb, args.tune_iters)
+        labels = ["LDS: A and G^-1, else A alone", "LDS: A and G^-1 only", "all streamed"]
+        if all(lp["m"] <= 256 for lp in lps):
+            labels.append("512 threads, streamed")
+        labels.append("per-LP mix of resident and streamed")
+        tune = {"iters_per_candidate": args.tune_iters,
+                "score": "sum over LPs of each LP's own device-clock time for the candidate's run, ms",
+                "candidates": [{"config": labels[i], "score_ms": r["ms"][i]} for i in range(len(r["ms"]))],
+                "chosen": labels[r["chosen"]], "seconds": time.perf_counter() - t0}
+        log(f"autotune: {tune}")
+
+    def step():
+        abip.abip_update_data(wb, As, bs, cs)
+        return abip.abip_solve_batch(wb)
+
     for i in range(args.warmup):
         t0 = time.perf_counter()
-        run_batch(abip, As, bs, cs, s32)
+        step()
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.perf_counter() - t0:.2f} s")
 
@@ -582,7 +653,7 @@ def main():
     t0 = time.perf_counter()
     results = []
     for i in range(args.steps):
-        results.append(run_batch(abip, As, bs, cs, s32))
+        results.append(step())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} step(s): {elapsed:.2f} s")
@@ -614,7 +685,9 @@ def main():
         "config": {"workload": f"batched dense LPs: {len(lps)} LPs, m~U[20,400], n~U[2m,3m], 10% "
                                f"primal infeasible, seed {args.seed}; eps 1e-6",
                    "global_batch": len(lps), "precision": "fp32 bulk + fp64 polish",
-                   "engine": "one workgroup per LP, persistent, largest first"},
+                   "engine": "one workgroup per LP, persistent, largest first; one handle reloaded "
+                             "per step (abip_update_data), graph replayed"},
+        "autotune": tune,
         "admm_iters_per_s": admm_per_s,
         "admm_iters_total": int(iters.sum()),
         "admm_iters_fp64_total": int(sum(i["admm_iters_fp64"] for i in infos)),

@@ -72,6 +72,12 @@ extern "C" {
 #define ABIP_LIN_AUTO    0  /* dense -> direct, CSR -> CG */
 #define ABIP_LIN_DIRECT  1  /* cached FP64 factorization of G = I + A A^T */
 #define ABIP_LIN_CG      2  /* Jacobi-preconditioned CG on G, matrix-free (CSR) */
+#define ABIP_LIN_TRSV    3  /* dense, one-workgroup engine: the cached Cholesky factor L of G
+                               (G = L L^T) kept, and every update solves L z = t, L^T a = z by
+                               blocked substitution (64-row blocks through the inverses of L's
+                               diagonal blocks) instead of the product with G^{-1}; every LP is
+                               streamed from device memory.  ABIP_E_INVALID for the grid engine,
+                               CSR input and settings.bb. */
 
 #define ABIP_ENGINE_AUTO   0 /* pick by size */
 #define ABIP_ENGINE_WG     1 /* one workgroup owns one LP for the whole solve (persistent) */
@@ -114,6 +120,28 @@ typedef struct {
                                   fit; 0: the CG passes read them from global memory.  Same
                                   iteration and tests; the sums are formed in a different order,
                                   so results agree to rounding, not bitwise. */
+    int32_t bb;                /* 1: Section 4.3's adaptive beta (one-workgroup engine only;
+                                  ABIP_E_INVALID at setup for the grid and sparse engines): every
+                                  outer iteration that starts with ||Q u - v||^2 > mu takes two
+                                  probe iterations from its initial point, estimates beta from the
+                                  curvature of the three iterates (steepest-descent / minimum-
+                                  gradient hybrid, correlation safeguard bb_eps_cor), keeps it,
+                                  averages it or redoes the probes from the same point with the
+                                  estimate (bb_eps_penalty, at most bb_max_redo redos); the probes
+                                  are discarded and count in admm_iters.  0 (default): beta fixed */
+    int32_t bb_max_redo;       /* default 10 */
+    double  bb_eps_cor;        /* default 0.2 (Section 5) */
+    double  bb_eps_penalty;    /* default 0.1 (Section 5) */
+    int32_t scale_iters;       /* dense A: rounds of Ruiz equilibration at setup (the scaling of
+                                  Section 4.5's remark, which defers to SCS): each round multiplies
+                                  D_i by 1/sqrt(max_j |(D_i a_ij) E_j|) and E_j by
+                                  1/sqrt(max_i |(D_i a_ij) E_j|); the solver then runs on
+                                  (D A E, D b, E c) -- the Section 4.1 tests on that LP -- and
+                                  returns x = E x', y = D y', s = s' / E; err_vs_fp64 measures the LP
+                                  as given.  abip_backward refuses scaled handles; abip_set_state,
+                                  abip_get_state, abip_iterate and abip_apply_iq work in the scaled
+                                  variables.  0 (default): no scaling; at most 100.  CSR input:
+                                  ABIP_E_INVALID. */
 } abip_settings;
 
 /* Per-LP result summary (host struct). */
@@ -156,6 +184,9 @@ typedef struct {
                                   ||A^T y + s|| ||b|| of the returned certificate (b^T y = 1);
                                   DUAL_INFEASIBLE: ||A x|| ||c|| of the returned ray (c^T x = -1).
                                   Each passes the Section 4.1 test when <= eps. */
+    double  beta;              /* the last outer iteration's beta (settings.beta unless settings.bb) */
+    int64_t bb_probe_iters;    /* of admm_iters: the probe iterations of the beta estimates */
+    int32_t bb_estimates;      /* beta estimates taken (redos included) */
 } abip_info;
 
 /* A matrix description.  All pointers are device pointers; abip_setup copies
@@ -197,6 +228,16 @@ int abip_setup(abip_work** out, const abip_matrix* A, const double* b, const dou
 int abip_setup_batch(abip_work** out, int32_t B, const abip_matrix* A,
                      const double* const* b, const double* const* c,
                      const abip_settings* settings, void* stream);
+
+/* Load new data into a dense handle: A[k], b[k], c[k] (host arrays of B
+ * entries, each as in abip_setup_batch; B and every LP's m and n must equal
+ * those given at setup, else ABIP_E_DIM) replace the handle's LPs, and the whole
+ * setup (copies, HSD constants, the factorization of G = I + A A^T and G^{-1},
+ * the border) runs again in the buffers the handle already owns: no device
+ * allocation, and the batched launch's captured graph is replayed by the next
+ * solve.  For serving loops that solve new LPs of fixed shapes.  CSR handles:
+ * ABIP_E_STATE.  On an error the handle must be loaded again or freed. */
+int abip_update_data(abip_work* w, const abip_matrix* A, const double* const* b, const double* const* c);
 
 /* Run Algorithm 2 from its start point (mu^0 = beta, (y,x,tau,theta) = (0,e,1,1),
  * (s,kappa) = (e,1)) until a test of Section 4.1 passes or max_admm_iters.
@@ -264,19 +305,85 @@ int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_fp32);
 /* Launch-configuration autotuner (project extension).  Runs `iters` ADMM
  * updates from Algorithm 2's start point with each candidate configuration of
  * the handle's engine, timed with HIP events on the work stream, and keeps the
- * fastest for later solves: one-workgroup engine 256 or 512 threads (LPs with
- * m <= 256; larger ones have the single 256 candidate), grid engine about
- * 0.5 / 1 / 2 / 4 workgroups per CU, sparse engine the setup's workgroup count
- * (one per 256 rows or columns, at most one per CU) then 32 / 64 / 128 / 256
- * workgroups (up to what can be co-resident; its updates use the solve's CG
- * stopping rule).  ms (host, may be NULL) receives
- * the time of each candidate (up to max_cand), *ncand their number, *chosen
- * the kept value (threads or workgroups); both may be NULL.  The iterate is
- * reset to the start point.  A configuration change can change the last bits
- * of later results (sums are reduced in a different fixed order), not their
- * correctness. */
+ * fastest for later solves.  Candidates, in this order:
+ *   one-workgroup engine (dense batch), 256 threads unless noted:
+ *     0  LDS residency as the settings allow (A and G^{-1} in LDS where they
+ *        fit, else A alone where it fits),
+ *     1  only LPs whose A and G^{-1} both fit run LDS-resident,
+ *     2  every LP streamed from device memory,
+ *     -  512 threads, streamed (only when every LP has m <= 256),
+ *     -  per-LP mix: policy 0, except that the LPs whose own clock ran faster
+ *        in candidate 2 than in candidate 0 are streamed
+ *     (settings.lds_resident == 0 leaves candidate 0, and the 512-thread one);
+ *   grid engine: about 0.5 / 1 / 2 / 4 workgroups per CU;
+ *   sparse engine: the setup's workgroup count (one per 256 rows or columns,
+ *     at most one per CU) then 32 / 64 / 128 / 256 workgroups (up to what can
+ *     be co-resident; its updates use the solve's CG stopping rule).
+ * ms (host, may be NULL) receives each candidate's score, the quantity the
+ * choice minimises (up to max_cand): for the grid and sparse engines the time
+ * of the launch, for the one-workgroup engine the sum over LPs of each LP's own
+ * device-clock time, in ms (a fixed-iteration launch lasts as long as its
+ * largest LP alone, while a batch's throughput depends on every LP);
+ * *ncand their number, *chosen the kept one: its index in the list above for
+ * the one-workgroup engine, its workgroup count for the grid and sparse
+ * engines; both may be NULL.  The per-LP LDS modes that a solve then uses are
+ * reported in abip_info.lds_mode.  The iterate is reset to the start point.  A
+ * configuration change can change the last bits of later results (sums are
+ * reduced in a different fixed order), not their correctness. */
 int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t max_cand, int32_t* ncand,
                   int32_t* chosen);
+
+/* The row and column factors D (m) and E (n) of LP k's scaling
+ * (settings.scale_iters; all 1 otherwise), copied to device buffers. */
+int abip_get_scaling(abip_work* w, int32_t k, double* D, double* E);
+
+/* ---- presolve / postsolve (Section 4.5), host ------------------------------
+ * For LPs given in the bounded form  min c^T x  s.t.  A x = b,  l <= x <= w
+ * (l_j may be -INFINITY, w_j +INFINITY).  abip_presolve applies the paper's
+ * reductions on the host, repeated until none applies, each scan in ascending
+ * index order: P3 (l_j > w_j: infeasible), P4 (l_j = w_j: fixed and substituted
+ * out), P1 (an empty row: dropped when |b_i| <= 1e-9 (1 + max|b|), else
+ * infeasible), P2 (an empty column: at the bound its cost favours; unbounded
+ * when that bound is infinite), P6 (a singleton row fixes its variable;
+ * infeasible outside the bounds by more than 1e-9 (1 + |bound|)).  The rest is
+ * rewritten in the standard form of Section 2 as the paper describes: free
+ * variables split (P5), variables bounded only above reflected, lower bounds
+ * shifted to 0, each finite upper bound a row with a slack column.  Dependent
+ * rows are kept (the linear step uses I + A A^T).  Host arrays: A dense
+ * row-major m x n; l, w may be NULL (0 and +INFINITY).  *out receives a record
+ * (free it with abip_presolve_free) whenever the return is ABIP_OK; *status is
+ * ABIP_PRESOLVE_REDUCED (the standard form has *m_std rows and *n_std columns)
+ * or a verdict.  Errors: ABIP_E_DIM, ABIP_E_INVALID (null arrays, NaN bounds),
+ * ABIP_E_NONFINITE (non-finite A, b, c). */
+#define ABIP_PRESOLVE_REDUCED    0
+#define ABIP_PRESOLVE_INFEASIBLE 1
+#define ABIP_PRESOLVE_UNBOUNDED  2
+typedef struct abip_presolve_t abip_presolve_t;
+int abip_presolve(int32_t m, int32_t n, const double* A, const double* b, const double* c, const double* l,
+                  const double* w, abip_presolve_t** out, int32_t* status, int32_t* m_std, int32_t* n_std);
+
+/* The standard form (host: A_std m_std x n_std row-major, b_std, c_std; any may
+ * be NULL) and the objective constant of the removed part (c^T x = c_std^T x_std
+ * + obj_offset).  ABIP_E_STATE after a verdict. */
+int abip_presolve_get(const abip_presolve_t* p, double* A_std, double* b_std, double* c_std, double* obj_offset);
+
+/* What the presolve did (host arrays, any may be NULL): *where = the row or
+ * column that decided a verdict (-1 otherwise); rows_kept / cols_kept (as many
+ * as remain, ascending); row_kind[m]: -1 kept, 0 removed empty, 1 removed
+ * singleton; fixed_cols / fixed_vals in fixing order, *nfixed their number. */
+int abip_presolve_info(const abip_presolve_t* p, int32_t* where, int32_t* rows_kept, int32_t* cols_kept,
+                       int32_t* row_kind, int32_t* fixed_cols, double* fixed_vals, int32_t* nfixed);
+
+/* Postsolve (host): from a solution (x_std, y_std) of the standard form, the
+ * original x[n], the multipliers y[m] of the original rows (0 for removed empty
+ * rows; for removed singleton rows, in reverse order of removal, the value that
+ * makes the reduced cost of the variable it fixed zero) and the reduced costs
+ * r[n] = c - A^T y (r_j > 0 at a lower bound, < 0 at an upper bound at an
+ * optimum).  ABIP_E_STATE after a verdict. */
+int abip_postsolve(const abip_presolve_t* p, const double* x_std, const double* y_std, double* x, double* y,
+                   double* r);
+
+int abip_presolve_free(abip_presolve_t* p);
 
 /* ---- allocation-free solve -------------------------------------------------
  * For callers that cannot allocate device memory: tight serving loops that

@@ -11,6 +11,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -23,7 +25,7 @@ ABIP_UNSOLVED, ABIP_SOLVED, ABIP_PRIMAL_INFEASIBLE, ABIP_DUAL_INFEASIBLE, ABIP_M
 ABIP_DENSE_ROWMAJOR, ABIP_CSR = 0, 1
 ABIP_PREC_FP64, ABIP_PREC_FP32_POLISH = 0, 1
 ABIP_RESTART_HEURISTIC, ABIP_RESTART_SQRT = 0, 1
-ABIP_LIN_AUTO, ABIP_LIN_DIRECT, ABIP_LIN_CG = 0, 1, 2
+ABIP_LIN_AUTO, ABIP_LIN_DIRECT, ABIP_LIN_CG, ABIP_LIN_TRSV = 0, 1, 2, 3
 ABIP_ENGINE_AUTO, ABIP_ENGINE_WG, ABIP_ENGINE_GRID = 0, 1, 2
 
 STATUS_NAMES = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasible", 4: "max_iters"}
@@ -40,6 +42,8 @@ class abip_settings(ctypes.Structure):
         ("adjoint_tol", ctypes.c_double), ("adjoint_max_iters", ctypes.c_int64),
         ("cg_rule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("lds_resident", ctypes.c_int32),
+        ("bb", ctypes.c_int32), ("bb_max_redo", ctypes.c_int32), ("bb_eps_cor", ctypes.c_double),
+        ("bb_eps_penalty", ctypes.c_double), ("scale_iters", ctypes.c_int32),
     ]
 
 
@@ -57,6 +61,7 @@ class abip_info(ctypes.Structure):
         ("colpass_lds_fp32", ctypes.c_int64), ("colpass_lds_fp64", ctypes.c_int64),
         ("ginv_hbm_fp32", ctypes.c_int64), ("ginv_hbm_fp64", ctypes.c_int64),
         ("lds_mode", ctypes.c_int32), ("fp32_exit_kkt", ctypes.c_double), ("err_vs_fp64", ctypes.c_double),
+        ("beta", ctypes.c_double), ("bb_probe_iters", ctypes.c_int64), ("bb_estimates", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -77,7 +82,9 @@ EXPORTS = [
     "abip_default_settings", "abip_setup", "abip_setup_batch", "abip_solve", "abip_solve_batch",
     "abip_backward", "abip_backward_batch", "abip_apply_iq", "abip_set_state", "abip_get_state",
     "abip_iterate", "abip_free", "abip_last_error", "abip_version", "abip_backward_stats",
-    "abip_autotune", "abip_solve_noalloc",
+    "abip_autotune", "abip_solve_noalloc", "abip_update_data",
+    "abip_presolve", "abip_presolve_get", "abip_presolve_info", "abip_postsolve", "abip_presolve_free",
+    "abip_get_scaling",
 ]
 
 
@@ -113,6 +120,14 @@ def load_library(path: str = LIB_PATH):
                                         ctypes.POINTER(ctypes.c_double)]
     lib.abip_autotune.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.abip_update_data.argtypes = [P, ctypes.POINTER(abip_matrix), ctypes.POINTER(P), ctypes.POINTER(P)]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.abip_presolve.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, ctypes.POINTER(P), i32p, i32p, i32p]
+    lib.abip_presolve_get.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.abip_presolve_info.argtypes = [P, i32p, P, P, P, P, P, i32p]
+    lib.abip_postsolve.argtypes = [P, P, P, P, P, P]
+    lib.abip_presolve_free.argtypes = [P]
+    lib.abip_get_scaling.argtypes = [P, ctypes.c_int32, P, P]
     lib.abip_solve_noalloc.argtypes = [ctypes.POINTER(abip_matrix), P, P, P, P, P, ctypes.POINTER(abip_info),
                                        ctypes.POINTER(abip_settings), P]
     lib.abip_last_error.restype = ctypes.c_char_p
@@ -246,6 +261,114 @@ def abip_setup_batch(As, bs, cs, settings: abip_settings | None = None) -> Work:
     return Work(h, [(A.shape[0], A.shape[1]) for A in As], (As, bs, cs, s))
 
 
+def abip_update_data(w: Work, As, bs, cs):
+    """Load new dense LPs of the same shapes into a handle (abip_update_data);
+    As, bs, cs: lists of B arrays / tensors (one LP: single-element lists)."""
+    B = w.B
+    if len(As) != B or len(bs) != B or len(cs) != B:
+        raise ValueError(f"expected {B} LPs")
+    As = [_dev(A) for A in As]
+    bs = [_dev(b, (A.shape[0],)) for A, b in zip(As, bs)]
+    cs = [_dev(c, (A.shape[1],)) for A, c in zip(As, cs)]
+    mats = (abip_matrix * B)(*[abip_matrix(A.shape[0], A.shape[1], ABIP_DENSE_ROWMAJOR, A.data_ptr(),
+                                           None, None, 0) for A in As])
+    bp = (ctypes.c_void_p * B)(*[b.data_ptr() for b in bs])
+    cp = (ctypes.c_void_p * B)(*[c.data_ptr() for c in cs])
+    _check(lib().abip_update_data(w.handle, mats, bp, cp))
+    w._keep = (As, bs, cs, w._keep[3] if isinstance(w._keep, tuple) and len(w._keep) > 3 else None)
+
+
+ABIP_PRESOLVE_REDUCED, ABIP_PRESOLVE_INFEASIBLE, ABIP_PRESOLVE_UNBOUNDED = 0, 1, 2
+
+
+class Presolved:
+    """A presolve record (abip_presolve) and what it produced, as host numpy
+    arrays: status, A/b/c (the standard form, when REDUCED), obj_offset, where,
+    rows_kept, cols_kept, row_kind, fixed (list of (column, value))."""
+
+    def __init__(self, handle, m, n, status, m_std, n_std):
+        self.handle, self.m, self.n, self.status = handle, m, n, status
+        self.m_std, self.n_std = m_std, n_std
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.abip_presolve_free(self.handle)
+            self.handle = None
+
+
+def _host64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a.detach().cpu() if hasattr(a, "detach") else a, dtype=np.float64))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def abip_presolve(A, b, c, l=None, w=None) -> Presolved:
+    """Section 4.5's presolve of min c^T x s.t. A x = b, l <= x <= w (host data)."""
+    A = _host64(A)
+    m, n = A.shape
+    b, c = _host64(b, (m,)), _host64(c, (n,))
+    lv = None if l is None else _host64(l, (n,))
+    wv = None if w is None else _host64(w, (n,))
+    h = ctypes.c_void_p()
+    st, ms, ns = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().abip_presolve(m, n, ptr(A), ptr(b), ptr(c), ptr(lv), ptr(wv), ctypes.byref(h), ctypes.byref(st),
+                               ctypes.byref(ms), ctypes.byref(ns)))
+    p = Presolved(h, m, n, st.value, ms.value, ns.value)
+    p.__dict__.update(abip_presolve_info(p))
+    if p.status == ABIP_PRESOLVE_REDUCED:
+        p.A, p.b, p.c, p.obj_offset = abip_presolve_get(p)
+    return p
+
+
+def abip_presolve_info(p: Presolved) -> dict:
+    """where, rows_kept, cols_kept, row_kind, fixed [(column, value)] of a presolve."""
+    m, n = p.m, p.n
+    where = ctypes.c_int32()
+    rows = np.zeros(m, dtype=np.int32)
+    cols = np.zeros(n, dtype=np.int32)
+    kind = np.zeros(m, dtype=np.int32)
+    fc = np.zeros(n, dtype=np.int32)
+    fv = np.zeros(n)
+    nf = ctypes.c_int32()
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().abip_presolve_info(p.handle, ctypes.byref(where), vp(rows), vp(cols), vp(kind), vp(fc), vp(fv),
+                                    ctypes.byref(nf)))
+    reduced = p.status == ABIP_PRESOLVE_REDUCED
+    return dict(where=where.value, row_kind=kind, fixed=[(int(fc[t]), float(fv[t])) for t in range(nf.value)],
+                rows_kept=rows[: int(np.sum(kind == -1))] if reduced else None,
+                cols_kept=cols[: n - nf.value] if reduced else None)
+
+
+def abip_presolve_get(p: Presolved):
+    """(A_std, b_std, c_std, obj_offset) of a presolve that reduced the LP."""
+    A = np.zeros((p.m_std, p.n_std))
+    b = np.zeros(p.m_std)
+    c = np.zeros(p.n_std)
+    off = ctypes.c_double()
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().abip_presolve_get(p.handle, vp(A), vp(b), vp(c), ctypes.byref(off)))
+    return A, b, c, off.value
+
+
+def abip_presolve_free(p: Presolved):
+    if p.handle:
+        _check(lib().abip_presolve_free(p.handle))
+        p.handle = None
+
+
+def abip_postsolve(p: Presolved, x_std, y_std):
+    """(x, y, r) of the original LP from a solution of the standard form (host arrays)."""
+    xs = _host64(x_std, (p.n_std,))
+    ys = _host64(y_std, (p.m_std,))
+    x, y, r = np.zeros(p.n), np.zeros(p.m), np.zeros(p.n)
+    _check(lib().abip_postsolve(p.handle, xs.ctypes.data_as(ctypes.c_void_p), ys.ctypes.data_as(ctypes.c_void_p),
+                                x.ctypes.data_as(ctypes.c_void_p), y.ctypes.data_as(ctypes.c_void_p),
+                                r.ctypes.data_as(ctypes.c_void_p)))
+    return x, y, r
+
+
 def abip_solve(w: Work):
     """Returns (x, y, s, info_dict) as new CUDA float64 tensors."""
     m, n = w.dims[0]
@@ -329,13 +452,24 @@ def abip_get_state(w: Work, k: int):
     return y, x, s, dict(tau=sc[0], kappa=sc[1], theta=sc[2], mu=sc[3])
 
 
+def abip_get_scaling(w: Work, k: int = 0):
+    """(D, E): LP k's row and column scaling factors (CUDA float64 tensors)."""
+    m, n = w.dims[k]
+    D = torch.empty(m, dtype=torch.float64, device="cuda")
+    E = torch.empty(n, dtype=torch.float64, device="cuda")
+    _check(lib().abip_get_scaling(w.handle, k, _ptr(D), _ptr(E)))
+    return D, E
+
+
 def abip_iterate(w: Work, k: int, iters: int, use_fp32: bool = False):
     _check(lib().abip_iterate(w.handle, k, int(iters), int(use_fp32)))
 
 
 def abip_autotune(w: Work, iters: int = 50):
     """Try the engine's launch configurations for `iters` updates each; keep the fastest.
-    Returns dict(chosen=threads-or-workgroups, ms=[time per candidate])."""
+    Returns dict(chosen=..., ms=[time per candidate]): `chosen` is the kept
+    candidate's index for the one-workgroup engine, its workgroup count for the
+    grid and sparse engines (order and meaning as in abip_autotune)."""
     ms = (ctypes.c_double * 8)()
     nc = ctypes.c_int32()
     ch = ctypes.c_int32()

@@ -21,8 +21,14 @@ hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const
                            const PoolPtrs& P, const SolveParams& prm, const int32_t* order, int32_t B,
                            int32_t* queue, int64_t fixed_iters, int32_t ldmax, size_t smem);
 size_t wg_smem_bytes(int ldmax, int W);
-int lib_setup_one(const LPDesc& d, const LPDesc* ddesc, const double* A64, double* G64, float* G32, double* Mv,
-                  double* Nv, int64_t Mtot, int64_t Ntot, LPCtrl* dctrl, hipStream_t st);
+// the cached factorization G = I + A A^T -> G^{-1} on the matrix cores (abip_factor.hip)
+hipError_t factor_ginv(const LPDesc* ddesc, int B, int mmax, const double* A64, double* G64, float* G32, double* Lv,
+                       const int64_t* oL, double* Wpool, const int64_t* oW, int* err, const FactorKeep* keep,
+                       hipStream_t st);
+// border of one large LP over the whole GPU (abip_setup_lib.hip)
+int64_t grid_border_scratch(int m, int n, int ld);
+hipError_t grid_border(const LPDesc& d, const LPDesc* ddesc, const double* A64, const double* G64, double* Mv,
+                       double* Nv, int64_t Mtot, int64_t Ntot, LPCtrl* dctrl, double* scratch, hipStream_t st);
 struct AdjArgs {
     double* ws;
     const int64_t* ows;
@@ -50,10 +56,12 @@ hipError_t launch_recheck_csr(const int32_t* rp, const int32_t* ci, const double
 
 // setup kernels (abip_setup.hip)
 __global__ void k_setup_copy(const LPDesc*, const double* const*, double*, float*, int*);
+__global__ void k_ruiz_init(const LPDesc*, double*, double*, int64_t, int64_t);
+__global__ void k_ruiz_max(const LPDesc*, const double*, double*, double*, int64_t, int64_t);
+__global__ void k_ruiz_apply(const LPDesc*, double*, double*, int64_t, int64_t);
+__global__ void k_ruiz_scale(const LPDesc*, double*, float*, const double*, const double*, int64_t, int64_t);
 __global__ void k_setup_rows(const LPDesc*, const double* const*, const double* const*, const double*,
                              double*, double*, int64_t, int64_t, int*);
-__global__ void k_syrk(const LPDesc*, const double*, double*);
-__global__ void k_chol_inv(const LPDesc*, double*, float*, double*, const int64_t*, int*);
 __global__ void k_setup_border(const LPDesc*, const double*, const double*, double*, double*, int64_t,
                                int64_t, LPCtrl*, int);
 
@@ -63,6 +71,17 @@ __global__ void k_setup_border(const LPDesc*, const double*, const double*, doub
 static thread_local std::string g_err;
 
 static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+// the same for the library's host-only sources (presolve)
+int abip_internal_fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -89,7 +108,8 @@ __global__ void k_reset_queue(int32_t* q) {
 }
 
 __global__ void k_init_state(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl, double* __restrict__ Mv,
-                             double* __restrict__ Nv, int64_t Mtot, int64_t Ntot, double beta, int phase) {
+                             double* __restrict__ Nv, int64_t Mtot, int64_t Ntot, double beta, int phase,
+                             int bb) {
     const int k = blockIdx.x;
     const LPDesc d = desc[k];
     for (int i = threadIdx.x; i < d.ld; i += blockDim.x) Mv[MF_Y * Mtot + d.om + i] = 0.0;
@@ -106,7 +126,8 @@ __global__ void k_init_state(const LPDesc* __restrict__ desc, LPCtrl* __restrict
         c.clk[0] = c.clk[1] = c.clk[2] = c.clk[3] = c.clk[4] = 0;
         c.cpl32 = c.cpl64 = c.gh32 = c.gh64 = 0;
         c.kfx = NAN; c.err64 = NAN;
-        c.status = 0; c.phase = phase; c.mode = OP_REFRESH; c.flags = 0;
+        c.beta = beta; c.bbp = 0; c.bbe = 0;
+        c.status = 0; c.phase = phase; c.mode = OP_REFRESH; c.flags = bb ? 16 : 0;
     }
 }
 
@@ -128,12 +149,16 @@ __global__ void k_write_outputs(const LPDesc* __restrict__ desc, const LPCtrl* _
     bool nx = false, ny = false, ns = false;
     if (c.status == ABIP_PRIMAL_INFEASIBLE) { fy = fs = 1.0 / c.by; nx = true; }
     else if (c.status == ABIP_DUAL_INFEASIBLE) { fx = -1.0 / c.cx; ny = ns = true; }
+    // back to the LP as given: x = E x', y = D y', s = s' / E (D = E = 1 when
+    // the LP was not scaled)
+    const double* Dv = Mv + MF_SD * Mtot + d.om;
+    const double* Ev = Nv + NF_SE * Ntot + d.on;
     for (int j = threadIdx.x; j < d.n; j += blockDim.x) {
-        if (xo) xo[j] = nx ? NAN : x[j] * fx;
-        if (so) so[j] = ns ? NAN : s[j] * fs;
+        if (xo) xo[j] = nx ? NAN : (x[j] * fx) * Ev[j];
+        if (so) so[j] = ns ? NAN : (s[j] * fs) / Ev[j];
     }
     for (int i = threadIdx.x; i < d.m; i += blockDim.x)
-        if (yo) yo[i] = ny ? NAN : y[i] * fy;
+        if (yo) yo[i] = ny ? NAN : (y[i] * fy) * Dv[i];
 }
 
 // Copy LP k's iterate in or out (device vectors) -- step-level API.
@@ -246,8 +271,21 @@ struct abip_work {
     double** outp = nullptr;     // 3*B device pointer table
     double* rchk = nullptr;      // partial sums of the FP64 recheck (B * rchk_P * 8)
     int rchk_P = 1;              // workgroups per LP of the recheck
+    // setup scratch kept with a dense handle, so abip_update_data can redo the
+    // setup in place: W = L^{-1} (ld x ld per LP), the inverses of L's 64 x 64
+    // diagonal blocks, the grid border's vectors, the caller's pointer tables
+    double* suW = nullptr; int64_t* suoW = nullptr; double* suL = nullptr; int64_t* suoL = nullptr;
+    double* suB = nullptr;
+    FactorKeep keep{};               // L for the triangular-solve path (ABIP_LIN_TRSV), else null
+    const double** suA = nullptr; const double** sub = nullptr; const double** suc = nullptr;
+    int64_t suWtot = 0;
+    int mmax = 0;
     int ldmax = 0, nch = 1, threads = 512;
     size_t wg_smem = 0;              // LDS bytes of the batched launch (streamed or LDS-resident)
+    // LDS residency chosen by the autotuner: 0 = A and G^{-1}, else A alone, where
+    // they fit; 1 = only A and G^{-1}; 2 = none.  lds_stream[k] != 0 streams LP k.
+    int lds_policy = 0;
+    std::vector<uint8_t> lds_stream;
     int lds_cap = 0;                 // the device's largest LDS allocation per workgroup
     int cu_count = 256;
     bool solved = false;
@@ -313,6 +351,10 @@ static void release(abip_work* w) {
     (void)hipFree(w->Mv); (void)hipFree(w->Nv);
     (void)hipFree(w->order); (void)hipFree(w->queue); (void)hipFree(w->errflag); (void)hipFree(w->outp);
     (void)hipFree(w->rchk);
+    (void)hipFree(w->suW); (void)hipFree(w->suoW); (void)hipFree(w->suL); (void)hipFree(w->suoL);
+    (void)hipFree(w->suB); (void)hipFree((void*)w->suA); (void)hipFree((void*)w->sub); (void)hipFree((void*)w->suc);
+    (void)hipFree(w->keep.L64); (void)hipFree(w->keep.Lt64); (void)hipFree(w->keep.L32); (void)hipFree(w->keep.Lt32);
+    (void)hipFree(w->keep.Li64); (void)hipFree(w->keep.Lit64); (void)hipFree(w->keep.Li32); (void)hipFree(w->keep.Lit32);
     (void)hipFree(w->adj_ws); (void)hipFree(w->adj_ows); (void)hipFree(w->adj_ptrs);
     (void)hipFree(w->adj_iters); (void)hipFree(w->adj_resid);
     (void)hipFree(w->gbuf); (void)hipFree(w->gctl);
@@ -350,6 +392,11 @@ extern "C" int abip_default_settings(abip_settings* s) {
     s->cg_rule = 0;
     s->use_graph = 1;
     s->lds_resident = 1;
+    s->bb = 0;
+    s->bb_max_redo = 10;
+    s->bb_eps_cor = 0.2;
+    s->bb_eps_penalty = 0.1;
+    s->scale_iters = 0;
     return ABIP_OK;
 }
 
@@ -368,12 +415,27 @@ static int check_settings(const abip_settings& s) {
     if (s.lds_resident != 0 && s.lds_resident != 1) return fail(ABIP_E_INVALID, "settings.lds_resident must be 0 or 1");
     if (s.block_threads != 0 && s.block_threads != 256 && s.block_threads != 512)
         return fail(ABIP_E_INVALID, "settings.block_threads must be 0, 256 or 512");
+    if (s.bb != 0 && s.bb != 1) return fail(ABIP_E_INVALID, "settings.bb must be 0 or 1");
+    if (s.bb_max_redo < 0) return fail(ABIP_E_INVALID, "settings.bb_max_redo must be >= 0");
+    if (!(s.bb_eps_cor >= 0.0 && s.bb_eps_cor < 1.0))
+        return fail(ABIP_E_INVALID, "settings.bb_eps_cor must lie in [0,1)");
+    if (!(s.bb_eps_penalty >= 0.0) || !std::isfinite(s.bb_eps_penalty))
+        return fail(ABIP_E_INVALID, "settings.bb_eps_penalty must be >= 0");
+    if (s.scale_iters < 0 || s.scale_iters > 100) return fail(ABIP_E_INVALID, "settings.scale_iters must lie in [0,100]");
+    if (s.lin_solver < ABIP_LIN_AUTO || s.lin_solver > ABIP_LIN_TRSV)
+        return fail(ABIP_E_INVALID, "settings.lin_solver: unknown value %d", s.lin_solver);
+    if (s.lin_solver == ABIP_LIN_TRSV && s.bb)
+        return fail(ABIP_E_INVALID, "settings.lin_solver = ABIP_LIN_TRSV does not combine with settings.bb");
     return ABIP_OK;
 }
 
 static SolveParams make_params(const abip_settings& s) {
     SolveParams p;
+    memset(&p, 0, sizeof p);
     p.eps = s.eps; p.alpha = s.alpha; p.beta = s.beta; p.gamma = s.gamma;
+    p.eps_cor = s.bb_eps_cor; p.eps_pen = s.bb_eps_penalty;
+    p.bb = s.bb; p.bb_max_redo = s.bb_max_redo;
+    p.trsv = (s.lin_solver == ABIP_LIN_TRSV) ? 1 : 0;
     p.max_iters = s.max_admm_iters;
     p.fp32_max_iters = (s.precision == ABIP_PREC_FP32_POLISH) ? s.fp32_max_iters : 0;
     p.restart_rule = s.restart_rule;
@@ -553,21 +615,27 @@ static void assign_lds(abip_work* w) {
     const int W = w->threads / 64;
     size_t smem = wg_smem_bytes(w->ldmax, W);
     const size_t cap = (w->lds_cap > 1024) ? (size_t)w->lds_cap - 1024 : 0;   // static LDS of the kernel
-    for (LPDesc& d : w->hdesc) {
+    for (size_t k = 0; k < w->hdesc.size(); ++k) {
+        LPDesc& d = w->hdesc[k];
         d.lds = 0;
         if (!w->set.lds_resident || w->grid || w->sparse || w->threads != 256) continue;
+        if (w->set.lin_solver == ABIP_LIN_TRSV) continue;     // the LDS-resident loop multiplies by G^{-1}
+        if (w->lds_policy == 2 || (k < w->lds_stream.size() && w->lds_stream[k])) continue;
         if (d.m > w->threads || d.n > 2 * w->threads) continue;
         const size_t b32 = (size_t)small_layout(d.m, d.n, 4, W).total;
         const size_t b64 = (size_t)small_layout(d.m, d.n, 8, W).total;
         const size_t a32 = (size_t)small_layout(d.m, d.n, 4, W, true).total;
         const size_t a64 = (size_t)small_layout(d.m, d.n, 8, W, true).total;
+        const bool aonly = w->lds_policy == 0;
         if (b32 <= cap) { d.lds |= DESC_LDS32; smem = std::max(smem, b32); }
-        else if (a32 <= cap) { d.lds |= DESC_LDSA32; smem = std::max(smem, a32); }
+        else if (aonly && a32 <= cap) { d.lds |= DESC_LDSA32; smem = std::max(smem, a32); }
         if (b64 <= cap) { d.lds |= DESC_LDS64; smem = std::max(smem, b64); }
-        else if (a64 <= cap) { d.lds |= DESC_LDSA64; smem = std::max(smem, a64); }
+        else if (aonly && a64 <= cap) { d.lds |= DESC_LDSA64; smem = std::max(smem, a64); }
     }
     w->wg_smem = smem;
 }
+
+static int load_dense(abip_work* w, const abip_matrix* A, const double* const* b, const double* const* c);
 
 // carve: when not null, every device buffer of the handle comes from this
 // region of carve_cap bytes (no hipMalloc) and the handle creates no events or
@@ -604,6 +672,8 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
                                             (s.engine == ABIP_ENGINE_AUTO &&
                                              (M.m > MAX_WG_M || (int64_t)M.m * M.n >= GRID_AUTO_MN)));
         if (want_grid) w->grid = true;
+        if (want_grid && s.bb) { delete w; return fail(ABIP_E_INVALID, "settings.bb: the adaptive beta runs in the one-workgroup engine only (this LP takes the grid engine)"); }
+        if (want_grid && s.lin_solver == ABIP_LIN_TRSV) { delete w; return fail(ABIP_E_INVALID, "settings.lin_solver = ABIP_LIN_TRSV runs in the one-workgroup engine only (this LP takes the grid engine)"); }
         if (want_grid && M.m > MAX_GRID_M) { delete w; return fail(ABIP_E_DIM, "m=%d exceeds the grid engine limit %d", M.m, MAX_GRID_M); }
         if (!want_grid && M.m > MAX_WG_M) { delete w; return fail(ABIP_E_DIM, "LP %d: m=%d exceeds the one-workgroup engine limit %d (use abip_setup for one large LP)", k, M.m, MAX_WG_M); }
         if (!M.val || !b[k] || !c[k]) { delete w; return fail(ABIP_E_INVALID, "LP %d: null data pointer", k); }
@@ -639,24 +709,63 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
         w->rchk_P = std::max(1, std::min(512, (mx + 255) / 256));
     }
     ALLOC(w->rchk, (int64_t)B * w->rchk_P * 8);
-    // scratch for the setup
-    std::vector<int64_t> hoW(B);
-    int64_t wtot = 0;
-    for (int k = 0; k < B; ++k) { hoW[k] = wtot; wtot += (int64_t)w->hdesc[k].ld * w->hdesc[k].ld; }
-    double* Wp = nullptr; int64_t* doW = nullptr;
-    const double** dAp = nullptr; const double** dbp = nullptr; const double** dcp = nullptr;
-    ALLOC(Wp, wtot); ALLOC(doW, B);
-    ALLOC(dAp, B); ALLOC(dbp, B); ALLOC(dcp, B);
+    // scratch for the setup: W = L^{-1} (ld x ld per LP), the inverses of the
+    // 64 x 64 diagonal blocks of L (per LP), the grid border's vectors
+    std::vector<int64_t> hoW(B), hoL(B);
+    int64_t wtot = 0, ltot = 0;
+    int mmax = 0;
+    for (int k = 0; k < B; ++k) {
+        const LPDesc& d = w->hdesc[k];
+        hoW[k] = wtot; wtot += (int64_t)d.ld * d.ld;
+        hoL[k] = ltot; ltot += (int64_t)((d.m + 63) / 64) * 64 * 64;
+        w->hdesc[k].oL = hoL[k];
+        mmax = std::max(mmax, d.m);
+    }
+    const int64_t btot = w->grid ? grid_border_scratch(w->hdesc[0].m, w->hdesc[0].n, w->hdesc[0].ld) : 1;
+    ALLOC(w->suW, wtot); ALLOC(w->suoW, B); ALLOC(w->suL, ltot); ALLOC(w->suoL, B); ALLOC(w->suB, btot);
+    ALLOC(w->suA, B); ALLOC(w->sub, B); ALLOC(w->suc, B);
+    if (s.lin_solver == ABIP_LIN_TRSV) {
+        ALLOC(w->keep.L64, oG); ALLOC(w->keep.Lt64, oG); ALLOC(w->keep.L32, oG); ALLOC(w->keep.Lt32, oG);
+        ALLOC(w->keep.Li64, ltot); ALLOC(w->keep.Lit64, ltot); ALLOC(w->keep.Li32, ltot); ALLOC(w->keep.Lit32, ltot);
+    }
 #undef ALLOC
-    auto cleanup_scratch = [&]() {
-        if (w->noalloc) return;
-        (void)hipFree(Wp); (void)hipFree(doW); (void)hipFree(dAp); (void)hipFree(dbp); (void)hipFree(dcp);
-    };
-    auto bail = [&](int code) { cleanup_scratch(); release(w); delete w; return code; };
+    w->suWtot = wtot;
+    w->mmax = mmax;
     hipStream_t st = w->stream;
-#define SCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return bail(fail(ABIP_E_HIP, "%s: %s", #call, hipGetErrorString(e_))); } while (0)
+    {
+        hipError_t e1 = hipMemcpyAsync(w->suoW, hoW.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, st);
+        hipError_t e2 = hipMemcpyAsync(w->suoL, hoL.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, st);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            release(w); delete w;
+            return fail(ABIP_E_HIP, "hipMemcpyAsync: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        }
+    }
+    rc = load_dense(w, A, b, c);
+    if (rc) { release(w); delete w; return rc; }
+    hipError_t e = w->grid ? grid_set_smem(w->ldmax) : set_solve_wg_smem_limit(w->wg_smem);
+    if (e != hipSuccess) { release(w); delete w; return fail(ABIP_E_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e)); }
+    if (w->grid) {
+        int rc2 = grid_prepare(w);
+        if (rc2) { release(w); delete w; return rc2; }
+    }
+    w->hctrl.resize(B);
+    w->setup_ms = now_ms() - t0;
+    *out = w;
+    return ABIP_OK;
+}
+
+// Load A, b, c of every LP into a dense handle whose buffers exist and run the
+// whole setup on them: copies in both precisions, HSD constants, G = I + A A^T,
+// its factorization and inverse, the border.  No allocation.  Errors leave the
+// handle's data undefined (the caller frees it or loads again).
+static int load_dense(abip_work* w, const abip_matrix* A, const double* const* b, const double* const* c) {
+    const int B = w->B;
+    const int64_t oA = w->Atot, oG = w->Gtot, om = w->Mtot, on = w->Ntot;
+    hipStream_t st = w->stream;
+#define SCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return fail(ABIP_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); } while (0)
     std::vector<const double*> hA(B), hb(B), hc(B);
     for (int k = 0; k < B; ++k) { hA[k] = A[k].val; hb[k] = b[k]; hc[k] = c[k]; }
+    const double** dAp = w->suA; const double** dbp = w->sub; const double** dcp = w->suc;
     SCHK(hipMemsetAsync(w->A64, 0, sizeof(double) * oA, st));
     SCHK(hipMemsetAsync(w->A32, 0, sizeof(float) * oA, st));
     SCHK(hipMemsetAsync(w->G64, 0, sizeof(double) * oG, st));
@@ -665,9 +774,7 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     SCHK(hipMemsetAsync(w->Nv, 0, sizeof(double) * NNF * on, st));
     SCHK(hipMemsetAsync(w->dctrl, 0, sizeof(LPCtrl) * B, st));
     SCHK(hipMemsetAsync(w->errflag, 0, sizeof(int), st));
-    SCHK(hipMemsetAsync(Wp, 0, sizeof(double) * wtot, st));
     SCHK(hipMemcpyAsync(w->ddesc, w->hdesc.data(), sizeof(LPDesc) * B, hipMemcpyHostToDevice, st));
-    SCHK(hipMemcpyAsync(doW, hoW.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, st));
     SCHK(hipMemcpyAsync(dAp, hA.data(), sizeof(double*) * B, hipMemcpyHostToDevice, st));
     SCHK(hipMemcpyAsync(dbp, hb.data(), sizeof(double*) * B, hipMemcpyHostToDevice, st));
     SCHK(hipMemcpyAsync(dcp, hc.data(), sizeof(double*) * B, hipMemcpyHostToDevice, st));
@@ -678,29 +785,42 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
         return (int64_t)w->hdesc[a].m * w->hdesc[a].n > (int64_t)w->hdesc[bb].m * w->hdesc[bb].n;
     });
     SCHK(hipMemcpyAsync(w->order, ord.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, st));
-    int maxtiles = 0, maxrowblk = 0, maxsyrk = 0;
+    int maxtiles = 0, maxrowblk = 0;
     for (auto& d : w->hdesc) {
         maxtiles = std::max(maxtiles, ((d.m + 63) / 64) * ((d.n + 63) / 64));
         maxrowblk = std::max(maxrowblk, (d.ld + 255) / 256);
-        const int nt = (d.m + 63) / 64;
-        maxsyrk = std::max(maxsyrk, nt * (nt + 1) / 2);
     }
     hipLaunchKernelGGL(k_setup_copy, dim3(maxtiles, B), dim3(256), 0, st, w->ddesc, dAp, w->A64, w->A32, w->errflag);
     SCHK(hipGetLastError());
+    // row / column factors of the scaled LP (all 1 unless settings.scale_iters > 0)
+    hipLaunchKernelGGL(k_ruiz_init, dim3(maxrowblk + 1, B), dim3(256), 0, st, w->ddesc, w->Mv, w->Nv, w->Mtot, w->Ntot);
+    SCHK(hipGetLastError());
+    if (w->set.scale_iters > 0) {
+        int nblk = 1;
+        for (auto& d : w->hdesc) nblk = std::max(nblk, (std::max(d.m, d.n) + 255) / 256);
+        for (int t = 0; t < w->set.scale_iters; ++t) {
+            hipLaunchKernelGGL(k_ruiz_max, dim3(maxtiles, B), dim3(256), 0, st, w->ddesc, w->A64, w->Mv, w->Nv,
+                               w->Mtot, w->Ntot);
+            SCHK(hipGetLastError());
+            hipLaunchKernelGGL(k_ruiz_apply, dim3(nblk, B), dim3(256), 0, st, w->ddesc, w->Mv, w->Nv, w->Mtot,
+                               w->Ntot);
+            SCHK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_ruiz_scale, dim3(maxtiles, B), dim3(256), 0, st, w->ddesc, w->A64, w->A32, w->Mv,
+                           w->Nv, w->Mtot, w->Ntot);
+        SCHK(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_setup_rows, dim3(maxrowblk, B), dim3(256), 0, st, w->ddesc, dbp, dcp, w->A64, w->Mv, w->Nv,
                        w->Mtot, w->Ntot, w->errflag);
     SCHK(hipGetLastError());
+    // G = I + A A^T, its Cholesky factor and G^{-1} on the matrix cores (every LP at once)
+    SCHK(factor_ginv(w->ddesc, B, w->mmax, w->A64, w->G64, w->G32, w->suL, w->suoL, w->suW, w->suoW, w->errflag,
+                     w->keep.L64 ? &w->keep : nullptr, st));
     if (w->grid) {
-        // one large LP: library SYRK / POTRF / POTRI and GEMV border
-        const int lrc = lib_setup_one(w->hdesc[0], w->ddesc, w->A64, w->G64, w->G32, w->Mv, w->Nv, w->Mtot,
-                                      w->Ntot, w->dctrl, st);
-        if (lrc == 2) return bail(fail(ABIP_E_HIP, "Cholesky of I + A A^T met a non-positive pivot"));
-        if (lrc) return bail(fail(ABIP_E_HIP, "rocBLAS / rocSOLVER setup of G = I + A A^T failed"));
+        // one large LP: the border's products over the whole GPU
+        SCHK(grid_border(w->hdesc[0], w->ddesc, w->A64, w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, w->dctrl, w->suB,
+                         st));
     } else {
-        hipLaunchKernelGGL(k_syrk, dim3(maxsyrk, B), dim3(256), 0, st, w->ddesc, w->A64, w->G64);
-        SCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_chol_inv, dim3(B), dim3(256), 0, st, w->ddesc, w->G64, w->G32, Wp, doW, w->errflag);
-        SCHK(hipGetLastError());
         for (int sgn = 1; sgn >= -1; sgn -= 2) {
             hipLaunchKernelGGL(k_setup_border, dim3(B), dim3(512), sizeof(double) * 2 * w->ldmax, st, w->ddesc,
                                w->A64, w->G64, w->Mv, w->Nv, w->Mtot, w->Ntot, w->dctrl, sgn);
@@ -711,18 +831,9 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     SCHK(hipMemcpyAsync(&hflag, w->errflag, sizeof(int), hipMemcpyDeviceToHost, st));
     SCHK(hipStreamSynchronize(st));
 #undef SCHK
-    cleanup_scratch();
-    if (hflag & 3) { release(w); delete w; return fail(ABIP_E_NONFINITE, "NaN or Inf in %s", (hflag & 1) ? "A" : "b or c"); }
-    if (hflag & 4) { release(w); delete w; return fail(ABIP_E_HIP, "Cholesky of I + A A^T met a non-positive pivot"); }
-    hipError_t e = w->grid ? grid_set_smem(w->ldmax) : set_solve_wg_smem_limit(w->wg_smem);
-    if (e != hipSuccess) { release(w); delete w; return fail(ABIP_E_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e)); }
-    if (w->grid) {
-        int rc2 = grid_prepare(w);
-        if (rc2) { release(w); delete w; return rc2; }
-    }
-    w->hctrl.resize(B);
-    w->setup_ms = now_ms() - t0;
-    *out = w;
+    if (hflag & 3) return fail(ABIP_E_NONFINITE, "NaN or Inf in %s", (hflag & 1) ? "A" : "b or c");
+    if (hflag & 4) return fail(ABIP_E_HIP, "Cholesky of I + A A^T met a non-positive pivot");
+    w->solved = false;
     return ABIP_OK;
 }
 
@@ -776,6 +887,9 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     if (!A->rowptr || (nnz > 0 && (!A->colidx || !A->val)) || !b || !c)
         return fail(ABIP_E_INVALID, "CSR: null rowptr / colidx / val / b / c");
     if (!(s.cg_tol > 0.0) || s.cg_max_iters < 1) return fail(ABIP_E_INVALID, "settings: cg_tol > 0 and cg_max_iters >= 1 required");
+    if (s.bb) return fail(ABIP_E_INVALID, "settings.bb: the adaptive beta runs in the one-workgroup engine only (CSR input takes the sparse engine)");
+    if (s.scale_iters) return fail(ABIP_E_INVALID, "settings.scale_iters: scaling is implemented for dense A only");
+    if (s.lin_solver == ABIP_LIN_TRSV) return fail(ABIP_E_INVALID, "settings.lin_solver = ABIP_LIN_TRSV needs dense A");
     const double t0 = now_ms();
     abip_work* w = new abip_work();
     w->B = 1;
@@ -785,7 +899,7 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     w->sparse = true;
     w->hdesc.resize(1);
     LPDesc& d = w->hdesc[0];
-    d.m = m; d.n = n; d.ld = (m + 3) & ~3; d.lds = 0; d.oA = 0; d.oG = 0; d.om = 0; d.on = 0;
+    d.m = m; d.n = n; d.ld = (m + 3) & ~3; d.lds = 0; d.oA = 0; d.oG = 0; d.om = 0; d.on = 0; d.oL = 0;
     w->ldmax = d.ld;
     w->Mtot = d.ld;
     w->Ntot = (n + 4) & ~3;
@@ -856,6 +970,11 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     SCHK(hipMemsetAsync(w->sp_bar, 0, 2 * sizeof(unsigned), st));
     SCHK(hipMemsetAsync(w->sp_err, 0, sizeof(int), st));
     SCHK(hipMemcpyAsync(w->ddesc, &d, sizeof d, hipMemcpyHostToDevice, st));
+    // scaling factors D = E = 1 (a CSR LP is not scaled): the output and recheck
+    // kernels apply them
+    hipLaunchKernelGGL(k_ruiz_init, dim3((std::max(d.ld, n) + 255) / 256, 1), dim3(256), 0, st, w->ddesc, w->Mv, w->Nv,
+                       w->Mtot, w->Ntot);
+    SCHK(hipGetLastError());
     SCHK(hipMemcpyAsync(rp, A->rowptr, sizeof(int32_t) * (size_t)(m + 1), hipMemcpyDeviceToDevice, st));
     if (nnz > 0) {
         SCHK(hipMemcpyAsync(ci, A->colidx, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, st));
@@ -1010,10 +1129,32 @@ extern "C" int abip_setup_batch(abip_work** out, int32_t B, const abip_matrix* A
     return setup_dense(out, B, A, b, c, settings, stream);
 }
 
+extern "C" int abip_update_data(abip_work* w, const abip_matrix* A, const double* const* b,
+                                const double* const* c) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_update_data: null handle");
+    if (w->sparse) return fail(ABIP_E_STATE, "abip_update_data: dense handles only");
+    if (!A || !b || !c) return fail(ABIP_E_INVALID, "abip_update_data: null A, b or c");
+    for (int k = 0; k < w->B; ++k) {
+        const abip_matrix& M = A[k];
+        if (M.format != ABIP_DENSE_ROWMAJOR) return fail(ABIP_E_INVALID, "LP %d: dense row-major A only", k);
+        if (M.m != w->hdesc[k].m || M.n != w->hdesc[k].n)
+            return fail(ABIP_E_DIM, "LP %d: %d x %d does not match the handle's %d x %d", k, M.m, M.n,
+                        w->hdesc[k].m, w->hdesc[k].n);
+        if (!M.val || !b[k] || !c[k]) return fail(ABIP_E_INVALID, "LP %d: null data pointer", k);
+    }
+    const double t0 = now_ms();
+    const int rc = load_dense(w, A, b, c);
+    if (rc) return rc;
+    w->setup_ms = now_ms() - t0;
+    return ABIP_OK;
+}
+
 static PoolPtrs pools(abip_work* w) {
     PoolPtrs P;
     P.A64 = w->A64; P.A32 = w->A32; P.G64 = w->G64; P.G32 = w->G32;
     P.Mv = w->Mv; P.Nv = w->Nv; P.Mtot = w->Mtot; P.Ntot = w->Ntot;
+    P.L64 = w->keep.L64; P.Lt64 = w->keep.Lt64; P.L32 = w->keep.L32; P.Lt32 = w->keep.Lt32;
+    P.Li64 = w->keep.Li64; P.Lit64 = w->keep.Lit64; P.Li32 = w->keep.Li32; P.Lit32 = w->keep.Lit32;
     return P;
 }
 
@@ -1034,9 +1175,9 @@ static int run_wg(abip_work* w, int32_t B, int64_t fixed_iters, const SolveParam
         // queue reset + the persistent launch as one graph, kept with the handle
         int rc = graph_stream(w);
         if (rc) return rc;
-        struct Key { SolveParams p; int threads, grid; } key;
+        struct Key { SolveParams p; int threads, grid; size_t smem; } key;
         memset(&key, 0, sizeof key);          // padding bytes take part in the comparison
-        key.p = prm; key.threads = w->threads; key.grid = grid;
+        key.p = prm; key.threads = w->threads; key.grid = grid; key.smem = w->wg_smem;
         const PoolPtrs P = pools(w);
         rc = capture_graph(w, &w->wgraph, &w->wexec, &w->wkey, key_bytes(key, B), [&](hipStream_t cs) {
             hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, cs, w->queue);
@@ -1073,6 +1214,9 @@ static void fill_info(abip_info* info, const LPCtrl& c, const LPDesc& d, double 
     info->lds_mode = d.lds;
     info->fp32_exit_kkt = c.kfx;
     info->err_vs_fp64 = c.err64;
+    info->beta = c.beta;
+    info->bb_probe_iters = c.bbp;
+    info->bb_estimates = c.bbe;
     info->ticks_colpass = c.clk[0];
     info->ticks_ginv = c.clk[1];
     info->ticks_total = c.clk[2];
@@ -1099,7 +1243,7 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
     const SolveParams prm = make_params(w->set);
     const int phase = (w->set.precision == ABIP_PREC_FP32_POLISH) ? 0 : 1;
     hipLaunchKernelGGL(k_init_state, dim3(w->B), dim3(256), 0, st, w->ddesc, w->dctrl, w->Mv, w->Nv, w->Mtot, w->Ntot,
-                       w->set.beta, phase);
+                       w->set.beta, phase, w->set.bb);
     HIPCHK(hipGetLastError());
     int rc = w->sparse ? sparse_run(w, 0) : w->grid ? grid_run(w, 0, phase) : run_wg(w, w->B, 0, prm);
     if (rc) return rc;
@@ -1150,6 +1294,7 @@ extern "C" int abip_solve_batch(abip_work* w, double* const* x, double* const* y
 static int backward_all(abip_work* w, const double* const* g, double* const* dc, double* const* db,
                         double* const* dA) {
     if (w->sparse) return fail(ABIP_E_STATE, "abip_backward: dense handles only");
+    if (w->set.scale_iters) return fail(ABIP_E_STATE, "abip_backward: not available for a scaled LP (settings.scale_iters)");
     if (!w->solved) return fail(ABIP_E_STATE, "abip_backward: call abip_solve first");
     for (int k = 0; k < w->B; ++k) {
         if (!g || !g[k] || !dc || !dc[k] || !db || !db[k])
@@ -1261,6 +1406,7 @@ extern "C" int abip_set_state(abip_work* w, int32_t k, const double* y, const do
     HIPCHK(hipStreamSynchronize(w->stream));
     c.tau = tau; c.kappa = kappa; c.theta = theta; c.mu = mu;
     c.status = 0; c.mode = OP_REFRESH; c.flags = 4;     // 4: loaded iterate, may be differentiated
+    c.beta = w->set.beta; c.bbp = 0; c.bbe = 0;        // abip_iterate runs at the settings' beta
     if (w->sparse) {
         HIPCHK(hipMemsetAsync(w->sa.a, 0, sizeof(double) * (size_t)w->sa.m, w->stream));
         HIPCHK(hipMemsetAsync(w->sa.ATA, 0, sizeof(double) * (size_t)w->sa.n, w->stream));
@@ -1328,13 +1474,24 @@ extern "C" int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_
 }
 
 // Launch-configuration autotuner: every candidate runs `iters` updates from
-// Algorithm 2's start point (fixed-iteration mode, no tests), timed with HIP
-// events on the work stream; the fastest is kept and the iterate is reset.
+// Algorithm 2's start point (fixed-iteration mode, no tests); the best is kept
+// and the iterate is reset.  Grid and sparse engines (one LP): the launch time
+// (HIP events on the work stream).  One-workgroup engine: the LDS policies (A
+// and G^{-1} or A alone resident, only A and G^{-1}, everything streamed) at
+// 256 threads, 512 streamed threads when every LP fits the 512-thread build,
+// then a per-LP mix that streams the LPs whose own clock ran faster streamed
+// than resident; scored by the sum of the LPs' own clocks, since a batch's
+// throughput depends on every LP's time per update while a fixed-iteration
+// launch lasts as long as its largest LP alone.
 extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t max_cand, int32_t* ncand,
                              int32_t* chosen) {
     if (!w) return fail(ABIP_E_INVALID, "abip_autotune: null handle");
     if (iters < 1) return fail(ABIP_E_INVALID, "abip_autotune: iters must be >= 1");
+    if (w->noalloc) return fail(ABIP_E_STATE, "abip_autotune: not available on an allocation-free handle");
+    struct WgCand { int threads, policy; bool mix; };
     std::vector<int> cand;
+    std::vector<WgCand> wc;
+    const bool wgeng = !w->sparse && !w->grid;
     if (w->sparse) {
         const int maxb = std::min(sp_max_blocks(w->cu_count, 0), 4 * w->cu_count);
         cand.push_back(std::min(w->sp_nb_default, maxb));
@@ -1343,16 +1500,30 @@ extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t ma
     } else if (w->grid) {
         for (int f : {1, 2, 4, 8}) cand.push_back(w->cu_count * f / 2);
     } else {
-        cand.push_back(256);
-        if (w->nch == 1) cand.push_back(512);
+        wc.push_back({256, 0, false});
+        if (w->set.lds_resident) {
+            wc.push_back({256, 1, false});
+            wc.push_back({256, 2, false});
+        }
+        if (w->nch == 1) wc.push_back({512, 2, false});
+        if (w->set.lds_resident) wc.push_back({256, 0, true});
+        for (size_t i = 0; i < wc.size(); ++i) cand.push_back((int)i);
     }
     const int phase = (w->set.precision == ABIP_PREC_FP32_POLISH && !w->sparse) ? 0 : 1;
     const SolveParams prm = make_params(w->set);
     hipStream_t st = w->stream;
+    const int B = w->B;
+    // per-LP clocks of the all-resident (candidate 0) and all-streamed (candidate 2) runs
+    std::vector<int64_t> tk_res(B, 0), tk_str(B, 0);
     auto configure = [&](int c) -> int {
         if (w->sparse) { w->sp_nb = c; return ABIP_OK; }
         if (w->grid) { grid_config(w, c); return ABIP_OK; }
-        w->threads = c;
+        const WgCand& C = wc[c];
+        w->threads = C.threads;
+        w->lds_policy = C.policy;
+        w->lds_stream.assign(B, 0);
+        if (C.mix)
+            for (int k = 0; k < B; ++k) w->lds_stream[k] = (tk_str[k] > 0 && tk_str[k] < tk_res[k]) ? 1 : 0;
         assign_lds(w);
         HIPCHK(hipMemcpyAsync(w->ddesc, w->hdesc.data(), sizeof(LPDesc) * w->B, hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1362,7 +1533,7 @@ extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t ma
     };
     auto reset = [&]() -> int {
         hipLaunchKernelGGL(k_init_state, dim3(w->B), dim3(256), 0, st, w->ddesc, w->dctrl, w->Mv, w->Nv, w->Mtot,
-                           w->Ntot, w->set.beta, phase);
+                           w->Ntot, w->set.beta, phase, 0);
         HIPCHK(hipGetLastError());
         return ABIP_OK;
     };
@@ -1378,8 +1549,18 @@ extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t ma
         HIPCHK(hipStreamSynchronize(st));
         float t = 0.0f;
         HIPCHK(hipEventElapsedTime(&t, w->ev0, w->ev1));
-        if (ms && (int32_t)i < max_cand) ms[i] = t;
-        if (t < best) { best = t; bi = (int)i; }
+        double score = t;
+        if (wgeng) {
+            w->hctrl.resize(B);
+            HIPCHK(hipMemcpy(w->hctrl.data(), w->dctrl, sizeof(LPCtrl) * B, hipMemcpyDeviceToHost));
+            int64_t sum = 0;
+            for (int k = 0; k < B; ++k) sum += w->hctrl[k].clk[2];
+            score = (double)sum / 1e5;           // 100 MHz ticks -> ms
+            if (i == 0 || (wc[i].policy == 2 && wc[i].threads == 256 && !wc[i].mix))
+                for (int k = 0; k < B; ++k) (i == 0 ? tk_res : tk_str)[k] = w->hctrl[k].clk[2];
+        }
+        if (ms && (int32_t)i < max_cand) ms[i] = score;
+        if (score < best) { best = score; bi = (int)i; }
     }
     int rc = configure(cand[bi]);
     if (rc) return rc;
@@ -1389,6 +1570,21 @@ extern "C" int abip_autotune(abip_work* w, int64_t iters, double* ms, int32_t ma
     w->solved = false;
     if (ncand) *ncand = (int32_t)cand.size();
     if (chosen) *chosen = cand[bi];
+    return ABIP_OK;
+}
+
+// The row / column factors of LP k's scaling (device outputs D[m], E[n]; all 1
+// when the LP is not scaled).
+extern "C" int abip_get_scaling(abip_work* w, int32_t k, double* D, double* E) {
+    if (!w) return fail(ABIP_E_INVALID, "abip_get_scaling: null handle");
+    if (k < 0 || k >= w->B) return fail(ABIP_E_INVALID, "abip_get_scaling: LP index %d out of range", k);
+    if (w->sparse) return fail(ABIP_E_STATE, "abip_get_scaling: dense handles only");
+    const LPDesc& d = w->hdesc[k];
+    if (D) HIPCHK(hipMemcpyAsync(D, w->Mv + MF_SD * w->Mtot + d.om, sizeof(double) * d.m, hipMemcpyDeviceToDevice,
+                                 w->stream));
+    if (E) HIPCHK(hipMemcpyAsync(E, w->Nv + NF_SE * w->Ntot + d.on, sizeof(double) * d.n, hipMemcpyDeviceToDevice,
+                                 w->stream));
+    HIPCHK(hipStreamSynchronize(w->stream));
     return ABIP_OK;
 }
 
@@ -1407,7 +1603,7 @@ extern "C" int abip_free(abip_work* w) {
 // precisions, G^{-1}, the border, the iterate, the control block, the setup's
 // Cholesky workspace, the recheck's partial sums) is carved out of this
 // file-scope array; each GPU the library runs on holds its own copy until the
-// process ends.  The largest LP (m = 256, n = 1024) takes about 4.4 MiB.
+// process ends.  The largest LP (m = 256, n = 1024) takes about 4.5 MiB.
 static const size_t NOALLOC_BYTES = (size_t)5 << 20;
 static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
 static const int NOALLOC_MAX_DEV = 64;

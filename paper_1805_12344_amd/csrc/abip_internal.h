@@ -15,9 +15,15 @@
 #define ABIP_WAVE 64
 
 // m-vector fields
-enum { MF_B = 0, MF_BBAR, MF_AC, MF_ACBAR, MF_ZY0, MF_ZY1, MF_Y, MF_ZY0A, MF_ZY1A, NMF };
+// (MF_BBY0 / MF_BBY1, NF_BBX0 ... NF_BBS1: the adaptive beta's copies of the
+// iterate at the start of an outer iteration and after its first probe)
+// MF_SD / NF_SE: the row / column factors D, E of the scaled LP (D A E, D b, E c)
+// (all 1 when the LP is not scaled); during the setup MF_BBY0 / NF_BBX0 hold the
+// row / column maxima of the scaling rounds.
+enum { MF_B = 0, MF_BBAR, MF_AC, MF_ACBAR, MF_ZY0, MF_ZY1, MF_Y, MF_ZY0A, MF_ZY1A, MF_BBY0, MF_BBY1, MF_SD, NMF };
 // n-vector fields
-enum { NF_C = 0, NF_CBAR, NF_ZX0, NF_ZX1, NF_X, NF_S, NF_ZX0A, NF_ZX1A, NNF };
+enum { NF_C = 0, NF_CBAR, NF_ZX0, NF_ZX1, NF_X, NF_S, NF_ZX0A, NF_ZX1A, NF_BBX0, NF_BBS0, NF_BBX1, NF_BBS1, NF_SE,
+       NNF };
 
 // column-pass operations
 enum { OP_REFRESH = 0, OP_PROX = 1, OP_RESTART = 2 };
@@ -31,6 +37,7 @@ struct LPDesc {
     int64_t oG;     // element offset of G^{-1} (ld*m)
     int64_t om;     // offset in each m-field (slice length ld)
     int64_t on;     // offset in each n-field (slice length n)
+    int64_t oL;     // offset of the LP's 64 x 64 diagonal-block inverses of L (triangular-solve path)
 };
 
 // Per-LP scalars kept in device memory between launches.
@@ -51,9 +58,21 @@ struct LPCtrl {
     double kfx;                           // relative KKT of the FP32 phase's last iterate, measured
                                           // with FP64 data at the handover (NaN: no handover)
     double err64;                         // FP64 recheck of the returned point (after the solve)
+    double beta;                          // the current outer iteration's beta (Section 4.3)
+    double bbs[6];                        // tau, kappa, theta at the outer iteration's start and
+                                          // after its first probe (adaptive beta)
+    int64_t bbp;                          // of iters: probe iterations of the beta estimates
     int32_t status, phase, mode, flags;  // phase 0 = FP32 bulk, 1 = FP64; mode = next op
                                           // flags: 1 test the loaded state first, 4 loaded iterate,
-                                          // 8 the next FP64 check measures the FP32 exit (kfx)
+                                          // 8 the next FP64 check measures the FP32 exit (kfx),
+                                          // 16 an outer iteration starts: choose its beta first
+    int32_t bbe, pad_;                    // beta estimates taken
+};
+
+// Where the factorization leaves L for the triangular-solve path (see PoolPtrs).
+struct FactorKeep {
+    double* L64; double* Lt64; float* L32; float* Lt32;
+    double* Li64; double* Lit64; float* Li32; float* Lit32;
 };
 
 // Solver parameters passed by value to kernels.
@@ -61,6 +80,9 @@ struct SolveParams {
     double eps, alpha, beta, gamma;
     int64_t max_iters, fp32_max_iters;
     int32_t restart_rule, precision;
+    double eps_cor, eps_pen;              // Section 4.3 safeguards
+    int32_t bb, bb_max_redo;              // adaptive beta on / most redos per outer iteration
+    int32_t trsv, pad_;                   // the linear step by triangular solves with L
 };
 
 struct PoolPtrs {
@@ -68,6 +90,11 @@ struct PoolPtrs {
     const double* G64; const float* G32;
     double* Mv; double* Nv;
     int64_t Mtot, Ntot;
+    // triangular-solve path (ABIP_LIN_TRSV): L and L^T (column-major, ld x m, at
+    // oG like G^{-1}), the inverses of L's diagonal blocks and their transposes
+    // (64 x 64 column-major each, at oL); null otherwise
+    const double* L64; const double* Lt64; const float* L32; const float* Lt32;
+    const double* Li64; const double* Lit64; const float* Li32; const float* Lit32;
 };
 
 // LDS layout of the LDS-resident variant of the one-workgroup solve (byte
@@ -110,6 +137,55 @@ __host__ __device__ inline SmallLayout small_layout(int m, int n, int esize, int
 // and G^{-1} in LDS (DESC_LDS32 / 64), or with A alone in LDS and G^{-1} read
 // from the pool (DESC_LDSA32 / 64)
 enum { DESC_LDS32 = 1, DESC_LDS64 = 2, DESC_LDSA32 = 4, DESC_LDSA64 = 8 };
+
+// ---- adaptive beta (Section 4.3) --------------------------------------------
+// Each outer iteration that starts with ||Q u - v||^2 > mu takes two probe
+// iterations from its initial point (u0, v0) with the current beta and estimates
+// a new beta from the curvature pairs of the three iterates.  With the dual
+// update v_k = v_{k-1} - uh_k + u_k, the paper's v-hat of iteration k equals
+// v_k - (1 - alpha) u_k, so per component, with du2 = u2 - u1, dv2 = v2 - v1,
+// dv1 = v1 - v0, the differences of the estimate are
+//   dvh = dv2 - (1 - alpha) du2,  dut = du2 - dv2 + dv1,  du = -du2
+// (v's y block is 0 and its theta entry -(n+1) at every iterate).
+// q = (dvh.dvh, dvh.dut, dut.dut, dvh.du, du.du).
+__device__ __forceinline__ void bb_acc(double du2, double dv2, double dv1, double alpha, double (&q)[5]) {
+    const double vh = dv2 - (1.0 - alpha) * du2;
+    const double ut = du2 - dv2 + dv1;
+    const double du = -du2;
+    q[0] = fma(vh, vh, q[0]);
+    q[1] = fma(vh, ut, q[1]);
+    q[2] = fma(ut, ut, q[2]);
+    q[3] = fma(vh, du, q[3]);
+    q[4] = fma(du, du, q[4]);
+}
+// the hybrid of the steepest-descent and minimum-gradient steps
+__device__ __forceinline__ double bb_hybrid(double sd, double mg) { return (2.0 * mg > sd) ? mg : sd - 0.5 * mg; }
+// The estimate: each pair whose correlation exceeds eps_cor gives a hybrid
+// step; both reliable: their geometric mean; none: beta itself.
+__device__ inline double bb_hat(const double (&q)[5], double beta, double eps_cor) {
+    const double nv = sqrt(q[0]), nt = sqrt(q[2]), nu = sqrt(q[4]);
+    const double phic = (nv > 0.0 && nt > 0.0) ? q[1] / (nv * nt) : 0.0;
+    const double psic = (nv > 0.0 && nu > 0.0) ? q[3] / (nv * nu) : 0.0;
+    const bool hp = phic > eps_cor, hs = psic > eps_cor;
+    const double phi = hp ? bb_hybrid(q[0] / q[1], q[1] / q[2]) : 0.0;
+    const double psi = hs ? bb_hybrid(q[0] / q[3], q[3] / q[4]) : 0.0;
+    if (hp && hs) return sqrt(phi * psi);
+    if (hp) return phi;
+    if (hs) return psi;
+    return beta;
+}
+// The selection heuristic after estimate number est (1-based): keep beta when
+// the estimate equals it, take the average when they are within eps_pen, else
+// redo the probes from the same initial point with beta = the estimate (a
+// non-positive or non-finite estimate keeps beta; after max_redo redos the last
+// estimate is taken).  Returns true when beta is final for this outer iteration.
+__device__ inline bool bb_choose(double& beta, double hat, double eps_pen, int est, int max_redo) {
+    if (hat == beta) return true;
+    if (fabs(hat - beta) <= eps_pen) { beta = 0.5 * (beta + hat); return true; }
+    if (!(hat > 0.0) || !isfinite(hat)) return true;
+    beta = hat;
+    return est >= max_redo + 1;
+}
 
 // Positive root of z^2 - w z - t = 0, cancellation free for w < 0
 // (closed form of the barrier prox, eqs. Simple-Update:Barrier-X/-tau).

@@ -10,11 +10,14 @@
 //                        (the certificate test of Section 4.1 passes when <= eps)
 //   DUAL_INFEASIBLE:     ||A xc|| ||c|| with xc = -x/(c^T x)
 // The result goes to LPCtrl.err64.  Partial sums are written per workgroup and
-// added in a fixed order, so the value is reproducible.
+// added in a fixed order, so the value is reproducible.  A scaled LP (pools
+// holding D A E, D b, E c and the iterate of that LP) is measured as the LP the
+// caller gave: row residuals times 1/D_i, column residuals times 1/E_j, and the
+// norms of the given b and c (c^T x and b^T y do not change under the scaling).
 #include <hip/hip_runtime.h>
 #include "abip_internal.h"
 
-enum { RC_PR2 = 0, RC_DR2, RC_CX, RC_BY, RC_AX2, RC_ATS2, RC_N = 8 };
+enum { RC_PR2 = 0, RC_DR2, RC_CX, RC_BY, RC_AX2, RC_ATS2, RC_B2, RC_C2, RC_N = 8 };
 
 // Per-workgroup sums for LP blockIdx.y, share blockIdx.x of P: rows
 // [r0, r1) (one thread per row, coalesced down the column-major columns) and
@@ -34,6 +37,8 @@ __global__ __launch_bounds__(256) void k_recheck_dense(const LPDesc* __restrict_
     const double* c = Nv + NF_C * Ntot + d.on;
     const double* x = Nv + NF_X * Ntot + d.on;
     const double* s = Nv + NF_S * Ntot + d.on;
+    const double* Dv = Mv + MF_SD * Mtot + d.om;
+    const double* Ev = Nv + NF_SE * Ntot + d.on;
     const double it = (tau > 0.0) ? 1.0 / tau : 0.0;
     double v[RC_N] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int rpb = (m + P - 1) / P, cpb = (n + P - 1) / P;
@@ -41,10 +46,13 @@ __global__ __launch_bounds__(256) void k_recheck_dense(const LPDesc* __restrict_
     for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
         double ax = 0.0;
         for (int j = 0; j < n; ++j) ax = fma(A[(int64_t)j * ld + i], x[j], ax);
-        const double r = ax * it - b[i];
+        const double wi = 1.0 / Dv[i];
+        const double r = (ax * it - b[i]) * wi;
+        const double axw = ax * wi, bw = b[i] * wi;
         v[RC_PR2] = fma(r, r, v[RC_PR2]);
-        v[RC_AX2] = fma(ax, ax, v[RC_AX2]);
+        v[RC_AX2] = fma(axw, axw, v[RC_AX2]);
         v[RC_BY] = fma(b[i], y[i], v[RC_BY]);
+        v[RC_B2] = fma(bw, bw, v[RC_B2]);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
     const int c0 = p * cpb, c1 = min(n, c0 + cpb);
@@ -53,11 +61,13 @@ __global__ __launch_bounds__(256) void k_recheck_dense(const LPDesc* __restrict_
         for (int i = lane; i < m; i += 64) aty = fma(A[(int64_t)j * ld + i], y[i], aty);
         aty = wave_sum(aty);
         if (lane == 0) {
-            const double r = (aty + s[j]) * it - c[j];
-            const double q = aty + s[j];
+            const double wj = 1.0 / Ev[j];
+            const double r = ((aty + s[j]) * it - c[j]) * wj;
+            const double q = (aty + s[j]) * wj, cw = c[j] * wj;
             v[RC_DR2] = fma(r, r, v[RC_DR2]);
             v[RC_ATS2] = fma(q, q, v[RC_ATS2]);
             v[RC_CX] = fma(c[j], x[j], v[RC_CX]);
+            v[RC_C2] = fma(cw, cw, v[RC_C2]);
         }
     }
     block_sum_n<RC_N>(v, sbuf);
@@ -88,6 +98,7 @@ __global__ __launch_bounds__(256) void k_recheck_csr(const int32_t* __restrict__
         v[RC_PR2] = fma(r, r, v[RC_PR2]);
         v[RC_AX2] = fma(ax, ax, v[RC_AX2]);
         v[RC_BY] = fma(b[i], y[i], v[RC_BY]);
+        v[RC_B2] = fma(b[i], b[i], v[RC_B2]);
     }
     const int c0 = p * cpb, c1 = min(n, c0 + cpb);
     for (int j = c0 + (int)threadIdx.x; j < c1; j += blockDim.x) {
@@ -98,6 +109,7 @@ __global__ __launch_bounds__(256) void k_recheck_csr(const int32_t* __restrict__
         v[RC_DR2] = fma(r, r, v[RC_DR2]);
         v[RC_ATS2] = fma(q, q, v[RC_ATS2]);
         v[RC_CX] = fma(c[j], x[j], v[RC_CX]);
+        v[RC_C2] = fma(c[j], c[j], v[RC_C2]);
     }
     block_sum_n<RC_N>(v, sbuf);
     if (threadIdx.x == 0)
@@ -112,7 +124,7 @@ __global__ void k_recheck_fin(LPCtrl* __restrict__ ctrl, const double* __restric
     for (int p = 0; p < P; ++p)
         for (int q = 0; q < RC_N; ++q) t[q] += part[((int64_t)k * P + p) * RC_N + q];
     LPCtrl& c = ctrl[k];
-    const double tau = c.tau, nb = c.nb, nc = c.nc;
+    const double tau = c.tau, nb = sqrt(t[RC_B2]), nc = sqrt(t[RC_C2]);
     double e = __builtin_nan("");
     if (c.status == 2) {
         const double by = t[RC_BY];

@@ -48,6 +48,111 @@ __global__ __launch_bounds__(256) void k_setup_copy(const LPDesc* __restrict__ d
 }
 
 // ---------------------------------------------------------------------------
+// Ruiz equilibration (the scaling that Section 4.5's remark adds after the
+// presolve): rounds of D_i *= 1/sqrt(max_j |(D_i a_ij) E_j|),
+// E_j *= 1/sqrt(max_i |(D_i a_ij) E_j|), both maxima taken from the same
+// matrix (a zero row or column keeps its factor); then A <- (D_i a_ij) E_j.
+// A64 keeps the original entries until the last kernel.  The maxima of a round
+// are kept as the bit patterns of non-negative doubles (ordered like their
+// values) in the m / n scratch fields rmax / cmax, which start at 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ruiz_init(const LPDesc* __restrict__ desc, double* __restrict__ Mv,
+                                                   double* __restrict__ Nv, int64_t Mtot, int64_t Ntot) {
+    const LPDesc d = desc[blockIdx.y];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.ld; i += gridDim.x * blockDim.x)
+        Mv[MF_SD * Mtot + d.om + i] = 1.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x)
+        Nv[NF_SE * Ntot + d.on + j] = 1.0;
+}
+
+// Row and column maxima of one 64 x 64 tile (grid: tiles, B).
+__global__ __launch_bounds__(256) void k_ruiz_max(const LPDesc* __restrict__ desc, const double* __restrict__ A64,
+                                                  double* __restrict__ Mv, double* __restrict__ Nv, int64_t Mtot,
+                                                  int64_t Ntot) {
+    const int k = blockIdx.y;
+    const LPDesc d = desc[k];
+    const int tr = (d.m + 63) / 64, tc = (d.n + 63) / 64;
+    const int tile = blockIdx.x;
+    if (tile >= tr * tc) return;
+    const int ti = tile / tc, tj = tile % tc;
+    __shared__ double rm[4][64], cm[4][64];
+    const double* Dv = Mv + MF_SD * Mtot + d.om;
+    const double* Ev = Nv + NF_SE * Ntot + d.on;
+    unsigned long long* rmax = reinterpret_cast<unsigned long long*>(Mv + MF_BBY0 * Mtot + d.om);
+    unsigned long long* cmax = reinterpret_cast<unsigned long long*>(Nv + NF_BBX0 * Ntot + d.on);
+    // thread (r = tid & 63, q = tid >> 6): row ti*64 + r (lanes down a column,
+    // coalesced), columns q, q+4, ... of the tile
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = ti * 64 + r;
+    const double di = (i < d.m) ? Dv[i] : 0.0;
+    double rowm = 0.0;
+    for (int c = q; c < 64; c += 4) {
+        const int j = tj * 64 + c;
+        double v = 0.0;
+        if (i < d.m && j < d.n) v = fabs((di * A64[d.oA + (int64_t)j * d.ld + i]) * Ev[j]);
+        rowm = fmax(rowm, v);
+        // column maxima: this wave's 64 rows of column c
+        double cv = v;
+        for (int off = 32; off >= 1; off >>= 1) cv = fmax(cv, __shfl_xor(cv, off));
+        if (r == 0) cm[q][c >> 2] = cv;
+    }
+    rm[q][r] = rowm;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int ii = ti * 64 + threadIdx.x;
+        const double v = fmax(fmax(rm[0][threadIdx.x], rm[1][threadIdx.x]), fmax(rm[2][threadIdx.x], rm[3][threadIdx.x]));
+        if (ii < d.m && v > 0.0) atomicMax(rmax + ii, (unsigned long long)__double_as_longlong(v));
+    } else if (threadIdx.x < 128) {
+        const int c = threadIdx.x - 64;
+        const int j = tj * 64 + c;
+        const double v = cm[c & 3][c >> 2];
+        if (j < d.n && v > 0.0) atomicMax(cmax + j, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+// Apply a round's maxima to D and E and clear them for the next round.
+__global__ __launch_bounds__(256) void k_ruiz_apply(const LPDesc* __restrict__ desc, double* __restrict__ Mv,
+                                                    double* __restrict__ Nv, int64_t Mtot, int64_t Ntot) {
+    const LPDesc d = desc[blockIdx.y];
+    double* Dv = Mv + MF_SD * Mtot + d.om;
+    double* Ev = Nv + NF_SE * Ntot + d.on;
+    unsigned long long* rmax = reinterpret_cast<unsigned long long*>(Mv + MF_BBY0 * Mtot + d.om);
+    unsigned long long* cmax = reinterpret_cast<unsigned long long*>(Nv + NF_BBX0 * Ntot + d.on);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += gridDim.x * blockDim.x) {
+        const double v = __longlong_as_double((long long)rmax[i]);
+        if (v > 0.0) Dv[i] = Dv[i] * (1.0 / sqrt(v));
+        rmax[i] = 0ull;
+    }
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
+        const double v = __longlong_as_double((long long)cmax[j]);
+        if (v > 0.0) Ev[j] = Ev[j] * (1.0 / sqrt(v));
+        cmax[j] = 0ull;
+    }
+}
+
+// A <- (D_i a_ij) E_j in both precisions (grid: tiles, B).
+__global__ __launch_bounds__(256) void k_ruiz_scale(const LPDesc* __restrict__ desc, double* __restrict__ A64,
+                                                    float* __restrict__ A32, const double* __restrict__ Mv,
+                                                    const double* __restrict__ Nv, int64_t Mtot, int64_t Ntot) {
+    const LPDesc d = desc[blockIdx.y];
+    const int tr = (d.m + 63) / 64, tc = (d.n + 63) / 64;
+    const int tile = blockIdx.x;
+    if (tile >= tr * tc) return;
+    const int ti = tile / tc, tj = tile % tc;
+    const double* Dv = Mv + MF_SD * Mtot + d.om;
+    const double* Ev = Nv + NF_SE * Ntot + d.on;
+    for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+        const int i = ti * 64 + (e & 63), j = tj * 64 + (e >> 6);
+        if (i < d.m && j < d.n) {
+            const int64_t o = d.oA + (int64_t)j * d.ld + i;
+            const double v = (Dv[i] * A64[o]) * Ev[j];
+            A64[o] = v;
+            A32[o] = (float)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per-row products with the column-major copy: bbar = b - A e, Ac = A c,
 // Acbar = A cbar (eq. bar-b-c-z-re and the border dot trick); copies b, c,
 // cbar into the vector pools.  Grid: (row blocks of 256, B).
@@ -65,9 +170,11 @@ __global__ __launch_bounds__(256) void k_setup_rows(const LPDesc* __restrict__ d
     const double* c = cuser[k];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     // copies of c and cbar: spread over the row blocks
+    // (the LP's scaled c: E_j c_j, with E = 1 when it is not scaled)
+    const double* Ev = Nv + NF_SE * Ntot + d.on;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
-        const double cj = c[j];
-        if (!isfinite(cj)) atomicOr(errflag, 2);
+        if (!isfinite(c[j])) atomicOr(errflag, 2);
+        const double cj = Ev[j] * c[j];
         Nv[NF_C * Ntot + d.on + j] = cj;
         Nv[NF_CBAR * Ntot + d.on + j] = cj - 1.0;
     }
@@ -79,262 +186,17 @@ __global__ __launch_bounds__(256) void k_setup_rows(const LPDesc* __restrict__ d
     double se = 0.0, sc = 0.0, scb = 0.0;
     for (int j = 0; j < d.n; ++j) {
         const double a = A[(int64_t)j * d.ld + i];
-        const double cj = c[j];
+        const double cj = Ev[j] * c[j];
         se += a;
         sc = fma(a, cj, sc);
         scb = fma(a, cj - 1.0, scb);
     }
-    const double bi = b[i];
-    if (!isfinite(bi)) atomicOr(errflag, 2);
+    if (!isfinite(b[i])) atomicOr(errflag, 2);
+    const double bi = Mv[MF_SD * Mtot + d.om + i] * b[i];
     Mv[MF_B * Mtot + d.om + i] = bi;
     Mv[MF_BBAR * Mtot + d.om + i] = bi - se;
     Mv[MF_AC * Mtot + d.om + i] = sc;
     Mv[MF_ACBAR * Mtot + d.om + i] = scb;
-}
-
-// ---------------------------------------------------------------------------
-// G = I + A A^T (FP64).  One 64x64 lower tile per workgroup, 4x4 outputs per
-// thread, K-loop over the n columns of A staged through LDS 16 at a time.
-// Writes both G[i][j] and G[j][i].
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_syrk(const LPDesc* __restrict__ desc, const double* __restrict__ A64,
-                                              double* __restrict__ G64) {
-    const int k = blockIdx.y;
-    const LPDesc d = desc[k];
-    const int nt = (d.m + 63) / 64;
-    const int t = blockIdx.x;
-    if (t >= nt * (nt + 1) / 2) return;
-    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > t) --I;
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    const int J = t - I * (I + 1) / 2;
-    const double* A = A64 + d.oA;
-    double* G = G64 + d.oG;
-    __shared__ double As[16][64];
-    __shared__ double Bs[16][64];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int j0 = 0; j0 < d.n; j0 += 16) {
-        for (int e = threadIdx.x; e < 1024; e += 256) {
-            const int jj = e >> 6, r = e & 63;
-            const int j = j0 + jj;
-            const int ri = I * 64 + r, rj = J * 64 + r;
-            As[jj][r] = (j < d.n && ri < d.ld) ? A[(int64_t)j * d.ld + ri] : 0.0;
-            Bs[jj][r] = (j < d.n && rj < d.ld) ? A[(int64_t)j * d.ld + rj] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int jj = 0; jj < 16; ++jj) {
-            double a[4], b[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) { a[q] = As[jj][ty * 4 + q]; b[q] = Bs[jj][tx * 4 + q]; }
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = I * 64 + ty * 4 + p, j = J * 64 + tx * 4 + q;
-            if (i < d.m && j < d.m && j <= i) {
-                const double v = acc[p][q] + (i == j ? 1.0 : 0.0);
-                G[(int64_t)i * d.ld + j] = v;
-                G[(int64_t)j * d.ld + i] = v;
-            }
-        }
-}
-
-// ---------------------------------------------------------------------------
-// In-place G -> G^{-1} for one LP per workgroup (FP64):
-//   blocked right-looking Cholesky G = L L^T (panel 32), W = L^{-1} by blocked
-//   forward substitution (the diagonal blocks come from the panel step), and
-//   G^{-1} = W^T W.  Writes G^{-1} in full into G64 and its FP32 copy into G32.
-// W is an ld x ld scratch per LP (offset oW).
-// ---------------------------------------------------------------------------
-#define CB 32
-
-__device__ __forceinline__ double gload(const double* M, int ld, int n, int i, int j) {
-    return (i < n && j < n) ? M[(int64_t)i * ld + j] : 0.0;
-}
-
-__global__ __launch_bounds__(256) void k_chol_inv(const LPDesc* __restrict__ desc, double* __restrict__ G64,
-                                                  float* __restrict__ G32, double* __restrict__ Wpool,
-                                                  const int64_t* __restrict__ oW, int* __restrict__ errflag) {
-    const int k = blockIdx.x;
-    const LPDesc d = desc[k];
-    const int m = d.m, ld = d.ld;
-    double* G = G64 + d.oG;
-    double* Wm = Wpool + oW[k];
-    const int tid = threadIdx.x;
-    __shared__ double D[CB][CB + 1];
-    __shared__ double Di[CB][CB + 1];
-    __shared__ double P[CB][CB + 1];
-    __shared__ double Q[CB][CB + 1];
-    const int nb = (m + CB - 1) / CB;
-    const int r4 = tid >> 3, c4 = (tid & 7) * 4;   // 32 rows x 8 groups of 4 columns
-
-    for (int kb = 0; kb < nb; ++kb) {
-        const int k0 = kb * CB;
-        const int w = min(CB, m - k0);
-        // (1) diagonal block into LDS
-        for (int e = tid; e < CB * CB; e += 256) {
-            const int r = e / CB, c = e % CB;
-            D[r][c] = (r < w && c < w) ? G[(int64_t)(k0 + r) * ld + k0 + c] : (r == c ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        // (2) unblocked Cholesky of the diagonal block
-        for (int p = 0; p < CB; ++p) {
-            if (tid == 0) {
-                const double v = D[p][p];
-                if (!(v > 0.0)) { atomicOr(errflag, 4); D[p][p] = 1.0; }
-                else D[p][p] = sqrt(v);
-            }
-            __syncthreads();
-            if (tid > p && tid < CB) D[tid][p] /= D[p][p];
-            __syncthreads();
-            for (int e = tid; e < CB * CB; e += 256) {
-                const int i = e / CB, j = e % CB;
-                if (j > p && i >= j) D[i][j] -= D[i][p] * D[j][p];
-            }
-            __syncthreads();
-        }
-        // (3) inverse of the lower-triangular diagonal block, column by column
-        if (tid < CB) {
-            const int j = tid;
-            for (int i = 0; i < CB; ++i) Di[i][j] = 0.0;
-            Di[j][j] = 1.0 / D[j][j];
-            for (int i = j + 1; i < CB; ++i) {
-                double s = 0.0;
-                for (int p = j; p < i; ++p) s = fma(D[i][p], Di[p][j], s);
-                Di[i][j] = -s / D[i][i];
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < CB * CB; e += 256) {
-            const int r = e / CB, c = e % CB;
-            if (r < w && c < w) {
-                G[(int64_t)(k0 + r) * ld + k0 + c] = (c <= r) ? D[r][c] : 0.0;
-                Wm[(int64_t)(k0 + r) * ld + k0 + c] = Di[r][c];
-            }
-        }
-        // (4) panel below the diagonal block: L_ik = G_ik L_kk^{-T}
-        for (int i = k0 + w + tid; i < m; i += 256) {
-            double row[CB];
-#pragma unroll
-            for (int p = 0; p < CB; ++p) row[p] = (p < w) ? G[(int64_t)i * ld + k0 + p] : 0.0;
-#pragma unroll 4
-            for (int c = 0; c < w; ++c) {
-                double s = 0.0;
-                for (int p = 0; p <= c; ++p) s = fma(row[p], Di[c][p], s);
-                G[(int64_t)i * ld + k0 + c] = s;
-            }
-        }
-        __syncthreads();
-        // (5) trailing update of the lower triangle: G_IJ -= L_I L_J^T
-        for (int I = kb + 1; I < nb; ++I) {
-            for (int J = kb + 1; J <= I; ++J) {
-                for (int e = tid; e < CB * CB; e += 256) {
-                    const int r = e / CB, c = e % CB;
-                    P[r][c] = (c < w) ? gload(G, ld, m, I * CB + r, k0 + c) : 0.0;
-                    Q[r][c] = (c < w) ? gload(G, ld, m, J * CB + r, k0 + c) : 0.0;
-                }
-                __syncthreads();
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
-                for (int p = 0; p < CB; ++p) {
-                    const double a = P[r4][p];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] = fma(a, Q[c4 + q][p], acc[q]);
-                }
-                const int i = I * CB + r4;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int j = J * CB + c4 + q;
-                    if (i < m && j < m && j <= i) G[(int64_t)i * ld + j] -= acc[q];
-                }
-                __syncthreads();
-            }
-        }
-    }
-    __syncthreads();
-    // W = L^{-1}: W_IK = -W_II * sum_{J=K}^{I-1} L_IJ W_JK, block column by block column
-    for (int K = 0; K < nb; ++K) {
-        for (int I = K + 1; I < nb; ++I) {
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int J = K; J < I; ++J) {
-                for (int e = tid; e < CB * CB; e += 256) {
-                    const int r = e / CB, c = e % CB;
-                    P[r][c] = gload(G, ld, m, I * CB + r, J * CB + c);       // L_IJ
-                    Q[r][c] = gload(Wm, ld, m, J * CB + r, K * CB + c);      // W_JK
-                }
-                __syncthreads();
-                for (int p = 0; p < CB; ++p) {
-                    const double a = P[r4][p];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] = fma(a, Q[p][c4 + q], acc[q]);
-                }
-                __syncthreads();
-            }
-            for (int e = tid; e < CB * CB; e += 256) {
-                const int r = e / CB, c = e % CB;
-                P[r][c] = gload(Wm, ld, m, I * CB + r, I * CB + c);          // W_II
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) Q[r4][c4 + q] = acc[q];
-            __syncthreads();
-            double o[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int p = 0; p <= r4; ++p) {
-                const double a = P[r4][p];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) o[q] = fma(a, Q[p][c4 + q], o[q]);
-            }
-            const int i = I * CB + r4;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int j = K * CB + c4 + q;
-                if (i < m && j < m) Wm[(int64_t)i * ld + j] = -o[q];
-            }
-            __syncthreads();
-        }
-    }
-    // G^{-1} = W^T W: (G^{-1})_IJ = sum_{K >= I} W_KI^T W_KJ, I >= J
-    for (int I = 0; I < nb; ++I) {
-        for (int J = 0; J <= I; ++J) {
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int K = I; K < nb; ++K) {
-                for (int e = tid; e < CB * CB; e += 256) {
-                    const int r = e / CB, c = e % CB;
-                    P[r][c] = gload(Wm, ld, m, K * CB + r, I * CB + c);      // W_KI
-                    Q[r][c] = gload(Wm, ld, m, K * CB + r, J * CB + c);      // W_KJ
-                }
-                __syncthreads();
-                for (int p = 0; p < CB; ++p) {
-                    const double a = P[p][r4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] = fma(a, Q[p][c4 + q], acc[q]);
-                }
-                __syncthreads();
-            }
-            const int i = I * CB + r4;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int j = J * CB + c4 + q;
-                if (i < m && j < m) {
-                    G[(int64_t)i * ld + j] = acc[q];
-                    G[(int64_t)j * ld + i] = acc[q];
-                    G32[d.oG + (int64_t)i * ld + j] = (float)acc[q];
-                    G32[d.oG + (int64_t)j * ld + i] = (float)acc[q];
-                }
-            }
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------

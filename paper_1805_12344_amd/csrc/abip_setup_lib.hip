@@ -1,34 +1,12 @@
-// Setup of one large dense LP (the grid engine's case) with the ROCm
-// libraries for the dense linear algebra that happens once per LP: G = I + A A^T
-// by rocBLAS SYRK, its Cholesky factor and inverse by rocSOLVER (POTRF, POTRI),
-// and the border columns Z = M^{-1} H (Section 4.4, rank 2) by GEMV products.
-// FP64 throughout; the batched path keeps its own one-workgroup-per-LP kernels.
+// Border of the Schur reduction for one large dense LP (the grid engine's
+// case): Z = M^{-1} H (Section 4.4, rank 2, theta column kept) and the 2 x 2
+// K = I2 + S + H^T Z, for I + Q and for I - Q (the adjoint's), after the
+// factorization kernels (abip_factor.hip) have left G^{-1} in G64.  The products
+// with A and G^{-1} run over the whole GPU (the batched path forms the same
+// border with one workgroup per LP, k_setup_border).  FP64 throughout.
 #include <hip/hip_runtime.h>
 #include <algorithm>
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 #include "abip_internal.h"
-
-__global__ void k_lib_diag(double* G, int m, int ld) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) G[(int64_t)i * ld + i] += 1.0;
-}
-
-// lower triangle -> full symmetric matrix, and its FP32 copy (rows past m stay 0)
-__global__ void k_lib_symmetrize(double* G64, float* G32, int m, int ld) {
-    const int j = blockIdx.y;                                     // column
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ld; i += gridDim.x * blockDim.x) {
-        double v = 0.0;
-        if (i < m) v = (i >= j) ? G64[(int64_t)j * ld + i] : G64[(int64_t)i * ld + j];
-        G32[(int64_t)j * ld + i] = (float)v;
-    }
-}
-__global__ void k_lib_copy_upper(double* G64, const float* G32, int m, int ld) {
-    // after the FP32 copy holds the full matrix in float, restore the full FP64 one
-    const int j = blockIdx.y;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
-        if (i < j) G64[(int64_t)j * ld + i] = G64[(int64_t)i * ld + j];
-}
 
 // e = es * ev, f = fs * fv
 __global__ void k_lib_scale(const double* ev, double es, int m, const double* fv, double fs, int n, double* e,
@@ -36,6 +14,46 @@ __global__ void k_lib_scale(const double* ev, double es, int m, const double* fv
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < m) e[t] = es * ev[t];
     if (t < n) f[t] = fs * fv[t];
+}
+
+// Partial products of a column-major M (rows < m, ld) with x over column
+// chunk blockIdx.y of cw columns: P[chunk * ld + i] = sum_j M[i + j ld] x[j].
+__global__ __launch_bounds__(256) void k_gemv_part(const double* __restrict__ M, int ld, int m, int n,
+                                                    const double* __restrict__ x, int cw, double* __restrict__ P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j0 = blockIdx.y * cw, j1 = min(n, j0 + cw);
+    if (i >= m) return;
+    double s0 = 0.0, s1 = 0.0;
+    int j = j0;
+    for (; j + 1 < j1; j += 2) {
+        s0 = fma(M[(int64_t)j * ld + i], x[j], s0);
+        s1 = fma(M[(int64_t)(j + 1) * ld + i], x[j + 1], s1);
+    }
+    if (j < j1) s0 = fma(M[(int64_t)j * ld + i], x[j], s0);
+    P[(int64_t)blockIdx.y * ld + i] = s0 + s1;
+}
+
+// y[i] = beta yin[i] + alpha sum_chunk P[chunk * ld + i] (fixed order; yin may be null)
+__global__ void k_gemv_sum(const double* __restrict__ P, int ld, int m, int nch, double alpha,
+                           const double* __restrict__ yin, double beta, double* __restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += P[(int64_t)c * ld + i];
+    y[i] = alpha * s + (yin ? beta * yin[i] : 0.0);
+}
+
+// z[j] = beta zin[j] + alpha sum_i M[i + j ld] v[i], one wave per column
+__global__ __launch_bounds__(256) void k_gemv_t(const double* __restrict__ M, int ld, int m, int n,
+                                                 const double* __restrict__ v, double alpha,
+                                                 const double* __restrict__ zin, double beta, double* __restrict__ z) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (j >= n) return;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s = fma(M[(int64_t)j * ld + i], v[i], s);
+    s = wave_sum(s);
+    if (lane == 0) z[j] = alpha * s + (zin ? beta * zin[j] : 0.0);
 }
 
 // K = I2 + S + H^T Z for the stored border (sgn = +1: I + Q; -1: I - Q), and
@@ -86,37 +104,24 @@ __global__ __launch_bounds__(512) void k_lib_border_k(const LPDesc* __restrict__
     }
 }
 
-#define RBCHK(x) do { if ((x) != rocblas_status_success) { rc = 1; goto done; } } while (0)
+// Scratch doubles the border of one m x n LP needs (e, f, partial products).
+int64_t grid_border_scratch(int m, int n, int ld) {
+    const int cw = 256;
+    const int nch = std::max((n + cw - 1) / cw, (m + cw - 1) / cw);
+    return (int64_t)ld + n + (int64_t)nch * ld;
+}
 
-// One LP (desc[0]) whose A64 (ld x n, column-major) and pools are filled and
-// whose G64 / G32 are zero.  Returns 0, 1 (library error) or 2 (G not positive
-// definite, which cannot happen for I + A A^T unless A is not finite).
-int lib_setup_one(const LPDesc& d, const LPDesc* ddesc, const double* A64, double* G64, float* G32, double* Mv,
-                  double* Nv, int64_t Mtot, int64_t Ntot, LPCtrl* dctrl, hipStream_t st) {
-    rocblas_handle h = nullptr;
-    int rc = 0;
-    rocblas_int* dinfo = nullptr;
-    double *e = nullptr, *f = nullptr;
+// Z and K for I + Q and I - Q of LP desc[0]: t = e - sgn A f, a = G^{-1} t,
+// z = f + sgn A^T a for the two columns of sgn H.
+hipError_t grid_border(const LPDesc& d, const LPDesc* ddesc, const double* A64, const double* G64, double* Mv,
+                       double* Nv, int64_t Mtot, int64_t Ntot, LPCtrl* dctrl, double* scratch, hipStream_t st) {
     const int m = d.m, n = d.n, ld = d.ld;
-    const double one = 1.0, zero = 0.0;
-    rocblas_int hinfo = 0;
-    if (rocblas_create_handle(&h) != rocblas_status_success) return 1;
-    if (hipMalloc((void**)&dinfo, sizeof(rocblas_int)) != hipSuccess) { rocblas_destroy_handle(h); return 1; }
-    if (hipMalloc((void**)&e, sizeof(double) * ld) != hipSuccess ||
-        hipMalloc((void**)&f, sizeof(double) * n) != hipSuccess) { rc = 1; goto done; }
-    RBCHK(rocblas_set_stream(h, st));
-    RBCHK(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
-    // G = I + A A^T (lower triangle), factor, inverse
-    hipLaunchKernelGGL(k_lib_diag, dim3((m + 255) / 256), dim3(256), 0, st, G64, m, ld);
-    RBCHK(rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, m, n, &one, A64, ld, &one, G64, ld));
-    RBCHK(rocsolver_dpotrf(h, rocblas_fill_lower, m, G64, ld, dinfo));
-    if (hipMemcpyAsync(&hinfo, dinfo, sizeof hinfo, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) { rc = 1; goto done; }
-    if (hinfo != 0) { rc = 2; goto done; }
-    RBCHK(rocsolver_dpotri(h, rocblas_fill_lower, m, G64, ld, dinfo));
-    hipLaunchKernelGGL(k_lib_symmetrize, dim3(std::max(1, (ld + 255) / 256), m), dim3(256), 0, st, G64, G32, m, ld);
-    hipLaunchKernelGGL(k_lib_copy_upper, dim3(std::max(1, (m + 255) / 256), m), dim3(256), 0, st, G64, G32, m, ld);
-    // border columns for I + Q (sgn = +1) and I - Q (sgn = -1)
+    const int cw = 256;
+    double* e = scratch;
+    double* f = e + ld;
+    double* P = f + n;
+    const int nchA = (n + cw - 1) / cw, nchG = (m + cw - 1) / cw;
+    const dim3 rows((m + 255) / 256);
     for (int sgn = 1; sgn >= -1; sgn -= 2) {
         const double sg = (double)sgn;
         const int fzy = (sgn > 0) ? MF_ZY0 : MF_ZY0A, fzx = (sgn > 0) ? NF_ZX0 : NF_ZX0A;
@@ -128,20 +133,14 @@ int lib_setup_one(const LPDesc& d, const LPDesc* ddesc, const double* A64, doubl
             double* zx = Nv + (fzx + hh) * Ntot + d.on;
             hipLaunchKernelGGL(k_lib_scale, dim3((std::max(m, n) + 255) / 256), dim3(256), 0, st, ev, es, m, fv, fs,
                                n, e, f);
-            const double msg = -sg;
-            RBCHK(rocblas_dgemv(h, rocblas_operation_none, m, n, &msg, A64, ld, f, 1, &one, e, 1));   // e - sg A f
-            RBCHK(rocblas_dgemv(h, rocblas_operation_none, m, m, &one, G64, ld, e, 1, &zero, zy, 1)); // a = G^-1 t
-            if (hipMemcpyAsync(zx, f, sizeof(double) * n, hipMemcpyDeviceToDevice, st) != hipSuccess) { rc = 1; goto done; }
-            RBCHK(rocblas_dgemv(h, rocblas_operation_transpose, m, n, &sg, A64, ld, zy, 1, &one, zx, 1)); // f + sg A^T a
+            hipLaunchKernelGGL(k_gemv_part, dim3(rows.x, nchA), dim3(256), 0, st, A64, ld, m, n, f, cw, P);
+            hipLaunchKernelGGL(k_gemv_sum, rows, dim3(256), 0, st, P, ld, m, nchA, -sg, e, 1.0, e);  // t = e - sg A f
+            hipLaunchKernelGGL(k_gemv_part, dim3(rows.x, nchG), dim3(256), 0, st, G64, ld, m, m, e, cw, P);
+            hipLaunchKernelGGL(k_gemv_sum, rows, dim3(256), 0, st, P, ld, m, nchG, 1.0, (const double*)nullptr, 0.0,
+                               zy);                                                                 // a = G^{-1} t
+            hipLaunchKernelGGL(k_gemv_t, dim3((n + 3) / 4), dim3(256), 0, st, A64, ld, m, n, zy, sg, f, 1.0, zx);
         }
         hipLaunchKernelGGL(k_lib_border_k, dim3(1), dim3(512), 0, st, ddesc, Mv, Nv, Mtot, Ntot, dctrl, sgn);
     }
-    if (hipStreamSynchronize(st) != hipSuccess) rc = 1;
-done:
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(dinfo);
-    (void)hipFree(e);
-    (void)hipFree(f);
-    rocblas_destroy_handle(h);
-    return rc;
+    return hipGetLastError();
 }

@@ -388,13 +388,88 @@ __device__ __forceinline__ void small_load_phase(int phase, const LPDesc& d, int
     __syncthreads();                       // av / tv are rewritten next
 }
 
+// ---- adaptive beta (Section 4.3), the LDS-resident variant's step ----------
+// The same stages as the streamed variant's (0 -> 1 keep the initial point,
+// 1 -> 2 keep the first probe's iterate, 2: estimate, choose, restore, 3 -> 0),
+// with the iterate in the owners' registers: lane values in, lane values out
+// (x0/s0: the lane's first column, x1/s1: its last; equal when CPT = 1).  The
+// copies go to the pools (each read back by the lane that wrote it) and the
+// scalars to ctrl[k].bbs; red: the LDS of the block sums (the caller's last
+// readers of it are past a barrier).
+struct SmallBB {
+    double y, x0, s0, x1, s1, tau, kappa, theta, beta;
+    int stage, est, bbe;
+    bool restored;
+};
+template <int CPT, bool PAIR>
+__device__ __noinline__ SmallBB bb_advance_small(int k, int m, int n, int64_t om, int64_t on, const PoolPtrs& P,
+                                                 LPCtrl* __restrict__ ctrl, double* __restrict__ red, int stage,
+                                                 bool was_update, int cb, int ri, bool rown, double y, double x0,
+                                                 double s0, double x1, double s1, double tau, double kappa,
+                                                 double theta, double beta, const SolveParams& prm, int est,
+                                                 int bbe) {
+    SmallBB r{y, x0, s0, x1, s1, tau, kappa, theta, beta, stage, est, bbe, false};
+    const int tid = threadIdx.x;
+    double* Y0 = P.Mv + MF_BBY0 * P.Mtot + om;
+    double* Y1 = P.Mv + MF_BBY1 * P.Mtot + om;
+    double* X0 = P.Nv + NF_BBX0 * P.Ntot + on;
+    double* S0 = P.Nv + NF_BBS0 * P.Ntot + on;
+    double* X1 = P.Nv + NF_BBX1 * P.Ntot + on;
+    double* S1 = P.Nv + NF_BBS1 * P.Ntot + on;
+    double* bbs = ctrl[k].bbs;             // every thread writes the same values
+    const int ja = small_col<CPT, PAIR>(0, cb, n), jb = small_col<CPT, PAIR>(CPT - 1, cb, n);
+    const bool lead = !PAIR || (tid & 1) == 0;
+    if (stage == 0) {
+        if (rown) Y0[ri] = y;
+        if (ja >= 0) { X0[ja] = x0; S0[ja] = s0; }
+        if (CPT > 1 && jb >= 0) { X0[jb] = x1; S0[jb] = s1; }
+        bbs[0] = tau; bbs[1] = kappa; bbs[2] = theta;
+        r.stage = 1;
+    } else if (stage == 1 && was_update) {
+        if (rown) Y1[ri] = y;
+        if (ja >= 0) { X1[ja] = x0; S1[ja] = s0; }
+        if (CPT > 1 && jb >= 0) { X1[jb] = x1; S1[jb] = s1; }
+        bbs[3] = tau; bbs[4] = kappa; bbs[5] = theta;
+        r.stage = 2;
+    } else if (stage == 2) {
+        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double qq[5] = {0, 0, 0, 0, 0};
+        if (rown) bb_acc(y - Y1[ri], 0.0, 0.0, prm.alpha, qq);
+        if (ja >= 0 && lead) bb_acc(x0 - X1[ja], s0 - S1[ja], S1[ja] - S0[ja], prm.alpha, qq);
+        if (CPT > 1 && jb >= 0 && lead) bb_acc(x1 - X1[jb], s1 - S1[jb], S1[jb] - S0[jb], prm.alpha, qq);
+#pragma unroll
+        for (int e = 0; e < 5; ++e) q[e] = qq[e];
+        __syncthreads();
+        small_bsum<8>(q, red);
+#pragma unroll
+        for (int e = 0; e < 5; ++e) qq[e] = q[e];
+        bb_acc(tau - bbs[3], kappa - bbs[4], bbs[4] - bbs[1], prm.alpha, qq);
+        bb_acc(theta - bbs[5], 0.0, 0.0, prm.alpha, qq);
+        r.bbe = bbe + 1;
+        r.est = est + 1;
+        const double hat = bb_hat(qq, beta, prm.eps_cor);
+        const bool fin = bb_choose(r.beta, hat, prm.eps_pen, r.est, prm.bb_max_redo);
+        if (rown) r.y = Y0[ri];
+        if (ja >= 0) { r.x0 = X0[ja]; r.s0 = S0[ja]; }
+        if (CPT > 1 && jb >= 0) { r.x1 = X0[jb]; r.s1 = S0[jb]; }
+        r.tau = bbs[0]; r.kappa = bbs[1]; r.theta = bbs[2];
+        r.stage = fin ? 3 : 1;
+        r.restored = true;
+    } else if (stage == 3) {
+        r.stage = 0;
+        r.est = 0;
+    }
+    return r;
+}
+
 // Solve one LP LDS-resident from the state in ctrl[k] and the pools.  Returns
 // true when the LP is finished here; false when the current phase does not fit
 // (on entry, or at the handover to FP64 data): then ctrl[k] and the pools hold
 // the state, with a tested FP64 refresh as the next pass, for the streamed
 // variant.  Requires four waves, m <= 64 RPL (and m <= 256) and
 // ceil(n/4) <= 64 CPT (<= 32 with PAIR).
-template <int CPT, int RPL, bool PAIR, bool GS>
+// BB: the adaptive beta of Section 4.3 compiled in (launches with settings.bb).
+template <int CPT, int RPL, bool PAIR, bool GS, bool BB>
 __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __restrict__ ctrl, const PoolPtrs& P_in,
                                          const SolveParams& prm_in, int64_t fixed_iters) {
     static_assert(!PAIR || CPT == 1, "column pairs own one column");
@@ -445,8 +520,15 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
     bool l_have = false;
     double by_last = cl.by, cx_last = cl.cx;
     const double zbar = cl.zbar, nb = cl.nb, nc = cl.nc;
-    const double alpha = prm.alpha, gamma = prm.gamma, beta = prm.beta, eps = prm.eps;
+    const double alpha = prm.alpha, gamma = prm.gamma, eps = prm.eps;
     const double np1 = (double)n + 1.0;
+    // Section 4.3 (as in the streamed variant): the outer iteration's beta, a
+    // pending choice, the probe stage (1 / 2: first / second probe update done,
+    // 3: initial point restored after the final estimate)
+    double beta = BB ? cl.beta : prm.beta;
+    bool bb_pend = BB && (cl.flags & 16) != 0;
+    int bb_stage = 0, bbe = cl.bbe, bb_est_run = 0;
+    int64_t bbp = cl.bbp;
 
     // row owner registers: lane l of wave w owns row w*rb + l (lanes past the
     // block or past m hold zeros and add nothing)
@@ -555,9 +637,11 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
                                  (pass_kind == OP_REFRESH && !first);
         const bool was_update = (pass_kind == OP_PROX);
+        const bool bb_pass = BB && bb_stage != 0;  // a probe iterate or the restored start: no tests
         if (pass_kind == OP_PROX) {
             ++iters;
             if (phase == 1) ++iters64;
+            if (BB && bb_pass) ++bbp;
             ++done_fixed;
         }
         first = false;
@@ -567,7 +651,7 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         const double by = v12[7], bby = v12[8];
         const double ms2 = v12[9], ms3 = v12[10], ms4 = v12[11];
         const double cs4 = v12[4], cs5 = v12[5], cs6 = v12[6];
-        if (fixed_iters == 0) {
+        if (fixed_iters == 0 && !bb_pass) {
             int to_phase1 = 0;
             if (post_update) {
                 int st = 0;
@@ -609,6 +693,7 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
                         y *= sg;
                     }
                     stall_reset(stall);
+                    bb_pend = BB;
                     pass_kind = OP_RESTART;
                     cyc_chk += wall_clock64() - tc;
                     continue;
@@ -633,7 +718,27 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
                 red = reinterpret_cast<double*>(smem + L.ored);
                 continue;
             }
-            if (iters >= prm.max_iters) { status = 4; break; }
+            // (an outer iteration that starts with a beta choice takes its probes first)
+            if (iters >= prm.max_iters && !(BB && bb_pend)) { status = 4; break; }
+        }
+        if (BB && fixed_iters == 0 && (bb_pend || bb_pass)) {
+            // ---- adaptive beta (Section 4.3), out of line: rare passes
+            const int prev = bb_stage;
+            if (!bb_pass) bb_pend = false;
+            const SmallBB r = bb_advance_small<CPT, PAIR>(
+                k, m, n, d.om, d.on, P_in, ctrl, red, bb_stage, was_update, cb, ri, rown, y, col[0].x, col[0].s,
+                col[CPT - 1].x, col[CPT - 1].s, tau, kappa, theta, beta, prm_in, bb_est_run, bbe);
+            tau = r.tau; kappa = r.kappa; theta = r.theta; beta = r.beta;
+            bb_stage = r.stage; bb_est_run = r.est; bbe = r.bbe;
+            if (r.restored) {
+                y = r.y;
+                col[0].x = r.x0; col[0].s = r.s0;
+                if constexpr (CPT > 1) { col[CPT - 1].x = r.x1; col[CPT - 1].s = r.s1; }
+                pass_kind = OP_REFRESH;        // exact A^T y and the products of the initial point
+                cyc_chk += wall_clock64() - tc;
+                continue;
+            }
+            if (prev == 3 && iters >= prm.max_iters) { status = 4; break; }
         }
         cyc_chk += wall_clock64() - tc;
 
@@ -684,9 +789,10 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
             o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
             o.cp32 = cp32; o.cp64 = cp64;
             o.cpl32 = cpl32; o.cpl64 = cpl64; o.gh32 = gh32; o.gh64 = gh64; o.kfx = kfx;
+            if (BB) { o.beta = beta; o.bbp = bbp; o.bbe = bbe; }
             o.status = 0; o.phase = 1;
             o.mode = OP_REFRESH;
-            o.flags = (cl.flags & 4) | 1 | (exit_pend ? 8 : 0);
+            o.flags = (cl.flags & 4) | 1 | (exit_pend ? 8 : 0) | (bb_pend ? 16 : 0);
         }
         __syncthreads();
         return false;
@@ -707,9 +813,10 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
         o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
         o.cp32 = cp32; o.cp64 = cp64;
         o.cpl32 = cpl32; o.cpl64 = cpl64; o.gh32 = gh32; o.gh64 = gh64; o.kfx = kfx;
+        if (BB) { o.beta = beta; o.bbp = bbp; o.bbe = bbe; }
         o.status = status; o.phase = phase;
         o.mode = OP_REFRESH;
-        o.flags = ((fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);
+        o.flags = ((fixed_iters > 0) ? 1 : 0) | (cl.flags & 4) | (bb_pend ? 16 : 0);
     }
     __syncthreads();
     return true;
@@ -717,32 +824,32 @@ __device__ __noinline__ bool solve_small(int k, const LPDesc& d_in, LPCtrl* __re
 
 // Pick the variant for this LP: rows per lane from m, column pairs when a
 // wave owns at most 32 columns, one or two columns per lane otherwise.
-template <bool GS>
+template <bool GS, bool BB>
 __device__ inline bool solve_small_shape(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
                                          const SolveParams& prm, int64_t fixed_iters) {
     const int rpl = (d.m + 63) >> 6;
     const int cb = (d.n + SMALL_W - 1) / SMALL_W;
     if (cb <= 32) {
         switch (rpl) {
-        case 1: return solve_small<1, 1, true, GS>(k, d, ctrl, P, prm, fixed_iters);
-        case 2: return solve_small<1, 2, true, GS>(k, d, ctrl, P, prm, fixed_iters);
-        case 3: return solve_small<1, 3, true, GS>(k, d, ctrl, P, prm, fixed_iters);
-        default: return solve_small<1, 4, true, GS>(k, d, ctrl, P, prm, fixed_iters);
+        case 1: return solve_small<1, 1, true, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+        case 2: return solve_small<1, 2, true, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+        case 3: return solve_small<1, 3, true, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+        default: return solve_small<1, 4, true, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
         }
     }
     if (cb <= 64) {
         switch (rpl) {
-        case 1: return solve_small<1, 1, false, GS>(k, d, ctrl, P, prm, fixed_iters);
-        case 2: return solve_small<1, 2, false, GS>(k, d, ctrl, P, prm, fixed_iters);
-        case 3: return solve_small<1, 3, false, GS>(k, d, ctrl, P, prm, fixed_iters);
-        default: return solve_small<1, 4, false, GS>(k, d, ctrl, P, prm, fixed_iters);
+        case 1: return solve_small<1, 1, false, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+        case 2: return solve_small<1, 2, false, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+        case 3: return solve_small<1, 3, false, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+        default: return solve_small<1, 4, false, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
         }
     }
     switch (rpl) {
-    case 1: return solve_small<2, 1, false, GS>(k, d, ctrl, P, prm, fixed_iters);
-    case 2: return solve_small<2, 2, false, GS>(k, d, ctrl, P, prm, fixed_iters);
-    case 3: return solve_small<2, 3, false, GS>(k, d, ctrl, P, prm, fixed_iters);
-    default: return solve_small<2, 4, false, GS>(k, d, ctrl, P, prm, fixed_iters);
+    case 1: return solve_small<2, 1, false, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+    case 2: return solve_small<2, 2, false, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+    case 3: return solve_small<2, 3, false, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
+    default: return solve_small<2, 4, false, GS, BB>(k, d, ctrl, P, prm, fixed_iters);
     }
 }
 
@@ -750,8 +857,9 @@ __device__ inline bool solve_small_shape(int k, const LPDesc& d, LPCtrl* __restr
 // way from the start, or the FP32 -> FP64 handover of the first variant may
 // have left a phase that is).  false: the streamed variant continues from the
 // state in ctrl[k] and the pools.
+template <bool BB>
 __device__ inline bool solve_small_any(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
                                        const SolveParams& prm, int64_t fixed_iters) {
-    if (solve_small_shape<false>(k, d, ctrl, P, prm, fixed_iters)) return true;
-    return solve_small_shape<true>(k, d, ctrl, P, prm, fixed_iters);
+    if (solve_small_shape<false, BB>(k, d, ctrl, P, prm, fixed_iters)) return true;
+    return solve_small_shape<true, BB>(k, d, ctrl, P, prm, fixed_iters);
 }

@@ -25,7 +25,7 @@ struct WGShared {
     double* t;      // ld
     double* Af;     // ld
     double* Ax;     // ld
-    double* red;    // 2 * W * ld
+    double* red;    // 2 * W * max(ld, 32) (at least 64 W: the triangular solves' block partials)
     double* scal;   // W * 8
     double* buf;    // W * 8
 };
@@ -353,12 +353,138 @@ __device__ __forceinline__ void ginv_rows(const T* __restrict__ G, int m, int ld
     __syncthreads();
 }
 
+// ---- the linear step by triangular solves (ABIP_LIN_TRSV) -----------------
+// a = G^{-1} t with the cached factor G = L L^T kept instead of G^{-1}:
+// L z = t, then L^T a = z, by blocked substitution over 64-row blocks.  A
+// block's unknowns come from the inverse of its diagonal block of L (a 64 x 64
+// product, so no step is sequential within a block); the rows below it
+// (forward) or above it (backward, through the column-major copy of L^T) then
+// lose the block's contribution.  L, Lt: ld x m column-major at the LP's G
+// offset; Li, Lit: the diagonal blocks' inverses and their transposes, 64 x 64
+// column-major each.  t (sh.t) is overwritten by z; the result goes to sh.a.
+// Three barriers per block and direction.
+template <typename T>
+__device__ void trsv_pass(const T* __restrict__ L, const T* __restrict__ Lt, const T* __restrict__ Li,
+                          const T* __restrict__ Lit, int m, int ld, const WGShared& sh) {
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, W = NT >> 6;
+    const int nb = (m + 63) >> 6;
+    const int kw = 64 / W;                     // contraction share of a wave in the block product
+    double* t = sh.t;
+    double* a = sh.a;
+    double* part = sh.red;                     // W x 64 partial sums
+    for (int dir = 0; dir < 2; ++dir) {
+        const T* Lm = dir == 0 ? L : Lt;
+        const T* Id = dir == 0 ? Li : Lit;
+        double* v = dir == 0 ? t : a;          // the block's unknowns land here
+        const double* rhs = t;                 // forward: t; backward: z, kept in t
+        for (int s = 0; s < nb; ++s) {
+            const int p = dir == 0 ? s : nb - 1 - s;
+            const int r0 = 64 * p, rb = min(64, m - r0);
+            // unknowns of block p: Id(64 x 64) times the block's right-hand side
+            const T* Ib = Id + (int64_t)p * 4096;
+            double acc = 0.0;
+            for (int k = wave * kw; k < (wave + 1) * kw; ++k)
+                if (k < rb) acc = fma((double)Ib[lane + 64 * k], rhs[r0 + k], acc);
+            part[wave * 64 + lane] = acc;
+            __syncthreads();
+            if (tid < rb) {
+                double z = 0.0;
+                for (int q = 0; q < W; ++q) z += part[q * 64 + tid];
+                v[r0 + tid] = z;
+            }
+            __syncthreads();
+            // the other rows lose the block's contribution: forward the rows below
+            // (L's block column p), backward the rows above (L^T's block column p)
+            const int i0 = dir == 0 ? r0 + rb : 0, i1 = dir == 0 ? m : r0;
+            for (int i = i0 + tid; i < i1; i += NT) {
+                const T* col = Lm + (int64_t)r0 * ld + i;
+                double acc2 = 0.0;
+                for (int k = 0; k < rb; ++k) acc2 = fma((double)col[(int64_t)k * ld], v[r0 + k], acc2);
+                t[i] -= acc2;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---- adaptive beta (Section 4.3) -------------------------------------------
+// One step of the choice of an outer iteration's beta, called after the tests
+// of a pass that starts the outer iteration (stage 0) or of a probe pass:
+//   stage 0 -> 1: the initial point (y, x, s, tau, kappa, theta) is kept, the
+//                 first probe update follows;
+//   stage 1, after the first probe's pass -> 2: its iterate is kept;
+//   stage 2, after the second probe's pass: the five sums of the estimate (every
+//                 thread gets the totals), the selection rule, the initial point
+//                 restored; -> 1 (a redo: the probes again with the estimate) or
+//                 3 (final); restored = true: the caller refreshes the products;
+//   stage 3, the refresh of the initial point -> 0: the outer iteration's own
+//                 updates begin.
+// The copies live in the pools (MF_BBY*, NF_BB*) and the scalars in ctrl[k].bbs.
+struct BBStep {
+    double tau, kappa, theta, beta;
+    int stage, est, bbe;
+    bool restored;
+};
+__device__ __noinline__ BBStep bb_advance_wg(int k, const LPDesc& d, const PoolPtrs& P, LPCtrl* __restrict__ ctrl,
+                                             const WGShared& sh, int stage, bool was_update, double tau,
+                                             double kappa, double theta, double beta, const SolveParams& prm,
+                                             int est, int bbe) {
+    BBStep r{tau, kappa, theta, beta, stage, est, bbe, false};
+    const int m = d.m, n = d.n, tid = threadIdx.x;
+    double* X = P.Nv + NF_X * P.Ntot + d.on;
+    double* S = P.Nv + NF_S * P.Ntot + d.on;
+    double* Y0 = P.Mv + MF_BBY0 * P.Mtot + d.om;
+    double* Y1 = P.Mv + MF_BBY1 * P.Mtot + d.om;
+    double* X0 = P.Nv + NF_BBX0 * P.Ntot + d.on;
+    double* S0 = P.Nv + NF_BBS0 * P.Ntot + d.on;
+    double* X1 = P.Nv + NF_BBX1 * P.Ntot + d.on;
+    double* S1 = P.Nv + NF_BBS1 * P.Ntot + d.on;
+    double* bbs = ctrl[k].bbs;             // every thread writes the same values
+    const double alpha = prm.alpha;
+    if (stage == 0) {
+        for (int i = tid; i < m; i += blockDim.x) Y0[i] = sh.y[i];
+        for (int j = tid; j < n; j += blockDim.x) { X0[j] = X[j]; S0[j] = S[j]; }
+        bbs[0] = tau; bbs[1] = kappa; bbs[2] = theta;
+        r.stage = 1;
+    } else if (stage == 1 && was_update) {
+        for (int i = tid; i < m; i += blockDim.x) Y1[i] = sh.y[i];
+        for (int j = tid; j < n; j += blockDim.x) { X1[j] = X[j]; S1[j] = S[j]; }
+        bbs[3] = tau; bbs[4] = kappa; bbs[5] = theta;
+        r.stage = 2;
+    } else if (stage == 2) {
+        double q[5] = {0, 0, 0, 0, 0};
+        for (int i = tid; i < m; i += blockDim.x) bb_acc(sh.y[i] - Y1[i], 0.0, 0.0, alpha, q);
+        for (int j = tid; j < n; j += blockDim.x) bb_acc(X[j] - X1[j], S[j] - S1[j], S1[j] - S0[j], alpha, q);
+        __syncthreads();
+        block_sum_n<5>(q, sh.buf);
+        bb_acc(tau - bbs[3], kappa - bbs[4], bbs[4] - bbs[1], alpha, q);
+        bb_acc(theta - bbs[5], 0.0, 0.0, alpha, q);
+        r.bbe = bbe + 1;
+        r.est = est + 1;
+        const double hat = bb_hat(q, beta, prm.eps_cor);
+        const bool fin = bb_choose(r.beta, hat, prm.eps_pen, r.est, prm.bb_max_redo);
+        for (int i = tid; i < m; i += blockDim.x) sh.y[i] = Y0[i];
+        for (int j = tid; j < n; j += blockDim.x) { X[j] = X0[j]; S[j] = S0[j]; }
+        r.tau = bbs[0]; r.kappa = bbs[1]; r.theta = bbs[2];
+        __syncthreads();
+        r.stage = fin ? 3 : 1;
+        r.restored = true;
+    } else if (stage == 3) {
+        r.stage = 0;
+        r.est = 0;
+    }
+    return r;
+}
+
 // Solve (or iterate) one LP with the calling workgroup.
 // fixed_iters > 0: run exactly that many PROX iterations with no tests and no
 // restarts (phase taken from ctrl.phase), for step-level parity checks.
 // NCH: 256-row chunks the LP needs; MAXT: the launch's largest block (512 leaves
 // 256 registers per lane, 256 leaves room for 8-column groups).
-template <int NCH, int MAXT>
+// BB: the adaptive beta of Section 4.3 is compiled in (launches with
+// settings.bb); the plain variant carries none of its code in the loop.
+template <int NCH, int MAXT, bool BB, bool TRSV>
 __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, const PoolPtrs& P,
                           const SolveParams& prm, int64_t fixed_iters, const WGShared& sh) {
     const int m = d.m, n = d.n, ld = d.ld;
@@ -398,8 +524,16 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
     bool l_have = false;
     double by_last = cl.by, cx_last = cl.cx;
     const double zbar = cl.zbar, nb = cl.nb, nc = cl.nc;
-    const double alpha = prm.alpha, gamma = prm.gamma, beta = prm.beta, eps = prm.eps;
+    const double alpha = prm.alpha, gamma = prm.gamma, eps = prm.eps;
     const double np1 = (double)n + 1.0;
+    // Section 4.3: beta of the current outer iteration; bb_pend: the outer
+    // iteration has not chosen it yet; bb_stage 1 / 2: the first / second probe
+    // update has run (its pass computes the probe iterate's x, s), 3: the
+    // initial point is restored after the final estimate
+    double beta = BB ? cl.beta : prm.beta;
+    bool bb_pend = BB && (cl.flags & 16) != 0;
+    int bb_stage = 0, bbe = cl.bbe, bb_est_run = 0;
+    int64_t bbp = cl.bbp;
 
     for (int i = tid; i < ld; i += blockDim.x) sh.y[i] = (i < m) ? Yg[i] : 0.0;
     for (int i = tid; i < ld; i += blockDim.x) sh.a[i] = 0.0;
@@ -446,9 +580,11 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         const bool post_update = (pass_kind == OP_PROX) || (first && check_final_first) ||
                                  (pass_kind == OP_REFRESH && !first);
         const bool was_update = (pass_kind == OP_PROX);
+        const bool bb_pass = BB && bb_stage != 0;  // a probe iterate or the restored start: no tests
         if (pass_kind == OP_PROX) {
             ++iters;
             if (phase == 1) ++iters64;
+            if (BB && bb_pass) ++bbp;
             ++done_fixed;
         }
         first = false;
@@ -471,7 +607,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         const double by = ms[0], bby = ms[1];
         const double cx = cs[0], cbx = cs[1];
 
-        if (fixed_iters == 0) {
+        if (fixed_iters == 0 && !bb_pass) {
             // ---- final test on a post-update iterate
             if (post_update) {
                 int st = 0;
@@ -526,6 +662,7 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
                     __syncthreads();
                 }
                 stall_reset(stall);
+                bb_pend = BB;
                 pass_kind = OP_RESTART;
                 continue;
             }
@@ -535,16 +672,40 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
                 pass_kind = OP_REFRESH;
                 continue;
             }
-            if (iters >= prm.max_iters) { status = 4; break; }
+            // (an outer iteration that starts with a beta choice takes its probes first)
+            if (iters >= prm.max_iters && !(BB && bb_pend)) { status = 4; break; }
         }
-
+        if (BB && fixed_iters == 0 && (bb_pend || bb_pass)) {
+            // ---- adaptive beta (Section 4.3), out of line: rare passes
+            const int prev = bb_stage;
+            if (!bb_pass) bb_pend = false;
+            const BBStep r = bb_advance_wg(k, d, P, ctrl, sh, bb_stage, was_update, tau, kappa, theta, beta, prm,
+                                           bb_est_run, bbe);
+            tau = r.tau; kappa = r.kappa; theta = r.theta; beta = r.beta;
+            bb_stage = r.stage; bb_est_run = r.est; bbe = r.bbe;
+            if (r.restored) {
+                pass_kind = OP_REFRESH;        // the passes' products of the initial point
+                continue;
+            }
+            if (prev == 3 && iters >= prm.max_iters) { status = 4; break; }
+        }
         // ---- the inner update: t = y - A f, a = G^{-1} t, border, scalars, y'
         cyc_chk += wall_clock64() - tc;
         for (int i = tid; i < ld; i += blockDim.x) sh.t[i] = (i < m) ? sh.y[i] - sh.Af[i] : 0.0;
         __syncthreads();
         const int64_t t1 = wall_clock64();
-        if (phase == 0) { ginv_pass<NCH, (NCH == 1 ? 8 : NCH == 2 ? 4 : 2), float>(G32, m, ld, sh); ++gh32; }
-        else { ginv_pass<NCH, (NCH == 1 ? 4 : 2), double>(G64, m, ld, sh); ++gh64; }
+        if constexpr (TRSV) {
+            if (phase == 0) {
+                trsv_pass<float>(P.L32 + d.oG, P.Lt32 + d.oG, P.Li32 + d.oL, P.Lit32 + d.oL, m, ld, sh);
+                ++gh32;
+            } else {
+                trsv_pass<double>(P.L64 + d.oG, P.Lt64 + d.oG, P.Li64 + d.oL, P.Lit64 + d.oL, m, ld, sh);
+                ++gh64;
+            }
+        } else {
+            if (phase == 0) { ginv_pass<NCH, (NCH == 1 ? 8 : NCH == 2 ? 4 : 2), float>(G32, m, ld, sh); ++gh32; }
+            else { ginv_pass<NCH, (NCH == 1 ? 4 : 2), double>(G64, m, ld, sh); ++gh64; }
+        }
         const int64_t t2 = wall_clock64();
         cyc_ginv += t2 - t1;
         double bs[4] = {0, 0, 0, 0};
@@ -598,14 +759,15 @@ __device__ void solve_one(int k, const LPDesc& d, LPCtrl* __restrict__ ctrl, con
         o.iters = iters; o.iters64 = iters64; o.ipm = ipm;
         o.cp32 = cp32; o.cp64 = cp64;
         o.gh32 = gh32; o.gh64 = gh64; o.kfx = kfx;
+        if (BB) { o.beta = beta; o.bbp = bbp; o.bbe = bbe; }
         o.status = status; o.phase = phase;
         o.mode = OP_REFRESH;
-        o.flags = ((fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);
+        o.flags = ((fixed_iters > 0) ? 1 : 0) | (cl.flags & 4) | (bb_pend ? 16 : 0);
     }
     __syncthreads();
 }
 
-template <int NCH, int MAXT>
+template <int NCH, int MAXT, bool BB, bool TRSV>
 __global__ __launch_bounds__(MAXT) void k_solve_wg(const LPDesc* __restrict__ desc, LPCtrl* __restrict__ ctrl,
                                                   PoolPtrs P, SolveParams prm, const int32_t* __restrict__ order,
                                                   int32_t B, int32_t* __restrict__ queue, int64_t fixed_iters,
@@ -620,7 +782,7 @@ __global__ __launch_bounds__(MAXT) void k_solve_wg(const LPDesc* __restrict__ de
     sh.Af = sh.t + ldmax;
     sh.Ax = sh.Af + ldmax;
     sh.red = sh.Ax + ldmax;
-    sh.scal = sh.red + 2 * W * ldmax;
+    sh.scal = sh.red + 2 * W * max(ldmax, 32);
     sh.buf = sh.scal + 8 * W;
     while (true) {
         if (threadIdx.x == 0) s_lp = atomicAdd(queue, 1);
@@ -633,22 +795,24 @@ __global__ __launch_bounds__(MAXT) void k_solve_wg(const LPDesc* __restrict__ de
         // an LP whose current phase fits in LDS runs LDS-resident; it comes
         // back here (state in ctrl[k] and the pools) only to hand over to FP64
         // data that does not fit
-        if (MAXT == 256 && d.lds != 0) {
-            if (solve_small_any(k, d, ctrl, P, prm, fixed_iters)) continue;
+        if (!TRSV && MAXT == 256 && d.lds != 0) {
+            if (solve_small_any<BB>(k, d, ctrl, P, prm, fixed_iters)) continue;
         }
         // each LP runs the variant for its own row count (the launch's NCH is
         // the batch maximum): a small LP in a mixed batch holds no idle rows
         const int nch = (d.ld + 255) >> 8;
-        if (NCH == 1 || nch <= 1) solve_one<1, MAXT>(k, d, ctrl, P, prm, fixed_iters, sh);
-        else if (NCH == 2 || nch == 2) solve_one<(NCH >= 2 ? 2 : 1), MAXT>(k, d, ctrl, P, prm, fixed_iters, sh);
-        else if (NCH == 3 || nch == 3) solve_one<(NCH >= 3 ? 3 : 1), MAXT>(k, d, ctrl, P, prm, fixed_iters, sh);
-        else solve_one<NCH, MAXT>(k, d, ctrl, P, prm, fixed_iters, sh);
+        if (NCH == 1 || nch <= 1) solve_one<1, MAXT, BB, TRSV>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else if (NCH == 2 || nch == 2)
+            solve_one<(NCH >= 2 ? 2 : 1), MAXT, BB, TRSV>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else if (NCH == 3 || nch == 3)
+            solve_one<(NCH >= 3 ? 3 : 1), MAXT, BB, TRSV>(k, d, ctrl, P, prm, fixed_iters, sh);
+        else solve_one<NCH, MAXT, BB, TRSV>(k, d, ctrl, P, prm, fixed_iters, sh);
     }
 }
 
 // LDS bytes for a launch
 size_t wg_smem_bytes(int ldmax, int W) {
-    return sizeof(double) * ((size_t)5 * ldmax + (size_t)2 * W * ldmax + 16 * (size_t)W);
+    return sizeof(double) * ((size_t)5 * ldmax + (size_t)2 * W * (ldmax > 32 ? ldmax : 32) + 16 * (size_t)W);
 }
 
 // smem: at least wg_smem_bytes(ldmax, threads / 64), and the LDS-resident
@@ -657,20 +821,54 @@ hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const
                            const PoolPtrs& P, const SolveParams& prm, const int32_t* order, int32_t B,
                            int32_t* queue, int64_t fixed_iters, int32_t ldmax, size_t smem) {
     if (threads > 256 && nch != 1) return hipErrorInvalidValue;      // only NCH = 1 has a 512-thread build
-    switch (nch * 1000 + threads) {
-    case 1512: hipLaunchKernelGGL((k_solve_wg<1, 512>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
-    case 1256: hipLaunchKernelGGL((k_solve_wg<1, 256>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
-    case 2256: hipLaunchKernelGGL((k_solve_wg<2, 256>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
-    case 3256: hipLaunchKernelGGL((k_solve_wg<3, 256>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
-    case 4256: hipLaunchKernelGGL((k_solve_wg<4, 256>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, B, queue, fixed_iters, ldmax); break;
-    default: return hipErrorInvalidValue;
+    // the adaptive beta (Section 4.3) has kernels of its own: the plain ones
+    // carry none of its code
+    const int key = nch * 1000 + threads;
+#define ABIP_LAUNCH_WG(N, T, BBV, TRV) \
+    hipLaunchKernelGGL((k_solve_wg<N, T, BBV, TRV>), dim3(grid), dim3(threads), smem, st, desc, ctrl, P, prm, order, \
+                       B, queue, fixed_iters, ldmax)
+    if (prm.bb) {
+        switch (key) {
+        case 1512: ABIP_LAUNCH_WG(1, 512, true, false); break;
+        case 1256: ABIP_LAUNCH_WG(1, 256, true, false); break;
+        case 2256: ABIP_LAUNCH_WG(2, 256, true, false); break;
+        case 3256: ABIP_LAUNCH_WG(3, 256, true, false); break;
+        case 4256: ABIP_LAUNCH_WG(4, 256, true, false); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else if (prm.trsv) {
+        switch (key) {
+        case 1512: ABIP_LAUNCH_WG(1, 512, false, true); break;
+        case 1256: ABIP_LAUNCH_WG(1, 256, false, true); break;
+        case 2256: ABIP_LAUNCH_WG(2, 256, false, true); break;
+        case 3256: ABIP_LAUNCH_WG(3, 256, false, true); break;
+        case 4256: ABIP_LAUNCH_WG(4, 256, false, true); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (key) {
+        case 1512: ABIP_LAUNCH_WG(1, 512, false, false); break;
+        case 1256: ABIP_LAUNCH_WG(1, 256, false, false); break;
+        case 2256: ABIP_LAUNCH_WG(2, 256, false, false); break;
+        case 3256: ABIP_LAUNCH_WG(3, 256, false, false); break;
+        case 4256: ABIP_LAUNCH_WG(4, 256, false, false); break;
+        default: return hipErrorInvalidValue;
+        }
     }
+#undef ABIP_LAUNCH_WG
     return hipGetLastError();
 }
 
 hipError_t set_solve_wg_smem_limit(size_t bytes) {
-    const void* fns[] = {(const void*)k_solve_wg<1, 512>, (const void*)k_solve_wg<1, 256>, (const void*)k_solve_wg<2, 256>,
-                         (const void*)k_solve_wg<3, 256>, (const void*)k_solve_wg<4, 256>};
+    const void* fns[] = {
+        (const void*)k_solve_wg<1, 512, false, false>, (const void*)k_solve_wg<1, 256, false, false>,
+        (const void*)k_solve_wg<2, 256, false, false>, (const void*)k_solve_wg<3, 256, false, false>,
+        (const void*)k_solve_wg<4, 256, false, false>, (const void*)k_solve_wg<1, 512, true, false>,
+        (const void*)k_solve_wg<1, 256, true, false>, (const void*)k_solve_wg<2, 256, true, false>,
+        (const void*)k_solve_wg<3, 256, true, false>, (const void*)k_solve_wg<4, 256, true, false>,
+        (const void*)k_solve_wg<1, 512, false, true>, (const void*)k_solve_wg<1, 256, false, true>,
+        (const void*)k_solve_wg<2, 256, false, true>, (const void*)k_solve_wg<3, 256, false, true>,
+        (const void*)k_solve_wg<4, 256, false, true>};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -966,7 +1164,7 @@ __global__ __launch_bounds__(512) void k_adjoint(const LPDesc* __restrict__ desc
     sh.Af = sh.t + ldmax;
     sh.Ax = sh.Af + ldmax;
     sh.red = sh.Ax + ldmax;
-    sh.scal = sh.red + 2 * W * ldmax;
+    sh.scal = sh.red + 2 * W * max(ldmax, 32);
     sh.buf = sh.scal + 8 * W;
     while (true) {
         if (threadIdx.x == 0) s_lp = atomicAdd(queue, 1);
