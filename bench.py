@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # (bench.py --copy-calibration).  Keyed by a hash of the kernel's sources: any
 # change to them voids the figure (reported as null until measured again).
 PMC_TRAFFIC = {
+    # k_solve_wg<2, 256> on the 256-LP batch, one step (profiles/k_solve_wg_batched256_pmc.md)
+    "b18b07d907567789": {"fetch_kib": 1020510046.25, "fetch_scale": 1048576.0 / 524315.3125,
+                         "write_kib": 19796195.8125, "write_scale": 1048576.0 / 1048576.0},
 }
 KERNEL_SOURCES = ["paper_1805_12344_amd/csrc/abip_solve_wg.hip", "paper_1805_12344_amd/csrc/abip_small.h",
                   "paper_1805_12344_amd/csrc/abip_internal.h"]
@@ -387,24 +390,40 @@ def extra_sparse(abip, torch, cpu=True):
     kkt = host_kkt(As, lp["b"], lp["c"], xh, yh, sh)
     it = max(1, info["admm_iters"])
     w.free()
-    # algorithmic bytes of one CG iteration (the dominant work): CSR(A^T) and CSR(A) once each
-    # (8-byte value + 4-byte index per entry, 4-byte row pointers), the 32-byte CG record of
-    # every row read by the column pass, q1 written and read (8 bytes per column), and the
-    # row update's reads and writes of r, G u, G p (record) and p, a, u (56 + 32 bytes per row)
     m, n, nnz = 10000, 30000, lp["nnz"]
-    cg_bytes = 24.0 * nnz + 4.0 * (m + n + 2) + 32.0 * m + 16.0 * n + 88.0 * m
+    gnnz = info["gram_nnz"]
+    if gnnz > 0:
+        # algorithmic bytes of one CG iteration with the explicit G~ = A A^T: its CSR rows once
+        # (8-byte value + 4-byte index per entry, 4-byte row pointers), the 32-byte record of
+        # every row read (the gathers) and written, and p, a, u read and written (48 bytes per row)
+        cg_bytes = 12.0 * gnnz + 4.0 * (m + 1) + 32.0 * m + 32.0 * m + 48.0 * m
+        count = "12 nnz(G~) + 4 (m + 1) + 112 m"
+    else:
+        # with the two products: CSR(A^T) and CSR(A) once each (8-byte value + 4-byte index per
+        # entry, 4-byte row pointers), the 32-byte CG record of every row read by the column pass,
+        # q1 written and read (8 bytes per column), and the row update's reads and writes of r,
+        # G u, G p (record) and p, a, u (56 + 32 bytes per row)
+        cg_bytes = 24.0 * nnz + 4.0 * (m + n + 2) + 32.0 * m + 16.0 * n + 88.0 * m
+        count = "24 nnz(A) + 4 (m + n + 2) + 120 m + 16 n"
     us_cg = info["kernel_ms"] * 1e3 / max(1, info["cg_iters"])
     achieved = cg_bytes / (us_cg * 1e-6) / 1e9
+    # the same solve with the explicit G~ = A A^T (one product, one barrier per CG iteration)
+    w2 = abip.abip_setup(As, lp["b"], lp["c"], abip.abip_default_settings(sparse_gram=1))
+    _, _, _, info2 = abip.abip_solve(w2)
+    w2.free()
+    two = {"gram_nnz": info2["gram_nnz"], "admm_iters": info2["admm_iters"], "cg_iters": info2["cg_iters"],
+           "us_per_iter": info2["kernel_ms"] * 1e3 / max(1, info2["admm_iters"]),
+           "us_per_cg_iter": info2["kernel_ms"] * 1e3 / max(1, info2["cg_iters"]), "status": info2["status_name"]}
     out = {"workload": "sparse planted LP 10000 x 30000, nnz %d, seed 1, eps 1e-6, CG on I + A A^T, fp64" % nnz,
            "status": info["status_name"], "admm_iters": info["admm_iters"], "cg_iters": info["cg_iters"],
            "setup_ms": setup_ms, "solve_s": solve_s, "admm_iters_per_s": info["admm_iters"] / solve_s,
            "us_per_iter": info["kernel_ms"] * 1e3 / it, "us_per_cg_iter": us_cg,
            "barrier_ticks_share": info["ticks_check"] / max(1, info["ticks_total"]),
            "host_kkt": list(kkt), "err_vs_fp64": info["err_vs_fp64"], "pobj": float(lp["c"] @ xh),
-           "pstar": lp["pstar"],
+           "pstar": lp["pstar"], "gram_nnz": gnnz, "explicit_gram_per_cg_iteration": two,
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_sp_solve (per CG iteration)",
-                        "algorithmic_bytes_per_cg_iteration": cg_bytes,
+                        "algorithmic_bytes_per_cg_iteration": cg_bytes, "count": count,
                         "note": "bound in practice by the grid barriers of each CG iteration, not by HBM"}}
     if cpu:
         import oracle

@@ -142,6 +142,14 @@ typedef struct {
                                   abip_get_state, abip_iterate and abip_apply_iq work in the scaled
                                   variables.  0 (default): no scaling; at most 100.  CSR input:
                                   ABIP_E_INVALID. */
+    int32_t sparse_gram;       /* sparse engine: 1 forms G~ = A A^T explicitly at setup (one
+                                  workgroup per row gathers the products a_ik a_jk, sorts them by
+                                  (j, k), sums each j in k order) when every row has at most 2048
+                                  products; each CG iteration is then one product with G~ and one
+                                  grid barrier instead of a product with A^T, one with A and two
+                                  barriers, but it gathers a 32-byte CG record per entry of G~, so
+                                  it pays only when G~ is about as sparse as A.  0 (default): the
+                                  two products.  abip_info.gram_nnz says which ran. */
 } abip_settings;
 
 /* Per-LP result summary (host struct). */
@@ -187,6 +195,8 @@ typedef struct {
     double  beta;              /* the last outer iteration's beta (settings.beta unless settings.bb) */
     int64_t bb_probe_iters;    /* of admm_iters: the probe iterations of the beta estimates */
     int32_t bb_estimates;      /* beta estimates taken (redos included) */
+    int64_t gram_nnz;          /* sparse engine: entries of the explicit G~ = A A^T, 0 when the CG
+                                  multiplies by A^T and A */
 } abip_info;
 
 /* A matrix description.  All pointers are device pointers; abip_setup copies

@@ -43,7 +43,7 @@ class abip_settings(ctypes.Structure):
         ("cg_rule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("lds_resident", ctypes.c_int32),
         ("bb", ctypes.c_int32), ("bb_max_redo", ctypes.c_int32), ("bb_eps_cor", ctypes.c_double),
-        ("bb_eps_penalty", ctypes.c_double), ("scale_iters", ctypes.c_int32),
+        ("bb_eps_penalty", ctypes.c_double), ("scale_iters", ctypes.c_int32), ("sparse_gram", ctypes.c_int32),
     ]
 
 
@@ -62,6 +62,7 @@ class abip_info(ctypes.Structure):
         ("ginv_hbm_fp32", ctypes.c_int64), ("ginv_hbm_fp64", ctypes.c_int64),
         ("lds_mode", ctypes.c_int32), ("fp32_exit_kkt", ctypes.c_double), ("err_vs_fp64", ctypes.c_double),
         ("beta", ctypes.c_double), ("bb_probe_iters", ctypes.c_int64), ("bb_estimates", ctypes.c_int32),
+        ("gram_nnz", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -311,7 +311,11 @@ struct abip_work {
     int sp_nb_default = 1;          // the setup's choice (one workgroup per 256 rows or columns)
     int32_t* sp_idx = nullptr;       // rp (m+1), ci (nnz), rpt (n+1), cit (nnz), cursor (n)
     double* sp_val = nullptr;        // va (nnz), vat (nnz)
-    double* sp_vec = nullptr;        // dG, a, z, p (m); CG records (4 m); ATZy0, ATZy1, ATY, ATA, q1 (n); part
+    double* sp_vec = nullptr;        // dG, a, z, p (m); CG records (2 x 4 m); ATZy0, ATZy1, ATY, ATA, q1 (n); part
+    int32_t* sp_grp = nullptr;       // explicit G~ = A A^T: row pointers (m + 1), columns
+    int32_t* sp_gci = nullptr;
+    double* sp_gva = nullptr;        // values
+    int64_t sp_gram_nnz = 0;
     std::vector<int32_t> sp_hrp, sp_hrpt;   // host copies of the row pointers of CSR(A), CSR(A^T)
     int sp_lds_cap = 0;              // dynamic LDS the cooperative kernels may use
     unsigned* sp_bar = nullptr;      // grid barrier words
@@ -359,6 +363,7 @@ static void release(abip_work* w) {
     (void)hipFree(w->adj_iters); (void)hipFree(w->adj_resid);
     (void)hipFree(w->gbuf); (void)hipFree(w->gctl);
     (void)hipFree(w->sp_idx); (void)hipFree(w->sp_val); (void)hipFree(w->sp_vec);
+    (void)hipFree(w->sp_grp); (void)hipFree(w->sp_gci); (void)hipFree(w->sp_gva);
     (void)hipFree(w->sp_bar); (void)hipFree(w->sp_err); (void)hipFree(w->sp_cgit);
     if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
     if (w->ggraph) (void)hipGraphDestroy(w->ggraph);
@@ -397,6 +402,7 @@ extern "C" int abip_default_settings(abip_settings* s) {
     s->bb_eps_cor = 0.2;
     s->bb_eps_penalty = 0.1;
     s->scale_iters = 0;
+    s->sparse_gram = 0;
     return ABIP_OK;
 }
 
@@ -422,6 +428,7 @@ static int check_settings(const abip_settings& s) {
     if (!(s.bb_eps_penalty >= 0.0) || !std::isfinite(s.bb_eps_penalty))
         return fail(ABIP_E_INVALID, "settings.bb_eps_penalty must be >= 0");
     if (s.scale_iters < 0 || s.scale_iters > 100) return fail(ABIP_E_INVALID, "settings.scale_iters must lie in [0,100]");
+    if (s.sparse_gram != 0 && s.sparse_gram != 1) return fail(ABIP_E_INVALID, "settings.sparse_gram must be 0 or 1");
     if (s.lin_solver < ABIP_LIN_AUTO || s.lin_solver > ABIP_LIN_TRSV)
         return fail(ABIP_E_INVALID, "settings.lin_solver: unknown value %d", s.lin_solver);
     if (s.lin_solver == ABIP_LIN_TRSV && s.bb)
@@ -702,7 +709,7 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     ALLOC(w->A64, oA); ALLOC(w->A32, oA);
     ALLOC(w->G64, oG); ALLOC(w->G32, oG);
     ALLOC(w->Mv, (int64_t)NMF * om); ALLOC(w->Nv, (int64_t)NNF * on);
-    ALLOC(w->order, B); ALLOC(w->queue, 1); ALLOC(w->errflag, 1);
+    ALLOC(w->order, B); ALLOC(w->queue, 2); ALLOC(w->errflag, 1);     // queue[1]: abip_iterate's one-LP order
     ALLOC(w->outp, 3 * B);
     if (B == 1) {
         const int mx = std::max(w->hdesc[0].m, w->hdesc[0].n);
@@ -916,7 +923,7 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
 #define SCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) return bail(fail(ABIP_E_HIP, "%s: %s", #call, hipGetErrorString(e_))); } while (0)
     const int64_t nidx = (int64_t)(m + 1) + nnz + (n + 1) + nnz + n;
     const int NBLK = 64;
-    const int64_t nvec = 8 * (int64_t)d.ld + 5 * (int64_t)w->Ntot + (int64_t)SP_PS * 4 * w->cu_count;
+    const int64_t nvec = 12 * (int64_t)d.ld + 5 * (int64_t)w->Ntot + (int64_t)SP_PS * 4 * w->cu_count;
     SALLOC(w->ddesc, 1); SALLOC(w->dctrl, 1);
     SALLOC(w->Mv, (int64_t)NMF * w->Mtot); SALLOC(w->Nv, (int64_t)NNF * w->Ntot);
     SALLOC(w->errflag, 1); SALLOC(w->outp, 3);
@@ -942,6 +949,8 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     double* dG = V; V += d.ld;
     g.a = V; V += d.ld; g.z = V; V += d.ld; g.p = V; V += d.ld;
     g.rw = reinterpret_cast<SpRow*>(V); V += 4 * (int64_t)d.ld;     // 32-byte records (ld is a multiple of 4)
+    g.rw2 = reinterpret_cast<SpRow*>(V); V += 4 * (int64_t)d.ld;
+    g.grp = nullptr; g.gci = nullptr; g.gva = nullptr; g.LG = 1;
     double* ATZy0 = V; V += w->Ntot;
     double* ATZy1 = V; V += w->Ntot;
     g.ATY = V; V += w->Ntot; g.ATA = V; V += w->Ntot; g.q1 = V; V += w->Ntot;
@@ -999,6 +1008,38 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     // CSR(A^T), Jacobi diagonal, HSD constants (eq. bar-b-c-z-re)
     SCHK(sp_transpose(g, rpt, cit, vat, cursor, st));
     SCHK(sp_rowsq(g, dG, st));
+    // G~ = A A^T explicitly (one product and one grid barrier per CG iteration)
+    // when asked for (settings.sparse_gram = 1) and every row's products fit the gather
+    if (s.sparse_gram == 1 && nnz > 0) {
+        int32_t* gcnt = nullptr;
+        SALLOC(gcnt, m);
+        std::vector<int32_t> hc(m);
+        hipError_t e1 = sp_gram_count(g, gcnt, st);
+        if (e1 == hipSuccess) e1 = hipMemcpyAsync(hc.data(), gcnt, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st);
+        if (e1 == hipSuccess) e1 = hipStreamSynchronize(st);
+        (void)hipFree(gcnt);
+        if (e1 != hipSuccess) return bail(fail(ABIP_E_HIP, "G = A A^T count: %s", hipGetErrorString(e1)));
+        bool fits = true;
+        int64_t tot = 0;
+        std::vector<int32_t> hp_(m + 1);
+        for (int i = 0; i < m; ++i) {
+            if (hc[i] < 0) { fits = false; break; }
+            hp_[i] = (int32_t)tot;
+            tot += hc[i];
+        }
+        hp_[m] = (int32_t)tot;
+        const bool want = fits && tot > 0 && tot < INT32_MAX;
+        if (want) {
+            SALLOC(w->sp_grp, (int64_t)m + 1);
+            SALLOC(w->sp_gci, tot);
+            SALLOC(w->sp_gva, tot);
+            SCHK(hipMemcpyAsync(w->sp_grp, hp_.data(), sizeof(int32_t) * ((size_t)m + 1), hipMemcpyHostToDevice, st));
+            SCHK(sp_gram_fill(g, w->sp_grp, w->sp_gci, w->sp_gva, st));
+            g.grp = w->sp_grp; g.gci = w->sp_gci; g.gva = w->sp_gva;
+            g.LG = lanes_for((double)tot / m);
+            w->sp_gram_nnz = tot;
+        }
+    }
     // row pointers on the host, to size each launch's LDS-resident slices
     w->sp_hrp.resize((size_t)m + 1);
     w->sp_hrpt.resize((size_t)n + 1);
@@ -1272,7 +1313,10 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
     float kms = NAN;
     if (!w->noalloc) HIPCHK(hipEventElapsedTime(&kms, w->ev0, w->ev1));
     if (info)
-        for (int k = 0; k < w->B; ++k) fill_info(&info[k], w->hctrl[k], w->hdesc[k], w->setup_ms, ms, (double)kms);
+        for (int k = 0; k < w->B; ++k) {
+            fill_info(&info[k], w->hctrl[k], w->hdesc[k], w->setup_ms, ms, (double)kms);
+            info[k].gram_nnz = w->sp_gram_nnz;
+        }
     w->solved = true;
     return ABIP_OK;
 }
@@ -1459,15 +1503,13 @@ extern "C" int abip_iterate(abip_work* w, int32_t k, int64_t iters, int32_t use_
         HIPCHK(hipMemcpy(w->dctrl, &c2, sizeof c2, hipMemcpyHostToDevice));
         return ABIP_OK;
     }
-    int32_t* ord1 = nullptr;
-    HIPCHK(hipMalloc((void**)&ord1, sizeof(int32_t)));
+    int32_t* ord1 = w->queue + 1;         // the handle's one-entry order slot (no allocation per call)
     hipLaunchKernelGGL(k_single_order, dim3(1), dim3(64), 0, w->stream, ord1, k);
     SolveParams prm = make_params(w->set);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, w->stream, w->queue);
     hipError_t e = launch_solve_wg(w->nch, 1, w->threads, w->stream, w->ddesc, w->dctrl, pools(w), prm, ord1, 1,
                                    w->queue, iters, w->ldmax, w->wg_smem);
     hipError_t e2 = hipStreamSynchronize(w->stream);
-    (void)hipFree(ord1);
     if (e != hipSuccess) return fail(ABIP_E_HIP, "abip_iterate launch: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(ABIP_E_HIP, "abip_iterate: %s", hipGetErrorString(e2));
     return ABIP_OK;

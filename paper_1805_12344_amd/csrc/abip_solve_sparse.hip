@@ -260,8 +260,81 @@ __device__ __forceinline__ double sp_u_next(const SpRow& q, double al, double be
     return fma(-al, fma(be, q.s, q.w), q.r) * q.idg;
 }
 
+// The same iteration with G~ = A A^T given explicitly: one pass and one grid
+// barrier per iteration.  Each workgroup forms d_i = sum_j G~_ij u'_j for its
+// rows (u' of every row from its record, as the column pass above does) and
+// updates its rows right away; so that no row's record changes while another
+// workgroup still gathers it, the records alternate between two buffers
+// (read one, write the other).  On return the records are back in g.rw.
+__device__ int cg_loop_gram(const SpArgs& g, double rr, double tol2, double (&bd)[4], double* sbuf, int maxit,
+                            int64_t (&tk)[4]) {
+    const Range R = my_range(g.m);
+    const int tid = threadIdx.x;
+    double al = 0.0, be = 0.0, gam_old = 1.0;
+    SpRow* rd = g.rw;
+    SpRow* wr = g.rw2;
+    int k = -1;
+    while (k < maxit && (k < 0 || rr > tol2) && !grid_failed(g.err)) {
+        int64_t t0 = wall_clock64();
+        double v[7] = {0, 0, 0, 0, 0, 0, 0};
+        const int Lg = g.LG, per = SP_THREADS / Lg;
+        for (int i0 = R.lo; i0 < R.hi; i0 += per) {
+            const int i = i0 + tid / Lg, sub = tid % Lg;
+            double d = 0.0;
+            if (i < R.hi) {
+                double o[1];
+                row_sums<1>(g.gci, g.gva, g.grp[i], g.grp[i + 1], sub, Lg,
+                            [&](int j, double* fv) { fv[0] = sp_u_next(rd[j], al, be); }, o);
+                d = o[0];
+            }
+            d = group_sum(d, Lg);
+            if (i < R.hi && sub == 0) {
+                const double pi = fma(be, g.p[i], g.z[i]);
+                const SpRow o = rd[i];
+                const double si = fma(be, o.s, o.w);
+                const double ai = fma(al, pi, g.a[i]);
+                const double ri = fma(-al, si, o.r);
+                const double ui = ri * o.idg;
+                const double wi = ui + d;
+                g.p[i] = pi; g.a[i] = ai; g.z[i] = ui;
+                wr[i] = SpRow{ri, wi, si, o.idg};
+                v[0] = fma(ri, ui, v[0]);
+                v[1] = fma(wi, ui, v[1]);
+                v[2] = fma(ri, ri, v[2]);
+                v[3] = fma(g.b[i], ai, v[3]);
+                v[4] = fma(g.bbar[i], ai, v[4]);
+                v[5] = fma(g.Ac[i], ai, v[5]);
+                v[6] = fma(g.Acb[i], ai, v[6]);
+            }
+        }
+        put_parts<7>(v, g.part, g.nbp, SP_CG, sbuf);
+        int64_t t1 = wall_clock64();
+        tk[1] += t1 - t0;
+        grid_sync(g.bar, g.err);
+        t0 = wall_clock64();
+        tk[2] += t0 - t1;
+        double t7[7];
+        get_parts<7>(g.part, g.nbp, SP_CG, t7, sbuf);
+        tk[3] += wall_clock64() - t0;
+        bd[0] = t7[3]; bd[1] = t7[4]; bd[2] = t7[5]; bd[3] = t7[6];
+        const double gam = t7[0], del = t7[1];
+        rr = t7[2];
+        if (k < 0) { be = 0.0; al = gam / del; }
+        else { be = gam / gam_old; al = gam / (del - be * gam / al); }
+        gam_old = gam;
+        ++k;
+        SpRow* tmp = rd; rd = wr; wr = tmp;
+    }
+    if (rd != g.rw) {
+        for (int i = R.lo + tid; i < R.hi; i += SP_THREADS) g.rw[i] = rd[i];
+        __syncthreads();
+    }
+    return k < 0 ? 0 : k;
+}
+
 __device__ int cg_loop(const SpArgs& g, const SpLds& L, double rr, double tol2, double (&bd)[4], double* sbuf,
                        int maxit, int64_t (&tk)[4]) {
+    if (g.grp) return cg_loop_gram(g, rr, tol2, bd, sbuf, maxit, tk);
     const Range R = my_range(g.m), Cc = my_range(g.n);
     const int tid = threadIdx.x;
     double al = 0.0, be = 0.0, gam_old = 1.0;
@@ -783,6 +856,130 @@ __global__ void k_sp_dots(const double* x, const double* const* ys, int ny, int6
 hipError_t sp_dots(const double* x, const double* const* ys, int ny, int64_t len, double* partial, int nblk,
                    hipStream_t st) {
     hipLaunchKernelGGL(k_sp_dots, dim3(nblk), dim3(256), 0, st, x, ys, ny, len, partial);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// G~ = A A^T in CSR.  Row i: for every entry (i, k) of A and every entry (j, k)
+// of row k of CSR(A^T), the product a_ik a_jk at column j.  One workgroup per
+// row gathers the products with keys (j, k) into LDS in a fixed order (entries
+// of row i in order, each with its column's entries in order), sorts them by
+// key (bitonic), and either counts the distinct j (k_sp_gcount) or writes each
+// j once with the sum of its products in k order (k_sp_gfill).  A row with
+// more than SP_GCAND products reports -1 (the engine then keeps the two
+// products per CG iteration).
+// ---------------------------------------------------------------------------
+#define SP_GCAND 2048
+__device__ int sp_gram_gather(const SpArgs& g, int i, unsigned long long* key, double* val) {
+    const int eb = g.rp[i], ee = g.rp[i + 1];
+    int base = 0;
+    for (int e = eb; e < ee; ++e) {
+        const int k = g.ci[e];
+        const double aik = g.va[e];
+        const int fb = g.rpt[k], cnt = g.rpt[k + 1] - fb;
+        if (base + cnt > SP_GCAND) return -1;
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            key[base + t] = ((unsigned long long)(unsigned)g.cit[fb + t] << 32) | (unsigned)k;
+            val[base + t] = aik * g.vat[fb + t];
+        }
+        base += cnt;
+    }
+    // pad to a power of two with keys past every real one, then sort
+    int P = 1;
+    while (P < base) P <<= 1;
+    for (int t = base + threadIdx.x; t < P; t += blockDim.x) { key[t] = ~0ull; val[t] = 0.0; }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < P; t += blockDim.x) {
+                const int u = t ^ stride;
+                if (u > t) {
+                    const bool up = (t & size) == 0;
+                    const unsigned long long ka = key[t], kb = key[u];
+                    if ((ka > kb) == up) {
+                        key[t] = kb; key[u] = ka;
+                        const double va = val[t];
+                        val[t] = val[u]; val[u] = va;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return base;
+}
+
+__global__ __launch_bounds__(256) void k_sp_gcount(SpArgs g, int32_t* cnt) {
+    __shared__ unsigned long long key[SP_GCAND];
+    __shared__ double val[SP_GCAND];
+    __shared__ int sred[4];
+    const int i = blockIdx.x;
+    const int nc = sp_gram_gather(g, i, key, val);
+    if (nc < 0) {
+        if (threadIdx.x == 0) cnt[i] = -1;
+        return;
+    }
+    int c = 0;
+    for (int t = threadIdx.x; t < nc; t += blockDim.x)
+        c += (t == 0 || (key[t] >> 32) != (key[t - 1] >> 32)) ? 1 : 0;
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[i] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+__global__ __launch_bounds__(256) void k_sp_gfill(SpArgs g, const int32_t* grp, int32_t* gci, double* gva) {
+    __shared__ unsigned long long key[SP_GCAND];
+    __shared__ double val[SP_GCAND];
+    __shared__ int rank[SP_GCAND];
+    __shared__ int scan[256];
+    const int i = blockIdx.x;
+    const int nc = sp_gram_gather(g, i, key, val);
+    if (nc <= 0) return;
+    // rank of each distinct column: exclusive scan of the segment-start flags,
+    // eight consecutive positions per thread
+    const int tid = threadIdx.x;
+    int loc = 0;
+    for (int q = 0; q < 8; ++q) {
+        const int t = tid * 8 + q;
+        if (t < nc && (t == 0 || (key[t] >> 32) != (key[t - 1] >> 32))) ++loc;
+    }
+    scan[tid] = loc;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = (tid >= off) ? scan[tid - off] : 0;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    int run = scan[tid] - loc;
+    for (int q = 0; q < 8; ++q) {
+        const int t = tid * 8 + q;
+        if (t < nc && (t == 0 || (key[t] >> 32) != (key[t - 1] >> 32))) rank[t] = run++;
+    }
+    __syncthreads();
+    const int64_t o = grp[i];
+    for (int t = tid; t < nc; t += blockDim.x) {
+        if (t == 0 || (key[t] >> 32) != (key[t - 1] >> 32)) {
+            const unsigned j = (unsigned)(key[t] >> 32);
+            double sum = 0.0;
+            for (int u = t; u < nc && (unsigned)(key[u] >> 32) == j; ++u) sum += val[u];
+            gci[o + rank[t]] = (int32_t)j;
+            gva[o + rank[t]] = sum;
+        }
+    }
+}
+
+hipError_t sp_gram_count(const SpArgs& g, int32_t* cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_gcount, dim3(g.m), dim3(256), 0, st, g, cnt);
+    return hipGetLastError();
+}
+hipError_t sp_gram_fill(const SpArgs& g, const int32_t* grp, int32_t* gci, double* gva, hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_gfill, dim3(g.m), dim3(256), 0, st, g, grp, gci, gva);
+    return hipGetLastError();
+}
+hipError_t sp_scan(const int32_t* cnt, int32_t n, int32_t* ptr, hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_scan, dim3(1), dim3(1024), 0, st, cnt, n, ptr);
     return hipGetLastError();
 }
 

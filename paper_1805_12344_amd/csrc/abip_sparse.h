@@ -35,6 +35,10 @@ struct SpArgs {
     double *ATY, *ATA;                   // n: A^T y of the current iterate, A^T a of the last solve
     double *a, *z, *p;                   // m: CG solution (warm start), u = D^{-1} r, search direction
     SpRow* rw;                           // m: r, G u, G p, 1 / diag(G)
+    SpRow* rw2;                          // m: the second record buffer of the explicit-G CG
+    // explicit G~ = A A^T in CSR (null: the CG multiplies by A^T then A)
+    const int32_t* grp; const int32_t* gci; const double* gva;
+    int32_t LG;                          // lanes per row of G~
     double *q1;                          // n: A^T u of the next CG iterate
     double* part;                        // SP_PS * nbp partial sums
     int32_t nbp;                         // workgroup capacity of part (>= gridDim.x)
@@ -80,5 +84,8 @@ hipError_t sp_dots(const double* x, const double* const* ys, int ny, int64_t len
 hipError_t sp_cg_solve(SpArgs g, const double* rhs, double* out, double tol, int32_t maxit, int nb,
                        int64_t* iters, hipStream_t st);
 hipError_t sp_solve(SpArgs g, int nb, hipStream_t st);
+hipError_t sp_gram_count(const SpArgs& g, int32_t* cnt, hipStream_t st);
+hipError_t sp_gram_fill(const SpArgs& g, const int32_t* grp, int32_t* gci, double* gva, hipStream_t st);
+hipError_t sp_scan(const int32_t* cnt, int32_t n, int32_t* ptr, hipStream_t st);
 hipError_t sp_set_lds_limit(int bytes);
 int sp_max_blocks(int cu_count, int lds_bytes);

@@ -26,18 +26,20 @@ def _tight(**kw):
 
 @pytest.mark.parametrize("m,n,seed,density", [(40, 90, 1, 0.08), (150, 420, 2, 0.02), (600, 1700, 3, 0.004)])
 @pytest.mark.parametrize("rule", ["heuristic", "sqrt"])
-@pytest.mark.parametrize("lds", [1, 0])
-def test_sparse_iterations_match_oracle(m, n, seed, density, rule, lds):
+@pytest.mark.parametrize("lds,gram", [(1, 0), (0, 0), (1, 1)])
+def test_sparse_iterations_match_oracle(m, n, seed, density, rule, lds, gram):
     """Fixed updates from the same restarted iterate: the CG-based step equals the exact one,
-    with the CSR rows held in LDS (lds=1) and read from global memory (lds=0)."""
-    print(f"sparse iterate m={m} n={n} seed={seed} rule={rule} lds={lds}", flush=True)
+    with the CSR rows held in LDS (lds=1) and read from global memory (lds=0), or with the CG
+    multiplying by the explicit G~ = A A^T (gram=1)."""
+    print(f"sparse iterate m={m} n={n} seed={seed} rule={rule} lds={lds} gram={gram}", flush=True)
     lp = lpgen.sparse_planted(m, n, seed, density=density)
     A = _csr(lp)
     prob = Problem(A.toarray(), lp["b"], lp["c"])
     s = Settings(restart_rule=rule)
     st = oracle.initial_state(prob, s)
     st = oracle.restart(st, s.gamma, rule)
-    w = abip.abip_setup(A, lp["b"], lp["c"], _tight(restart_rule=0 if rule == "heuristic" else 1, lds_resident=lds))
+    w = abip.abip_setup(A, lp["b"], lp["c"], _tight(restart_rule=0 if rule == "heuristic" else 1, lds_resident=lds,
+                                                    sparse_gram=gram))
     abip.abip_set_state(w, 0, st.y, st.x, st.s, st.tau, st.kappa, st.theta, st.mu)
     solver = oracle.SchurIQSolver(prob)
     N = 25
@@ -55,14 +57,20 @@ def test_sparse_iterations_match_oracle(m, n, seed, density, rule, lds):
 
 
 @pytest.mark.parametrize("seed", [1, 2])
-@pytest.mark.parametrize("lds", [1, 0])
-def test_sparse_solve_matches_oracle(seed, lds):
+@pytest.mark.parametrize("lds,gram", [(1, 0), (0, 0), (1, 1)])
+def test_sparse_solve_matches_oracle(seed, lds, gram):
     lp = lpgen.sparse_planted(60, 150, seed, density=0.05)
     A = _csr(lp)
     ref = oracle.solve(A.toarray(), lp["b"], lp["c"], Settings())
-    w = abip.abip_setup(A, lp["b"], lp["c"], _tight(lds_resident=lds))
+    w = abip.abip_setup(A, lp["b"], lp["c"], _tight(lds_resident=lds, sparse_gram=gram))
     x, y, s, info = abip.abip_solve(w)
     print(info, ref["admm_iters"], flush=True)
+    G = (A @ A.T).tocsr()
+    G.eliminate_zeros()
+    if gram == 1:
+        assert info["gram_nnz"] >= G.nnz          # structural entries (exact cancellations kept)
+    else:
+        assert info["gram_nnz"] == 0
     assert info["status"] == abip.ABIP_SOLVED == ref["status"]
     kk = oracle.kkt_relative(A.toarray(), lp["b"], lp["c"], _np(x), _np(y), _np(s))
     assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-6, kk
