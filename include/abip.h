@@ -207,8 +207,8 @@ typedef struct {
  * handle runs the sparse engine: FP64 throughout (settings.precision is not
  * used), the linear step by Jacobi-preconditioned CG on G = I + A A^T
  * (Section 4.4, indirect variant) with settings.cg_tol / cg_max_iters, in one
- * cooperative launch.  abip_backward and abip_apply_iq take dense handles
- * only (ABIP_E_STATE otherwise). */
+ * cooperative launch.  abip_apply_iq takes dense handles only (ABIP_E_STATE
+ * otherwise). */
 typedef struct {
     int32_t m, n;
     int32_t format;            /* ABIP_DENSE_ROWMAJOR or ABIP_CSR */
@@ -272,9 +272,17 @@ int abip_solve_batch(abip_work* w, double* const* x, double* const* y, double* c
  * ADMM step that reuses the cached factor ((I+Q)^T = I - Q has the same
  * G = I + A A^T).  Then contract with d(Q u)/d(c, b, A).  At the final iterate
  * this equals the adjoint of the central-path system (HSD-log-kkt) there.
- * Outputs (device, caller-owned): dL_dc (n), dL_db (m), dL_dA (m*n row-major,
- * may be NULL).  Requires a prior successful abip_solve with status SOLVED,
- * else ABIP_E_STATE. */
+ * Outputs (device, caller-owned): dL_dc (n), dL_db (m), dL_dA (may be NULL):
+ * m*n row-major for a dense LP; for a CSR LP the nnz values of dL/dA on the
+ * stored entries, in the order of the CSR input.  Requires a prior successful
+ * abip_solve with status SOLVED (or a state loaded by abip_set_state), else
+ * ABIP_E_STATE; ABIP_E_STATE also for a scaled handle (settings.scale_iters).
+ * Batch handles: one workgroup per LP, the Krylov vectors in device memory.
+ * One large dense LP and CSR LPs: the same recurrence driven from the host,
+ * each product over the whole GPU (dense: A and G^{-1} from the cached pools;
+ * CSR: products with A and A^T and G^{-1} by CG to max(1e-13, 0.1 adjoint_tol),
+ * the border of I - Q computed by CG at the first call).  The CSR engine's CG
+ * warm start is kept across the call. */
 int abip_backward(abip_work* w, const double* dL_dx, double* dL_dc, double* dL_db,
                   double* dL_dA);
 

@@ -189,6 +189,7 @@ class Work:
         self.dims = dims          # list of (m, n)
         self._keep = keep
         self.last_info = None
+        self.nnz = None           # CSR handles: stored entries of A
 
     @property
     def B(self):
@@ -235,7 +236,9 @@ def abip_setup(A, b, c, settings: abip_settings | None = None) -> Work:
         h = ctypes.c_void_p()
         s = settings or abip_default_settings()
         _check(lib().abip_setup(ctypes.byref(h), ctypes.byref(mat), _ptr(b), _ptr(c), ctypes.byref(s), _stream()))
-        return Work(h, [(m, n)], (rp, ci, va, b, c, s))
+        w = Work(h, [(m, n)], (rp, ci, va, b, c, s))
+        w.nnz = int(va.numel())
+        return w
     A = _dev(A)
     m, n = A.shape
     b = _dev(b, (m,))
@@ -402,7 +405,9 @@ def abip_backward(w: Work, dL_dx, want_A: bool = False):
     g = _dev(dL_dx, (n,))
     dc = torch.empty(n, dtype=torch.float64, device="cuda")
     db = torch.empty(m, dtype=torch.float64, device="cuda")
-    dA = torch.empty((m, n), dtype=torch.float64, device="cuda") if want_A else None
+    dA = None
+    if want_A:     # CSR handles: dL/dA on the stored entries, in their CSR order
+        dA = torch.empty((m, n) if w.nnz is None else (w.nnz,), dtype=torch.float64, device="cuda")
     _check(lib().abip_backward(w.handle, _ptr(g), _ptr(dc), _ptr(db), _ptr(dA)))
     return dc, db, dA
 

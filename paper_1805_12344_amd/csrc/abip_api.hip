@@ -15,6 +15,7 @@
 #include "abip_internal.h"
 #include "abip_grid.h"
 #include "abip_sparse.h"
+#include "abip_adjoint.h"
 
 // defined in abip_solve_wg.hip
 hipError_t launch_solve_wg(int nch, int grid, int threads, hipStream_t st, const LPDesc* desc, LPCtrl* ctrl,
@@ -296,6 +297,10 @@ struct abip_work {
     double** adj_ptrs = nullptr;                 // 4*B device pointers: g, dc, db, dA
     int64_t* adj_iters = nullptr; double* adj_resid = nullptr;
     std::vector<int64_t> h_adj_iters; std::vector<double> h_adj_resid;
+    // adjoint of a one-LP handle over the whole GPU (grid and sparse engines)
+    double* big_ws = nullptr;
+    double* sp_abak = nullptr;       // sparse: the solve's CG warm start, kept across a backward
+    bool sp_adjb = false;            // sparse: the border of I - Q is computed
     // grid engine (one LP over the whole GPU)
     bool grid = false;
     int grid_nchw = 1;
@@ -361,6 +366,7 @@ static void release(abip_work* w) {
     (void)hipFree(w->keep.Li64); (void)hipFree(w->keep.Lit64); (void)hipFree(w->keep.Li32); (void)hipFree(w->keep.Lit32);
     (void)hipFree(w->adj_ws); (void)hipFree(w->adj_ows); (void)hipFree(w->adj_ptrs);
     (void)hipFree(w->adj_iters); (void)hipFree(w->adj_resid);
+    (void)hipFree(w->big_ws); (void)hipFree(w->sp_abak);
     (void)hipFree(w->gbuf); (void)hipFree(w->gctl);
     (void)hipFree(w->sp_idx); (void)hipFree(w->sp_val); (void)hipFree(w->sp_vec);
     (void)hipFree(w->sp_grp); (void)hipFree(w->sp_gci); (void)hipFree(w->sp_gva);
@@ -1335,9 +1341,116 @@ extern "C" int abip_solve_batch(abip_work* w, double* const* x, double* const* y
     return solve_all(w, x, y, s, info);
 }
 
+// Sparse engine: the border of I - Q = (I + Q)^T for the adjoint (Section 4.4's
+// Schur reduction with A, H and S changing sign; G = I + A A^T unchanged), by
+// CG to near machine precision, as the setup does for I + Q:
+//   Z_y0 = G^{-1}(b - A c),        Z_x0 = -c - A^T Z_y0,
+//   Z_y1 = G^{-1}(A cbar - bbar),  Z_x1 = cbar - A^T Z_y1,
+//   K_A = I2 - S - H^T Z,  stored inverted in the control block.
+static int sparse_adjoint_border(abip_work* w, double* part) {
+    hipStream_t st = w->stream;
+    const SpArgs& g0 = w->sa;
+    SpArgs g = g0;
+    g.lds_bytes = w->set.lds_resident ? sp_lds_for(w, w->sp_nb) : 0;
+    const int m = g.m, n = g.n;
+    double* Mv = w->Mv;
+    double* Nv = w->Nv;
+    double* zy0 = Mv + MF_ZY0A * w->Mtot; double* zy1 = Mv + MF_ZY1A * w->Mtot;
+    double* zx0 = Nv + NF_ZX0A * w->Ntot; double* zx1 = Nv + NF_ZX1A * w->Ntot;
+    const int32_t bmax = std::max<int32_t>(5000, 20 * w->set.cg_max_iters);
+    HIPCHK(sp_spmv(g.rp, g.ci, g.va, m, g.C, -1.0, g.b, 1.0, zy0, st));        // b - A c (right-hand side in place)
+    HIPCHK(sp_cg_solve(g, zy0, zy0, 1e-14, bmax, w->sp_nb, w->sp_cgit, st));
+    HIPCHK(sp_spmv(g.rp, g.ci, g.va, m, g.CB, 1.0, g.bbar, -1.0, zy1, st));    // A cbar - bbar
+    HIPCHK(sp_cg_solve(g, zy1, zy1, 1e-14, bmax, w->sp_nb, w->sp_cgit, st));
+    HIPCHK(sp_spmv(g.rpt, g.cit, g.vat, n, zy0, -1.0, g.C, -1.0, zx0, st));    // -c - A^T Z_y0
+    HIPCHK(sp_spmv(g.rpt, g.cit, g.vat, n, zy1, -1.0, g.CB, 1.0, zx1, st));    // cbar - A^T Z_y1
+    double bz0, bz1, bbz0, bbz1, cz0, cz1, cbz0, cbz1;
+    HIPCHK(big_dot2(g.b, zy0, g.b, zy1, m, part, &bz0, &bz1, st));
+    HIPCHK(big_dot2(g.bbar, zy0, g.bbar, zy1, m, part, &bbz0, &bbz1, st));
+    HIPCHK(big_dot2(g.C, zx0, g.C, zx1, n, part, &cz0, &cz1, st));
+    HIPCHK(big_dot2(g.CB, zx0, g.CB, zx1, n, part, &cbz0, &cbz1, st));
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, w->sp_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    LPCtrl c;
+    HIPCHK(hipMemcpyAsync(&c, w->dctrl, sizeof c, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (herr) return fail(ABIP_E_HIP, "abip_backward: a grid barrier of the sparse CG timed out");
+    // (H^T Z)_{rq} = h_r^T z_q with h_0 = (-b; c), h_1 = (bbar; -cbar)
+    const double hz0 = -bz0 + cz0, hz1 = -bz1 + cz1, hz2 = bbz0 - cbz0, hz3 = bbz1 - cbz1;
+    const double k00 = 1.0 - hz0, k01 = -c.zbar - hz1, k10 = c.zbar - hz2, k11 = 1.0 - hz3;
+    const double det = k00 * k11 - k01 * k10;
+    c.KA00 = k11 / det; c.KA01 = -k01 / det; c.KA10 = -k10 / det; c.KA11 = k00 / det;
+    HIPCHK(hipMemcpyAsync(w->dctrl, &c, sizeof c, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!w->hctrl.empty()) {
+        w->hctrl[0].KA00 = c.KA00; w->hctrl[0].KA01 = c.KA01; w->hctrl[0].KA10 = c.KA10; w->hctrl[0].KA11 = c.KA11;
+    }
+    w->sp_adjb = true;
+    return ABIP_OK;
+}
+
+// abip_backward on a handle holding one LP for the whole GPU (grid or sparse engine)
+static int backward_big(abip_work* w, const double* gin, double* dc, double* db, double* dA) {
+    hipStream_t st = w->stream;
+    const LPDesc& d = w->hdesc[0];
+    const int m = d.m, n = d.n;
+    const int ldw = w->sparse ? 0 : d.ld;
+    if (!w->big_ws) HIPCHK(hipMalloc((void**)&w->big_ws, sizeof(double) * big_adj_ws_doubles(m, n, ldw)));
+    if (w->h_adj_iters.size() != 1) { w->h_adj_iters.assign(1, 0); w->h_adj_resid.assign(1, 0.0); }
+    BigAdj B{};
+    B.m = m; B.n = n; B.ld = ldw;
+    B.sparse = w->sparse;
+    B.alpha = w->set.alpha;
+    B.ws = w->big_ws;
+    if (w->sparse) {
+        if (!w->sp_abak) HIPCHK(hipMalloc((void**)&w->sp_abak, sizeof(double) * (size_t)m));
+        HIPCHK(hipMemsetAsync(w->sp_bar, 0, 2 * sizeof(unsigned), st));
+        HIPCHK(hipMemsetAsync(w->sp_err, 0, sizeof(int), st));
+        // the last 2 x 512 doubles of the workspace serve the border's dot products
+        double* part = w->big_ws + big_adj_ws_doubles(m, n, ldw) - 1024;
+        HIPCHK(hipMemcpyAsync(w->sp_abak, w->sa.a, sizeof(double) * (size_t)m, hipMemcpyDeviceToDevice, st));
+        if (!w->sp_adjb) {
+            const int rc = sparse_adjoint_border(w, part);
+            if (rc) return rc;
+        }
+        B.sp = w->sa;
+        B.sp.lds_bytes = w->set.lds_resident ? sp_lds_for(w, w->sp_nb) : 0;
+        B.sp_nb = w->sp_nb;
+        B.cg_tol = std::max(1e-13, 0.1 * w->set.adjoint_tol);
+        B.cg_max = std::max<int32_t>(5000, 20 * w->set.cg_max_iters);
+        B.cg_iters = w->sp_cgit;
+        B.A = nullptr; B.G = nullptr;
+    } else {
+        B.A = w->A64 + d.oA;
+        B.G = w->G64 + d.oG;
+    }
+    double* Mv = w->Mv;
+    double* Nv = w->Nv;
+    B.X = Nv + NF_X * w->Ntot + d.on; B.S = Nv + NF_S * w->Ntot + d.on; B.Y = Mv + MF_Y * w->Mtot + d.om;
+    B.b = Mv + MF_B * w->Mtot + d.om; B.bbar = Mv + MF_BBAR * w->Mtot + d.om;
+    B.C = Nv + NF_C * w->Ntot + d.on; B.CB = Nv + NF_CBAR * w->Ntot + d.on;
+    B.zy0 = Mv + MF_ZY0A * w->Mtot + d.om; B.zy1 = Mv + MF_ZY1A * w->Mtot + d.om;
+    B.zx0 = Nv + NF_ZX0A * w->Ntot + d.on; B.zx1 = Nv + NF_ZX1A * w->Ntot + d.on;
+    HIPCHK(hipMemcpyAsync(&B.cl, w->dctrl, sizeof(LPCtrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int herr = 0;
+    int64_t it = 0;
+    double rel = 0.0;
+    const hipError_t e = big_adjoint(B, gin, dc, db, dA, w->sparse ? w->sa.rp : nullptr,
+                                     w->sparse ? w->sa.ci : nullptr, w->set.adjoint_max_iters, w->set.adjoint_tol,
+                                     &it, &rel, &herr, st);
+    if (w->sparse)        // the solve's CG warm start, as it was
+        HIPCHK(hipMemcpyAsync(w->sa.a, w->sp_abak, sizeof(double) * (size_t)m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(e);
+    HIPCHK(hipStreamSynchronize(st));
+    if (herr) return fail(ABIP_E_HIP, "abip_backward: a grid barrier of the sparse CG timed out");
+    w->h_adj_iters[0] = it;
+    w->h_adj_resid[0] = rel;
+    return ABIP_OK;
+}
+
 static int backward_all(abip_work* w, const double* const* g, double* const* dc, double* const* db,
                         double* const* dA) {
-    if (w->sparse) return fail(ABIP_E_STATE, "abip_backward: dense handles only");
     if (w->set.scale_iters) return fail(ABIP_E_STATE, "abip_backward: not available for a scaled LP (settings.scale_iters)");
     if (!w->solved) return fail(ABIP_E_STATE, "abip_backward: call abip_solve first");
     for (int k = 0; k < w->B; ++k) {
@@ -1346,6 +1459,7 @@ static int backward_all(abip_work* w, const double* const* g, double* const* dc,
         if (w->hctrl[k].status != ABIP_SOLVED && !(w->hctrl[k].flags & 4) && w->B == 1)
             return fail(ABIP_E_STATE, "abip_backward: the solve ended with status %d, not SOLVED", w->hctrl[k].status);
     }
+    if (w->grid || w->sparse) return backward_big(w, g[0], dc[0], db[0], dA ? dA[0] : nullptr);
     hipStream_t st = w->stream;
     if (!w->adj_ws) {
         std::vector<int64_t> ows(w->B);
@@ -1382,7 +1496,6 @@ static int backward_all(abip_work* w, const double* const* g, double* const* dc,
     const SolveParams prm = make_params(w->set);
     const int threads = 512;
     const int grid = std::max(1, std::min<int>(w->B, w->cu_count));
-    if (w->grid) return fail(ABIP_E_STATE, "abip_backward: not available for the grid engine (one large LP)");
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, w->queue);
     HIPCHK(hipGetLastError());
     HIPCHK(launch_adjoint(grid, threads, st, w->ddesc, w->dctrl, pools(w), prm, aa, w->order, w->B, w->queue,

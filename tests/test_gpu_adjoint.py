@@ -119,3 +119,84 @@ def test_backward_recovers_from_bicgstab_breakdown():
         # to the vertex derivative depends on how close the planted vertex is to
         # degenerate, so only the KKT adjoint at the same iterate is a bar here
         assert e_kkt <= 1e-3
+
+
+def _csr(lp):
+    import scipy.sparse as sp
+    A = lp["A_csr"]
+    return sp.csr_matrix((A["data"], A["indices"], A["indptr"]), shape=A["shape"])
+
+
+def _one_lp_handle(engine, m, n, seed, **kw):
+    """(handle, dense A, b, c, CSR A or None) of a planted LP on the grid or the sparse engine."""
+    if engine == "grid":
+        lp = lpgen.dense_planted(m, n, seed)
+        w = abip.abip_setup(lp["A"], lp["b"], lp["c"], abip.abip_default_settings(engine=abip.ABIP_ENGINE_GRID, **kw))
+        return w, lp["A"], lp["b"], lp["c"], None
+    lp = lpgen.sparse_planted(m, n, seed, density=0.05)
+    A = _csr(lp)
+    w = abip.abip_setup(A, lp["b"], lp["c"], abip.abip_default_settings(cg_tol=1e-13, cg_max_iters=2000, cg_rule=1,
+                                                                         **kw))
+    return w, A.toarray(), lp["b"], lp["c"], A
+
+
+def _check_against_kkt(engine, A, b, c, st, g, dc, db, dA, Acsr, bar):
+    lam = oracle.kkt_adjoint(A, b, c, st, g)
+    ref = oracle.contract_adjoint(A, b, c, st, lam, want_A=True)
+    dA_ref = ref["dA"]
+    if Acsr is not None:      # the CSR engine returns dL/dA on the stored entries, in CSR order
+        rows = np.repeat(np.arange(Acsr.shape[0]), np.diff(Acsr.indptr))
+        dA_ref = ref["dA"][rows, Acsr.indices]
+    for got, want in [(db, ref["db"]), (dA, dA_ref)]:
+        err = np.abs(_np(got) - want).max() / (1e-12 + np.abs(want).max())
+        assert err < bar, (engine, err)
+    scale = np.abs(lam).max() * (1.0 + np.abs(st.u()).max())
+    assert np.abs(_np(dc) - ref["dc"]).max() <= 1e-2 * bar * scale
+
+
+@pytest.mark.parametrize("engine", ["grid", "sparse"])
+@pytest.mark.parametrize("m,n,seed,t", [(5, 12, 1, 1e-3), (30, 75, 2, 1e-5), (130, 300, 3, 1e-7)])
+def test_backward_one_lp_engines_at_central_point(engine, m, n, seed, t):
+    """The adjoint driven from the host over the whole GPU (one large dense LP, CSR LP)
+    equals the dense KKT adjoint of the central-path system at a central point."""
+    print(f"adjoint {engine} central m={m} n={n} t={t}", flush=True)
+    w, A, b, c, Acsr = _one_lp_handle(engine, m, n, seed)
+    cp = oracle.central_point(A, b, c, t=t)
+    abip.abip_set_state(w, 0, cp.y, cp.x, cp.s, cp.tau, cp.kappa, cp.theta, t)
+    g = np.random.default_rng(seed).standard_normal(n)
+    dc, db, dA = abip.abip_backward(w, g, want_A=True)
+    it, rr = abip.abip_backward_stats(w)
+    print("bicgstab iters", it, "resid", rr, flush=True)
+    assert rr <= 1e-12
+    _check_against_kkt(engine, A, b, c, cp, g, dc, db, dA, Acsr, 1e-7)
+    # a second call reuses the workspace (and, for CSR, the border of I - Q)
+    dc2, db2, _ = abip.abip_backward(w, g)
+    assert np.array_equal(_np(dc2), _np(dc)) and np.array_equal(_np(db2), _np(db))
+
+
+@pytest.mark.parametrize("engine,m,n,seed", [("grid", 300, 700, 5), ("sparse", 150, 420, 6)])
+def test_backward_one_lp_engines_after_solve(engine, m, n, seed):
+    """After a full solve: against the KKT adjoint at the returned iterate; the grid
+    engine's gradients also against the one-workgroup engine's on the same LP."""
+    print(f"adjoint {engine} after solve m={m} n={n}", flush=True)
+    w, A, b, c, Acsr = _one_lp_handle(engine, m, n, seed, eps=1e-7)
+    x, y, s, info = abip.abip_solve(w)
+    assert info["status"] == abip.ABIP_SOLVED
+    g = np.random.default_rng(seed).standard_normal(n)
+    dc, db, dA = abip.abip_backward(w, g, want_A=True)
+    it, rr = abip.abip_backward_stats(w)
+    print("bicgstab iters", it, "resid", rr, flush=True)
+    yv, xv, sv, sc = abip.abip_get_state(w, 0)
+    st = oracle.State(_np(yv), _np(xv), sc["tau"], sc["theta"], _np(sv), sc["kappa"], sc["mu"])
+    # near the optimum the adjoint system is ill conditioned (see the breakdown test)
+    _check_against_kkt(engine, A, b, c, st, g, dc, db, dA, Acsr, 1e-5)
+    if engine == "grid":
+        w1 = abip.abip_setup(A, b, c, abip.abip_default_settings(engine=abip.ABIP_ENGINE_WG))
+        abip.abip_set_state(w1, 0, yv, xv, sv, sc["tau"], sc["kappa"], sc["theta"], sc["mu"])
+        dc1, db1, dA1 = abip.abip_backward(w1, g, want_A=True)
+        for got, want in [(db, db1), (dA, dA1)]:
+            assert np.abs(_np(got) - _np(want)).max() <= 1e-6 * (1 + np.abs(_np(want)).max())
+    if engine == "sparse":   # the solve's state is untouched: solving again gives the same point
+        x2, _, _, info2 = abip.abip_solve(w)
+        assert info2["admm_iters"] == info["admm_iters"]
+        assert np.array_equal(_np(x2), _np(x))
