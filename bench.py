@@ -358,7 +358,7 @@ def extra_basis_pursuit(abip, torch, cpu=True):
                         "frac": survey / ks / 1e9 / HBM_PEAK_GBS,
                         "frac_design_bytes": design / ks / 1e9 / HBM_PEAK_GBS,
                         "bytes_per_update_survey": survey_bytes_per_update(m, n, 4),
-                        "kernel": "grid engine (col + G^-1 + reductions + border)"}}
+                        "kernel": "grid engine (column pass + reduction + G^-1 slice)"}}
     if cpu:
         import oracle
         out["cpu_baseline"] = {

@@ -307,7 +307,7 @@ struct abip_work {
     int grid_wgs = 0;                // workgroups per grid kernel (autotuned)
     GridArgs ga{};
     double* gbuf = nullptr;          // Y2, Pf, Px, pcol, prow, pa, t, a
-    GridCtl* gctl = nullptr;         // 2 control blocks
+    GridCtl* gctl = nullptr;         // 2 control blocks: the pass's state, the decision
     std::vector<LPCtrl> hctrl;
     // sparse engine (one LP, A in CSR, CG on I + A A^T)
     bool sparse = false;
@@ -476,7 +476,7 @@ static void grid_config(abip_work* w, int wgs) {
     cw = ((cw + 7) / 8) * 8;
     g.cw = cw;
     g.NB = (d.n + cw - 1) / cw;
-    g.NR = (d.ld + 31) / 32;       // rows per workgroup of k_grid_red
+    g.NR = (d.ld + GRID_RED_ROWS - 1) / GRID_RED_ROWS;   // workgroups of k_grid_red
     int gw = (d.m + wgs - 1) / wgs;
     gw = ((gw + 7) / 8) * 8;
     g.gw = gw;
@@ -499,11 +499,14 @@ static int grid_prepare(abip_work* w) {
     g.m = d.m; g.n = d.n; g.ld = d.ld;
     w->grid_nchw = grid_nchw(d.ld);
     const int64_t cap = 4 * (int64_t)w->cu_count;
-    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * cap * d.ld + 8 * cap + 8 * (int64_t)((d.ld + 31) / 32) +
-                         4 * cap + 2 * (int64_t)d.ld;
+    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * cap * d.ld + 8 * cap +
+                         8 * (int64_t)((d.ld + GRID_RED_ROWS - 1) / GRID_RED_ROWS) + 4 * cap + 2 * (int64_t)d.ld;
     HIPCHK(hipMalloc((void**)&w->gbuf, sizeof(double) * nbuf));
     HIPCHK(hipMalloc((void**)&w->gctl, sizeof(GridCtl) * 2));
     grid_config(w, w->cu_count);
+    // k_grid_col reads at most two partial sums per thread of each kernel (2 x 512 workgroups)
+    if (g.NR > 1024 || 4 * w->cu_count > 1024)
+        return fail(ABIP_E_INVALID, "grid engine: %d rows or %d compute units exceed its partial-sum layout", d.m, w->cu_count);
     g.A64 = w->A64 + d.oA; g.A32 = w->A32 + d.oA;
     g.G64 = w->G64 + d.oG; g.G32 = w->G32 + d.oG;
     g.b = w->Mv + MF_B * w->Mtot + d.om; g.bbar = w->Mv + MF_BBAR * w->Mtot + d.om;
@@ -596,7 +599,7 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
             for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(w->gexec, w->gstream));
             HIPCHK(hipEventRecord(w->gjoin1, w->gstream));
             HIPCHK(hipStreamWaitEvent(st, w->gjoin1, 0));
-            HIPCHK(hipMemcpyAsync(&hc, w->gctl, sizeof hc, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&hc, w->gctl + 1, sizeof hc, hipMemcpyDeviceToHost, st));   // the decision
             HIPCHK(hipStreamSynchronize(st));
             if (hc.status != 0) break;
             if (reps < 16) reps *= 2;
@@ -605,7 +608,7 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
         int chunk = 16;
         while (true) {
             for (int i = 0; i < chunk; ++i) HIPCHK(grid_launch_iteration(w->grid_nchw, g, st));
-            HIPCHK(hipMemcpyAsync(&hc, w->gctl, sizeof hc, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&hc, w->gctl + 1, sizeof hc, hipMemcpyDeviceToHost, st));   // the decision
             HIPCHK(hipStreamSynchronize(st));
             if (hc.status != 0) break;
             if (chunk < 256) chunk *= 2;
@@ -755,7 +758,7 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
     }
     rc = load_dense(w, A, b, c);
     if (rc) { release(w); delete w; return rc; }
-    hipError_t e = w->grid ? grid_set_smem(w->ldmax) : set_solve_wg_smem_limit(w->wg_smem);
+    hipError_t e = w->grid ? hipSuccess : set_solve_wg_smem_limit(w->wg_smem);
     if (e != hipSuccess) { release(w); delete w; return fail(ABIP_E_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e)); }
     if (w->grid) {
         int rc2 = grid_prepare(w);

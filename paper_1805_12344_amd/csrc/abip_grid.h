@@ -2,6 +2,9 @@
 #pragma once
 #include "abip_internal.h"
 
+// rows per workgroup of k_grid_red (host and device)
+#define GRID_RED_ROWS 8
+
 // Host-visible control block of the grid engine (device memory).
 struct GridCtl {
     // the state the next k_grid_col starts from
@@ -16,7 +19,7 @@ struct GridCtl {
     int64_t iters, iters64, ipm, cp32, cp64, passes;
     int64_t fixed_left;        // fixed mode: updates still to run
     int32_t fixed_mode;        // 1: run exactly fixed_left updates, no tests or restarts
-    int32_t pad2;
+    int32_t decide;            // 1: this block describes a pass whose decision is pending
     // last check
     double pres, dres, gap, pobj, dobj, by, cx;
     double kfx;                // relative KKT of the FP32 phase's last iterate with FP64 data
@@ -42,8 +45,10 @@ struct GridArgs {
     double* pa;                // NG * 4 border dots of a
     double* t;                 // ld
     double* a;                 // ld
-    GridCtl* ctl;              // read-only inside k_grid_col / k_grid_red / k_grid_ginv
-    GridCtl* ctl_next;         // written by k_grid_ginv (workgroup 0), consumed by k_grid_border
+    GridCtl* ctl;              // the pass's state: written by k_grid_col (workgroup 0), read by
+                               // k_grid_red / k_grid_ginv
+    GridCtl* ctl_next;         // its copy for the next k_grid_col (written by k_grid_ginv's
+                               // workgroup 0) and the host
     const LPCtrl* lc;          // K^{-1}, zbar, norms
     SolveParams prm;
 };
@@ -51,7 +56,6 @@ struct GridArgs {
 
 int grid_nchw(int ld);
 hipError_t grid_launch_iteration(int nchw, const GridArgs& g, hipStream_t st);
-hipError_t grid_set_smem(int ld);
 __global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed);
 __global__ void k_grid_finish(GridArgs g, double* Ypool_slice, LPCtrl* lc);
 __global__ void k_grid_from_state(GridArgs g, const double* Yslice, const LPCtrl* lc, int phase, int64_t fixed);
