@@ -37,12 +37,19 @@ HBM_PEAK_GBS = 8000.0
 # (bench.py --copy-calibration).  Keyed by a hash of the kernel's sources: any
 # change to them voids the figure (reported as null until measured again).
 PMC_TRAFFIC = {
-    # k_solve_wg<2, 256> on the 256-LP batch, one step (profiles/k_solve_wg_batched256_pmc.md)
-    "b18b07d907567789": {"fetch_kib": 1020510046.25, "fetch_scale": 1048576.0 / 524315.3125,
+    # k_solve_wg<2, 256, false, false> (beta fixed) on the 256-LP batch, one step
+    "b18b07d907567789:bb0": {"fetch_kib": 1020510046.25, "fetch_scale": 1048576.0 / 524315.3125,
                          "write_kib": 19796195.8125, "write_scale": 1048576.0 / 1048576.0},
+    # k_solve_wg<2, 256, true, false> (adaptive beta, the default) on the same batch, one step
+    # (profiles/k_solve_wg_batched256_pmc.md)
+    "b18b07d907567789:bb1": {"fetch_kib": 1245388554.0, "fetch_scale": 1048576.0 / 524315.3125,
+                             "write_kib": 24280125.4375, "write_scale": 1048576.0 / 1048576.0},
 }
 KERNEL_SOURCES = ["paper_1805_12344_amd/csrc/abip_solve_wg.hip", "paper_1805_12344_amd/csrc/abip_small.h",
                   "paper_1805_12344_amd/csrc/abip_internal.h"]
+
+
+BB_MODE = [1]   # the run's settings.bb (the kernel variant the counters belong to)
 
 
 def kernel_hash():
@@ -156,7 +163,7 @@ def launch_bytes(lps, infos):
 
 
 def traffic_bytes():
-    t = PMC_TRAFFIC.get(kernel_hash())
+    t = PMC_TRAFFIC.get(f"{kernel_hash()}:bb{BB_MODE[0]}")
     if t is None:
         return None
     return t["fetch_kib"] * 1024.0 * t["fetch_scale"] + t["write_kib"] * 1024.0 * t["write_scale"]
@@ -237,7 +244,7 @@ def host_info():
     return model, nproc
 
 
-def cpu_baseline(lps, iters64, correct, budget_iters=1500):
+def cpu_baseline(lps, iters64, correct, budget_iters=1500, bb=False):
     """The FP64 oracle as it stands, timed on the host on a stratified sample of
     the batch, at one BLAS thread and at all host cores.
 
@@ -247,14 +254,16 @@ def cpu_baseline(lps, iters64, correct, budget_iters=1500):
     (1, m n, m^2) and of the setup time against (1, m^2 n) over the sample then
     prices every LP of the batch at its FP64 iteration count (the same count the
     oracle takes: the GPU's FP64 path matches it to 1%), so the estimate covers
-    the whole batch, including the LPs that run to the iteration cap.
+    the whole batch, including the LPs that run to the iteration cap.  bb: the
+    oracle takes the same adaptive beta (Section 4.3) as the GPU solves.
     """
     from threadpoolctl import threadpool_limits
     import oracle
     model, nproc = host_info()
     order = np.argsort([lp["m"] * lp["n"] for lp in lps])
     sample = sorted(set(int(order[i]) for i in np.linspace(0, len(lps) - 1, 10).round().astype(int)) |
-                    {k for k in range(len(lps)) if iters64[k] >= 10 ** 6})
+                    {k for k in range(len(lps)) if iters64[k] >= 10 ** 6} |
+                    {int(k) for k in np.argsort(iters64)[-2:]})
     out = {}
     for label, threads in (("1_thread", 1), ("all_cores", nproc)):
         rows_it, rows_su = [], []
@@ -268,11 +277,12 @@ def cpu_baseline(lps, iters64, correct, budget_iters=1500):
                 t_setup = time.perf_counter() - t0
                 cap = int(min(max(1, iters64[k]), budget_iters))
                 t0 = time.perf_counter()
-                out_k = oracle.solve(prob, settings=oracle.Settings(max_admm_iters=cap), solver=solver)
+                out_k = oracle.solve(prob, settings=oracle.Settings(max_admm_iters=cap, bb=bb), solver=solver)
                 t_it = (time.perf_counter() - t0) / max(1, out_k["admm_iters"])
                 rows_it.append((lp["m"] * lp["n"], lp["m"] ** 2, t_it))
                 rows_su.append((lp["m"] ** 2 * lp["n"], t_setup))
         wall = time.perf_counter() - t_all
+        log(f"cpu_baseline {label}: {wall:.1f} s over {len(sample)} LPs")
         X = np.array([[1.0, r[0], r[1]] for r in rows_it])
         ci, *_ = np.linalg.lstsq(X, np.array([r[2] for r in rows_it]), rcond=None)
         Xs = np.array([[1.0, r[0]] for r in rows_su])
@@ -288,7 +298,7 @@ def cpu_baseline(lps, iters64, correct, budget_iters=1500):
     one = out["1_thread"]
     return {"value": one["value"], "unit": "LP solves/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(sample)} LPs of the batch stratified by m n (indices {sample}, including every LP "
-                      f"at the iteration cap), setup + min(FP64 count, {budget_iters}) oracle iterations each; "
+                      f"at the iteration cap and the two with the most iterations), setup + min(FP64 count, {budget_iters}) oracle iterations each; "
                       f"per-iteration and setup times fitted against (1, m n, m^2) and (1, m^2 n) and summed "
                       f"over all {len(lps)} LPs at their FP64 iteration counts; {one['sample_cpu_seconds']:.1f} s "
                       f"of CPU work at 1 thread",
@@ -600,8 +610,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baselines")
-    ap.add_argument("--plain-sample", type=int, default=0,
-                    help="time the plain FP64 path on this many LPs (0: all LPs of the batch)")
+    ap.add_argument("--plain-sample", type=int, default=48,
+                    help="time the plain FP64 path on this many LPs stratified by m n, plus the two "
+                         "slowest (0: all LPs of the batch)")
     ap.add_argument("--per-lp-out", default=None, help="write the per-LP table (TSV) to this file")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra measurements (basis pursuit, sparse CG, differentiable batch, "
@@ -609,6 +620,9 @@ def main():
     ap.add_argument("--extra-only", default=None,
                     choices=["basis_pursuit", "sparse_cg", "differentiable", "paper_random", "sice", "trsv"],
                     help="run one extra measurement alone, print its JSON object and exit (for profiling)")
+    ap.add_argument("--bb", type=int, default=1, choices=[0, 1],
+                    help="1 (default): the adaptive beta of Section 4.3 in every solve of the headline, "
+                         "its FP64 comparisons and the oracle baseline; 0: beta fixed at settings.beta")
     ap.add_argument("--tune-iters", type=int, default=200,
                     help="updates per autotuner candidate on the batch handle (0: no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -633,7 +647,8 @@ def main():
         return
     lps = make_workload(args.batch, args.seed)
     As, bs, cs = to_device(lps)
-    s32 = abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH)
+    BB_MODE[0] = args.bb
+    s32 = abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH, bb=args.bb)
     log(f"workload: {len(lps)} LPs, sum m*n = {sum(lp['m'] * lp['n'] for lp in lps):.3e}")
 
     # one handle for every step: its buffers are allocated once, each step loads the
@@ -704,6 +719,7 @@ def main():
         "config": {"workload": f"batched dense LPs: {len(lps)} LPs, m~U[20,400], n~U[2m,3m], 10% "
                                f"primal infeasible, seed {args.seed}; eps 1e-6",
                    "global_batch": len(lps), "precision": "fp32 bulk + fp64 polish",
+                   "beta": "adaptive (Section 4.3)" if args.bb else "fixed (settings.beta = 1)",
                    "engine": "one workgroup per LP, persistent, largest first; one handle reloaded "
                              "per step (abip_update_data), graph replayed"},
         "autotune": tune,
@@ -736,13 +752,14 @@ def main():
 
     r64 = None
     if not args.no_compare:
-        s64 = abip.abip_default_settings(precision=abip.ABIP_PREC_FP64)
+        s64 = abip.abip_default_settings(precision=abip.ABIP_PREC_FP64, bb=args.bb)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         xs64, ys64, ss64, infos64 = run_batch(abip, As, bs, cs, s64)
         torch.cuda.synchronize()
         e64 = time.perf_counter() - t1
         r64 = (_host(xs64), _host(ys64), _host(ss64), infos64)
+        log(f"fp64 batched: {e64:.2f} s")
         ok64, worst64, _ = verify(lps, *r64)
         it64 = np.array([i["admm_iters"] for i in infos64])
         line["fp64_batched"] = {"solves_per_s": ok64 / e64, "ms": e64 * 1e3, "correct": ok64,
@@ -750,26 +767,49 @@ def main():
                                 "admm_iters_total": int(it64.sum()), "worst_kkt": worst64}
         line["speedup_vs_fp64_batched"] = solves_per_s / max(1e-12, ok64 / e64)
         line["fp32_error"] = error_report(lps, r32, r64)
-        # the plain FP64 path: one LP per setup/solve call, sequentially
+        # the plain FP64 path: one LP per setup/solve call, sequentially; with
+        # --plain-sample N, N LPs stratified by m n plus the two with the most FP64
+        # iterations, each timed alone, and the batch's sequential time estimated
+        # as the slow two plus the rest scaled to the other LPs
         idx = list(range(len(lps)))
-        if args.plain_sample:
-            rng = np.random.default_rng(0)
-            caps = [k for k in idx if infos64[k]["status"] == 4]
-            rest = sorted(set(rng.choice(len(lps), size=args.plain_sample, replace=False).tolist()) - set(caps))
-            idx = sorted(caps + rest[:max(0, args.plain_sample - len(caps))])
+        slow = set()
+        if args.plain_sample and args.plain_sample < len(lps):
+            order = np.argsort([lp["m"] * lp["n"] for lp in lps])
+            slow = {int(k) for k in np.argsort(it64)[-2:]}
+            strat = {int(order[i]) for i in np.linspace(0, len(lps) - 1, args.plain_sample).round().astype(int)}
+            idx = sorted(slow | strat)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         okp = 0
-        for k in idx:
+        t_slow = t_rest = 0.0
+        for q, k in enumerate(idx):
+            tk = time.perf_counter()
             w = abip.abip_setup(As[k], bs[k], cs[k], s64)
             x, y, s_, info = abip.abip_solve(w)
             w.free()
             okp += verify([lps[k]], [x.cpu().numpy()], [y.cpu().numpy()], [s_.cpu().numpy()], [info])[0]
+            tk = time.perf_counter() - tk
+            if k in slow:
+                t_slow += tk
+            else:
+                t_rest += tk
+            if (q + 1) % 32 == 0:
+                log(f"fp64 plain: {q + 1}/{len(idx)} LPs, {time.perf_counter() - t2:.1f} s")
         torch.cuda.synchronize()
         ep = time.perf_counter() - t2
-        line["fp64_plain_sequential"] = {"solves_per_s": okp / ep, "lps": len(idx), "correct": okp, "ms": ep * 1e3,
-                                         "sample": None if len(idx) == len(lps) else idx}
-        line["speedup_vs_fp64_plain"] = solves_per_s / max(1e-12, okp / ep)
+        if len(idx) == len(lps):
+            est, rate = ep, okp / ep
+        else:
+            est = t_slow + t_rest * (len(lps) - len(slow)) / max(1, len(idx) - len(slow))
+            rate = len(lps) * (okp / len(idx)) / est
+        line["fp64_plain_sequential"] = {
+            "solves_per_s": rate, "lps": len(idx), "correct": okp, "ms": ep * 1e3,
+            "batch_seconds": est,
+            "sample": None if len(idx) == len(lps) else
+            f"{len(idx)} LPs (indices {idx}): {args.plain_sample} stratified by m n plus the two with the most "
+            f"FP64 iterations ({sorted(slow)}); the batch's sequential time is those two plus the others "
+            f"scaled by {len(lps) - len(slow)}/{len(idx) - len(slow)}"}
+        line["speedup_vs_fp64_plain"] = solves_per_s / max(1e-12, rate)
         iters64 = it64
     else:
         iters64 = iters
@@ -791,7 +831,7 @@ def main():
 
     if not args.no_cpu:
         t0 = time.perf_counter()
-        line["cpu_baseline"] = cpu_baseline(lps, iters64, ok)
+        line["cpu_baseline"] = cpu_baseline(lps, iters64, ok, bb=bool(args.bb))
         log(f"cpu_baseline: {time.perf_counter() - t0:.1f} s")
 
     print(json.dumps(line), flush=True)
