@@ -244,45 +244,68 @@ def host_info():
     return model, nproc
 
 
-def cpu_baseline(lps, iters64, correct, budget_iters=1500, bb=False):
+def _oracle_lp_times(A, b, c, cap, bb):
+    """(setup seconds, seconds per iteration) of the oracle on one LP, at the
+    caller's BLAS thread setting: Schur solver set up once, then `cap` updates."""
+    import oracle
+    prob = oracle.Problem(A, b, c)
+    t0 = time.perf_counter()
+    solver = oracle.SchurIQSolver(prob)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    out = oracle.solve(prob, settings=oracle.Settings(max_admm_iters=cap, bb=bb), solver=solver)
+    return t_setup, (time.perf_counter() - t0) / max(1, out["admm_iters"])
+
+
+def _pool_job(args):
+    """One oracle job of the process-pool measurement (a worker process, one BLAS thread)."""
+    from threadpoolctl import threadpool_limits
+    A, b, c, cap, bb = args
+    with threadpool_limits(limits=1):
+        return _oracle_lp_times(A, b, c, cap, bb)[1]
+
+
+def cpu_baseline(lps, iters64, correct, budget_iters=1500, bb=False, reps=3):
     """The FP64 oracle as it stands, timed on the host on a stratified sample of
-    the batch, at one BLAS thread and at all host cores.
+    the batch: at one BLAS thread, at all host cores, and as a process pool.
 
     Every sampled LP runs its setup (Schur solver: Cholesky of G, border) and
     min(its FP64 iteration count, budget_iters) oracle iterations (tests every
-    iteration).  A least-squares fit of the per-iteration time against
-    (1, m n, m^2) and of the setup time against (1, m^2 n) over the sample then
-    prices every LP of the batch at its FP64 iteration count (the same count the
-    oracle takes: the GPU's FP64 path matches it to 1%), so the estimate covers
-    the whole batch, including the LPs that run to the iteration cap.  bb: the
-    oracle takes the same adaptive beta (Section 4.3) as the GPU solves.
+    iteration), `reps` times; the medians are kept.  A least-squares fit of the
+    per-iteration time against (1, m n, m^2) and of the setup time against
+    (1, m^2 n) over the sample then prices every LP of the batch at its FP64
+    iteration count (the same count the oracle takes: the GPU's FP64 path
+    matches it to 1%), so the estimate covers the whole batch, including the
+    slowest LPs.  bb: the oracle takes the same adaptive beta (Section 4.3) as
+    the GPU solves.  Process pool: one worker per host core, one BLAS thread
+    each, the LPs spread over the workers; its rate is the one-thread rate times
+    the number of workers times their parallel efficiency, measured by running
+    one job per worker at once on the sample's median LP.
     """
     from threadpoolctl import threadpool_limits
-    import oracle
     model, nproc = host_info()
     order = np.argsort([lp["m"] * lp["n"] for lp in lps])
     sample = sorted(set(int(order[i]) for i in np.linspace(0, len(lps) - 1, 10).round().astype(int)) |
                     {k for k in range(len(lps)) if iters64[k] >= 10 ** 6} |
                     {int(k) for k in np.argsort(iters64)[-2:]})
     out = {}
+    per_it_1 = {}
     for label, threads in (("1_thread", 1), ("all_cores", nproc)):
         rows_it, rows_su = [], []
         t_all = time.perf_counter()
         with threadpool_limits(limits=threads):
             for k in sample:
                 lp = lps[k]
-                prob = oracle.Problem(lp["A"], lp["b"], lp["c"])
-                t0 = time.perf_counter()
-                solver = oracle.SchurIQSolver(prob)
-                t_setup = time.perf_counter() - t0
                 cap = int(min(max(1, iters64[k]), budget_iters))
-                t0 = time.perf_counter()
-                out_k = oracle.solve(prob, settings=oracle.Settings(max_admm_iters=cap, bb=bb), solver=solver)
-                t_it = (time.perf_counter() - t0) / max(1, out_k["admm_iters"])
+                runs = [_oracle_lp_times(lp["A"], lp["b"], lp["c"], cap, bb) for _ in range(reps)]
+                t_setup = float(np.median([r[0] for r in runs]))
+                t_it = float(np.median([r[1] for r in runs]))
+                if threads == 1:
+                    per_it_1[k] = t_it
                 rows_it.append((lp["m"] * lp["n"], lp["m"] ** 2, t_it))
                 rows_su.append((lp["m"] ** 2 * lp["n"], t_setup))
         wall = time.perf_counter() - t_all
-        log(f"cpu_baseline {label}: {wall:.1f} s over {len(sample)} LPs")
+        log(f"cpu_baseline {label}: {wall:.1f} s over {len(sample)} LPs x {reps}")
         X = np.array([[1.0, r[0], r[1]] for r in rows_it])
         ci, *_ = np.linalg.lstsq(X, np.array([r[2] for r in rows_it]), rcond=None)
         Xs = np.array([[1.0, r[0]] for r in rows_su])
@@ -295,14 +318,35 @@ def cpu_baseline(lps, iters64, correct, budget_iters=1500, bb=False):
             total += t_su + t_it * iters64[k]
         out[label] = {"value": correct / total, "threads": threads, "batch_seconds_estimated": total,
                       "sample_cpu_seconds": wall}
+    # process pool: parallel efficiency of nproc concurrent one-thread jobs
+    pool = None
+    try:
+        import multiprocessing as mp
+        kmid = sorted(sample, key=lambda k: lps[k]["m"] * lps[k]["n"])[len(sample) // 2]   # median size
+        lp = lps[kmid]
+        cap = int(min(max(1, iters64[kmid]), budget_iters))
+        t0 = time.perf_counter()
+        from concurrent.futures import ProcessPoolExecutor
+        # spawned workers (no GPU state), one job each; a failed worker raises instead of hanging
+        with ProcessPoolExecutor(max_workers=nproc, mp_context=mp.get_context("spawn")) as ex:
+            list(ex.map(_pool_job, [(lp["A"], lp["b"], lp["c"], 50, bb)] * nproc, timeout=600))   # workers warm
+            times = list(ex.map(_pool_job, [(lp["A"], lp["b"], lp["c"], cap, bb)] * nproc, timeout=600))
+        eff = per_it_1[kmid] / float(np.median(times))
+        one_total = out["1_thread"]["batch_seconds_estimated"]
+        pool = {"value": correct / (one_total / (nproc * eff)), "workers": nproc, "parallel_efficiency": eff,
+                "probe_lp": kmid, "seconds": time.perf_counter() - t0}
+        log(f"cpu_baseline process_pool: efficiency {eff:.2f} over {nproc} workers")
+    except Exception as exc:          # the pool is a reported extra, never a failure of the bench
+        pool = {"error": repr(exc)}
     one = out["1_thread"]
     return {"value": one["value"], "unit": "LP solves/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(sample)} LPs of the batch stratified by m n (indices {sample}, including every LP "
-                      f"at the iteration cap and the two with the most iterations), setup + min(FP64 count, {budget_iters}) oracle iterations each; "
+                      f"at the iteration cap and the two with the most iterations), setup + min(FP64 count, "
+                      f"{budget_iters}) oracle iterations each, median of {reps} runs; "
                       f"per-iteration and setup times fitted against (1, m n, m^2) and (1, m^2 n) and summed "
                       f"over all {len(lps)} LPs at their FP64 iteration counts; {one['sample_cpu_seconds']:.1f} s "
                       f"of CPU work at 1 thread",
-            "all_cores": out["all_cores"], "host_cpu": model, "nproc": nproc}
+            "all_cores": out["all_cores"], "process_pool": pool, "host_cpu": model, "nproc": nproc}
 
 
 def cpu_time_single(A, b, c, iters_total, sample_iters, solver_fn, threads):
