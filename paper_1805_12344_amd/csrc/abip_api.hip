@@ -78,6 +78,10 @@ static int fail(int code, const char* fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    // a failed runtime call (an allocation beyond the device's memory, say) also
+    // leaves HIP's last-error state set; read it here, so that the next call's
+    // launch checks do not report this failure again
+    (void)hipGetLastError();
     return code;
 }
 

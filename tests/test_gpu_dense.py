@@ -187,6 +187,32 @@ def test_boundary_errors():
     assert info["status"] == abip.ABIP_MAX_ITERS and info["admm_iters"] == 5
 
 
+def test_out_of_device_memory_is_reported_and_frees_what_it_took():
+    """A batch whose pools exceed the GPU's memory (every LP points at the same 1000 x 3000
+    A, so the caller holds one copy): ABIP_E_OOM, the allocations made before the failing
+    one released, and a normal setup and solve afterwards."""
+    m, n = 1000, 3000
+    total = torch.cuda.get_device_properties(0).total_memory
+    B = int(1.25 * total // (8 * m * n)) + 1          # the FP64 copies of A alone exceed the memory
+    print(f"oom batch B={B} of {m}x{n}", flush=True)
+    A = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+    b = torch.zeros(m, dtype=torch.float64, device="cuda")
+    c = torch.ones(n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    with pytest.raises(abip.ABIPError) as e:
+        abip.abip_setup_batch([A] * B, [b] * B, [c] * B)
+    assert e.value.code == abip.ABIP_E_OOM, str(e.value)
+    assert "out of device memory" in str(e.value) or "hipMalloc" in str(e.value)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 >= free0 - (64 << 20), (free0, free1)
+    lp = lpgen.dense_planted(30, 75, 2)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"])
+    x, y, s, info = abip.abip_solve(w)
+    assert info["status"] == abip.ABIP_SOLVED
+
+
 @pytest.mark.parametrize("engine", ["wg", "grid"])
 def test_fp32_floor_hands_over_to_fp64(engine):
     """Infeasible LPs whose FP32 inner loop settles above mu: the FP32 phase must
