@@ -62,7 +62,12 @@ __global__ void k_ruiz_max(const LPDesc*, const double*, double*, double*, int64
 __global__ void k_ruiz_apply(const LPDesc*, double*, double*, int64_t, int64_t);
 __global__ void k_ruiz_scale(const LPDesc*, double*, float*, const double*, const double*, int64_t, int64_t);
 __global__ void k_setup_rows(const LPDesc*, const double* const*, const double* const*, const double*,
-                             double*, double*, int64_t, int64_t, int*);
+                             double*, double*, int64_t, int64_t, int*, int);
+__global__ void k_setup_rows_part(const LPDesc*, const double* const*, const double*, const double*, int64_t, int,
+                                  double*);
+__global__ void k_setup_rows_fin(const LPDesc*, const double* const*, const double*, int, double*, int64_t, int*);
+static const int ROWS_CW = 64;     // columns per chunk of the one-large-LP row sums
+static int64_t grid_rows_scratch(int n, int ld) { return (int64_t)3 * ((n + ROWS_CW - 1) / ROWS_CW) * ld; }
 __global__ void k_setup_border(const LPDesc*, const double*, const double*, double*, double*, int64_t,
                                int64_t, LPCtrl*, int);
 
@@ -741,7 +746,8 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
         w->hdesc[k].oL = hoL[k];
         mmax = std::max(mmax, d.m);
     }
-    const int64_t btot = w->grid ? grid_border_scratch(w->hdesc[0].m, w->hdesc[0].n, w->hdesc[0].ld) : 1;
+    const int64_t btot = w->grid ? std::max(grid_border_scratch(w->hdesc[0].m, w->hdesc[0].n, w->hdesc[0].ld),
+                                            grid_rows_scratch(w->hdesc[0].n, w->hdesc[0].ld)) : 1;
     ALLOC(w->suW, wtot); ALLOC(w->suoW, B); ALLOC(w->suL, ltot); ALLOC(w->suoL, B); ALLOC(w->suB, btot);
     ALLOC(w->suA, B); ALLOC(w->sub, B); ALLOC(w->suc, B);
     if (s.lin_solver == ABIP_LIN_TRSV) {
@@ -831,8 +837,18 @@ static int load_dense(abip_work* w, const abip_matrix* A, const double* const* b
         SCHK(hipGetLastError());
     }
     hipLaunchKernelGGL(k_setup_rows, dim3(maxrowblk, B), dim3(256), 0, st, w->ddesc, dbp, dcp, w->A64, w->Mv, w->Nv,
-                       w->Mtot, w->Ntot, w->errflag);
+                       w->Mtot, w->Ntot, w->errflag, w->grid ? 0 : 1);
     SCHK(hipGetLastError());
+    if (w->grid) {     // one large LP: its row sums over column chunks, on every CU
+        const LPDesc& d0 = w->hdesc[0];
+        const int nch = (d0.n + ROWS_CW - 1) / ROWS_CW;
+        hipLaunchKernelGGL(k_setup_rows_part, dim3((d0.m + 255) / 256, nch), dim3(256), 0, st, w->ddesc, dcp,
+                           w->A64, w->Nv, w->Ntot, ROWS_CW, w->suB);
+        SCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_setup_rows_fin, dim3((d0.ld + 255) / 256), dim3(256), 0, st, w->ddesc, dbp, w->suB, nch,
+                           w->Mv, w->Mtot, w->errflag);
+        SCHK(hipGetLastError());
+    }
     // G = I + A A^T, its Cholesky factor and G^{-1} on the matrix cores (every LP at once)
     SCHK(factor_ginv(w->ddesc, B, w->mmax, w->A64, w->G64, w->G32, w->suL, w->suoL, w->suW, w->suoW, w->errflag,
                      w->keep.L64 ? &w->keep : nullptr, st));

@@ -162,7 +162,8 @@ __global__ __launch_bounds__(256) void k_setup_rows(const LPDesc* __restrict__ d
                                                     const double* const* __restrict__ cuser,
                                                     const double* __restrict__ A64,
                                                     double* __restrict__ Mv, double* __restrict__ Nv,
-                                                    int64_t Mtot, int64_t Ntot, int* __restrict__ errflag) {
+                                                    int64_t Mtot, int64_t Ntot, int* __restrict__ errflag,
+                                                    int rows) {
     const int k = blockIdx.y;
     const LPDesc d = desc[k];
     const double* A = A64 + d.oA;
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_setup_rows(const LPDesc* __restrict__ d
         Nv[NF_C * Ntot + d.on + j] = cj;
         Nv[NF_CBAR * Ntot + d.on + j] = cj - 1.0;
     }
-    if (i >= d.ld) return;
+    if (!rows || i >= d.ld) return;      // rows == 0: k_setup_rows_part / _fin form them
     if (i >= d.m) {   // zero padding rows of every m-field
         for (int f = 0; f < NMF; ++f) Mv[f * Mtot + d.om + i] = 0.0;
         return;
@@ -191,6 +192,64 @@ __global__ __launch_bounds__(256) void k_setup_rows(const LPDesc* __restrict__ d
         sc = fma(a, cj, sc);
         scb = fma(a, cj - 1.0, scb);
     }
+    if (!isfinite(b[i])) atomicOr(errflag, 2);
+    const double bi = Mv[MF_SD * Mtot + d.om + i] * b[i];
+    Mv[MF_B * Mtot + d.om + i] = bi;
+    Mv[MF_BBAR * Mtot + d.om + i] = bi - se;
+    Mv[MF_AC * Mtot + d.om + i] = sc;
+    Mv[MF_ACBAR * Mtot + d.om + i] = scb;
+}
+
+// One large LP (LP 0): the row sums of k_setup_rows (A e, A c, A cbar with the
+// scaled c) over column chunks of cw columns, so that every CU takes part:
+// P[(3 chunk + q) ld + i], q = 0, 1, 2 for e, c, cbar; k_setup_rows_fin adds
+// the chunks of a row in chunk order.
+__global__ __launch_bounds__(256) void k_setup_rows_part(const LPDesc* __restrict__ desc,
+                                                         const double* const* __restrict__ cuser,
+                                                         const double* __restrict__ A64,
+                                                         const double* __restrict__ Nv, int64_t Ntot, int cw,
+                                                         double* __restrict__ P) {
+    const LPDesc d = desc[0];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.m) return;
+    const double* A = A64 + d.oA;
+    const double* c = cuser[0];
+    const double* Ev = Nv + NF_SE * Ntot + d.on;
+    const int j0 = blockIdx.y * cw, j1 = min(d.n, j0 + cw);
+    double se = 0.0, sc = 0.0, scb = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const double a = A[(int64_t)j * d.ld + i];
+        const double cj = Ev[j] * c[j];
+        se += a;
+        sc = fma(a, cj, sc);
+        scb = fma(a, cj - 1.0, scb);
+    }
+    const int64_t o = (int64_t)3 * blockIdx.y * d.ld + i;
+    P[o] = se;
+    P[o + d.ld] = sc;
+    P[o + 2 * (int64_t)d.ld] = scb;
+}
+
+__global__ __launch_bounds__(256) void k_setup_rows_fin(const LPDesc* __restrict__ desc,
+                                                        const double* const* __restrict__ buser,
+                                                        const double* __restrict__ P, int nch,
+                                                        double* __restrict__ Mv, int64_t Mtot,
+                                                        int* __restrict__ errflag) {
+    const LPDesc d = desc[0];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.ld) return;
+    if (i >= d.m) {   // zero padding rows of every m-field
+        for (int f = 0; f < NMF; ++f) Mv[f * Mtot + d.om + i] = 0.0;
+        return;
+    }
+    double se = 0.0, sc = 0.0, scb = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int64_t o = (int64_t)3 * ch * d.ld + i;
+        se += P[o];
+        sc += P[o + d.ld];
+        scb += P[o + 2 * (int64_t)d.ld];
+    }
+    const double* b = buser[0];
     if (!isfinite(b[i])) atomicOr(errflag, 2);
     const double bi = Mv[MF_SD * Mtot + d.om + i] * b[i];
     Mv[MF_B * Mtot + d.om + i] = bi;
