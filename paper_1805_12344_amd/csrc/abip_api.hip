@@ -494,7 +494,8 @@ static void grid_config(abip_work* w, int wgs) {
     g.Y2 = p; p += 2 * d.ld;
     g.Pf = p; p += (int64_t)cap * d.ld;
     g.Px = p; p += (int64_t)cap * d.ld;
-    g.pcol = p; p += 8 * (int64_t)cap;
+    g.pcol = p; p += 16 * (int64_t)cap;
+    g.pcol_stride = 8 * cap;
     g.prow = p; p += 8 * (int64_t)g.NR;
     g.pa = p; p += 4 * (int64_t)cap;
     g.t = p; p += d.ld;
@@ -508,7 +509,7 @@ static int grid_prepare(abip_work* w) {
     g.m = d.m; g.n = d.n; g.ld = d.ld;
     w->grid_nchw = grid_nchw(d.ld);
     const int64_t cap = 4 * (int64_t)w->cu_count;
-    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * cap * d.ld + 8 * cap +
+    const int64_t nbuf = 2 * (int64_t)d.ld + 2 * cap * d.ld + 16 * cap +
                          8 * (int64_t)((d.ld + GRID_RED_ROWS - 1) / GRID_RED_ROWS) + 4 * cap + 2 * (int64_t)d.ld;
     HIPCHK(hipMalloc((void**)&w->gbuf, sizeof(double) * nbuf));
     HIPCHK(hipMalloc((void**)&w->gctl, sizeof(GridCtl) * 2));

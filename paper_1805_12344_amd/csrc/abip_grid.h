@@ -40,7 +40,8 @@ struct GridArgs {
     double* Y2;                // 2 * ld: current / next y
     double* Pf;                // NB * ld partial A(x+s)
     double* Px;                // NB * ld partial A x
-    double* pcol;              // NB * 8 column-side sums
+    double* pcol;              // 2 x pcol_stride column-side sums (NB * 8 used), by pass parity
+    int32_t pcol_stride;
     double* prow;              // NR * 8 row-side sums
     double* pa;                // NG * 4 border dots of a
     double* t;                 // ld

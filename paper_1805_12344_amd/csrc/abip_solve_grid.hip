@@ -302,16 +302,20 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
     // thread), then with one row chunk per lane this lane's rows of a, Z_y and
     // the current y, then the first group of columns.  No loop among them, so
     // waiting for the first loads leaves the later ones in flight.
+    // The column sums sit in two buffers by the parity of the pass count: this
+    // pass reads the last pass's while its own workgroups, which may finish
+    // before a late one starts, write the other.
     double sm[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) sm[k] = 0.0;
     if (decide) {
+        const double* pc = g.pcol + (c.passes & 1) * (int64_t)g.pcol_stride;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int q = threadIdx.x + h * 512;
             if (q < g.NB) {
 #pragma unroll
-                for (int k = 0; k < 7; ++k) sm[k] += g.pcol[q * 8 + k];
+                for (int k = 0; k < 7; ++k) sm[k] += pc[q * 8 + k];
             }
             if (q < g.NR) {
 #pragma unroll
@@ -427,8 +431,10 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
     // column-side sums (only threads < U hold them)
     double t8[8] = {acc7[0], acc7[1], acc7[2], acc7[3], acc7[4], acc7[5], acc7[6], 0.0};
     block_sum_n<8>(t8, sd + 2 * GRID_W * 2 * GRID_UNR);      // apart from the halves the last group read
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 8; ++q) g.pcol[blockIdx.x * 8 + q] = t8[q];
+    if (threadIdx.x == 0) {
+        double* pc = g.pcol + (c.passes & 1) * (int64_t)g.pcol_stride;   // after this pass's decision
+        for (int q = 0; q < 8; ++q) pc[blockIdx.x * 8 + q] = t8[q];
+    }
     return false;
 }
 
