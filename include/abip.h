@@ -150,6 +150,16 @@ typedef struct {
                                   barriers, but it gathers a 32-byte CG record per entry of G~, so
                                   it pays only when G~ is about as sparse as A.  0 (default): the
                                   two products.  abip_info.gram_nnz says which ran. */
+    int32_t grid_mirror;       /* one large dense LP (grid engine): 1 (default) tests at setup (and at
+                                  each abip_update_data) whether n is even and the last n/2 columns of
+                                  A are exactly the negated first n/2 (A = [A0, -A0], the split of a
+                                  free variable into x+ - x-, as in basis pursuit); if so, each column
+                                  pass reads A0 alone and treats column j and column j + n/2 together
+                                  (their A^T products differ only in sign; their contributions to
+                                  A (x+s) and A x are formed as A0 (f_j - f_{j+n/2})), so A is read
+                                  half as often.  Same iteration and tests; the row sums are formed
+                                  in a different order, so results agree to rounding, not bitwise.
+                                  0: every column is read.  abip_info.grid_mirror says which ran. */
 } abip_settings;
 
 /* Per-LP result summary (host struct). */
@@ -197,6 +207,8 @@ typedef struct {
     int32_t bb_estimates;      /* beta estimates taken (redos included) */
     int64_t gram_nnz;          /* sparse engine: entries of the explicit G~ = A A^T, 0 when the CG
                                   multiplies by A^T and A */
+    int32_t grid_mirror;       /* 1: the grid engine's column passes read A0 of A = [A0, -A0] alone
+                                  (settings.grid_mirror and the pairing test passed); 0 otherwise */
 } abip_info;
 
 /* A matrix description.  All pointers are device pointers; abip_setup copies

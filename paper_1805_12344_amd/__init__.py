@@ -44,6 +44,7 @@ class abip_settings(ctypes.Structure):
         ("lds_resident", ctypes.c_int32),
         ("bb", ctypes.c_int32), ("bb_max_redo", ctypes.c_int32), ("bb_eps_cor", ctypes.c_double),
         ("bb_eps_penalty", ctypes.c_double), ("scale_iters", ctypes.c_int32), ("sparse_gram", ctypes.c_int32),
+        ("grid_mirror", ctypes.c_int32),
     ]
 
 
@@ -62,7 +63,7 @@ class abip_info(ctypes.Structure):
         ("ginv_hbm_fp32", ctypes.c_int64), ("ginv_hbm_fp64", ctypes.c_int64),
         ("lds_mode", ctypes.c_int32), ("fp32_exit_kkt", ctypes.c_double), ("err_vs_fp64", ctypes.c_double),
         ("beta", ctypes.c_double), ("bb_probe_iters", ctypes.c_int64), ("bb_estimates", ctypes.c_int32),
-        ("gram_nnz", ctypes.c_int64),
+        ("gram_nnz", ctypes.c_int64), ("grid_mirror", ctypes.c_int32),
     ]
 
     def as_dict(self):

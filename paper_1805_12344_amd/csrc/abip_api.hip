@@ -314,6 +314,7 @@ struct abip_work {
     bool grid = false;
     int grid_nchw = 1;
     int grid_wgs = 0;                // workgroups per grid kernel (autotuned)
+    int grid_pairs = 0;              // A = [A0, -A0] detected (settings.grid_mirror): n / 2, else 0
     GridArgs ga{};
     double* gbuf = nullptr;          // Y2, Pf, Px, pcol, prow, pa, t, a
     GridCtl* gctl = nullptr;         // 2 control blocks: the pass's state, the decision
@@ -418,6 +419,7 @@ extern "C" int abip_default_settings(abip_settings* s) {
     s->bb_eps_penalty = 0.1;
     s->scale_iters = 0;
     s->sparse_gram = 0;
+    s->grid_mirror = 1;
     return ABIP_OK;
 }
 
@@ -444,6 +446,7 @@ static int check_settings(const abip_settings& s) {
         return fail(ABIP_E_INVALID, "settings.bb_eps_penalty must be >= 0");
     if (s.scale_iters < 0 || s.scale_iters > 100) return fail(ABIP_E_INVALID, "settings.scale_iters must lie in [0,100]");
     if (s.sparse_gram != 0 && s.sparse_gram != 1) return fail(ABIP_E_INVALID, "settings.sparse_gram must be 0 or 1");
+    if (s.grid_mirror != 0 && s.grid_mirror != 1) return fail(ABIP_E_INVALID, "settings.grid_mirror must be 0 or 1");
     if (s.lin_solver < ABIP_LIN_AUTO || s.lin_solver > ABIP_LIN_TRSV)
         return fail(ABIP_E_INVALID, "settings.lin_solver: unknown value %d", s.lin_solver);
     if (s.lin_solver == ABIP_LIN_TRSV && s.bb)
@@ -481,10 +484,12 @@ static void grid_config(abip_work* w, int wgs) {
     GridArgs& g = w->ga;
     const int cap = 4 * w->cu_count;
     wgs = std::max(1, std::min(wgs, cap));
-    int cw = (d.n + wgs - 1) / wgs;
+    const int ncol = w->grid_pairs > 0 ? w->grid_pairs : d.n;   // the column pass walks pairs when paired
+    int cw = (ncol + wgs - 1) / wgs;
     cw = ((cw + 7) / 8) * 8;
     g.cw = cw;
-    g.NB = (d.n + cw - 1) / cw;
+    g.NB = (ncol + cw - 1) / cw;
+    g.n2 = w->grid_pairs;
     g.NR = (d.ld + GRID_RED_ROWS - 1) / GRID_RED_ROWS;   // workgroups of k_grid_red
     int gw = (d.m + wgs - 1) / wgs;
     gw = ((gw + 7) / 8) * 8;
@@ -864,12 +869,21 @@ static int load_dense(abip_work* w, const abip_matrix* A, const double* const* b
             SCHK(hipGetLastError());
         }
     }
+    // one large LP with an even column count: is A = [A0, -A0]? (bit 16 when not)
+    const bool pair_test = w->grid && w->set.grid_mirror && w->hdesc[0].n % 2 == 0;
+    if (pair_test) {
+        const LPDesc& d0 = w->hdesc[0];
+        hipLaunchKernelGGL(k_grid_pair_check, dim3(d0.n / 2), dim3(256), 0, st, w->A64 + d0.oA, d0.m, d0.ld,
+                           d0.n / 2, w->errflag);
+        SCHK(hipGetLastError());
+    }
     int hflag = 0;
     SCHK(hipMemcpyAsync(&hflag, w->errflag, sizeof(int), hipMemcpyDeviceToHost, st));
     SCHK(hipStreamSynchronize(st));
 #undef SCHK
     if (hflag & 3) return fail(ABIP_E_NONFINITE, "NaN or Inf in %s", (hflag & 1) ? "A" : "b or c");
     if (hflag & 4) return fail(ABIP_E_HIP, "Cholesky of I + A A^T met a non-positive pivot");
+    w->grid_pairs = (pair_test && !(hflag & 16)) ? w->hdesc[0].n / 2 : 0;
     w->solved = false;
     return ABIP_OK;
 }
@@ -1216,6 +1230,7 @@ extern "C" int abip_update_data(abip_work* w, const abip_matrix* A, const double
     const double t0 = now_ms();
     const int rc = load_dense(w, A, b, c);
     if (rc) return rc;
+    if (w->grid) grid_config(w, w->grid_wgs);     // the column split follows the new data's pairing
     w->setup_ms = now_ms() - t0;
     return ABIP_OK;
 }
@@ -1346,6 +1361,7 @@ static int solve_all(abip_work* w, double* const* x, double* const* y, double* c
         for (int k = 0; k < w->B; ++k) {
             fill_info(&info[k], w->hctrl[k], w->hdesc[k], w->setup_ms, ms, (double)kms);
             info[k].gram_nnz = w->sp_gram_nnz;
+            info[k].grid_mirror = w->grid && w->grid_pairs > 0 ? 1 : 0;
         }
     w->solved = true;
     return ABIP_OK;

@@ -31,7 +31,8 @@ struct GridCtl {
 struct GridArgs {
     int32_t m, n, ld;
     int32_t NB, NR, NG;        // workgroups of the three kernels
-    int32_t cw, gw;            // columns per workgroup (k_grid_col, k_grid_ginv)
+    int32_t cw, gw;            // columns (column pairs when n2 > 0) per workgroup (k_grid_col, k_grid_ginv)
+    int32_t n2;                // A = [A0, -A0]: n / 2, and k_grid_col reads A0 only; 0 otherwise
     const double* A64; const float* A32;
     const double* G64; const float* G32;
     const double *b, *bbar, *Ac, *Acb, *Zy0, *Zy1;
@@ -58,5 +59,6 @@ struct GridArgs {
 int grid_nchw(int ld);
 hipError_t grid_launch_iteration(int nchw, const GridArgs& g, hipStream_t st);
 __global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed);
+__global__ void k_grid_pair_check(const double* A, int m, int ld, int n2, int* flag);
 __global__ void k_grid_finish(GridArgs g, double* Ypool_slice, LPCtrl* lc);
 __global__ void k_grid_from_state(GridArgs g, const double* Yslice, const LPCtrl* lc, int phase, int64_t fixed);

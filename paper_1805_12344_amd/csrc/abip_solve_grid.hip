@@ -154,7 +154,10 @@ __device__ __forceinline__ void grid_decide(const GridArgs& g, GridCtl& c, const
 // Takes the pending decision of the last pass first.  Returns true when that
 // decision moves the LP to FP64 data: the caller then runs the FP64
 // instantiation, which takes the same decision again from the same inputs.
-template <int NCHW, typename T, int U>
+// MIR (A = [A0, -A0], g.n2 = n / 2 column pairs): the pass reads the columns of
+// A0 only; column j + n2 of A takes the negated products of column j, and the
+// pair adds A0 (f_j - f_{j+n2}) to the row sums.
+template <int NCHW, typename T, int U, bool MIR>
 __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double* sd) {
     GridCtl c = *g.ctl_next;                   // the last pass, its decision pending (c.decide)
     const bool decide = c.decide != 0;
@@ -172,19 +175,28 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
     const double alpha = g.prm.alpha, gamma = g.prm.gamma;
     const double sg = sqrt(gamma);
     const int rule = g.prm.restart_rule;
+    const int ncol = MIR ? g.n2 : n;               // columns (pairs) the pass walks
     const int j_begin = blockIdx.x * g.cw;
-    const int j_end = min(n, j_begin + g.cw);
+    const int j_end = min(ncol, j_begin + g.cw);
+    constexpr int LU = MIR ? 2 * U : U;            // lanes that own a column of a group
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     T va[U][R], vb[U][R];
-    // per-column data of a group, loaded with it by lanes u < U (lane u: column
-    // col0 + u; the other lanes load a valid neighbour and ignore it)
+    // per-column data of a group, loaded with it by lanes u < LU (lane u: column
+    // col0 + u, with MIR lane U + u: its pair col0 + u + n2; the other lanes load
+    // a valid neighbour and ignore it)
     struct ColData { double x, s, z0, z1, c, cb; };
     ColData da_, db_;
     // unmasked loads from clamped addresses: rows past ld have zero weights,
     // columns past j_end are skipped with a uniform test in step()
     const int rl = min(lane * 4, ld - 4);
     auto load_cols = [&](int col0, ColData& cd) {
-        const int j = min(col0 + (lane < U ? lane : 0), j_end - 1);
+        int j;
+        if constexpr (MIR) {
+            j = min(col0 + (lane < LU ? (lane & (U - 1)) : 0), j_end - 1);
+            if (lane >= U && lane < LU) j += g.n2;
+        } else {
+            j = min(col0 + (lane < U ? lane : 0), j_end - 1);
+        }
         cd.x = g.X[j]; cd.s = g.S[j]; cd.z0 = g.Zx0[j]; cd.z1 = g.Zx1[j]; cd.c = g.C[j]; cd.cb = g.CB[j];
     };
     auto load = [&](int col0, T (&v)[U][R]) {
@@ -242,11 +254,12 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
         }
         __syncthreads();
         double x1 = 0.0, s1 = 0.0;
-        if (lane < U) {
-            const int u = lane;
+        if (lane < LU) {
+            const int u = MIR ? (lane & (U - 1)) : lane;
             const int j = col0 + u;
             double ata = 0.0, aty = 0.0;
             for (int w = 0; w < GRID_W; ++w) { ata += sdh[w * 2 * U + 2 * u]; aty += sdh[w * 2 * U + 2 * u + 1]; }
+            if (MIR && lane >= U) { ata = -ata; aty = -aty; }   // column j + n2 = -(column j)
             if (j < j_end) {
                 const double x0 = cd.x, s0 = cd.s;
                 x1 = x0; s1 = s0;
@@ -264,7 +277,8 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
                     }
                 }
                 if (wave == 0) {
-                    if (op != OP_REFRESH) { g.X[j] = x1; g.S[j] = s1; }
+                    const int jj = (MIR && lane >= U) ? j + g.n2 : j;
+                    if (op != OP_REFRESH) { g.X[jj] = x1; g.S[jj] = s1; }
                     const double c0 = cd.c, cb0 = cd.cb;
                     const double r1 = aty + s1 - c0 * tau;
                     const double r2 = aty + s1;
@@ -282,7 +296,8 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
         const double f1 = x1 + s1;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const double xu = bcast_lane(x1, u), fu = bcast_lane(f1, u);   // 0 past j_end
+            double xu = bcast_lane(x1, u), fu = bcast_lane(f1, u);   // 0 past j_end
+            if constexpr (MIR) { xu -= bcast_lane(x1, U + u); fu -= bcast_lane(f1, U + u); }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 accf[r] = fma((double)v[u][r], fu, accf[r]);
@@ -366,6 +381,8 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
     }
     c.decide = 1;                                  // this pass's decision comes next
     if (blockIdx.x == 0 && threadIdx.x == 0) *g.ctl = c;      // the state k_grid_red / k_grid_ginv read
+    // the buffer this pass's column sums go to (pass parity after its decision)
+    const int pw = __builtin_amdgcn_readfirstlane((int)(c.passes & 1));
     tau = c.tau; theta = c.theta;
     if (prox) { p0 = c.p0; p1 = c.p1; tau = c.tau_n; theta = c.theta_n; }   // scalars of the new state
     else if (op == OP_RESTART) { tau = c.tau_n; theta = c.theta_n; }
@@ -432,13 +449,13 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
     double t8[8] = {acc7[0], acc7[1], acc7[2], acc7[3], acc7[4], acc7[5], acc7[6], 0.0};
     block_sum_n<8>(t8, sd + 2 * GRID_W * 2 * GRID_UNR);      // apart from the halves the last group read
     if (threadIdx.x == 0) {
-        double* pc = g.pcol + (c.passes & 1) * (int64_t)g.pcol_stride;   // after this pass's decision
+        double* pc = g.pcol + pw * (int64_t)g.pcol_stride;
         for (int q = 0; q < 8; ++q) pc[blockIdx.x * 8 + q] = t8[q];
     }
     return false;
 }
 
-template <int NCHW>
+template <int NCHW, bool MIR>
 __global__ __launch_bounds__(512) void k_grid_col(GridArgs g) {
     __shared__ double sd[2 * GRID_W * 2 * GRID_UNR + 64];
     const GridCtl& c = *g.ctl_next;
@@ -448,10 +465,10 @@ __global__ __launch_bounds__(512) void k_grid_col(GridArgs g) {
     }
     constexpr int U32 = NCHW == 1 ? 8 : 4, U64 = NCHW == 1 ? 4 : 2;
     if (c.phase == 0) {
-        if (grid_col_body<NCHW, float, U32>(g, g.A32, sd))
-            grid_col_body<NCHW, double, U64>(g, g.A64, sd);     // switched to FP64 data
+        if (grid_col_body<NCHW, float, U32, MIR>(g, g.A32, sd))
+            grid_col_body<NCHW, double, U64, MIR>(g, g.A64, sd);     // switched to FP64 data
     } else {
-        grid_col_body<NCHW, double, U64>(g, g.A64, sd);
+        grid_col_body<NCHW, double, U64, MIR>(g, g.A64, sd);
     }
 }
 
@@ -625,6 +642,19 @@ __global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
 }
 
 // Initial control block: Algorithm 2's start, first pass = refresh.
+// Column pairing test of one large LP: sets bit 16 of *flag unless column
+// j + n2 of A equals the negated column j exactly for every j < n2 (one
+// workgroup per pair; A column-major with leading dimension ld).
+__global__ void k_grid_pair_check(const double* __restrict__ A, int m, int ld, int n2, int* flag) {
+    const int j = blockIdx.x;
+    const double* a0 = A + (int64_t)j * ld;
+    const double* a1 = A + (int64_t)(j + n2) * ld;
+    int bad = 0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x)
+        if (a1[i] != -a0[i]) bad = 1;
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 16);
+}
+
 __global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed) {
     const int tid = threadIdx.x + blockIdx.x * blockDim.x;
     for (int i = tid; i < 2 * g.ld; i += blockDim.x * gridDim.x) g.Y2[i] = 0.0;
@@ -701,12 +731,18 @@ __global__ void k_grid_finish(GridArgs g, double* Ypool_slice, LPCtrl* lc) {
 
 int grid_nchw(int ld) { return (ld + 256 * GRID_W - 1) / (256 * GRID_W); }
 
+template <int NCHW>
+static void launch_col(const GridArgs& g, hipStream_t st) {
+    if (g.n2 > 0) hipLaunchKernelGGL((k_grid_col<NCHW, true>), dim3(g.NB), dim3(512), 0, st, g);
+    else hipLaunchKernelGGL((k_grid_col<NCHW, false>), dim3(g.NB), dim3(512), 0, st, g);
+}
+
 hipError_t grid_launch_iteration(int nchw, const GridArgs& g, hipStream_t st) {
     switch (nchw) {
-    case 1: hipLaunchKernelGGL(k_grid_col<1>, dim3(g.NB), dim3(512), 0, st, g); break;
-    case 2: hipLaunchKernelGGL(k_grid_col<2>, dim3(g.NB), dim3(512), 0, st, g); break;
-    case 3: hipLaunchKernelGGL(k_grid_col<3>, dim3(g.NB), dim3(512), 0, st, g); break;
-    case 4: hipLaunchKernelGGL(k_grid_col<4>, dim3(g.NB), dim3(512), 0, st, g); break;
+    case 1: launch_col<1>(g, st); break;
+    case 2: launch_col<2>(g, st); break;
+    case 3: launch_col<3>(g, st); break;
+    case 4: launch_col<4>(g, st); break;
     default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k_grid_red, dim3(g.NR), dim3(256), 0, st, g);

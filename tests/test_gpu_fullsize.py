@@ -39,14 +39,19 @@ def test_sparse_10000_by_30000_cg_engine():
     _check_solution(As.toarray(), lp, x, y, s, 1e-5)      # the pinned checker takes a dense A (2.4 GB)
 
 
-def test_basis_pursuit_2000_by_16000_grid_engine_fp32_bulk():
-    print("basis pursuit 2000 x 16000", flush=True)
+@pytest.mark.parametrize("mirror", [1, 0])
+def test_basis_pursuit_2000_by_16000_grid_engine_fp32_bulk(mirror):
+    """Both column passes of the bench: A0 read once per pair (the default for A = [A0, -A0])
+    and every column streamed."""
+    print(f"basis pursuit 2000 x 16000 grid_mirror={mirror}", flush=True)
     lp = lpgen.basis_pursuit(2000, 8000, 400, 2)
     A = torch.tensor(lp["A"], device="cuda")
-    w = abip.abip_setup(A, lp["b"], lp["c"], abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH))
+    w = abip.abip_setup(A, lp["b"], lp["c"], abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH,
+                                                                         grid_mirror=mirror))
     x, y, s, info = abip.abip_solve(w)
     print(info["status_name"], info["admm_iters"], info["admm_iters_fp64"], flush=True)
     assert info["status"] == abip.ABIP_SOLVED
+    assert info["grid_mirror"] == mirror
     _check_solution(lp["A"], lp, x, y, s, 1e-5)
     # the planted sparse signal is recovered: x+ - x- against x_true
     xv = _np(x)
