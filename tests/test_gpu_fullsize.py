@@ -85,3 +85,24 @@ def test_differentiable_batch_64_of_200_by_500():
         e = np.abs(_np(dbs[k]) - ref["db"]).max() / (1 + np.abs(ref["db"]).max())
         print(k, "db vs KKT adjoint", e, flush=True)
         assert e <= 1e-7
+
+
+def test_paper_random_4000_by_20000_scaled_grid_engine():
+    """The largest size of the paper's random-LP table (eps 1e-3) as the bench runs it: FP64 after
+    10 Ruiz rounds; the solve must pass the Section 4.1 tests on the LP as given (host recheck)."""
+    print("paper random 4000 x 20000, scaled", flush=True)
+    lp = lpgen.paper_random(4000, 20000, 1)
+    A = torch.tensor(lp["A"], device="cuda")
+    s = abip.abip_default_settings(eps=1e-3, engine=abip.ABIP_ENGINE_GRID, precision=abip.ABIP_PREC_FP64,
+                                   scale_iters=10)
+    w = abip.abip_setup(A, lp["b"], lp["c"], s)
+    x, y, sv, info = abip.abip_solve(w)
+    print(info["status_name"], info["admm_iters"], info["err_vs_fp64"], flush=True)
+    assert info["status"] == abip.ABIP_SOLVED
+    kk = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(sv))
+    assert max(kk["pres"], kk["dres"], kk["gap"]) <= 1e-3 * (1 + 1e-9), kk
+    assert np.all(_np(x) >= 0) and np.all(_np(sv) >= 0)
+    assert info["err_vs_fp64"] <= 1e-3 * (1 + 1e-9)
+    pobj = float(lp["c"] @ _np(x))
+    assert abs(pobj - lp["pstar"]) <= 1e-2 * (1 + abs(lp["pstar"])), (pobj, lp["pstar"])
+    w.free()
