@@ -115,3 +115,38 @@ def test_grid_mirror_setting_is_validated():
     lp = lpgen.basis_pursuit(10, 20, 2, 1)
     with pytest.raises(Exception):
         abip.abip_setup(lp["A"], lp["b"], lp["c"], _settings(grid_mirror=2))
+
+
+@pytest.mark.parametrize("mirror", [1, 0])
+@pytest.mark.parametrize("m,N,seed", [(120, 500, 4), (2100, 2300, 5)])
+def test_paired_fp32_data_iterations_match_model(m, N, seed, mirror):
+    """FP32 data (the bulk phase): the oracle iterating with its FP32-data model of
+    the step (A and G^{-1} rounded to FP32, FP64 arithmetic).  Rounding commutes
+    with negation, so the model's A is what the paired pass reads as [A0, -A0]."""
+    print(f"paired fp32 iterate m={m} N={N} mirror={mirror}", flush=True)
+    lp = lpgen.basis_pursuit(m, N, max(2, N // 25), seed)
+    prob = Problem(lp["A"], lp["b"], lp["c"])
+    s = Settings()
+    st = oracle.restart(oracle.initial_state(prob, s), s.gamma, s.restart_rule)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"],
+                        _settings(grid_mirror=mirror, precision=abip.ABIP_PREC_FP32_POLISH))
+    abip.abip_set_state(w, 0, st.y, st.x, st.s, st.tau, st.kappa, st.theta, st.mu)
+    model = oracle.Fp32DataSchurSolver(prob)
+    exact = oracle.SchurIQSolver(prob)
+    N_IT = 30
+    st_m, st_e = st.copy(), st.copy()
+    for _ in range(N_IT):
+        st_m = oracle.admm_iteration(prob, model, st_m, s)
+        st_e = oracle.admm_iteration(prob, exact, st_e, s)
+    abip.abip_iterate(w, 0, N_IT, use_fp32=True)
+    y, x, sv, sc = abip.abip_get_state(w, 0)
+    y, x, sv = _np(y), _np(x), _np(sv)
+    scale = 1.0 + np.abs(st_m.u()).max()
+    dev = max(np.abs(y - st_m.y).max(), np.abs(x - st_m.x).max(), np.abs(sv - st_m.s).max())
+    gap32 = max(np.abs(st_m.x - st_e.x).max(), np.abs(st_m.y - st_e.y).max())
+    print(f"  |gpu - model| = {dev:.3e}, |model - exact| = {gap32:.3e}", flush=True)
+    assert dev <= 1e-9 * scale, dev
+    for key, ref in [("tau", st_m.tau), ("kappa", st_m.kappa), ("theta", st_m.theta)]:
+        assert abs(sc[key] - ref) <= 1e-9 * scale, (key, sc[key], ref)
+    assert gap32 > 10 * dev          # FP32 rounding moves the iterate far more than the bar
+    w.free()
