@@ -517,7 +517,7 @@ static int grid_prepare(abip_work* w) {
     const int64_t nbuf = 2 * (int64_t)d.ld + 2 * cap * d.ld + 16 * cap +
                          8 * (int64_t)((d.ld + GRID_RED_ROWS - 1) / GRID_RED_ROWS) + 4 * cap + 2 * (int64_t)d.ld;
     HIPCHK(hipMalloc((void**)&w->gbuf, sizeof(double) * nbuf));
-    HIPCHK(hipMalloc((void**)&w->gctl, sizeof(GridCtl) * 2));
+    HIPCHK(hipMalloc((void**)&w->gctl, sizeof(GridCtl) * 3));   // ctl, ctl_next, then the GridBB record
     grid_config(w, w->cu_count);
     // k_grid_col reads at most two partial sums per thread of each kernel (2 x 512 workgroups)
     if (g.NR > 1024 || 4 * w->cu_count > 1024)
@@ -530,7 +530,12 @@ static int grid_prepare(abip_work* w) {
     g.C = w->Nv + NF_C * w->Ntot + d.on; g.CB = w->Nv + NF_CBAR * w->Ntot + d.on;
     g.Zx0 = w->Nv + NF_ZX0 * w->Ntot + d.on; g.Zx1 = w->Nv + NF_ZX1 * w->Ntot + d.on;
     g.X = w->Nv + NF_X * w->Ntot + d.on; g.S = w->Nv + NF_S * w->Ntot + d.on;
+    g.X0 = w->Nv + NF_BBX0 * w->Ntot + d.on; g.S0 = w->Nv + NF_BBS0 * w->Ntot + d.on;
+    g.X1 = w->Nv + NF_BBX1 * w->Ntot + d.on; g.S1 = w->Nv + NF_BBS1 * w->Ntot + d.on;
+    g.Y0 = w->Mv + MF_BBY0 * w->Mtot + d.om; g.Y1 = w->Mv + MF_BBY1 * w->Mtot + d.om;
     g.ctl = w->gctl; g.ctl_next = w->gctl + 1;
+    static_assert(sizeof(GridBB) <= sizeof(GridCtl), "GridBB fits the third slot");
+    g.bb = reinterpret_cast<GridBB*>(w->gctl + 2);
     g.lc = w->dctrl;
     return ABIP_OK;
 }
@@ -586,13 +591,16 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
         hipLaunchKernelGGL(k_grid_from_state, dim3(16), dim3(256), 0, st, g, w->Mv + MF_Y * w->Mtot + d0.om,
                            w->dctrl, phase, fixed);
     } else {
-        hipLaunchKernelGGL(k_grid_init, dim3(64), dim3(256), 0, st, g, w->set.beta, phase, fixed);
+        hipLaunchKernelGGL(k_grid_init, dim3(64), dim3(256), 0, st, g, w->set.beta, phase, fixed, w->set.bb);
     }
     HIPCHK(hipGetLastError());
     if (!w->ev0) HIPCHK(hipEventCreate(&w->ev0));
     if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
     HIPCHK(hipEventRecord(w->ev0, st));
     GridCtl hc;
+    // with the adaptive beta the grid pauses at every outer iteration's choice: look
+    // at the status every 32 iterations at most, so that little work runs idle
+    const int bb_reps = (w->set.bb && fixed == 0) ? 2 : 16;
     if (w->set.use_graph) {
         // the iteration kernels take the same arguments every time (state lives in
         // the device control block): 16 iterations as one graph, replayed
@@ -616,8 +624,14 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
             HIPCHK(hipStreamWaitEvent(st, w->gjoin1, 0));
             HIPCHK(hipMemcpyAsync(&hc, w->gctl + 1, sizeof hc, hipMemcpyDeviceToHost, st));   // the decision
             HIPCHK(hipStreamSynchronize(st));
+            if (hc.status == -2) {             // paused for a beta step (Section 4.3)
+                hipLaunchKernelGGL(k_grid_bb_step, dim3(1), dim3(1024), 0, st, g);
+                HIPCHK(hipGetLastError());
+                reps = 1;
+                continue;
+            }
             if (hc.status != 0) break;
-            if (reps < 16) reps *= 2;
+            if (reps < bb_reps) reps *= 2;
         }
     } else {
         int chunk = 16;
@@ -625,8 +639,14 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
             for (int i = 0; i < chunk; ++i) HIPCHK(grid_launch_iteration(w->grid_nchw, g, st));
             HIPCHK(hipMemcpyAsync(&hc, w->gctl + 1, sizeof hc, hipMemcpyDeviceToHost, st));   // the decision
             HIPCHK(hipStreamSynchronize(st));
+            if (hc.status == -2) {             // paused for a beta step (Section 4.3)
+                hipLaunchKernelGGL(k_grid_bb_step, dim3(1), dim3(1024), 0, st, g);
+                HIPCHK(hipGetLastError());
+                chunk = 16;
+                continue;
+            }
             if (hc.status != 0) break;
-            if (chunk < 256) chunk *= 2;
+            if (chunk < 16 * bb_reps) chunk *= 2;
         }
     }
     HIPCHK(hipEventRecord(w->ev1, st));
@@ -703,7 +723,6 @@ static int setup_dense(abip_work** out, int32_t B, const abip_matrix* A, const d
                                             (s.engine == ABIP_ENGINE_AUTO &&
                                              (M.m > MAX_WG_M || (int64_t)M.m * M.n >= GRID_AUTO_MN)));
         if (want_grid) w->grid = true;
-        if (want_grid && s.bb) { delete w; return fail(ABIP_E_INVALID, "settings.bb: the adaptive beta runs in the one-workgroup engine only (this LP takes the grid engine)"); }
         if (want_grid && s.lin_solver == ABIP_LIN_TRSV) { delete w; return fail(ABIP_E_INVALID, "settings.lin_solver = ABIP_LIN_TRSV runs in the one-workgroup engine only (this LP takes the grid engine)"); }
         if (want_grid && M.m > MAX_GRID_M) { delete w; return fail(ABIP_E_DIM, "m=%d exceeds the grid engine limit %d", M.m, MAX_GRID_M); }
         if (!want_grid && M.m > MAX_WG_M) { delete w; return fail(ABIP_E_DIM, "LP %d: m=%d exceeds the one-workgroup engine limit %d (use abip_setup for one large LP)", k, M.m, MAX_WG_M); }

@@ -26,6 +26,28 @@ struct GridCtl {
     // scalars of the state produced by the last column pass (for the decision)
     double tau_n, kappa_n, theta_n;
     StallTrack stall;          // FP32 precision-floor test of the current inner loop
+    // adaptive beta (Section 4.3)
+    double beta;               // the outer iteration's beta (settings.beta unless chosen)
+    int32_t bbf;               // GBB_* bits
+};
+
+// GridCtl.bbf: adaptive beta on (a full solve), the outer iteration's choice
+// pending, the stage of the choice (1 / 2: first / second probe, 3: start point
+// restored), the paused pass was an update, and resume: the pass's decision was
+// taken before a beta step paused the grid (status -2), so the next column pass
+// takes the paused pass's sums without deciding again.
+#define GBB_ON 1
+#define GBB_PEND 2
+#define GBB_STAGE_SHIFT 2      // two bits
+#define GBB_WAS_UPDATE 16
+#define GBB_RESUME 32
+
+// The rest of the choice's state, touched only by k_grid_bb_step (one workgroup,
+// while the grid is paused) and by the init / finish kernels.
+struct GridBB {
+    double bbs[6];             // tau, kappa, theta of the start point and of the first probe
+    int64_t bbp;               // probe updates
+    int32_t est, bbe;          // estimates of this choice (redos included) / of the solve
 };
 
 struct GridArgs {
@@ -38,6 +60,7 @@ struct GridArgs {
     const double *b, *bbar, *Ac, *Acb, *Zy0, *Zy1;
     const double *C, *CB, *Zx0, *Zx1;
     double *X, *S;
+    double *X0, *S0, *X1, *S1, *Y0, *Y1;   // adaptive beta: start point and first probe
     double* Y2;                // 2 * ld: current / next y
     double* Pf;                // NB * ld partial A(x+s)
     double* Px;                // NB * ld partial A x
@@ -51,6 +74,7 @@ struct GridArgs {
                                // k_grid_red / k_grid_ginv
     GridCtl* ctl_next;         // its copy for the next k_grid_col (written by k_grid_ginv's
                                // workgroup 0) and the host
+    GridBB* bb;                // adaptive beta: the choice's state
     const LPCtrl* lc;          // K^{-1}, zbar, norms
     SolveParams prm;
 };
@@ -58,7 +82,8 @@ struct GridArgs {
 
 int grid_nchw(int ld);
 hipError_t grid_launch_iteration(int nchw, const GridArgs& g, hipStream_t st);
-__global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed);
+__global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed, int bb);
+__global__ void k_grid_bb_step(GridArgs g);
 __global__ void k_grid_pair_check(const double* A, int m, int ld, int n2, int* flag);
 __global__ void k_grid_finish(GridArgs g, double* Ypool_slice, LPCtrl* lc);
 __global__ void k_grid_from_state(GridArgs g, const double* Yslice, const LPCtrl* lc, int phase, int64_t fixed);

@@ -52,7 +52,7 @@ __device__ __forceinline__ Pending finish_border(const GridArgs& g, const GridCt
     Pending P;
     P.p0 = L.K00 * q0 + L.K01 * q1;
     P.p1 = L.K10 * q0 + L.K11 * q1;
-    const double tmu = c.mu / g.prm.beta;
+    const double tmu = c.mu / c.beta;
     const double uh_tau = alpha * P.p0 + (1.0 - alpha) * c.tau;
     P.theta1 = alpha * P.p1 + (1.0 - alpha) * c.theta;
     P.tau1 = prox_root(uh_tau - c.kappa, tmu);
@@ -73,6 +73,8 @@ __device__ __forceinline__ void grid_decide(const GridArgs& g, GridCtl& c, const
     const SolveParams& prm = g.prm;
     const double eps = prm.eps, nb = L.nb, nc = L.nc, zbar = L.zbar, gamma = prm.gamma;
     const int pass = c.mode;
+    const bool bb_on = (c.bbf & GBB_ON) != 0;
+    const bool bb_pass = bb_on && ((c.bbf >> GBB_STAGE_SHIFT) & 3) != 0;   // a probe or the restored start: no tests
     if (c.phase == 0) ++c.cp32; else ++c.cp64;
     if (pass == OP_PROX) { ++c.iters; if (c.phase == 1) ++c.iters64; }
     ++c.passes;
@@ -86,8 +88,8 @@ __device__ __forceinline__ void grid_decide(const GridArgs& g, GridCtl& c, const
         if (c.fixed_left <= 0) c.status = -1;
     } else {
         const bool post_update = (pass == OP_PROX) || (pass == OP_REFRESH && !c.first);
-        bool decided = false;
-        if (post_update) {
+        bool decided = bb_pass;
+        if (post_update && !bb_pass) {
             int st = 0;
             if (tau > 0.0) {
                 const double pres = sqrt(ms[2]) / tau, dres = sqrt(cs[4]) / tau;
@@ -131,6 +133,7 @@ __device__ __forceinline__ void grid_decide(const GridArgs& g, GridCtl& c, const
                 else { const double sg = sqrt(gamma); tn *= sg; kn *= sg; hn *= sg; }
                 c.tau_n = tn; c.kappa_n = kn; c.theta_n = hn;
                 stall_reset(c.stall);
+                if (bb_on) c.bbf |= GBB_PEND;                        // the new outer iteration chooses its beta
                 next = OP_RESTART;
                 decided = true;
             } else if (c.phase == 0 && pass == OP_PROX && stall_sample(c.stall, inner, c.mu)) {
@@ -138,10 +141,16 @@ __device__ __forceinline__ void grid_decide(const GridArgs& g, GridCtl& c, const
                 c.exit_pend = 1;
                 next = OP_REFRESH;
                 decided = true;
-            } else if (c.iters >= prm.max_iters || c.passes > prm.max_iters + 4096) {
+            } else if ((c.iters >= prm.max_iters && !(bb_on && (c.bbf & GBB_PEND))) || c.passes > prm.max_iters + 4096) {
                 c.status = 4;
                 decided = true;
             }
+        }
+        // a beta step (Section 4.3) after the tests of an outer iteration's first pass
+        // or of a probe: the grid pauses (status -2) and the host runs k_grid_bb_step
+        if ((!decided || bb_pass) && c.status == 0 && bb_on && ((c.bbf & GBB_PEND) || bb_pass)) {
+            c.bbf = (c.bbf & ~GBB_WAS_UPDATE) | (pass == OP_PROX ? GBB_WAS_UPDATE : 0);
+            c.status = -2;
         }
     }
     c.first = 0;
@@ -161,6 +170,7 @@ template <int NCHW, typename T, int U, bool MIR>
 __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double* sd) {
     GridCtl c = *g.ctl_next;                   // the last pass, its decision pending (c.decide)
     const bool decide = c.decide != 0;
+    const bool resume = (c.bbf & GBB_RESUME) != 0;   // decided before a beta step: take its sums only
     const int lane = threadIdx.x & 63, wave = wave_id();
     constexpr int R = NCHW * 4;
     const int ld = g.ld, n = g.n, m = g.m;
@@ -324,7 +334,7 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
 #pragma unroll
     for (int k = 0; k < 16; ++k) sm[k] = 0.0;
     if (decide) {
-        const double* pc = g.pcol + (c.passes & 1) * (int64_t)g.pcol_stride;
+        const double* pc = g.pcol + ((resume ? c.passes - 1 : c.passes) & 1) * (int64_t)g.pcol_stride;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int q = threadIdx.x + h * 512;
@@ -346,7 +356,7 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
     constexpr int RE = EARLY ? 4 : 1;
     double ea[RE], ez0[RE], ez1[RE], ey[RE];
     if constexpr (EARLY) {
-        const double* yc0 = g.Y2 + (int64_t)(decide ? 1 - c.ybuf : c.ybuf) * ld;   // the decision flips it
+        const double* yc0 = g.Y2 + (int64_t)(decide && !resume ? 1 - c.ybuf : c.ybuf) * ld;   // a decision flips it
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = wave * 256 + lane * 4 + q;
@@ -361,7 +371,8 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
     if (c0 < j_end) { load(c0, va); load_cols(c0, da_); }
     if (decide) {
         block_sum_n<16>(sm, sd);
-        grid_decide(g, c, sm);
+        if (!resume) grid_decide(g, c, sm);
+        c.bbf &= ~GBB_RESUME;
         if (c.status != 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) *g.ctl = c;
             return false;
@@ -386,7 +397,7 @@ __device__ bool grid_col_body(const GridArgs& g, const T* __restrict__ A, double
     tau = c.tau; theta = c.theta;
     if (prox) { p0 = c.p0; p1 = c.p1; tau = c.tau_n; theta = c.theta_n; }   // scalars of the new state
     else if (op == OP_RESTART) { tau = c.tau_n; theta = c.theta_n; }
-    tmu = c.mu / g.prm.beta;
+    tmu = c.mu / c.beta;
     // the same in every lane: scalar registers for the column loop
     op = __builtin_amdgcn_readfirstlane(op);
     prox = op == OP_PROX;
@@ -642,6 +653,78 @@ __global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
 }
 
 // Initial control block: Algorithm 2's start, first pass = refresh.
+// One step of the choice of an outer iteration's beta (Section 4.3), run by one
+// workgroup while the grid is paused (status -2) after the tests of the pass
+// that starts the outer iteration (stage 0) or of a probe pass; the same steps
+// as the one-workgroup engines':
+//   stage 0 -> 1: the start point (y, x, s, tau, kappa, theta) is kept, the first
+//                 probe update follows;
+//   stage 1, after the first probe's pass -> 2: its iterate is kept;
+//   stage 2, after the second probe's pass: the five sums of the estimate, the
+//                 selection rule, the start point restored; -> 1 (a redo: the
+//                 probes again with the estimate) or 3 (final), the next pass a
+//                 refresh of the restored point;
+//   stage 3, after that refresh -> 0: the outer iteration's own updates begin.
+// Then the grid resumes: the next column pass takes the paused pass's sums.
+__global__ __launch_bounds__(1024) void k_grid_bb_step(GridArgs g) {
+    __shared__ double sbuf[16 * 5];
+    GridCtl c = *g.ctl_next;
+    GridBB B = *g.bb;
+    const int tid = threadIdx.x, nt = blockDim.x, m = g.m, n = g.n;
+    double* y = g.Y2 + (int64_t)c.ybuf * g.ld;
+    const double alpha = g.prm.alpha;
+    int stage = (c.bbf >> GBB_STAGE_SHIFT) & 3;
+    const int prev = stage;
+    const bool bb_pass = stage != 0;
+    const bool was_update = (c.bbf & GBB_WAS_UPDATE) != 0;
+    bool pend = (c.bbf & GBB_PEND) != 0;
+    if (bb_pass && was_update) ++B.bbp;        // a probe update
+    if (!bb_pass) pend = false;
+    bool restored = false;
+    if (stage == 0) {
+        for (int i = tid; i < m; i += nt) g.Y0[i] = y[i];
+        for (int j = tid; j < n; j += nt) { g.X0[j] = g.X[j]; g.S0[j] = g.S[j]; }
+        B.bbs[0] = c.tau; B.bbs[1] = c.kappa; B.bbs[2] = c.theta;
+        stage = 1;
+    } else if (stage == 1 && was_update) {
+        for (int i = tid; i < m; i += nt) g.Y1[i] = y[i];
+        for (int j = tid; j < n; j += nt) { g.X1[j] = g.X[j]; g.S1[j] = g.S[j]; }
+        B.bbs[3] = c.tau; B.bbs[4] = c.kappa; B.bbs[5] = c.theta;
+        stage = 2;
+    } else if (stage == 2) {
+        double q[5] = {0, 0, 0, 0, 0};
+        for (int i = tid; i < m; i += nt) bb_acc(y[i] - g.Y1[i], 0.0, 0.0, alpha, q);
+        for (int j = tid; j < n; j += nt) bb_acc(g.X[j] - g.X1[j], g.S[j] - g.S1[j], g.S1[j] - g.S0[j], alpha, q);
+        __syncthreads();
+        block_sum_n<5>(q, sbuf);
+        bb_acc(c.tau - B.bbs[3], c.kappa - B.bbs[4], B.bbs[4] - B.bbs[1], alpha, q);
+        bb_acc(c.theta - B.bbs[5], 0.0, 0.0, alpha, q);
+        B.bbe += 1;
+        B.est += 1;
+        const double hat = bb_hat(q, c.beta, g.prm.eps_cor);
+        const bool fin = bb_choose(c.beta, hat, g.prm.eps_pen, B.est, g.prm.bb_max_redo);
+        for (int i = tid; i < m; i += nt) y[i] = g.Y0[i];
+        for (int j = tid; j < n; j += nt) { g.X[j] = g.X0[j]; g.S[j] = g.S0[j]; }
+        c.tau = B.bbs[0]; c.kappa = B.bbs[1]; c.theta = B.bbs[2];
+        stage = fin ? 3 : 1;
+        restored = true;
+    } else if (stage == 3) {
+        stage = 0;
+        B.est = 0;
+    }
+    c.status = 0;
+    if (restored) {
+        c.mode = OP_REFRESH;                   // the products of the restored point
+        c.tau_n = c.tau; c.kappa_n = c.kappa; c.theta_n = c.theta;
+    } else {
+        c.mode = OP_PROX;
+        if (prev == 3 && c.iters >= g.prm.max_iters) c.status = 4;
+    }
+    c.bbf = GBB_ON | (pend ? GBB_PEND : 0) | (stage << GBB_STAGE_SHIFT) | GBB_RESUME;
+    __syncthreads();
+    if (tid == 0) { *g.ctl = c; *g.ctl_next = c; *g.bb = B; }
+}
+
 // Column pairing test of one large LP: sets bit 16 of *flag unless column
 // j + n2 of A equals the negated column j exactly for every j < n2 (one
 // workgroup per pair; A column-major with leading dimension ld).
@@ -655,7 +738,7 @@ __global__ void k_grid_pair_check(const double* __restrict__ A, int m, int ld, i
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 16);
 }
 
-__global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed) {
+__global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed, int bb) {
     const int tid = threadIdx.x + blockIdx.x * blockDim.x;
     for (int i = tid; i < 2 * g.ld; i += blockDim.x * gridDim.x) g.Y2[i] = 0.0;
     for (int j = tid; j < g.n; j += blockDim.x * gridDim.x) { g.X[j] = 1.0; g.S[j] = 1.0; }
@@ -674,8 +757,14 @@ __global__ void k_grid_init(GridArgs g, double beta, int phase, int64_t fixed) {
         c.by = c.cx = 0.0;
         c.kfx = NAN;
         c.tau_n = c.kappa_n = c.theta_n = 1.0;
+        c.beta = beta;
+        c.bbf = (bb && fixed == 0) ? (GBB_ON | GBB_PEND) : 0;
         *g.ctl = c;
         *g.ctl_next = c;
+        GridBB B;
+        for (int q = 0; q < 6; ++q) B.bbs[q] = 0.0;
+        B.bbp = 0; B.est = 0; B.bbe = 0;
+        *g.bb = B;
     }
 }
 
@@ -703,8 +792,14 @@ __global__ void k_grid_from_state(GridArgs g, const double* Yslice, const LPCtrl
         c.by = c.cx = 0.0;
         c.kfx = NAN;
         c.tau_n = L.tau; c.kappa_n = L.kappa; c.theta_n = L.theta;
+        c.beta = g.prm.beta;
+        c.bbf = 0;
         *g.ctl = c;
         *g.ctl_next = c;
+        GridBB B;
+        for (int q = 0; q < 6; ++q) B.bbs[q] = 0.0;
+        B.bbp = 0; B.est = 0; B.bbe = 0;
+        *g.bb = B;
     }
 }
 
@@ -723,6 +818,7 @@ __global__ void k_grid_finish(GridArgs g, double* Ypool_slice, LPCtrl* lc) {
         o.cpl32 = 0; o.cpl64 = 0;
         o.gh64 = c.iters64; o.gh32 = c.iters - c.iters64;   // one pass over G^{-1} per update
         o.kfx = c.kfx;
+        o.beta = c.beta; o.bbp = g.bb->bbp; o.bbe = g.bb->bbe;
         o.status = (c.status < 0) ? 0 : c.status;
         o.phase = c.phase;
         o.mode = OP_REFRESH;

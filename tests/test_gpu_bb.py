@@ -27,7 +27,7 @@ abip = pytest.importorskip("paper_1805_12344_amd")
 
 # (m, n, seed): column pairs / one column / two columns per lane in the LDS variant
 LPS = [(30, 70, 1), (76, 159, 23), (120, 260, 7)]
-ENGINES = ["lds", "streamed"]
+ENGINES = ["lds", "streamed", "grid"]
 
 
 def _np(t):
@@ -35,6 +35,8 @@ def _np(t):
 
 
 def _gpu(lp, lds, **kw):
+    if lds == "grid":          # one LP over the whole GPU: the beta steps run while the grid waits
+        kw["engine"] = abip.ABIP_ENGINE_GRID
     s = abip.abip_default_settings(bb=1, lds_resident=1 if lds == "lds" else 0, **kw)
     w = abip.abip_setup(lp["A"], lp["b"], lp["c"], s)
     x, y, sv, info = abip.abip_solve(w)
@@ -117,11 +119,22 @@ def test_bb_fp32_bulk_and_batch():
     w.free()
 
 
-def test_bb_rejected_outside_the_one_workgroup_engine():
-    lp = lpgen.dense_planted(300, 900, 1)
-    with pytest.raises(abip.ABIPError) as e:
-        abip.abip_setup(lp["A"], lp["b"], lp["c"], abip.abip_default_settings(bb=1, engine=abip.ABIP_ENGINE_GRID))
-    assert e.value.code == abip.ABIP_E_INVALID
+def test_bb_grid_fp32_bulk_basis_pursuit():
+    """The grid engine with the adaptive beta and FP32 bulk on a basis-pursuit LP (paired
+    column pass): solved, host KKT, the planted l1 value."""
+    lp = lpgen.basis_pursuit(120, 480, 6, 2)
+    s = abip.abip_default_settings(bb=1, engine=abip.ABIP_ENGINE_GRID, precision=abip.ABIP_PREC_FP32_POLISH)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"], s)
+    x, y, sv, info = abip.abip_solve(w)
+    print(info["status_name"], info["admm_iters"], info["bb_estimates"], info["beta"], info["grid_mirror"], flush=True)
+    assert info["status"] == abip.ABIP_SOLVED and info["bb_estimates"] > 0 and info["grid_mirror"] == 1
+    k = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(sv))
+    assert max(k["pres"], k["dres"], k["gap"]) <= 1e-6
+    assert abs(k["pobj"] - lp["pstar"]) <= 1e-4 * (1 + lp["pstar"])
+    w.free()
+
+
+def test_bb_rejected_by_the_sparse_engine():
     sl = lpgen.sparse_planted(200, 500, 2, density=0.02)
     A = sl["A_csr"]
     As = sp.csr_matrix((A["data"], A["indices"], A["indptr"]), shape=A["shape"])
