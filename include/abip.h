@@ -120,9 +120,10 @@ typedef struct {
                                   fit; 0: the CG passes read them from global memory.  Same
                                   iteration and tests; the sums are formed in a different order,
                                   so results agree to rounding, not bitwise. */
-    int32_t bb;                /* 1: Section 4.3's adaptive beta (one-workgroup and grid engines;
-                                  ABIP_E_INVALID at setup for the sparse engine; in the grid
-                                  engine each step of the choice runs while the grid waits): every
+    int32_t bb;                /* 1: Section 4.3's adaptive beta (every engine; in the grid engine
+                                  each step of the choice runs while the grid waits, in the
+                                  sparse engine inside its launch on each workgroup's rows and
+                                  columns): every
                                   outer iteration that starts with ||Q u - v||^2 > mu takes two
                                   probe iterations from its initial point, estimates beta from the
                                   curvature of the three iterates (steepest-descent / minimum-

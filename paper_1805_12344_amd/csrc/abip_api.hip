@@ -957,7 +957,6 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     if (!A->rowptr || (nnz > 0 && (!A->colidx || !A->val)) || !b || !c)
         return fail(ABIP_E_INVALID, "CSR: null rowptr / colidx / val / b / c");
     if (!(s.cg_tol > 0.0) || s.cg_max_iters < 1) return fail(ABIP_E_INVALID, "settings: cg_tol > 0 and cg_max_iters >= 1 required");
-    if (s.bb) return fail(ABIP_E_INVALID, "settings.bb: the adaptive beta runs in the one-workgroup engine only (CSR input takes the sparse engine)");
     if (s.scale_iters) return fail(ABIP_E_INVALID, "settings.scale_iters: scaling is implemented for dense A only");
     if (s.lin_solver == ABIP_LIN_TRSV) return fail(ABIP_E_INVALID, "settings.lin_solver = ABIP_LIN_TRSV needs dense A");
     const double t0 = now_ms();
@@ -1031,6 +1030,8 @@ static int setup_sparse(abip_work** out, const abip_matrix* A, const double* b, 
     g.b = fb; g.bbar = fbb; g.Ac = fAc; g.Acb = fAcb; g.Zy0 = fZy0; g.Zy1 = fZy1;
     g.C = fC; g.CB = fCB; g.Zx0 = fZx0; g.Zx1 = fZx1;
     g.Y = Mv + MF_Y * w->Mtot; g.X = Nv + NF_X * w->Ntot; g.S = Nv + NF_S * w->Ntot;
+    g.Y0 = Mv + MF_BBY0 * w->Mtot; g.X0 = Nv + NF_BBX0 * w->Ntot; g.S0 = Nv + NF_BBS0 * w->Ntot;
+    g.Y1 = Mv + MF_BBY1 * w->Mtot; g.X1 = Nv + NF_BBX1 * w->Ntot; g.S1 = Nv + NF_BBS1 * w->Ntot;
     g.bar = w->sp_bar; g.err = w->sp_err; g.lc = w->dctrl;
     g.LA = lanes_for((double)nnz / m);
     g.LT = lanes_for((double)nnz / n);

@@ -439,7 +439,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
     const SpLds L = sp_lds_init(g, R, Cc, sp_lds);
     const LPCtrl cl = *g.lc;
     const SolveParams& prm = g.prm;
-    const double alpha = prm.alpha, gamma = prm.gamma, beta = prm.beta, eps = prm.eps;
+    const double alpha = prm.alpha, gamma = prm.gamma, eps = prm.eps;
     const double zbar = cl.zbar, nb = cl.nb, nc = cl.nc, np1 = (double)n + 1.0;
     const double sg = sqrt(gamma);
     double tau = cl.tau, kappa = cl.kappa, theta = cl.theta, mu = cl.mu;
@@ -453,6 +453,15 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
     bool l_have = false;
     const int64_t t_start = wall_clock64();
     int64_t tk[4] = {0, 0, 0, 0};      // ticks: column passes, row passes, barriers, reductions
+    // Section 4.3: the outer iteration's beta and the state of its choice (every
+    // workgroup holds the same values); bb_stage 1 / 2: first / second probe,
+    // 3: start point restored
+    const bool bb_on = prm.bb != 0 && g.fixed_iters == 0;
+    double beta = bb_on ? cl.beta : prm.beta;
+    bool bb_pend = bb_on && (cl.flags & 16) != 0;
+    int bb_stage = 0, bb_est = 0, bbe = cl.bbe;
+    int64_t bbp = cl.bbp;
+    double bbs[6] = {0, 0, 0, 0, 0, 0};
 
     while (true) {
         if (grid_failed(g.err)) { status = -1; break; }
@@ -519,7 +528,8 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
         }
         put_parts<7>(cs, g.part, g.nbp, SP_COL, sbuf);
         const bool was_update = (op == OP_PROX);
-        if (was_update) { ++iters; ++done; }
+        const bool bb_pass = bb_on && bb_stage != 0;   // a probe or the restored start: no tests
+        if (was_update) { ++iters; ++done; if (bb_pass) ++bbp; }
         int64_t tb = wall_clock64();
         tk[0] += tb - ta;
         grid_sync(g.bar, g.err);
@@ -588,7 +598,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
         } else {
             const bool post_update = was_update || (op == OP_REFRESH && !first) || (first && check_final_first);
             first = false;
-            if (post_update) {
+            if (post_update && !bb_pass) {
                 // Section 4.1, multiplied through by tau and squared
                 int st = 0;
                 if (tau > 0.0) {
@@ -601,23 +611,71 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
                 l_ms2 = tr[2]; l_cs4 = tc[4]; l_tau = tau; l_by = by; l_cx = cx; l_have = true;
                 if (st) { status = st; break; }
             }
-            // inner test ||Q u - v||^2 <= mu (eq. inner-stop)
-            const double rt = by - cx + zbar * theta - kappa;
-            const double rth = -bby + cbx - zbar * tau + np1;
-            const double inner = tr[4] + tc[6] + rt * rt + rth * rth;
-            if (inner <= mu) {
-                mu *= gamma;
-                ++ipm;
-                if (prm.restart_rule == 0) {
-                    if (tau >= kappa) kappa *= gamma;
-                    else tau *= gamma;
-                } else {
-                    tau *= sg; kappa *= sg; theta *= sg;
+            if (!bb_pass) {
+                // inner test ||Q u - v||^2 <= mu (eq. inner-stop)
+                const double rt = by - cx + zbar * theta - kappa;
+                const double rth = -bby + cbx - zbar * tau + np1;
+                const double inner = tr[4] + tc[6] + rt * rt + rth * rth;
+                if (inner <= mu) {
+                    mu *= gamma;
+                    ++ipm;
+                    if (prm.restart_rule == 0) {
+                        if (tau >= kappa) kappa *= gamma;
+                        else tau *= gamma;
+                    } else {
+                        tau *= sg; kappa *= sg; theta *= sg;
+                    }
+                    bb_pend = bb_on;             // the new outer iteration chooses its beta
+                    op = OP_RESTART;
+                    continue;
                 }
-                op = OP_RESTART;
-                continue;
+                // (an outer iteration that starts with a beta choice takes its probes first)
+                if (iters >= prm.max_iters && !(bb_on && bb_pend)) { status = 4; break; }
             }
-            if (iters >= prm.max_iters) { status = 4; break; }
+            if (bb_on && (bb_pend || bb_pass)) {
+                // ---- a step of the beta choice (Section 4.3) on this workgroup's rows
+                // and columns: keep the start point, keep the first probe, or form the
+                // estimate's sums over the whole LP, choose and restore the start point
+                const int prev = bb_stage;
+                if (!bb_pass) bb_pend = false;
+                if (bb_stage == 0) {
+                    for (int i = R.lo + tid; i < R.hi; i += SP_THREADS) g.Y0[i] = g.Y[i];
+                    for (int j = Cc.lo + tid; j < Cc.hi; j += SP_THREADS) { g.X0[j] = g.X[j]; g.S0[j] = g.S[j]; }
+                    bbs[0] = tau; bbs[1] = kappa; bbs[2] = theta;
+                    bb_stage = 1;
+                } else if (bb_stage == 1 && was_update) {
+                    for (int i = R.lo + tid; i < R.hi; i += SP_THREADS) g.Y1[i] = g.Y[i];
+                    for (int j = Cc.lo + tid; j < Cc.hi; j += SP_THREADS) { g.X1[j] = g.X[j]; g.S1[j] = g.S[j]; }
+                    bbs[3] = tau; bbs[4] = kappa; bbs[5] = theta;
+                    bb_stage = 2;
+                } else if (bb_stage == 2) {
+                    double q[5] = {0, 0, 0, 0, 0};
+                    for (int i = R.lo + tid; i < R.hi; i += SP_THREADS) bb_acc(g.Y[i] - g.Y1[i], 0.0, 0.0, alpha, q);
+                    for (int j = Cc.lo + tid; j < Cc.hi; j += SP_THREADS)
+                        bb_acc(g.X[j] - g.X1[j], g.S[j] - g.S1[j], g.S1[j] - g.S0[j], alpha, q);
+                    put_parts<5>(q, g.part, g.nbp, SP_BB, sbuf);
+                    grid_sync(g.bar, g.err);
+                    get_parts<5>(g.part, g.nbp, SP_BB, q, sbuf);
+                    bb_acc(tau - bbs[3], kappa - bbs[4], bbs[4] - bbs[1], alpha, q);
+                    bb_acc(theta - bbs[5], 0.0, 0.0, alpha, q);
+                    ++bbe;
+                    ++bb_est;
+                    const double hat = bb_hat(q, beta, prm.eps_cor);
+                    const bool fin = bb_choose(beta, hat, prm.eps_pen, bb_est, prm.bb_max_redo);
+                    for (int i = R.lo + tid; i < R.hi; i += SP_THREADS) g.Y[i] = g.Y0[i];
+                    for (int j = Cc.lo + tid; j < Cc.hi; j += SP_THREADS) { g.X[j] = g.X0[j]; g.S[j] = g.S0[j]; }
+                    tau = bbs[0]; kappa = bbs[1]; theta = bbs[2];
+                    bb_stage = fin ? 3 : 1;
+                    grid_sync(g.bar, g.err);     // every row of the restored y before the next column pass
+                    if (grid_failed(g.err)) { status = -1; break; }
+                    op = OP_REFRESH;             // the products of the restored point
+                    continue;
+                } else if (bb_stage == 3) {
+                    bb_stage = 0;
+                    bb_est = 0;
+                }
+                if (prev == 3 && iters >= prm.max_iters) { status = 4; break; }
+            }
         }
 
         // ---- the linear step: G a = t by CG from the previous a
@@ -668,7 +726,8 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_solve(SpArgs g) {
         o.status = (status < 0) ? 0 : status;
         o.phase = 1;
         o.mode = OP_REFRESH;
-        o.flags = ((g.fixed_iters > 0) ? 1 : 0) | (cl.flags & 4);
+        o.flags = ((g.fixed_iters > 0) ? 1 : 0) | (cl.flags & 4) | (bb_pend ? 16 : 0);
+        if (bb_on) { o.beta = beta; o.bbp = bbp; o.bbe = bbe; }
         o.clk[2] += wall_clock64() - t_start;
         o.clk[0] += tk[0]; o.clk[1] += tk[1]; o.clk[3] += tk[2]; o.clk[4] += tk[3];
     }

@@ -11,6 +11,7 @@
 #define SP_COL 0       // 7 column-side sums of the check
 #define SP_ROW 7       // 12 row-side sums: 5 of the check, one unused, r^T r and t^T t of the CG start,
                        // 4 border dots of a
+#define SP_BB 26       // the five sums of the adaptive beta's estimate (Section 4.3)
 #define SP_CG 19       // per CG iteration: r^T u, w^T u, r^T r, then b^T a, bbar^T a, (A c)^T a, (A cbar)^T a
 
 // CG state of one row i of G a = t, read together by the column pass of every
@@ -32,6 +33,7 @@ struct SpArgs {
     const double *C, *CB, *Zx0, *Zx1, *ATZy0, *ATZy1;          // n
     // state and work vectors (written during the solve)
     double *Y, *X, *S;                   // iterate (Y: m, X, S: n)
+    double *Y0, *X0, *S0, *Y1, *X1, *S1; // adaptive beta: start point and first probe
     double *ATY, *ATA;                   // n: A^T y of the current iterate, A^T a of the last solve
     double *a, *z, *p;                   // m: CG solution (warm start), u = D^{-1} r, search direction
     SpRow* rw;                           // m: r, G u, G p, 1 / diag(G)

@@ -134,10 +134,51 @@ def test_bb_grid_fp32_bulk_basis_pursuit():
     w.free()
 
 
-def test_bb_rejected_by_the_sparse_engine():
-    sl = lpgen.sparse_planted(200, 500, 2, density=0.02)
+def _sparse(sl, **kw):
     A = sl["A_csr"]
     As = sp.csr_matrix((A["data"], A["indices"], A["indptr"]), shape=A["shape"])
-    with pytest.raises(abip.ABIPError) as e:
-        abip.abip_setup(As, sl["b"], sl["c"], abip.abip_default_settings(bb=1))
-    assert e.value.code == abip.ABIP_E_INVALID
+    s = abip.abip_default_settings(bb=1, cg_tol=1e-13, cg_rule=1, cg_max_iters=2000, **kw)
+    w = abip.abip_setup(As, sl["b"], sl["c"], s)
+    x, y, sv, info = abip.abip_solve(w)
+    st = abip.abip_get_state(w, 0)
+    w.free()
+    return As, x, y, sv, info, st
+
+
+def test_bb_sparse_first_selection_matches_oracle():
+    """The sparse engine (CG on G to 1e-13): the first choice against the oracle's."""
+    sl = lpgen.sparse_planted(150, 420, 2, density=0.02)
+    As, x, y, sv, info, (gy, gx, gs, sc) = _sparse(sl, max_admm_iters=1)
+    ref = oracle.solve(As.toarray(), sl["b"], sl["c"], Settings(bb=True, max_admm_iters=1))
+    _, beta_ref, trail = ref["betas"][0]
+    print(f"sparse: beta {info['beta']:.12g} oracle {beta_ref:.12g}, estimates {info['bb_estimates']} {len(trail)}",
+          flush=True)
+    assert info["status"] == abip.ABIP_MAX_ITERS
+    assert info["bb_estimates"] == len(trail)
+    assert info["bb_probe_iters"] == 2 * len(trail) == info["admm_iters"] == ref["admm_iters"]
+    assert abs(info["beta"] - beta_ref) <= 1e-8 * beta_ref
+    st = ref["state"]
+    scale = 1.0 + np.abs(st.u()).max()
+    for g, r in [(gy, st.y), (gx, st.x), (gs, st.s)]:
+        assert np.abs(_np(g) - r).max() <= 1e-10 * scale
+
+
+def test_bb_sparse_trajectory_and_full_solve():
+    sl = lpgen.sparse_planted(150, 420, 2, density=0.02)
+    As, x, y, sv, info, (gy, gx, gs, sc) = _sparse(sl, max_admm_iters=300)
+    ref = oracle.solve(As.toarray(), sl["b"], sl["c"], Settings(bb=True, max_admm_iters=300))
+    print(f"sparse 300: {info['status_name']} iters {info['admm_iters']} {ref['admm_iters']} ipm {info['ipm_iters']} "
+          f"{ref['ipm_iters']} beta {info['beta']:.10g} {ref['betas'][-1][1]:.10g}", flush=True)
+    assert info["status_name"] == ref["status_name"]
+    assert info["ipm_iters"] == ref["ipm_iters"] and info["admm_iters"] == ref["admm_iters"]
+    assert info["bb_estimates"] == sum(len(t) for (_, _, t) in ref["betas"])
+    assert abs(info["beta"] - ref["betas"][-1][1]) <= 1e-6 * ref["betas"][-1][1]
+    # a full solve with the default CG rule
+    A = sl["A_csr"]
+    w = abip.abip_setup(As, sl["b"], sl["c"], abip.abip_default_settings(bb=1))
+    x, y, sv, info = abip.abip_solve(w)
+    print("sparse full:", info["status_name"], info["admm_iters"], info["bb_estimates"], info["beta"], flush=True)
+    assert info["status"] == abip.ABIP_SOLVED and info["bb_estimates"] > 0
+    k = oracle.kkt_relative(As.toarray(), sl["b"], sl["c"], _np(x), _np(y), _np(sv))
+    assert max(k["pres"], k["dres"], k["gap"]) <= 1e-6
+    w.free()
