@@ -369,9 +369,9 @@ def cpu_time_single(A, b, c, iters_total, sample_iters, solver_fn, threads):
 # extra workloads
 # ---------------------------------------------------------------------------
 
-def _bp_solve(abip, torch, lp, A, b, c, mirror):
+def _bp_solve(abip, torch, lp, A, b, c, mirror, bb=0):
     """One timed basis-pursuit solve on a fresh handle (grid engine, FP32 bulk + FP64 polish)."""
-    s = abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH, grid_mirror=mirror)
+    s = abip.abip_default_settings(precision=abip.ABIP_PREC_FP32_POLISH, grid_mirror=mirror, bb=bb)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     w = abip.abip_setup(A, b, c, s)
@@ -443,6 +443,14 @@ def extra_basis_pursuit(abip, torch, cpu=True):
                               / (pinfo["kernel_ms"] / max(1, pinfo["admm_iters"])),
         "note": "A0 (2000 x 8000) is read once per column pass instead of A (2000 x 16000); the method's "
                 "byte count of the main line does not apply"}
+    log("basis pursuit 2000 x 16000: paired columns, adaptive beta")
+    binfo, _, bsolve, _, bkkt, bxh = _bp_solve(abip, torch, lp, A, b, c, 1, bb=1)
+    out["paired_columns_adaptive_beta"] = {
+        "status": binfo["status_name"], "admm_iters": binfo["admm_iters"],
+        "bb_probe_iters": binfo["bb_probe_iters"], "bb_estimates": binfo["bb_estimates"], "beta": binfo["beta"],
+        "solve_s": bsolve, "us_per_iter": binfo["kernel_ms"] * 1e3 / max(1, binfo["admm_iters"]),
+        "host_kkt": list(bkkt), "obj_vs_planted": abs(float(lp["c"] @ bxh) - lp["pstar"]) / (1 + lp["pstar"]),
+        "note": "each step of a beta choice pauses the grid for one host round trip"}
     if cpu:
         import oracle
         out["cpu_baseline"] = {
