@@ -598,9 +598,6 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
     if (!w->ev1) HIPCHK(hipEventCreate(&w->ev1));
     HIPCHK(hipEventRecord(w->ev0, st));
     GridCtl hc;
-    // with the adaptive beta the grid pauses at every outer iteration's choice: look
-    // at the status every 32 iterations at most, so that little work runs idle
-    const int bb_reps = (w->set.bb && fixed == 0) ? 2 : 16;
     if (w->set.use_graph) {
         // the iteration kernels take the same arguments every time (state lives in
         // the device control block): 16 iterations as one graph, replayed
@@ -624,14 +621,14 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
             HIPCHK(hipStreamWaitEvent(st, w->gjoin1, 0));
             HIPCHK(hipMemcpyAsync(&hc, w->gctl + 1, sizeof hc, hipMemcpyDeviceToHost, st));   // the decision
             HIPCHK(hipStreamSynchronize(st));
-            if (hc.status == -2) {             // paused for a beta step (Section 4.3)
+            if (hc.status == -2) {             // paused for a beta step the iterations did not take
                 hipLaunchKernelGGL(k_grid_bb_step, dim3(1), dim3(1024), 0, st, g);
                 HIPCHK(hipGetLastError());
                 reps = 1;
                 continue;
             }
             if (hc.status != 0) break;
-            if (reps < bb_reps) reps *= 2;
+            if (reps < 16) reps *= 2;
         }
     } else {
         int chunk = 16;
@@ -639,14 +636,14 @@ static int grid_run(abip_work* w, int64_t fixed, int phase) {
             for (int i = 0; i < chunk; ++i) HIPCHK(grid_launch_iteration(w->grid_nchw, g, st));
             HIPCHK(hipMemcpyAsync(&hc, w->gctl + 1, sizeof hc, hipMemcpyDeviceToHost, st));   // the decision
             HIPCHK(hipStreamSynchronize(st));
-            if (hc.status == -2) {             // paused for a beta step (Section 4.3)
+            if (hc.status == -2) {             // paused for a beta step the iterations did not take
                 hipLaunchKernelGGL(k_grid_bb_step, dim3(1), dim3(1024), 0, st, g);
                 HIPCHK(hipGetLastError());
                 chunk = 16;
                 continue;
             }
             if (hc.status != 0) break;
-            if (chunk < 16 * bb_reps) chunk *= 2;
+            if (chunk < 256) chunk *= 2;
         }
     }
     HIPCHK(hipEventRecord(w->ev1, st));

@@ -37,6 +37,8 @@
 #define GRID_W 8               // waves per workgroup (512 threads)
 #define GRID_UNR 8             // columns per step in the column kernels
 
+__device__ __forceinline__ void grid_bb_step(const GridArgs& g, const GridCtl& c, double* sbuf, bool write_ctl);
+
 // Border, scalars and y' of a pending update, computed identically by every
 // workgroup from the published partial dots.
 struct Pending {
@@ -653,7 +655,13 @@ __global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
     const GridCtl& c = *g.ctl;
     // the pass's state, for the next column pass (which decides on it)
     if (blockIdx.x == 0 && threadIdx.x == 0) *g.ctl_next = c;
-    if (c.status != 0) return;
+    if (c.status != 0) {
+        if (c.status == -2 && blockIdx.x == 0) {   // the decision paused for a beta step: take it here
+            __syncthreads();
+            grid_bb_step(g, c, sd, false);
+        }
+        return;
+    }
     if (c.phase == 0) grid_ginv_body<NCHW, float>(g, g.G32, sd);
     else grid_ginv_body<NCHW, double>(g, g.G64, sd);
 }
@@ -672,30 +680,42 @@ __global__ __launch_bounds__(512) void k_grid_ginv(GridArgs g) {
 //                 refresh of the restored point;
 //   stage 3, after that refresh -> 0: the outer iteration's own updates begin.
 // Then the grid resumes: the next column pass takes the paused pass's sums.
-__global__ __launch_bounds__(1024) void k_grid_bb_step(GridArgs g) {
-    __shared__ double sbuf[16 * 5];
-    GridCtl c = *g.ctl_next;
-    GridBB B = *g.bb;
+// Run by workgroup 0 of the k_grid_ginv launch that follows the pausing
+// decision (the other workgroups have nothing to do then), so a step costs no
+// kernel and no host round trip; k_grid_bb_step runs it for a pause that a
+// solve left to the host.  sbuf: 5 doubles per wave.  Inside k_grid_ginv the
+// resumed state goes to ctl_next alone: the launch's other workgroups read ctl
+// and must keep seeing the pause (their slice of a would use a stale t).
+__device__ __forceinline__ void grid_bb_step(const GridArgs& g, const GridCtl& c, double* sbuf, bool write_ctl) {
+    // the fields the step reads, before any thread writes (thread 0 writes at the end)
     const int tid = threadIdx.x, nt = blockDim.x, m = g.m, n = g.n;
     double* y = g.Y2 + (int64_t)c.ybuf * g.ld;
     const double alpha = g.prm.alpha;
-    int stage = (c.bbf >> GBB_STAGE_SHIFT) & 3;
+    const int bbf = c.bbf;
+    const int64_t iters = c.iters;
+    double tau = c.tau, kappa = c.kappa, theta = c.theta, beta = c.beta;
+    double bbs[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) bbs[q] = g.bb->bbs[q];
+    int64_t bbp = g.bb->bbp;
+    int est = g.bb->est, bbe = g.bb->bbe;
+    int stage = (bbf >> GBB_STAGE_SHIFT) & 3;
     const int prev = stage;
     const bool bb_pass = stage != 0;
-    const bool was_update = (c.bbf & GBB_WAS_UPDATE) != 0;
-    bool pend = (c.bbf & GBB_PEND) != 0;
-    if (bb_pass && was_update) ++B.bbp;        // a probe update
+    const bool was_update = (bbf & GBB_WAS_UPDATE) != 0;
+    bool pend = (bbf & GBB_PEND) != 0;
+    if (bb_pass && was_update) ++bbp;          // a probe update
     if (!bb_pass) pend = false;
     bool restored = false;
     if (stage == 0) {
         for (int i = tid; i < m; i += nt) g.Y0[i] = y[i];
         for (int j = tid; j < n; j += nt) { g.X0[j] = g.X[j]; g.S0[j] = g.S[j]; }
-        B.bbs[0] = c.tau; B.bbs[1] = c.kappa; B.bbs[2] = c.theta;
+        bbs[0] = tau; bbs[1] = kappa; bbs[2] = theta;
         stage = 1;
     } else if (stage == 1 && was_update) {
         for (int i = tid; i < m; i += nt) g.Y1[i] = y[i];
         for (int j = tid; j < n; j += nt) { g.X1[j] = g.X[j]; g.S1[j] = g.S[j]; }
-        B.bbs[3] = c.tau; B.bbs[4] = c.kappa; B.bbs[5] = c.theta;
+        bbs[3] = tau; bbs[4] = kappa; bbs[5] = theta;
         stage = 2;
     } else if (stage == 2) {
         double q[5] = {0, 0, 0, 0, 0};
@@ -703,32 +723,46 @@ __global__ __launch_bounds__(1024) void k_grid_bb_step(GridArgs g) {
         for (int j = tid; j < n; j += nt) bb_acc(g.X[j] - g.X1[j], g.S[j] - g.S1[j], g.S1[j] - g.S0[j], alpha, q);
         __syncthreads();
         block_sum_n<5>(q, sbuf);
-        bb_acc(c.tau - B.bbs[3], c.kappa - B.bbs[4], B.bbs[4] - B.bbs[1], alpha, q);
-        bb_acc(c.theta - B.bbs[5], 0.0, 0.0, alpha, q);
-        B.bbe += 1;
-        B.est += 1;
-        const double hat = bb_hat(q, c.beta, g.prm.eps_cor);
-        const bool fin = bb_choose(c.beta, hat, g.prm.eps_pen, B.est, g.prm.bb_max_redo);
+        bb_acc(tau - bbs[3], kappa - bbs[4], bbs[4] - bbs[1], alpha, q);
+        bb_acc(theta - bbs[5], 0.0, 0.0, alpha, q);
+        bbe += 1;
+        est += 1;
+        const double hat = bb_hat(q, beta, g.prm.eps_cor);
+        const bool fin = bb_choose(beta, hat, g.prm.eps_pen, est, g.prm.bb_max_redo);
         for (int i = tid; i < m; i += nt) y[i] = g.Y0[i];
         for (int j = tid; j < n; j += nt) { g.X[j] = g.X0[j]; g.S[j] = g.S0[j]; }
-        c.tau = B.bbs[0]; c.kappa = B.bbs[1]; c.theta = B.bbs[2];
+        tau = bbs[0]; kappa = bbs[1]; theta = bbs[2];
         stage = fin ? 3 : 1;
         restored = true;
     } else if (stage == 3) {
         stage = 0;
-        B.est = 0;
+        est = 0;
     }
-    c.status = 0;
-    if (restored) {
-        c.mode = OP_REFRESH;                   // the products of the restored point
-        c.tau_n = c.tau; c.kappa_n = c.kappa; c.theta_n = c.theta;
-    } else {
-        c.mode = OP_PROX;
-        if (prev == 3 && c.iters >= g.prm.max_iters) c.status = 4;
-    }
-    c.bbf = GBB_ON | (pend ? GBB_PEND : 0) | (stage << GBB_STAGE_SHIFT) | GBB_RESUME;
+    int status = 0, mode = OP_PROX;
+    if (restored) mode = OP_REFRESH;           // the products of the restored point
+    else if (prev == 3 && iters >= g.prm.max_iters) status = 4;
+    const int nbbf = GBB_ON | (pend ? GBB_PEND : 0) | (stage << GBB_STAGE_SHIFT) | GBB_RESUME;
     __syncthreads();
-    if (tid == 0) { *g.ctl = c; *g.ctl_next = c; *g.bb = B; }
+    if (tid == 0) {
+        for (int t = 0; t < (write_ctl ? 2 : 1); ++t) {
+            GridCtl* o = (t == 0) ? g.ctl_next : g.ctl;
+            o->tau = tau; o->kappa = kappa; o->theta = theta; o->beta = beta;
+            if (restored) { o->tau_n = tau; o->kappa_n = kappa; o->theta_n = theta; }
+            o->status = status;
+            o->mode = mode;
+            o->bbf = nbbf;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) g.bb->bbs[q] = bbs[q];
+        g.bb->bbp = bbp; g.bb->est = est; g.bb->bbe = bbe;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_grid_bb_step(GridArgs g) {
+    __shared__ double sbuf[16 * 5];
+    const GridCtl& c = *g.ctl_next;
+    if (c.status != -2) return;                // not paused: nothing to do
+    grid_bb_step(g, c, sbuf, true);
 }
 
 // Column pairing test of one large LP: sets bit 16 of *flag unless column
