@@ -27,8 +27,8 @@
 // no workgroup reads sums that its launch is writing.  For A = [A0, -A0] the
 // column pass reads A0 alone and handles column j and j + n/2 together.  With
 // the adaptive beta (Section 4.3) a decision that reaches a step of the beta
-// choice pauses the grid; k_grid_bb_step takes the step on one workgroup and
-// the next column pass resumes from the paused pass's sums.
+// choice pauses the pass; workgroup 0 of the k_grid_ginv launch that follows
+// takes the step and the next column pass resumes from the paused pass's sums.
 // All sums are reduced in a fixed order, so runs are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include "abip_internal.h"
