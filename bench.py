@@ -450,7 +450,7 @@ def extra_basis_pursuit(abip, torch, cpu=True):
         "bb_probe_iters": binfo["bb_probe_iters"], "bb_estimates": binfo["bb_estimates"], "beta": binfo["beta"],
         "solve_s": bsolve, "us_per_iter": binfo["kernel_ms"] * 1e3 / max(1, binfo["admm_iters"]),
         "host_kkt": list(bkkt), "obj_vs_planted": abs(float(lp["c"] @ bxh) - lp["pstar"]) / (1 + lp["pstar"]),
-        "note": "each step of a beta choice pauses the grid for one host round trip"}
+        "note": "each step of a beta choice runs in workgroup 0 of the G^-1 kernel of the pass that reaches it"}
     if cpu:
         import oracle
         out["cpu_baseline"] = {
