@@ -482,7 +482,8 @@ __global__ __launch_bounds__(512) void k_grid_col(GridArgs g) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *g.ctl = c;
         return;
     }
-    constexpr int U32 = NCHW == 1 ? 8 : 4, U64 = NCHW == 1 ? 4 : 2;
+    // paired: half the columns per group (each owns two columns of the pass)
+    constexpr int U32 = (NCHW == 1 && !MIR) ? 8 : 4, U64 = NCHW == 1 ? 4 : 2;
     if (c.phase == 0) {
         if (grid_col_body<NCHW, float, U32, MIR>(g, g.A32, sd))
             grid_col_body<NCHW, double, U64, MIR>(g, g.A64, sd);     // switched to FP64 data
