@@ -182,3 +182,29 @@ def test_bb_sparse_trajectory_and_full_solve():
     k = oracle.kkt_relative(As.toarray(), sl["b"], sl["c"], _np(x), _np(y), _np(sv))
     assert max(k["pres"], k["dres"], k["gap"]) <= 1e-6
     w.free()
+
+
+@pytest.mark.parametrize("engine", ["grid", "streamed", "sparse"])
+def test_bb_with_sqrt_restart_matches_oracle(engine):
+    """The sqrt(gamma) restart (Algorithm 2) scales y in the pass that precedes the start point
+    a beta choice keeps: 300-update trajectories against the oracle under that rule."""
+    cap = 300
+    if engine == "sparse":
+        sl = lpgen.sparse_planted(150, 420, 2, density=0.02)
+        As, x, y, sv, info, (gy, gx, gs, sc) = _sparse(sl, max_admm_iters=cap, restart_rule=abip.ABIP_RESTART_SQRT)
+        A, b, c = As.toarray(), sl["b"], sl["c"]
+    else:
+        lp = lpgen.dense_planted(76, 159, 23)
+        x, y, sv, info, (gy, gx, gs, sc) = _gpu(lp, engine, max_admm_iters=cap, restart_rule=abip.ABIP_RESTART_SQRT)
+        A, b, c = lp["A"], lp["b"], lp["c"]
+    ref = oracle.solve(A, b, c, Settings(bb=True, max_admm_iters=cap, restart_rule="sqrt"))
+    print(f"{engine} sqrt: iters {info['admm_iters']} {ref['admm_iters']} ipm {info['ipm_iters']} {ref['ipm_iters']} "
+          f"beta {info['beta']:.10g} {ref['betas'][-1][1]:.10g}", flush=True)
+    assert info["status_name"] == ref["status_name"]
+    assert info["ipm_iters"] == ref["ipm_iters"] and info["admm_iters"] == ref["admm_iters"]
+    assert info["bb_estimates"] == sum(len(t) for (_, _, t) in ref["betas"])
+    assert abs(info["beta"] - ref["betas"][-1][1]) <= 1e-6 * ref["betas"][-1][1]
+    st = ref["state"]
+    scale = 1.0 + np.abs(st.u()).max()
+    for g, r in [(gy, st.y), (gx, st.x), (gs, st.s)]:
+        assert np.abs(_np(g) - r).max() <= 1e-6 * scale
