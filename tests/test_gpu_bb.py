@@ -208,3 +208,17 @@ def test_bb_with_sqrt_restart_matches_oracle(engine):
     scale = 1.0 + np.abs(st.u()).max()
     for g, r in [(gy, st.y), (gx, st.x), (gs, st.s)]:
         assert np.abs(_np(g) - r).max() <= 1e-6 * scale
+
+
+def test_bb_grid_two_row_chunks_fp32_bulk():
+    """The grid engine's two-chunk variant (2100 rows) with the adaptive beta and FP32 bulk."""
+    lp = lpgen.dense_planted(2100, 2300, 7)
+    s = abip.abip_default_settings(bb=1, engine=abip.ABIP_ENGINE_GRID, precision=abip.ABIP_PREC_FP32_POLISH)
+    w = abip.abip_setup(lp["A"], lp["b"], lp["c"], s)
+    x, y, sv, info = abip.abip_solve(w)
+    print(info["status_name"], info["admm_iters"], info["bb_estimates"], info["beta"], flush=True)
+    assert info["status"] == abip.ABIP_SOLVED and info["bb_estimates"] > 0
+    k = oracle.kkt_relative(lp["A"], lp["b"], lp["c"], _np(x), _np(y), _np(sv))
+    assert max(k["pres"], k["dres"], k["gap"]) <= 1e-6
+    assert abs(k["pobj"] - lp["pstar"]) <= 1e-5 * (1 + abs(lp["pstar"]))
+    w.free()
